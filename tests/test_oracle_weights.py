@@ -1,0 +1,112 @@
+"""Pins for O3 (Algorithm 3.6, density-compensation factors) -- CPU only."""
+import numpy as np
+import pytest
+
+from oracle import ndft, weights, metrics
+from paper_2302_00414_amd import workloads as wl
+
+
+@pytest.mark.parametrize("d,n,M", [(1, 16, 4), (1, 12, 8), (2, 12, 4), (2, 7, 6), (3, 6, 2)])
+def test_equispaced_weights_are_one_over_N(d, n, M):
+    """P2: for equispaced nodes with n > M, w = 1/N solves (3.14) exactly and
+    is the minimum-norm (n >= 2M) resp. unique least-squares (M < n < 2M)
+    solution, so Algorithm 3.6 must return 1/N."""
+    x = wl.equispaced_nodes(n, d)
+    N = x.shape[0]
+    w = weights.weights_lstsq(x, M)
+    np.testing.assert_allclose(w, np.full(N, 1.0 / N), atol=1e-14)
+    wc, info = weights.weights_cg(x, M)
+    np.testing.assert_allclose(wc, np.full(N, 1.0 / N), atol=1e-12)
+
+
+@pytest.mark.parametrize("d,N,M", [(1, 256, 32), (2, 1024, 8), (3, 4096, 4)])
+def test_exact_reconstruction_random_nodes(d, N, M):
+    """P3, Corollary 3.4 / Example 5.2: with |I_2M| < N the weights solve
+    (3.14), hence A^* W A = I and trigonometric polynomials are reconstructed
+    exactly."""
+    x = wl.uniform_nodes(N, d, 80 + d)
+    w = weights.weights_lstsq(x, M)
+    assert weights.residual(x, w, M) < 1e-12
+    A = ndft.fourier_matrix(x, M)
+    AWA = A.conj().T @ (w[:, None] * A)
+    assert np.abs(AWA - np.eye(M ** d)).max() < 1e-11
+    fh = wl.uniform_coefficients(M ** d, 81)
+    f = ndft.forward(x, fh, M)
+    assert metrics.rel_err(ndft.adjoint(x, w * f, M), fh) < 1e-12
+
+
+def test_overdetermined_is_not_exact():
+    """Example 5.2: once |I_2M| > N the least-squares weights no longer give
+    exact reconstruction."""
+    x = wl.uniform_nodes(64, 1, 90)
+    w = weights.weights_lstsq(x, 48)
+    fh = wl.uniform_coefficients(48, 91)
+    f = ndft.forward(x, fh, 48)
+    assert metrics.rel_err(ndft.adjoint(x, w * f, 48), fh) > 1e-3
+
+
+@pytest.mark.parametrize("d,N,M,pert", [(1, 80, 32, 0.0), (1, 256, 32, 1e-7), (2, 300, 8, 0.0),
+                                        (2, 1024, 8, 1e-8)])
+def test_error_bound(d, N, M, pert):
+    """P4, Theorem 3.14 (3.37): ||fhat - A^* W f||_p <= |I_M| eps ||fhat||_p
+    for p in {2, inf}, for any weights with residual eps on I_2M."""
+    x = wl.uniform_nodes(N, d, 100 + N)
+    w = weights.weights_lstsq(x, M) + pert * wl.complex_normal(N, 5)
+    eps = weights.residual(x, w, M)
+    for seed in range(3):
+        fh = wl.complex_normal(M ** d, 200 + seed)
+        rec = ndft.adjoint(x, w * ndft.forward(x, fh, M), M)
+        for p in (2, np.inf):
+            assert metrics.rel_err(rec, fh, p) <= M ** d * eps * (1 + 1e-9) + 1e-14
+
+
+@pytest.mark.parametrize("d,N,M,pert", [(1, 256, 32, 1e-6), (2, 1024, 8, 3e-6), (2, 600, 6, 1e-5)])
+def test_condition_bound(d, N, M, pert):
+    """P5, Theorem 3.15 (3.46): kappa_2(A^* W A) <= (1 + eps|I_M|)/(1 - eps|I_M|)."""
+    x = wl.uniform_nodes(N, d, 300 + N)
+    w = weights.weights_lstsq(x, M) + pert * wl.complex_normal(N, 6)
+    eps = weights.residual(x, w, M)
+    q = eps * M ** d
+    assert 0 < q < 1
+    A = ndft.fourier_matrix(x, M)
+    kappa = np.linalg.cond(A.conj().T @ (w[:, None] * A))
+    assert 1.0 <= kappa <= (1 + q) / (1 - q) * (1 + 1e-12)
+
+
+def test_conjugate_weights_solve_relaxed_system():
+    """P12: if A^T w = delta on I_M then A A^* conj(w) = 1_N (the link between
+    (3.10) and (3.63))."""
+    x = wl.uniform_nodes(500, 2, 400)
+    w = weights.weights_lstsq(x, 6)        # satisfies (3.14) on I_12, hence on I_6
+    got = ndft.forward(x, ndft.adjoint(x, np.conj(w), 6), 6)
+    np.testing.assert_allclose(got, np.ones(500), atol=1e-11)
+
+
+@pytest.mark.parametrize("d,N,M", [(1, 200, 16), (2, 700, 6), (1, 40, 32)])
+def test_cg_matches_dense(d, N, M):
+    """Algorithm 3.6 via CG on (3.15)/(3.16) (both branches) agrees with the
+    dense minimum-norm least-squares solution, with exact and NFFT matvecs."""
+    x = wl.uniform_nodes(N, d, 500 + N)
+    w = weights.weights_lstsq(x, M)
+    wc, info = weights.weights_cg(x, M, matvec="ndft", maxit=3000, tol=1e-14)
+    assert info["branch"] == ("3.15" if (2 * M) ** d <= N else "3.16")
+    if info["branch"] == "3.15":
+        assert metrics.rel_err(wc, w) < 1e-9
+    else:
+        # least squares: compare residual quality, the solution may be ill-determined
+        assert weights.residual(x, wc, M) <= 1.01 * weights.residual(x, w, M) + 1e-12
+    wn, _ = weights.weights_cg(x, M, matvec="nfft", m=8, maxit=3000, tol=1e-14)
+    assert metrics.rel_err(wn, wc) < 1e-8
+
+
+def test_planted_unaugmented_system_is_caught(monkeypatch):
+    """Solving (3.10) on I_M instead of the augmented (3.14) on I_2M (Corollary
+    3.4 says this is not enough) must break the exact-reconstruction pin."""
+    x = wl.uniform_nodes(256, 1, 81)
+    orig_A, orig_e0 = weights.fourier_matrix, weights._e0
+    monkeypatch.setattr(weights, "fourier_matrix", lambda x, M2: orig_A(x, M2 // 2))
+    monkeypatch.setattr(weights, "_e0", lambda M2, d: orig_e0(M2 // 2, d))
+    w = weights.weights_lstsq(x, 32)
+    fh = wl.uniform_coefficients(32, 81)
+    f = ndft.forward(x, fh, 32)
+    assert metrics.rel_err(ndft.adjoint(x, w * f, 32), fh) > 1e-3
