@@ -1,0 +1,170 @@
+/*
+ * nfft.h -- C ABI of the MI355X (gfx950) weighted adjoint NFFT library.
+ *
+ * Operations (Kircheis & Potts, arXiv 2302.00414):
+ *
+ *   adjoint : fhat ~ D^* F^* B^* W f                (eq. (3.7), Algorithm 3.7 step 1,
+ *                                                     evaluated by Algorithm 2.4)
+ *   forward : f    ~ B F D fhat                     (Algorithm 2.1, A ~ B F D)
+ *
+ * with the nonequispaced Fourier matrix A of eq. (2.7), W = diag(w) the
+ * density-compensation weights of eq. (3.6), D (2.13), F (2.14) and B (2.15).
+ * The window is the Kaiser-Bessel pair with shape b = pi (2 - 1/sigma),
+ * truncated to the closed cube |M_sigma x_t - l_t| <= m (index set (2.12)).
+ *
+ * Conventions shared by every entry point
+ *   - d in {1, 2, 3}; M even; I_M = {-M/2, ..., M/2-1}^d; M_sigma =
+ *     2 ceil(ceil(sigma M) / 2) as in the definition before (2.9).
+ *   - Nodes: N x d float64, row-major (node j at nodes[j*d .. j*d+d-1]), any
+ *     real coordinates; they are wrapped onto the torus [-1/2, 1/2)^d
+ *     (A is 1-periodic).
+ *   - Coefficient vectors fhat: M^d complex values in C order of k in I_M
+ *     (k_1 slowest, each k_t running from -M/2 to M/2-1).
+ *   - Sample vectors f: N complex values in the caller's node order.
+ *   - Complex numbers are interleaved (re, im): complex128 for an NFFT_F64
+ *     plan, complex64 for an NFFT_F32 plan. With nrhs right-hand sides the
+ *     vectors are stacked, right-hand side r at offset r*N (resp. r*M^d).
+ *   - Pointers passed to nfft_plan / nfft_set_weights may be host or device
+ *     memory; they are copied before the call returns and the caller keeps
+ *     ownership. Pointers passed to nfft_adjoint / nfft_forward must be
+ *     device memory of the plan's device; the work is enqueued on `stream`
+ *     (a hipStream_t, NULL = default stream) and the call returns without
+ *     waiting. The buffers must stay valid until the stream reaches that
+ *     point. Outputs are overwritten, never accumulated.
+ *   - Every entry point returns a status code (nfft_status); nothing is thrown
+ *     across the ABI. Arguments are validated before anything is enqueued; on
+ *     a validation failure the outputs are left untouched and a detail string
+ *     is available from nfft_last_error(plan) (or nfft_last_error(NULL) when
+ *     no plan exists). A device failure after enqueueing is reported by the
+ *     next call on the plan.
+ *   - A plan owns device workspace that each transform reuses: transforms of
+ *     one plan must not run concurrently on different streams.
+ */
+#ifndef NFFT_MI355X_H
+#define NFFT_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nfft_plan_s *nfft_plan_t;
+
+enum nfft_status {
+  NFFT_OK = 0,
+  NFFT_EINVAL = 1,       /* invalid argument (shape, range, non-finite node, null pointer) */
+  NFFT_ENOMEM = 2,       /* device allocation failed */
+  NFFT_EDEVICE = 3,      /* HIP runtime or kernel failure */
+  NFFT_ESTATE = 4,       /* call not allowed in the plan's state (e.g. adjoint before weights) */
+  NFFT_EUNSUPPORTED = 5  /* valid but not implemented (e.g. M_sigma not a power of two, m > 8) */
+};
+
+enum nfft_precision {
+  NFFT_F64 = 0, /* float64 nodes offsets, float64 window, complex128 data */
+  NFFT_F32 = 1  /* float32 node offsets (cell index kept as an integer), float32
+                   window and accumulation, complex64 data; deconvolution factors
+                   and plan-time geometry are computed in float64 */
+};
+
+/*
+ * nfft_plan -- precomputation for one node set (done once, Algorithm 3.7 step 0
+ * minus the weights). Wraps the nodes onto [-1/2, 1/2)^d, splits
+ * M_sigma x_j into a grid cell and an offset, sorts the nodes into spatial
+ * tiles of the oversampled grid (the column index sets (4.7) grouped by
+ * tile), and tabulates the deconvolution factors 1/(|I_Msigma| hat w(k)) of D.
+ *
+ *   out      receives the plan handle (set to NULL on failure)
+ *   d        dimension, 1..3
+ *   M        bandwidth per dimension, even, >= 2
+ *   sigma    oversampling factor, >= 1; M_sigma must be a power of two in
+ *            [8, 4096] (else NFFT_EUNSUPPORTED)
+ *   m        window truncation, 1..8, with M_sigma >= 2m + 2
+ *   N        number of nodes, 1 .. 2^31 - 1
+ *   nodes    N*d float64 (host or device), finite
+ *   precision  NFFT_F64 or NFFT_F32
+ *   max_rhs  largest nrhs later passed to adjoint/forward (workspace is sized for it), >= 1
+ *   stream   hipStream_t used for the plan's kernels; the call synchronises it
+ * Returns NFFT_OK, NFFT_EINVAL, NFFT_EUNSUPPORTED, NFFT_ENOMEM or NFFT_EDEVICE.
+ */
+int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
+              const double *nodes, int precision, int max_rhs, void *stream);
+
+/*
+ * nfft_set_weights -- store W = diag(w) of eq. (3.6); the weights are complex in general.
+ *   w  N complex128 values (host or device) in the caller's node order.
+ * The plan keeps its own copy (permuted to its internal order, rounded to
+ * complex64 for an NFFT_F32 plan); the call synchronises `stream`.
+ */
+int nfft_set_weights(nfft_plan_t plan, const double *w, void *stream);
+
+/*
+ * nfft_adjoint -- fhat = D^* F^* B^* W f for nrhs right-hand sides (eq. (3.7)):
+ * scale by w_j and spread with the window (Algorithm 2.4 step 1), d-variate FFT
+ * of the M_sigma^d grid (step 2), deconvolve by hat w and crop to I_M (step 3).
+ *   f     device, nrhs*N complex (plan precision), caller's node order
+ *   fhat  device, nrhs*M^d complex (plan precision), output
+ *   nrhs  1 .. max_rhs
+ * NFFT_ESTATE if nfft_set_weights has not been called.
+ */
+int nfft_adjoint(nfft_plan_t plan, const void *f, void *fhat, int nrhs, void *stream);
+
+/*
+ * nfft_forward -- f = B F D fhat for nrhs right-hand sides (Algorithm 2.1):
+ * deconvolve and zero-pad (step 1), inverse FFT (step 2), window sums at the
+ * nodes (step 3). No weights are involved.
+ *   fhat  device, nrhs*M^d complex (plan precision)
+ *   f     device, nrhs*N complex (plan precision), output in the caller's order
+ */
+int nfft_forward(nfft_plan_t plan, const void *fhat, void *f, int nrhs, void *stream);
+
+/* nfft_destroy -- wait for the plan's outstanding work and free it. NULL is a no-op. */
+int nfft_destroy(nfft_plan_t plan);
+
+/*
+ * nfft_footprint -- device bytes a plan with these parameters allocates
+ * (independent of the node positions except through N). -1 on invalid arguments.
+ */
+int64_t nfft_footprint(int d, int M, double sigma, int m, int64_t N, int precision, int max_rhs);
+
+/* nfft_strerror -- static text for a status code. */
+const char *nfft_strerror(int status);
+
+/* nfft_last_error -- detail of the last failure on `plan` (or of the last
+ * failure with no plan when plan is NULL); owned by the library. */
+const char *nfft_last_error(nfft_plan_t plan);
+
+/*
+ * nfft_plan_info -- plan geometry, written to out[0..n-1] (n <= 12):
+ *   0 d, 1 M, 2 M_sigma, 3 m, 4 N, 5 precision, 6 max_rhs,
+ *   7 tile edge (cells), 8 number of tiles, 9 number of spreading work items,
+ *   10 largest tile population, 11 device bytes allocated.
+ */
+int nfft_plan_info(nfft_plan_t plan, int64_t *out, int n);
+
+/*
+ * nfft_permutation -- the plan's internal node order: perm[i] is the caller
+ * index of the i-th node in tile order (int32, host memory, N entries).
+ */
+int nfft_permutation(nfft_plan_t plan, int32_t *perm_host);
+
+/*
+ * Stage timing. With profiling on, nfft_adjoint and nfft_forward record HIP
+ * events on their stream around each kernel stage; nfft_stage_times waits for
+ * them and returns, per stage, the accumulated milliseconds and the number of
+ * calls since the last reset:
+ *   out[2*s] = milliseconds, out[2*s+1] = calls, for s = 0..NFFT_STAGES-1
+ * Stages: 0 spread (adjoint step 1), 1 FFT pass with tile merge (first pass of
+ * step 2), 2 remaining FFT passes with deconvolution (step 2 and 3),
+ * 3 forward FFT passes with deconvolution (Algorithm 2.1 steps 1-2),
+ * 4 forward window sums (Algorithm 2.1 step 3).
+ */
+#define NFFT_STAGES 5
+int nfft_set_profiling(nfft_plan_t plan, int enable);
+int nfft_stage_times(nfft_plan_t plan, double *out, int n, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NFFT_MI355X_H */

@@ -1,0 +1,699 @@
+// Host side of the library: plan construction, workspace, the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/nfft.h"
+#include "internal.hpp"
+
+using nfft::cplx;
+using nfft::Geom;
+
+namespace {
+
+constexpr int kItemNodes = 256;  // nodes per spreading work item
+
+thread_local std::string g_noplan_error;
+
+struct StageEvents {
+  hipEvent_t ev[4];
+  int n;       // events used
+  int kind;    // 0 adjoint, 1 forward
+};
+
+}  // namespace
+
+struct nfft_plan_s {
+  int device = 0;
+  int d = 0, M = 0, Ms = 0, m = 0, prec = 0, max_rhs = 1;
+  double sigma = 1.0, b = 0.0;
+  int64_t N = 0;
+  Geom g{};
+  int maxpop = 0;
+  int64_t bytes = 0;
+  bool has_weights = false;
+  std::string last_error;
+  // device buffers
+  int32_t* perm = nullptr;
+  uint32_t* loc = nullptr;
+  void* frac = nullptr;
+  void* w = nullptr;
+  int32_t* item_start = nullptr;
+  int32_t* item_count = nullptr;
+  int32_t* item_bin = nullptr;
+  int32_t* item_first = nullptr;
+  void* sub = nullptr;
+  void* bufA = nullptr;
+  void* bufB = nullptr;
+  void* grid = nullptr;
+  void* tw = nullptr;
+  void* fac = nullptr;
+  std::vector<void*> allocs;
+  // profiling
+  bool profiling = false;
+  std::vector<StageEvents> pending;
+  std::vector<hipEvent_t> event_pool;
+  double stage_ms[NFFT_STAGES] = {0};
+  int64_t stage_calls[NFFT_STAGES] = {0};
+};
+
+namespace {
+
+int fail(nfft_plan_t p, int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (p)
+    p->last_error = buf;
+  else
+    g_noplan_error = buf;
+  return status;
+}
+
+#define HIP_TRY(p, expr)                                                                     \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail((p), e_ == hipErrorOutOfMemory ? NFFT_ENOMEM : NFFT_EDEVICE, "%s: %s (%s)", \
+                  #expr, hipGetErrorString(e_), __func__);                                   \
+  } while (0)
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int oversampled(int M, double sigma) {
+  double a = std::ceil(sigma * (double)M);
+  return 2 * (int)std::ceil(a / 2.0);
+}
+
+int tile_edge(int d, int Ms) {
+  // tile-local cells are packed into 8 bits per dimension, so T <= 256
+  const int t = d == 1 ? 256 : (d == 2 ? 32 : 8);
+  return std::min(t, Ms);
+}
+
+size_t cbytes(int prec) { return prec == NFFT_F64 ? 16 : 8; }
+size_t rbytes(int prec) { return prec == NFFT_F64 ? 8 : 4; }
+
+// Largest padded-tile LDS size a spreading work-group may use.
+constexpr size_t kMaxTileLds = 144 * 1024;
+
+int validate(int d, int M, double sigma, int m, int64_t N, int precision, int max_rhs,
+             nfft_plan_t p) {
+  if (d < 1 || d > 3) return fail(p, NFFT_EINVAL, "d = %d, expected 1, 2 or 3", d);
+  if (M < 2 || (M % 2) != 0) return fail(p, NFFT_EINVAL, "M = %d, expected an even M >= 2", M);
+  if (!(sigma >= 1.0) || !std::isfinite(sigma))
+    return fail(p, NFFT_EINVAL, "sigma = %g, expected a finite sigma >= 1", sigma);
+  if (m < 1) return fail(p, NFFT_EINVAL, "m = %d, expected m >= 1", m);
+  if (N < 1 || N > 0x7fffffffLL) return fail(p, NFFT_EINVAL, "N = %lld out of range", (long long)N);
+  if (precision != NFFT_F64 && precision != NFFT_F32)
+    return fail(p, NFFT_EINVAL, "precision = %d, expected NFFT_F64 or NFFT_F32", precision);
+  if (max_rhs < 1 || max_rhs > 65535)
+    return fail(p, NFFT_EINVAL, "max_rhs = %d, expected 1..65535", max_rhs);
+  if (sigma * M > 1e7) return fail(p, NFFT_EUNSUPPORTED, "sigma * M too large");
+  const int Ms = oversampled(M, sigma);
+  if (Ms < 2 * m + 2)
+    return fail(p, NFFT_EINVAL, "M_sigma = %d < 2m + 2 = %d (window wraps onto itself)", Ms,
+                2 * m + 2);
+  if (m > 8) return fail(p, NFFT_EUNSUPPORTED, "m = %d > 8 is not built", m);
+  if (!is_pow2(Ms) || Ms < 8 || Ms > 4096)
+    return fail(p, NFFT_EUNSUPPORTED, "M_sigma = %d: only powers of two in [8, 4096] are built",
+                Ms);
+  const int T = tile_edge(d, Ms);
+  const int P = T + 2 * m;
+  size_t Ptot = 1;
+  for (int t = 0; t < d; ++t) Ptot *= (size_t)P;
+  if (Ptot * cbytes(precision) > kMaxTileLds)
+    return fail(p, NFFT_EUNSUPPORTED, "padded tile of %zu cells does not fit in LDS (d = %d, m = %d)",
+                Ptot, d, m);
+  if (M > Ms) return fail(p, NFFT_EINVAL, "M_sigma < M");
+  return NFFT_OK;
+}
+
+int64_t ipow(int64_t a, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= a;
+  return r;
+}
+
+// Modified Bessel function I_0 by its power series (all terms positive).
+long double bessel_i0(long double z) {
+  const long double q = z * z / 4.0L;
+  long double term = 1.0L, sum = 1.0L;
+  for (int n = 1; n < 2000; ++n) {
+    term *= q / ((long double)n * (long double)n);
+    sum += term;
+    if (term < 1e-24L * sum) break;
+  }
+  return sum;
+}
+
+template <typename T>
+int dalloc(nfft_plan_t p, T** ptr, size_t bytes) {
+  *ptr = nullptr;
+  if (bytes == 0) bytes = 16;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess)
+    return fail(p, e == hipErrorOutOfMemory ? NFFT_ENOMEM : NFFT_EDEVICE,
+                "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  p->allocs.push_back(q);
+  p->bytes += (int64_t)bytes;
+  *ptr = static_cast<T*>(q);
+  return NFFT_OK;
+}
+
+#define TRY(expr)                  \
+  do {                             \
+    int s_ = (expr);               \
+    if (s_ != NFFT_OK) return s_;  \
+  } while (0)
+
+void free_plan(nfft_plan_t p) {
+  if (!p) return;
+  for (auto& se : p->pending)
+    for (int i = 0; i < se.n; ++i) p->event_pool.push_back(se.ev[i]);
+  for (auto e : p->event_pool) (void)hipEventDestroy(e);
+  for (void* q : p->allocs) (void)hipFree(q);
+  delete p;
+}
+
+struct ScopedFree {
+  std::vector<void*> ptrs;
+  ~ScopedFree() {
+    for (void* q : ptrs) (void)hipFree(q);
+  }
+};
+
+template <typename R>
+int build_tables(nfft_plan_t p) {
+  const int Ms = p->Ms, M = p->M, m = p->m;
+  const long double b = (long double)p->b;
+  std::vector<R> fac(M);
+  for (int kidx = 0; kidx < M; ++kidx) {
+    const int k = kidx - M / 2;
+    const long double a = 2.0L * 3.14159265358979323846264338327950288L * k / Ms;
+    const long double arg = (long double)m * std::sqrt(b * b - a * a);
+    const long double val = std::exp(b * m) /
+                            (3.14159265358979323846264338327950288L * bessel_i0(arg));
+    fac[kidx] = (R)((k % 2 == 0) ? val : -val);
+  }
+  std::vector<cplx<R>> tw(Ms);
+  for (int q = 0; q < Ms; ++q) {
+    const long double ang = 2.0L * 3.14159265358979323846264338327950288L * q / Ms;
+    tw[q].x = (R)std::cos(ang);
+    tw[q].y = (R)(-std::sin(ang));
+  }
+  TRY(dalloc(p, &p->fac, M * sizeof(R)));
+  TRY(dalloc(p, &p->tw, Ms * sizeof(cplx<R>)));
+  HIP_TRY(p, hipMemcpy(p->fac, fac.data(), M * sizeof(R), hipMemcpyHostToDevice));
+  HIP_TRY(p, hipMemcpy(p->tw, tw.data(), Ms * sizeof(cplx<R>), hipMemcpyHostToDevice));
+  return NFFT_OK;
+}
+
+template <typename R>
+int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
+  const int64_t N = p->N;
+  const int d = p->d;
+  Geom& g = p->g;
+  ScopedFree tmp;
+  auto talloc = [&](void** q, size_t bytes) -> int {
+    hipError_t e = hipMalloc(q, bytes ? bytes : 16);
+    if (e != hipSuccess)
+      return fail(p, e == hipErrorOutOfMemory ? NFFT_ENOMEM : NFFT_EDEVICE,
+                  "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    tmp.ptrs.push_back(*q);
+    return NFFT_OK;
+  };
+  void *d_nodes, *bin, *loc_u, *frac_u, *err, *counts, *rank, *chunk_count, *offsets, *bstart;
+  const int64_t nchunks = (N + nfft::kRankChunk - 1) / nfft::kRankChunk;
+  TRY(talloc(&d_nodes, N * d * sizeof(double)));
+  TRY(talloc(&bin, N * sizeof(int32_t)));
+  TRY(talloc(&loc_u, N * sizeof(uint32_t)));
+  TRY(talloc(&frac_u, N * d * sizeof(double)));
+  TRY(talloc(&err, sizeof(int)));
+  TRY(talloc(&counts, g.nbins * sizeof(int32_t)));
+  TRY(talloc(&rank, N * sizeof(int32_t)));
+  TRY(talloc(&chunk_count, (size_t)nchunks * g.nbins * sizeof(int32_t)));
+  TRY(talloc(&offsets, (size_t)nchunks * g.nbins * sizeof(int32_t)));
+  TRY(talloc(&bstart, (g.nbins + 1) * sizeof(int32_t)));
+
+  HIP_TRY(p, hipMemcpyAsync(d_nodes, nodes, N * d * sizeof(double), hipMemcpyDefault, s));
+  HIP_TRY(p, hipMemsetAsync(err, 0, sizeof(int), s));
+  HIP_TRY(p, hipMemsetAsync(counts, 0, g.nbins * sizeof(int32_t), s));
+  HIP_TRY(p, hipMemsetAsync(chunk_count, 0, (size_t)nchunks * g.nbins * sizeof(int32_t), s));
+  HIP_TRY(p, nfft::launch_encode((const double*)d_nodes, N, g, (int32_t*)bin, (uint32_t*)loc_u,
+                                 (double*)frac_u, (int*)err, s));
+  HIP_TRY(p, nfft::launch_count((const int32_t*)bin, N, (int32_t*)counts, s));
+  std::vector<int32_t> hc(g.nbins);
+  int herr = 0;
+  HIP_TRY(p, hipMemcpyAsync(hc.data(), counts, g.nbins * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipStreamSynchronize(s));
+  if (herr) return fail(p, NFFT_EINVAL, "nodes contain a non-finite coordinate");
+
+  // tile starts and work items (at most kItemNodes nodes of one tile each)
+  std::vector<int32_t> hstart(g.nbins + 1);
+  std::vector<int32_t> istart, icount, ibin, ifirst(g.nbins + 1);
+  int64_t acc = 0;
+  p->maxpop = 0;
+  for (int b = 0; b < g.nbins; ++b) {
+    hstart[b] = (int32_t)acc;
+    ifirst[b] = (int32_t)istart.size();
+    p->maxpop = std::max(p->maxpop, hc[b]);
+    for (int k = 0; k < hc[b]; k += kItemNodes) {
+      istart.push_back((int32_t)(acc + k));
+      icount.push_back(std::min(kItemNodes, hc[b] - k));
+      ibin.push_back(b);
+    }
+    acc += hc[b];
+  }
+  hstart[g.nbins] = (int32_t)acc;
+  ifirst[g.nbins] = (int32_t)istart.size();
+  g.nsub = (int)istart.size();
+  HIP_TRY(p, hipMemcpyAsync(bstart, hstart.data(), (g.nbins + 1) * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
+
+  HIP_TRY(p, nfft::launch_rank((const int32_t*)bin, N, g.nbins, (int32_t*)rank,
+                               (int32_t*)chunk_count, s));
+  HIP_TRY(p, nfft::launch_chunk_offsets((const int32_t*)chunk_count, (const int32_t*)bstart,
+                                        nchunks, g.nbins, (int32_t*)offsets, s));
+  TRY(dalloc(p, &p->perm, N * sizeof(int32_t)));
+  TRY(dalloc(p, &p->loc, N * sizeof(uint32_t)));
+  TRY(dalloc(p, &p->frac, N * d * sizeof(R)));
+  HIP_TRY(p, nfft::launch_scatter<R>((const int32_t*)bin, (const int32_t*)rank,
+                                     (const int32_t*)offsets, (const uint32_t*)loc_u,
+                                     (const double*)frac_u, N, d, g.nbins, p->perm, p->loc,
+                                     (R*)p->frac, s));
+
+  const size_t ni = std::max<size_t>(1, istart.size());
+  TRY(dalloc(p, &p->item_start, ni * sizeof(int32_t)));
+  TRY(dalloc(p, &p->item_count, ni * sizeof(int32_t)));
+  TRY(dalloc(p, &p->item_bin, ni * sizeof(int32_t)));
+  TRY(dalloc(p, &p->item_first, (g.nbins + 1) * sizeof(int32_t)));
+  if (!istart.empty()) {
+    HIP_TRY(p, hipMemcpyAsync(p->item_start, istart.data(), istart.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(p, hipMemcpyAsync(p->item_count, icount.data(), icount.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(p, hipMemcpyAsync(p->item_bin, ibin.data(), ibin.size() * 4, hipMemcpyHostToDevice, s));
+  }
+  HIP_TRY(p, hipMemcpyAsync(p->item_first, ifirst.data(), (g.nbins + 1) * 4, hipMemcpyHostToDevice, s));
+
+  TRY(dalloc(p, &p->w, N * sizeof(cplx<R>)));
+  const int64_t R_ = p->max_rhs;
+  TRY(dalloc(p, &p->sub, (size_t)R_ * g.nsub * g.Ptot * sizeof(cplx<R>)));
+  const int64_t Ms = p->Ms, M = p->M;
+  if (d >= 2) TRY(dalloc(p, &p->bufA, (size_t)R_ * ipow(Ms, d - 1) * M * sizeof(cplx<R>)));
+  if (d == 3) TRY(dalloc(p, &p->bufB, (size_t)R_ * Ms * M * M * sizeof(cplx<R>)));
+  TRY(dalloc(p, &p->grid, (size_t)R_ * ipow(Ms, d) * sizeof(cplx<R>)));
+  TRY(build_tables<R>(p));
+  HIP_TRY(p, hipStreamSynchronize(s));
+  return NFFT_OK;
+}
+
+template <typename R>
+int lines_per_wg(int L, bool inner_major) {
+  const int budget = 64 * 1024;
+  int lmax = std::max(1, budget / (2 * L * (int)sizeof(cplx<R>)));
+  int want = inner_major ? 16 : std::max(1, 2048 / L);
+  return std::max(1, std::min(lmax, want));
+}
+
+template <typename R>
+nfft::FftArgs<R> fft_args(nfft_plan_t p) {
+  nfft::FftArgs<R> a{};
+  a.tw = (const cplx<R>*)p->tw;
+  a.fac = (const R*)p->fac;
+  a.g = p->g;
+  a.item_first = p->item_first;
+  a.sub = (const cplx<R>*)p->sub;
+  a.sub_bs = (int64_t)p->g.nsub * p->g.Ptot;
+  return a;
+}
+
+void record(nfft_plan_t p, StageEvents& se, hipStream_t s) {
+  if (!p->profiling) return;
+  hipEvent_t e;
+  if (!p->event_pool.empty()) {
+    e = p->event_pool.back();
+    p->event_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    return;
+  }
+  (void)hipEventRecord(e, s);
+  se.ev[se.n++] = e;
+}
+
+template <typename R>
+int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t s) {
+  const Geom& g = p->g;
+  const int64_t Ms = p->Ms, M = p->M;
+  StageEvents se{};
+  se.kind = 0;
+  record(p, se, s);
+  nfft::SpreadArgs<R> sa{};
+  sa.loc = p->loc;
+  sa.frac = (const R*)p->frac;
+  sa.w = (const cplx<R>*)p->w;
+  sa.perm = p->perm;
+  sa.f = (const cplx<R>*)f;
+  sa.sub = (cplx<R>*)p->sub;
+  sa.item_start = p->item_start;
+  sa.item_count = p->item_count;
+  sa.f_rs = p->N;
+  sa.sub_rs = (int64_t)g.nsub * g.Ptot;
+  sa.b = (R)p->b;
+  sa.mr = (R)p->m;
+  sa.edge = (R)(p->b * std::exp(-p->b * p->m));
+  sa.g = g;
+  HIP_TRY(p, nfft::launch_spread<R>(sa, nrhs, s));
+  record(p, se, s);
+
+  const int L = (int)Ms;
+  nfft::FftArgs<R> a = fft_args<R>(p);
+  cplx<R>* out = (cplx<R>*)fhat;
+  if (p->d == 1) {
+    a.n_outer = 1; a.n_inner = 1;
+    a.out = out; a.out_bs = M; a.out_os = 0; a.out_is = 0; a.out_es = 1;
+    a.inner_major = 0; a.lpw = 1;
+    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, nfft::kLoadMerge, nfft::kStoreCropScaled, nrhs, s));
+    record(p, se, s);
+  } else if (p->d == 2) {
+    cplx<R>* A = (cplx<R>*)p->bufA;
+    a.n_outer = Ms; a.n_inner = 1;
+    a.out = A; a.out_bs = Ms * M; a.out_os = M; a.out_is = 0; a.out_es = 1;
+    a.inner_major = 0; a.lpw = lines_per_wg<R>(L, false);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, nfft::kLoadMerge, nfft::kStoreCropScaled, nrhs, s));
+    record(p, se, s);
+    nfft::FftArgs<R> c = fft_args<R>(p);
+    c.n_outer = 1; c.n_inner = M;
+    c.in = A; c.in_bs = Ms * M; c.in_os = 0; c.in_is = 1; c.in_es = M;
+    c.out = out; c.out_bs = M * M; c.out_os = 0; c.out_is = 1; c.out_es = M;
+    c.inner_major = 1; c.lpw = lines_per_wg<R>(L, true);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, false, nfft::kLoadStrided, nfft::kStoreCropScaled, nrhs, s));
+  } else {
+    cplx<R>* A = (cplx<R>*)p->bufA;
+    cplx<R>* B = (cplx<R>*)p->bufB;
+    a.n_outer = Ms * Ms; a.n_inner = 1;
+    a.out = A; a.out_bs = Ms * Ms * M; a.out_os = M; a.out_is = 0; a.out_es = 1;
+    a.inner_major = 0; a.lpw = lines_per_wg<R>(L, false);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, nfft::kLoadMerge, nfft::kStoreCropScaled, nrhs, s));
+    record(p, se, s);
+    nfft::FftArgs<R> c = fft_args<R>(p);
+    c.n_outer = Ms; c.n_inner = M;
+    c.in = A; c.in_bs = Ms * Ms * M; c.in_os = Ms * M; c.in_is = 1; c.in_es = M;
+    c.out = B; c.out_bs = Ms * M * M; c.out_os = M * M; c.out_is = 1; c.out_es = M;
+    c.inner_major = 1; c.lpw = lines_per_wg<R>(L, true);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, false, nfft::kLoadStrided, nfft::kStoreCropScaled, nrhs, s));
+    nfft::FftArgs<R> e = fft_args<R>(p);
+    e.n_outer = 1; e.n_inner = M * M;
+    e.in = B; e.in_bs = Ms * M * M; e.in_os = 0; e.in_is = 1; e.in_es = M * M;
+    e.out = out; e.out_bs = M * M * M; e.out_os = 0; e.out_is = 1; e.out_es = M * M;
+    e.inner_major = 1; e.lpw = lines_per_wg<R>(L, true);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(e, L, false, nfft::kLoadStrided, nfft::kStoreCropScaled, nrhs, s));
+  }
+  record(p, se, s);
+  if (p->profiling && se.n > 0) p->pending.push_back(se);
+  return NFFT_OK;
+}
+
+template <typename R>
+int run_forward(nfft_plan_t p, const void* fhat, void* f, int nrhs, hipStream_t s) {
+  const Geom& g = p->g;
+  const int64_t Ms = p->Ms, M = p->M;
+  const int L = (int)Ms;
+  StageEvents se{};
+  se.kind = 1;
+  record(p, se, s);
+  const cplx<R>* in = (const cplx<R>*)fhat;
+  cplx<R>* G = (cplx<R>*)p->grid;
+  if (p->d == 1) {
+    nfft::FftArgs<R> a = fft_args<R>(p);
+    a.n_outer = 1; a.n_inner = 1;
+    a.in = in; a.in_bs = M; a.in_os = 0; a.in_is = 0; a.in_es = 1;
+    a.out = G; a.out_bs = Ms; a.out_os = 0; a.out_is = 0; a.out_es = 1;
+    a.inner_major = 0; a.lpw = 1;
+    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, true, nfft::kLoadPadScaled, nfft::kStoreFull, nrhs, s));
+  } else if (p->d == 2) {
+    cplx<R>* A = (cplx<R>*)p->bufA;
+    nfft::FftArgs<R> a = fft_args<R>(p);
+    a.n_outer = 1; a.n_inner = M;
+    a.in = in; a.in_bs = M * M; a.in_os = 0; a.in_is = 1; a.in_es = M;
+    a.out = A; a.out_bs = Ms * M; a.out_os = 0; a.out_is = 1; a.out_es = M;
+    a.inner_major = 1; a.lpw = lines_per_wg<R>(L, true);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, true, nfft::kLoadPadScaled, nfft::kStoreFull, nrhs, s));
+    nfft::FftArgs<R> c = fft_args<R>(p);
+    c.n_outer = Ms; c.n_inner = 1;
+    c.in = A; c.in_bs = Ms * M; c.in_os = M; c.in_is = 0; c.in_es = 1;
+    c.out = G; c.out_bs = Ms * Ms; c.out_os = Ms; c.out_is = 0; c.out_es = 1;
+    c.inner_major = 0; c.lpw = lines_per_wg<R>(L, false);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, true, nfft::kLoadPadScaled, nfft::kStoreFull, nrhs, s));
+  } else {
+    cplx<R>* A = (cplx<R>*)p->bufA;
+    cplx<R>* B = (cplx<R>*)p->bufB;
+    nfft::FftArgs<R> a = fft_args<R>(p);
+    a.n_outer = 1; a.n_inner = M * M;
+    a.in = in; a.in_bs = M * M * M; a.in_os = 0; a.in_is = 1; a.in_es = M * M;
+    a.out = B; a.out_bs = Ms * M * M; a.out_os = 0; a.out_is = 1; a.out_es = M * M;
+    a.inner_major = 1; a.lpw = lines_per_wg<R>(L, true);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, true, nfft::kLoadPadScaled, nfft::kStoreFull, nrhs, s));
+    nfft::FftArgs<R> c = fft_args<R>(p);
+    c.n_outer = Ms; c.n_inner = M;
+    c.in = B; c.in_bs = Ms * M * M; c.in_os = M * M; c.in_is = 1; c.in_es = M;
+    c.out = A; c.out_bs = Ms * Ms * M; c.out_os = Ms * M; c.out_is = 1; c.out_es = M;
+    c.inner_major = 1; c.lpw = lines_per_wg<R>(L, true);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, true, nfft::kLoadPadScaled, nfft::kStoreFull, nrhs, s));
+    nfft::FftArgs<R> e = fft_args<R>(p);
+    e.n_outer = Ms * Ms; e.n_inner = 1;
+    e.in = A; e.in_bs = Ms * Ms * M; e.in_os = M; e.in_is = 0; e.in_es = 1;
+    e.out = G; e.out_bs = Ms * Ms * Ms; e.out_os = Ms; e.out_is = 0; e.out_es = 1;
+    e.inner_major = 0; e.lpw = lines_per_wg<R>(L, false);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(e, L, true, nfft::kLoadPadScaled, nfft::kStoreFull, nrhs, s));
+  }
+  record(p, se, s);
+  nfft::InterpArgs<R> ia{};
+  ia.loc = p->loc;
+  ia.frac = (const R*)p->frac;
+  ia.perm = p->perm;
+  ia.grid = G;
+  ia.f = (cplx<R>*)f;
+  ia.item_start = p->item_start;
+  ia.item_count = p->item_count;
+  ia.item_bin = p->item_bin;
+  ia.grid_rs = ipow(Ms, p->d);
+  ia.f_rs = p->N;
+  ia.b = (R)p->b;
+  ia.mr = (R)p->m;
+  ia.edge = (R)(p->b * std::exp(-p->b * p->m));
+  ia.g = g;
+  HIP_TRY(p, nfft::launch_interp<R>(ia, nrhs, s));
+  record(p, se, s);
+  if (p->profiling && se.n > 0) p->pending.push_back(se);
+  return NFFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nfft_strerror(int status) {
+  switch (status) {
+    case NFFT_OK: return "success";
+    case NFFT_EINVAL: return "invalid argument";
+    case NFFT_ENOMEM: return "device memory allocation failed";
+    case NFFT_EDEVICE: return "HIP device or kernel failure";
+    case NFFT_ESTATE: return "call not allowed in the plan's current state";
+    case NFFT_EUNSUPPORTED: return "parameters valid but not supported by this build";
+    default: return "unknown status";
+  }
+}
+
+const char* nfft_last_error(nfft_plan_t plan) {
+  return plan ? plan->last_error.c_str() : g_noplan_error.c_str();
+}
+
+int64_t nfft_footprint(int d, int M, double sigma, int m, int64_t N, int precision, int max_rhs) {
+  if (validate(d, M, sigma, m, N, precision, max_rhs, nullptr) != NFFT_OK) return -1;
+  const int64_t Ms = oversampled(M, sigma);
+  const int T = tile_edge(d, (int)Ms);
+  const int64_t nb = Ms / T;
+  const int64_t nbins = ipow(nb, d);
+  const int64_t P = T + 2 * m;
+  const int64_t Ptot = ipow(P, d);
+  const int64_t cb = (int64_t)cbytes(precision), rb = (int64_t)rbytes(precision);
+  const int64_t nsub_max = nbins + (N + kItemNodes - 1) / kItemNodes;
+  const int64_t R_ = max_rhs;
+  int64_t bytes = 0;
+  bytes += N * 4 + N * 4 + N * d * rb;                     // perm, loc, frac
+  bytes += std::max<int64_t>(1, nsub_max) * 4 * 3 + (nbins + 1) * 4;  // item tables
+  bytes += N * cb;                                        // weights
+  bytes += R_ * nsub_max * Ptot * cb;                     // padded tile sums
+  if (d >= 2) bytes += R_ * ipow(Ms, d - 1) * M * cb;
+  if (d == 3) bytes += R_ * Ms * M * M * cb;
+  bytes += R_ * ipow(Ms, d) * cb;                         // forward grid
+  bytes += M * rb + Ms * cb;                              // tables
+  return bytes;
+}
+
+int nfft_plan(nfft_plan_t* out, int d, int M, double sigma, int m, int64_t N,
+              const double* nodes, int precision, int max_rhs, void* stream) {
+  if (!out) return fail(nullptr, NFFT_EINVAL, "out is NULL");
+  *out = nullptr;
+  int st = validate(d, M, sigma, m, N, precision, max_rhs, nullptr);
+  if (st != NFFT_OK) return st;
+  if (!nodes) return fail(nullptr, NFFT_EINVAL, "nodes is NULL");
+  nfft_plan_t p = new (std::nothrow) nfft_plan_s();
+  if (!p) return fail(nullptr, NFFT_ENOMEM, "host allocation failed");
+  p->d = d;
+  p->M = M;
+  p->sigma = sigma;
+  p->m = m;
+  p->N = N;
+  p->prec = precision;
+  p->max_rhs = max_rhs;
+  p->Ms = oversampled(M, sigma);
+  p->b = M_PI * (2.0 - 1.0 / sigma);
+  Geom& g = p->g;
+  g.d = d;
+  g.Ms = p->Ms;
+  g.M = M;
+  g.m = m;
+  g.T = tile_edge(d, p->Ms);
+  g.nb = p->Ms / g.T;
+  g.P = g.T + 2 * m;
+  g.Ptot = (int)ipow(g.P, d);
+  g.nbins = (int)ipow(g.nb, d);
+  g.N = N;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    free_plan(p);
+    return fail(nullptr, NFFT_EDEVICE, "no HIP device available");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  st = precision == NFFT_F64 ? build_plan<double>(p, nodes, s) : build_plan<float>(p, nodes, s);
+  if (st != NFFT_OK) {
+    g_noplan_error = p->last_error;
+    (void)hipStreamSynchronize(s);
+    free_plan(p);
+    return st;
+  }
+  *out = p;
+  return NFFT_OK;
+}
+
+int nfft_set_weights(nfft_plan_t p, const double* w, void* stream) {
+  if (!p) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
+  if (!w) return fail(p, NFFT_EINVAL, "w is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  void* dw = nullptr;
+  HIP_TRY(p, hipMalloc(&dw, p->N * 2 * sizeof(double)));
+  ScopedFree tmp;
+  tmp.ptrs.push_back(dw);
+  HIP_TRY(p, hipMemcpyAsync(dw, w, p->N * 2 * sizeof(double), hipMemcpyDefault, s));
+  if (p->prec == NFFT_F64)
+    HIP_TRY(p, nfft::launch_permute_weights<double>((const double*)dw, p->perm, p->N,
+                                                    (cplx<double>*)p->w, s));
+  else
+    HIP_TRY(p, nfft::launch_permute_weights<float>((const double*)dw, p->perm, p->N,
+                                                   (cplx<float>*)p->w, s));
+  HIP_TRY(p, hipStreamSynchronize(s));
+  p->has_weights = true;
+  return NFFT_OK;
+}
+
+int nfft_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, void* stream) {
+  if (!p) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
+  if (!f || !fhat) return fail(p, NFFT_EINVAL, "f or fhat is NULL");
+  if (nrhs < 1 || nrhs > p->max_rhs)
+    return fail(p, NFFT_EINVAL, "nrhs = %d outside 1..max_rhs = %d", nrhs, p->max_rhs);
+  if (!p->has_weights) return fail(p, NFFT_ESTATE, "nfft_set_weights has not been called");
+  HIP_TRY(p, hipGetLastError());
+  hipStream_t s = (hipStream_t)stream;
+  return p->prec == NFFT_F64 ? run_adjoint<double>(p, f, fhat, nrhs, s)
+                             : run_adjoint<float>(p, f, fhat, nrhs, s);
+}
+
+int nfft_forward(nfft_plan_t p, const void* fhat, void* f, int nrhs, void* stream) {
+  if (!p) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
+  if (!f || !fhat) return fail(p, NFFT_EINVAL, "f or fhat is NULL");
+  if (nrhs < 1 || nrhs > p->max_rhs)
+    return fail(p, NFFT_EINVAL, "nrhs = %d outside 1..max_rhs = %d", nrhs, p->max_rhs);
+  HIP_TRY(p, hipGetLastError());
+  hipStream_t s = (hipStream_t)stream;
+  return p->prec == NFFT_F64 ? run_forward<double>(p, fhat, f, nrhs, s)
+                             : run_forward<float>(p, fhat, f, nrhs, s);
+}
+
+int nfft_destroy(nfft_plan_t p) {
+  if (!p) return NFFT_OK;
+  int st = NFFT_OK;
+  if (hipDeviceSynchronize() != hipSuccess) st = NFFT_EDEVICE;
+  free_plan(p);
+  return st;
+}
+
+int nfft_plan_info(nfft_plan_t p, int64_t* out, int n) {
+  if (!p || !out || n < 0) return fail(p, NFFT_EINVAL, "bad arguments to nfft_plan_info");
+  const int64_t v[12] = {p->d, p->M, p->Ms, p->m, p->N, p->prec, p->max_rhs,
+                         p->g.T, p->g.nbins, p->g.nsub, p->maxpop, p->bytes};
+  for (int i = 0; i < n && i < 12; ++i) out[i] = v[i];
+  return NFFT_OK;
+}
+
+int nfft_permutation(nfft_plan_t p, int32_t* perm_host) {
+  if (!p || !perm_host) return fail(p, NFFT_EINVAL, "bad arguments to nfft_permutation");
+  HIP_TRY(p, hipMemcpy(perm_host, p->perm, p->N * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return NFFT_OK;
+}
+
+int nfft_set_profiling(nfft_plan_t p, int enable) {
+  if (!p) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
+  p->profiling = enable != 0;
+  return NFFT_OK;
+}
+
+int nfft_stage_times(nfft_plan_t p, double* out, int n, int reset) {
+  if (!p) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
+  for (auto& se : p->pending) {
+    HIP_TRY(p, hipEventSynchronize(se.ev[se.n - 1]));
+    float ms = 0.f;
+    if (se.kind == 0) {
+      // adjoint: start, after spread, after first FFT pass, end
+      const int map[3] = {0, 1, 2};
+      for (int i = 0; i + 1 < se.n && i < 3; ++i) {
+        HIP_TRY(p, hipEventElapsedTime(&ms, se.ev[i], se.ev[i + 1]));
+        p->stage_ms[map[i]] += ms;
+        p->stage_calls[map[i]] += 1;
+      }
+    } else {
+      const int map[2] = {3, 4};
+      for (int i = 0; i + 1 < se.n && i < 2; ++i) {
+        HIP_TRY(p, hipEventElapsedTime(&ms, se.ev[i], se.ev[i + 1]));
+        p->stage_ms[map[i]] += ms;
+        p->stage_calls[map[i]] += 1;
+      }
+    }
+    for (int i = 0; i < se.n; ++i) p->event_pool.push_back(se.ev[i]);
+  }
+  p->pending.clear();
+  if (out)
+    for (int sidx = 0; sidx < NFFT_STAGES && 2 * sidx + 1 < n; ++sidx) {
+      out[2 * sidx] = p->stage_ms[sidx];
+      out[2 * sidx + 1] = (double)p->stage_calls[sidx];
+    }
+  if (reset)
+    for (int sidx = 0; sidx < NFFT_STAGES; ++sidx) {
+      p->stage_ms[sidx] = 0;
+      p->stage_calls[sidx] = 0;
+    }
+  return NFFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,200 @@
+"""PyTorch binding of the C ABI (include/nfft.h).
+
+Device memory and streams come from PyTorch; every step of the transform runs
+in the HIP library. Function names mirror the C entry points; :class:`Plan`
+wraps them for convenience.
+
+    plan = Plan(nodes, M=256, sigma=2.0, m=6, precision="f32")
+    plan.set_weights(w)            # complex128, caller's node order
+    fhat = plan.adjoint(f)         # fhat ~ D^* F^* B^* W f   (eq. (3.7))
+    f2   = plan.forward(fhat)      # f ~ B F D fhat           (Algorithm 2.1)
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import NFFT_F32, NFFT_F64, NfftError, check  # noqa: F401
+
+_PREC = {"f64": NFFT_F64, "f32": NFFT_F32, NFFT_F64: NFFT_F64, NFFT_F32: NFFT_F32}
+_CDTYPE = {NFFT_F64: torch.complex128, NFFT_F32: torch.complex64}
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _as_f64_nodes(nodes) -> torch.Tensor:
+    if isinstance(nodes, np.ndarray):
+        nodes = torch.from_numpy(np.ascontiguousarray(nodes, dtype=np.float64))
+    t = nodes.to(torch.float64).contiguous()
+    if t.dim() == 1:
+        t = t.reshape(-1, 1)
+    return t
+
+
+def oversampled_size(M: int, sigma: float) -> int:
+    """M_sigma = 2 ceil(ceil(sigma M)/2) (host-side shape arithmetic)."""
+    import math
+    return 2 * math.ceil(math.ceil(sigma * M) / 2)
+
+
+# ------------------------------------------------------------ C-ABI mirrors
+def nfft_plan(d: int, M: int, sigma: float, m: int, nodes: torch.Tensor, precision=NFFT_F64,
+              max_rhs: int = 1, stream=None) -> ctypes.c_void_p:
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    st = lib.nfft_plan(ctypes.byref(h), d, M, float(sigma), m, nodes.shape[0],
+                       ctypes.c_void_p(nodes.data_ptr()), _PREC[precision], max_rhs,
+                       _stream_ptr(stream))
+    check(st, None)
+    return h
+
+
+def nfft_set_weights(plan, w: torch.Tensor, stream=None) -> None:
+    check(_lib.load().nfft_set_weights(plan, ctypes.c_void_p(w.data_ptr()), _stream_ptr(stream)), plan)
+
+
+def nfft_adjoint(plan, f: torch.Tensor, fhat: torch.Tensor, nrhs: int, stream=None) -> None:
+    check(_lib.load().nfft_adjoint(plan, ctypes.c_void_p(f.data_ptr()),
+                                   ctypes.c_void_p(fhat.data_ptr()), nrhs, _stream_ptr(stream)), plan)
+
+
+def nfft_forward(plan, fhat: torch.Tensor, f: torch.Tensor, nrhs: int, stream=None) -> None:
+    check(_lib.load().nfft_forward(plan, ctypes.c_void_p(fhat.data_ptr()),
+                                   ctypes.c_void_p(f.data_ptr()), nrhs, _stream_ptr(stream)), plan)
+
+
+def nfft_destroy(plan) -> None:
+    check(_lib.load().nfft_destroy(plan), None)
+
+
+def nfft_footprint(d: int, M: int, sigma: float, m: int, N: int, precision=NFFT_F64,
+                   max_rhs: int = 1) -> int:
+    return int(_lib.load().nfft_footprint(d, M, float(sigma), m, N, _PREC[precision], max_rhs))
+
+
+def nfft_strerror(status: int) -> str:
+    return _lib.load().nfft_strerror(status).decode()
+
+
+def nfft_last_error(plan=None) -> str:
+    return _lib.load().nfft_last_error(plan).decode(errors="replace")
+
+
+def nfft_plan_info(plan) -> dict:
+    out = (ctypes.c_int64 * 12)()
+    check(_lib.load().nfft_plan_info(plan, out, 12), plan)
+    keys = ("d", "M", "Ms", "m", "N", "precision", "max_rhs", "tile", "tiles", "items",
+            "max_tile_nodes", "bytes")
+    return dict(zip(keys, (int(v) for v in out)))
+
+
+def nfft_permutation(plan, N: int) -> np.ndarray:
+    out = np.empty(N, dtype=np.int32)
+    check(_lib.load().nfft_permutation(plan, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), plan)
+    return out
+
+
+def nfft_set_profiling(plan, enable: bool) -> None:
+    check(_lib.load().nfft_set_profiling(plan, int(bool(enable))), plan)
+
+
+STAGE_NAMES = ("spread", "fft_merge", "fft_rest_deconv", "fwd_fft_deconv", "fwd_sums")
+
+
+def nfft_stage_times(plan, reset: bool = False) -> dict:
+    n = 2 * _lib.NFFT_STAGES
+    out = (ctypes.c_double * n)()
+    check(_lib.load().nfft_stage_times(plan, out, n, int(bool(reset))), plan)
+    return {name: (out[2 * i], int(out[2 * i + 1])) for i, name in enumerate(STAGE_NAMES)}
+
+
+# ------------------------------------------------------------------- Plan
+class Plan:
+    """One node set on one device (nodes wrapped onto [-1/2, 1/2)^d)."""
+
+    def __init__(self, nodes, M: int, sigma: float = 2.0, m: int = 6, precision="f64",
+                 max_rhs: int = 1, device: Optional[torch.device] = None, stream=None):
+        self.device = torch.device(device or "cuda")
+        x = _as_f64_nodes(nodes).to(self.device)
+        self.N, self.d = x.shape
+        self.M, self.sigma, self.m = M, float(sigma), m
+        self.prec = _PREC[precision]
+        self.cdtype = _CDTYPE[self.prec]
+        self.max_rhs = max_rhs
+        self.Ms = oversampled_size(M, sigma)
+        self._h = None
+        with torch.cuda.device(self.device):
+            self._h = nfft_plan(self.d, M, sigma, m, x, self.prec, max_rhs, stream)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_weights(self, w, stream=None) -> None:
+        if isinstance(w, np.ndarray):
+            w = torch.from_numpy(np.ascontiguousarray(w, dtype=np.complex128))
+        w = w.to(torch.complex128).reshape(-1).contiguous().to(self.device)
+        if w.numel() != self.N:
+            raise ValueError(f"expected {self.N} weights, got {w.numel()}")
+        nfft_set_weights(self._h, w, stream)
+
+    def _coerce(self, t, n):
+        if isinstance(t, np.ndarray):
+            t = torch.from_numpy(t)
+        t = t.to(device=self.device, dtype=self.cdtype).contiguous()
+        if t.numel() % n:
+            raise ValueError(f"size {t.numel()} is not a multiple of {n}")
+        return t
+
+    def adjoint(self, f, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """fhat = D^* F^* B^* W f; f is (N,) or (nrhs, N)."""
+        single = f.dim() == 1 if isinstance(f, torch.Tensor) else np.ndim(f) == 1
+        f = self._coerce(f, self.N)
+        nrhs = f.numel() // self.N
+        K = self.M ** self.d
+        if out is None:
+            out = torch.empty((nrhs, K), dtype=self.cdtype, device=self.device)
+        nfft_adjoint(self._h, f, out, nrhs, stream)
+        return out.reshape(K) if single else out
+
+    def forward(self, fhat, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """f = B F D fhat; fhat is (M^d,) or (nrhs, M^d)."""
+        K = self.M ** self.d
+        single = fhat.dim() == 1 if isinstance(fhat, torch.Tensor) else np.ndim(fhat) == 1
+        fhat = self._coerce(fhat, K)
+        nrhs = fhat.numel() // K
+        if out is None:
+            out = torch.empty((nrhs, self.N), dtype=self.cdtype, device=self.device)
+        nfft_forward(self._h, fhat, out, nrhs, stream)
+        return out.reshape(self.N) if single else out
+
+    def info(self) -> dict:
+        return nfft_plan_info(self._h)
+
+    def permutation(self) -> np.ndarray:
+        return nfft_permutation(self._h, self.N)
+
+    def set_profiling(self, on: bool) -> None:
+        nfft_set_profiling(self._h, on)
+
+    def stage_times(self, reset: bool = False) -> dict:
+        return nfft_stage_times(self._h, reset)
+
+    def close(self) -> None:
+        if self._h is not None:
+            nfft_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

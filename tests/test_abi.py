@@ -1,0 +1,98 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point that include/nfft.h declares, and validates arguments
+before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2302_00414_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "nfft.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nfft_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declarations_match_binding():
+    assert set(_declared()) == set(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_texts():
+    lib = _lib.load()
+    for s in range(6):
+        assert lib.nfft_strerror(s)
+    assert b"unknown" in lib.nfft_strerror(99)
+
+
+@pytest.mark.parametrize("args,status", [
+    ((0, 32, 2.0, 4), _lib.NFFT_EINVAL),       # d out of range
+    ((4, 32, 2.0, 4), _lib.NFFT_EINVAL),
+    ((2, 31, 2.0, 4), _lib.NFFT_EINVAL),       # odd M
+    ((2, 0, 2.0, 4), _lib.NFFT_EINVAL),
+    ((2, 32, 0.5, 4), _lib.NFFT_EINVAL),       # sigma < 1
+    ((2, 32, float("nan"), 4), _lib.NFFT_EINVAL),
+    ((2, 32, 2.0, 0), _lib.NFFT_EINVAL),       # m < 1
+    ((2, 4, 2.0, 4), _lib.NFFT_EINVAL),        # M_sigma = 8 < 2m + 2
+    ((2, 32, 2.0, 9), _lib.NFFT_EUNSUPPORTED),  # m > 8
+    ((2, 30, 2.0, 4), _lib.NFFT_EUNSUPPORTED),  # M_sigma = 60 not a power of two
+    ((3, 64, 2.0, 8), _lib.NFFT_OK),           # valid in float32 ...
+])
+def test_plan_validation_before_device(args, status):
+    lib = _lib.load()
+    x = np.zeros((4, args[0] if 1 <= args[0] <= 3 else 1))
+    h = ctypes.c_void_p(123)
+    st = lib.nfft_plan(ctypes.byref(h), *args, 4, x.ctypes.data, _lib.NFFT_F32, 1, None)
+    if status == _lib.NFFT_OK:
+        # validation passed; without a GPU the plan fails at the device
+        assert st in (_lib.NFFT_OK, _lib.NFFT_EDEVICE)
+        if st == _lib.NFFT_OK:
+            lib.nfft_destroy(h)
+    else:
+        assert st == status
+        assert h.value is None
+        assert lib.nfft_last_error(None)
+
+
+def test_f64_3d_large_m_unsupported():
+    """The padded tile of a 3-D float64 plan with m = 8 does not fit in LDS."""
+    lib = _lib.load()
+    x = np.zeros((4, 3))
+    h = ctypes.c_void_p()
+    st = lib.nfft_plan(ctypes.byref(h), 3, 64, 2.0, 8, 4, x.ctypes.data, _lib.NFFT_F64, 1, None)
+    assert st == _lib.NFFT_EUNSUPPORTED
+
+
+def test_bad_counts_and_pointers():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    x = np.zeros((4, 2))
+    assert lib.nfft_plan(ctypes.byref(h), 2, 32, 2.0, 4, 0, x.ctypes.data, 0, 1, None) == _lib.NFFT_EINVAL
+    assert lib.nfft_plan(ctypes.byref(h), 2, 32, 2.0, 4, 4, None, 0, 1, None) == _lib.NFFT_EINVAL
+    assert lib.nfft_plan(ctypes.byref(h), 2, 32, 2.0, 4, 4, x.ctypes.data, 7, 1, None) == _lib.NFFT_EINVAL
+    assert lib.nfft_plan(ctypes.byref(h), 2, 32, 2.0, 4, 4, x.ctypes.data, 0, 0, None) == _lib.NFFT_EINVAL
+    assert lib.nfft_plan(None, 2, 32, 2.0, 4, 4, x.ctypes.data, 0, 1, None) == _lib.NFFT_EINVAL
+    assert lib.nfft_adjoint(None, None, None, 1, None) == _lib.NFFT_EINVAL
+    assert lib.nfft_forward(None, None, None, 1, None) == _lib.NFFT_EINVAL
+    assert lib.nfft_set_weights(None, None, None) == _lib.NFFT_EINVAL
+    assert lib.nfft_destroy(None) == _lib.NFFT_OK
+
+
+def test_footprint_grows_with_inputs():
+    lib = _lib.load()
+    a = lib.nfft_footprint(2, 256, 2.0, 6, 262144, _lib.NFFT_F32, 1)
+    b = lib.nfft_footprint(2, 256, 2.0, 6, 262144, _lib.NFFT_F64, 1)
+    c = lib.nfft_footprint(2, 256, 2.0, 6, 262144, _lib.NFFT_F32, 32)
+    assert 0 < a < b and c > 16 * a
+    assert lib.nfft_footprint(2, 31, 2.0, 6, 10, 0, 1) == -1

@@ -1,0 +1,254 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Small cases compare every output element with the step-by-step oracle NFFT
+(O2, identical window) and with the exact sums (O1); full-size workloads
+compare sampled outputs computed one by one from the exact sums.
+Tolerances (relative l2 error): float64 path 1e-10, float32 path 1e-5; for
+float64 against O2 only rounding separates the two, so 1e-12 is used there.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ndft, nfft as onfft, metrics, window
+from paper_2302_00414_amd import workloads as wl
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+TOL_O2 = {"f64": 1e-12, "f32": 1e-5}
+TOL_EXACT = {"f64": 1e-10, "f32": 1e-5}
+
+
+def _plan(x, M, sigma, m, prec, max_rhs=1):
+    from paper_2302_00414_amd.nfft import Plan
+    print(f"[case] N={x.shape[0]} d={x.shape[1]} M={M} sigma={sigma} m={m} {prec} rhs={max_rhs}",
+          flush=True)
+    return Plan(x, M, sigma, m, precision=prec, max_rhs=max_rhs, device="cuda:0")
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+SMALL = [
+    # d, M, sigma, m, N
+    (1, 64, 2.0, 6, 900),
+    (1, 1024, 2.0, 4, 5000),     # 8 tiles of 256
+    (2, 32, 2.0, 4, 3000),       # 2 x 2 tiles
+    (2, 48, 4.0 / 3.0, 5, 2500),  # M_sigma = 64, sigma != 2
+    (2, 64, 2.0, 7, 7001),       # ragged N
+    (2, 8, 2.0, 3, 50),          # single tile (16 <= 32), periodic self-neighbour
+    (3, 16, 2.0, 4, 4000),       # 4^3 tiles of 8
+    (3, 8, 2.0, 2, 777),         # 2^3 tiles
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("d,M,sigma,m,N", SMALL)
+def test_adjoint_matches_oracle(d, M, sigma, m, N, prec):
+    x = wl.uniform_nodes(N, d, 100 + N)
+    w = (1.0 + 0.3 * wl.complex_normal(N, 101)) / N
+    f = wl.complex_normal(N, 102)
+    p = _plan(x, M, sigma, m, prec)
+    p.set_weights(w)
+    got = _np(p.adjoint(torch.from_numpy(f)))
+    ref = onfft.adjoint(x, w * f, M, sigma, m)
+    assert metrics.rel_err(got, ref) <= TOL_O2[prec]
+    if m >= 6 or prec == "f32":
+        exact = ndft.adjoint(x, w * f, M)
+        assert metrics.rel_err(got, exact) <= max(TOL_EXACT[prec], 2 * metrics.rel_err(ref, exact))
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("d,M,sigma,m,N", SMALL)
+def test_forward_matches_oracle(d, M, sigma, m, N, prec):
+    x = wl.uniform_nodes(N, d, 200 + N)
+    fh = wl.complex_normal(M ** d, 201)
+    p = _plan(x, M, sigma, m, prec)
+    got = _np(p.forward(torch.from_numpy(fh)))
+    ref = onfft.forward(x, fh, M, sigma, m)
+    assert metrics.rel_err(got, ref) <= TOL_O2[prec]
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_edge_cases(prec):
+    """Grid-aligned nodes (closed edge), duplicates in one cell, nodes at
+    -1/2 and just below +1/2, coordinates outside the torus (wrapped), a
+    crowded tile that splits into several work items, empty tiles."""
+    M, sigma, m = 32, 2.0, 6
+    Ms = window.oversampled_size(M, sigma)
+    rng = np.random.default_rng(7)
+    pts = [np.zeros((700, 2)),                                   # 700 duplicates at 0
+           (rng.integers(-Ms // 2, Ms // 2, size=(300, 2)) / Ms),  # on grid points
+           np.array([[-0.5, -0.5], [0.5 - 1e-17, 0.25], [0.4999999999, -0.5]]),
+           rng.uniform(-3.0, 3.0, size=(200, 2)),                 # outside, wraps
+           0.01 * rng.standard_normal((900, 2))]                  # crowded centre
+    x = np.concatenate(pts)
+    N = x.shape[0]
+    w = (1.0 + 0.5 * wl.complex_normal(N, 8)) / N
+    f = wl.complex_normal(N, 9)
+    p = _plan(x, M, sigma, m, prec)
+    info = p.info()
+    assert info["items"] > info["tiles"] - 3
+    p.set_weights(w)
+    got = _np(p.adjoint(torch.from_numpy(f)))
+    ref = onfft.adjoint(x, w * f, M, sigma, m)
+    assert metrics.rel_err(got, ref) <= TOL_O2[prec]
+    fh = wl.complex_normal(M * M, 10)
+    got_f = _np(p.forward(torch.from_numpy(fh)))
+    assert metrics.rel_err(got_f, onfft.forward(x, fh, M, sigma, m)) <= TOL_O2[prec]
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_single_node_closed_form(prec):
+    """P7 through the GPU: one node, f = 1, w = 1 gives h_k = exp(-2 pi i k.x)."""
+    x = np.array([[0.123456789, -0.3141592653]])
+    p = _plan(x, 16, 2.0, 6, prec)
+    p.set_weights(np.ones(1))
+    got = _np(p.adjoint(torch.ones(1, dtype=torch.complex128)))
+    K = ndft.index_set(16, 2)
+    assert metrics.rel_err(got, np.exp(-2j * math.pi * K @ x[0])) <= TOL_EXACT[prec]
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adjointness_on_gpu(prec):
+    """P6: <B F D fhat, g> = <fhat, D^* F^* B^* g> between the GPU forward
+    and the GPU adjoint (unit weights)."""
+    x = wl.uniform_nodes(5000, 2, 300)
+    p = _plan(x, 64, 2.0, 5, prec)
+    p.set_weights(np.ones(5000))
+    fh = wl.complex_normal(64 * 64, 301)
+    g = wl.complex_normal(5000, 302)
+    a = _np(p.forward(torch.from_numpy(fh)))
+    b = _np(p.adjoint(torch.from_numpy(g)))
+    lhs, rhs = np.vdot(g, a), np.vdot(b, fh)
+    assert abs(lhs - rhs) <= (1e-12 if prec == "f64" else 1e-5) * abs(lhs)
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_multi_rhs_equals_separate(prec):
+    x = wl.uniform_nodes(3000, 2, 310)
+    w = (1.0 + 0.2 * wl.complex_normal(3000, 311)) / 3000
+    F = wl.complex_normal((5, 3000), 312)
+    p = _plan(x, 32, 2.0, 6, prec, max_rhs=5)
+    p.set_weights(w)
+    both = _np(p.adjoint(torch.from_numpy(F)))
+    ref = onfft.adjoint(x, w[None, :] * F, 32, 2.0, 6)
+    for r in range(5):
+        one = _np(p.adjoint(torch.from_numpy(F[r])))
+        assert metrics.rel_err(both[r], one) <= (1e-14 if prec == "f64" else 1e-6)
+        assert metrics.rel_err(both[r], ref[r]) <= TOL_O2[prec]
+    fh = wl.complex_normal((5, 1024), 313)
+    fb = _np(p.forward(torch.from_numpy(fh)))
+    for r in range(5):
+        assert metrics.rel_err(fb[r], _np(p.forward(torch.from_numpy(fh[r])))) <= 1e-14
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_node_permutation_invariance(prec):
+    """P9: permuting the nodes (with their samples and weights) leaves the
+    result unchanged up to rounding."""
+    x = wl.uniform_nodes(4000, 2, 320)
+    w = (1.0 + 0.2 * wl.complex_normal(4000, 321)) / 4000
+    f = wl.complex_normal(4000, 322)
+    perm = np.random.default_rng(5).permutation(4000)
+    p1 = _plan(x, 32, 2.0, 6, prec)
+    p1.set_weights(w)
+    a = _np(p1.adjoint(torch.from_numpy(f)))
+    p2 = _plan(x[perm], 32, 2.0, 6, prec)
+    p2.set_weights(w[perm])
+    b = _np(p2.adjoint(torch.from_numpy(f[perm])))
+    assert metrics.rel_err(b, a) <= (1e-13 if prec == "f64" else 1e-6)
+    p1.close()
+    p2.close()
+
+
+def test_state_and_argument_errors():
+    from paper_2302_00414_amd import _lib
+    from paper_2302_00414_amd.nfft import NfftError, Plan
+    x = wl.uniform_nodes(100, 2, 330)
+    p = _plan(x, 16, 2.0, 4, "f64", max_rhs=2)
+    f = torch.zeros(100, dtype=torch.complex128, device="cuda:0")
+    with pytest.raises(NfftError) as e:
+        p.adjoint(f)
+    assert e.value.status == _lib.NFFT_ESTATE
+    p.set_weights(np.ones(100))
+    with pytest.raises(NfftError) as e:
+        p.adjoint(torch.zeros((3, 100), dtype=torch.complex128, device="cuda:0"))
+    assert e.value.status == _lib.NFFT_EINVAL
+    bad = x.copy()
+    bad[5, 1] = np.nan
+    with pytest.raises(NfftError) as e:
+        Plan(bad, 16, 2.0, 4, device="cuda:0")
+    assert e.value.status == _lib.NFFT_EINVAL
+    p.close()
+
+
+# ------------------------------------------------------------ full workloads
+def _sample_k(M, d, n, seed):
+    K = ndft.index_set(M, d)
+    rng = np.random.default_rng(seed)
+    sel = rng.choice(K.shape[0], size=n, replace=False)
+    corners = [0, K.shape[0] - 1, K.shape[0] // 2, K.shape[0] // 2 + M // 2]
+    sel = np.unique(np.concatenate([sel, corners]))
+    return sel, K[sel]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_polar_512x512_M256(prec):
+    """Polar grid R = T = 512 (N = 262144), M = 256, sigma = 2, m = 6, area
+    weights: sampled outputs against the exact weighted sums."""
+    R = T = 512
+    x = wl.polar_nodes(R, T)
+    w = wl.polar_area_weights(R, T)
+    f = wl.complex_normal(x.shape[0], 3)
+    p = _plan(x, 256, 2.0, 6, prec)
+    p.set_weights(w)
+    got = _np(p.adjoint(torch.from_numpy(f)))
+    sel, K = _sample_k(256, 2, 300, 11)
+    exact = ndft.adjoint_at(x, w * f, K)
+    assert metrics.rel_err(got[sel], exact) <= TOL_EXACT[prec]
+    p.close()
+
+
+def test_jittered_3d_M64():
+    """Jittered 128 x 64 x 64 grid (N = 524288), d = 3, M = 64, m = 4, float32:
+    sampled outputs against the exact sums."""
+    x = wl.jittered_nodes((128, 64, 64), 4)
+    N = x.shape[0]
+    w = np.full(N, 1.0 / N, dtype=np.complex128)
+    f = wl.complex_normal(N, 5)
+    p = _plan(x, 64, 2.0, 4, "f32")
+    p.set_weights(w)
+    got = _np(p.adjoint(torch.from_numpy(f)))
+    sel, K = _sample_k(64, 3, 200, 12)
+    exact = ndft.adjoint_at(x, w * f, K)
+    assert metrics.rel_err(got[sel], exact) <= TOL_EXACT["f32"]
+    p.close()
+
+
+def test_spiral_32_rhs():
+    """Archimedean spiral N = 131072, M = 256, m = 6, 32 right-hand sides in one
+    float32 call: every right-hand side's sampled outputs against the exact sums."""
+    N, M, nrhs = 131072, 256, 32
+    x = wl.spiral_nodes(N, M)
+    w = wl.spiral_area_weights(N, M)
+    F = wl.complex_normal((nrhs, N), 6)
+    p = _plan(x, M, 2.0, 6, "f32", max_rhs=nrhs)
+    p.set_weights(w)
+    got = _np(p.adjoint(torch.from_numpy(F)))
+    sel, K = _sample_k(M, 2, 60, 13)
+    exact = ndft.adjoint_at(x, w[None, :] * F, K)
+    errs = metrics.rel_err_rows(got[:, sel], exact)
+    assert errs.max() <= TOL_EXACT["f32"]
+    p.close()
