@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Throughput of the weighted adjoint NFFT on one MI355X.
+
+Workload: polar grid with signed radius, R = T = 512 (N = 262144 nodes), d = 2,
+M = 256, sigma = 2, Kaiser-Bessel m = 6, geometric area weights, one
+right-hand side of complex samples per step. A step is one reconstruction
+fhat = D^* F^* B^* W f (spreading, FFT, deconvolution and crop) with the plan,
+the weights and the samples already resident in device memory.
+
+Prints one JSON line: points/s of the float32 path (value), per-step latency
+percentiles, the float64 path's figures, the roofline position of the
+spreading kernel (timed with HIP events on the library's stream inside the
+timed region) and the FP64 CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "nonuniform points/s for weighted adjoint NFFT (2D M=256, rel err<=1e-5); p99 latency"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+R_POLAR = T_POLAR = 512
+M, SIGMA, MW, D = 256, 2.0, 6, 2
+
+
+def spread_algorithmic_bytes(N, Ms, d, prec):
+    """Minimum HBM bytes of one spreading launch: per node the encoded
+    position (d offsets + one packed cell word), the weight and the sample;
+    plus the M_sigma^d grid of cell sums once."""
+    rb = 8 if prec == "f64" else 4
+    cb = 2 * rb
+    per_node = d * rb + 4 + cb + cb
+    return N * per_node + Ms ** d * cb
+
+
+def spread_flops(N, m, d):
+    """Two real multiply-adds per complex-by-real cell update, (2m)^d cells."""
+    return 4 * (2 * m) ** d * N
+
+
+def run_gpu(prec, x, w, f, steps, warmup):
+    import torch
+    from paper_2302_00414_amd.nfft import Plan
+
+    dev = torch.device("cuda:0")
+    plan = Plan(x, M, SIGMA, MW, precision=prec, device=dev)
+    plan.set_weights(w)
+    cdt = torch.complex64 if prec == "f32" else torch.complex128
+    fd = torch.from_numpy(f).to(device=dev, dtype=cdt)
+    out = torch.empty(M ** D, dtype=cdt, device=dev)
+    for _ in range(warmup):
+        plan.adjoint(fd, out=out)
+    torch.cuda.synchronize()
+
+    # timed region: K back-to-back steps, stage events recorded by the library
+    plan.stage_times(reset=True)
+    plan.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        plan.adjoint(fd, out=out)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    plan.set_profiling(False)
+    stages = plan.stage_times(reset=True)
+
+    # per-request latency: one call at a time, synchronised
+    lat = []
+    for _ in range(min(steps, 300)):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        plan.adjoint(fd, out=out)
+        b.record()
+        b.synchronize()
+        lat.append(a.elapsed_time(b))
+    res = out.cpu().numpy().astype(np.complex128)
+    info = plan.info()
+    plan.close()
+    ms_per_step = max(gpu_ms, wall * 1e3) / steps
+    return dict(ms_per_step=ms_per_step, gpu_ms=gpu_ms, wall_s=wall, stages=stages,
+                lat=np.array(lat), out=res, info=info)
+
+
+def cpu_baseline(x, w, f, gpu_out32, gpu_out64, budget_s=12.0):
+    """The FP64 oracle on the host: the step-by-step NFFT (O2) on the whole
+    workload, repeated up to the time budget; the exact sums (O1) at sampled
+    frequencies for the accuracy of the GPU results."""
+    from oracle import ndft, nfft as onfft, metrics
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    c = w * f
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        ref = onfft.adjoint(x, c, M, SIGMA, MW)
+        reps += 1
+        if time.perf_counter() - t0 > budget_s or reps >= 20:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    K = ndft.index_set(M, D)
+    rng = np.random.default_rng(17)
+    sel = np.unique(np.concatenate([rng.choice(K.shape[0], 256, replace=False), [0, K.shape[0] - 1]]))
+    t1 = time.perf_counter()
+    exact = ndft.adjoint_at(x, c, K[sel])
+    t_exact = time.perf_counter() - t1
+    return dict(
+        baseline=dict(value=x.shape[0] / dt, unit="points/s", cores=int(cores), kind="oracle",
+                      sample=f"step-by-step FP64 NFFT oracle on the full polar 512x512 workload, "
+                             f"{reps} run(s), {dt:.2f} s each; exact sums at {len(sel)} sampled "
+                             f"frequencies took {t_exact:.2f} s"),
+        err32_vs_exact=metrics.rel_err(gpu_out32[sel], exact),
+        err64_vs_exact=metrics.rel_err(gpu_out64[sel], exact),
+        err32_vs_nfft_oracle=metrics.rel_err(gpu_out32, ref),
+        err64_vs_nfft_oracle=metrics.rel_err(gpu_out64, ref),
+    )
+
+
+def traffic_record(kernel_prefix):
+    """HBM bytes per launch from committed counter summaries, if they were taken
+    on the current kernel source (sha256 of csrc/spread.hip recorded with them)."""
+    path = os.path.join(ROOT, "profiles", "spread_traffic_polar512.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2302_00414_amd", "csrc", "spread.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != h:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the reconstruction of one request runs on one "
+              "device and this build has no multi-GPU path (run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2302_00414_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    x = wl.polar_nodes(R_POLAR, T_POLAR)
+    w = wl.polar_area_weights(R_POLAR, T_POLAR)
+    f = wl.complex_normal(x.shape[0], 3)
+    N = x.shape[0]
+    Ms = 2 * M
+
+    r32 = run_gpu("f32", x, w, f, args.steps, args.warmup)
+    r64 = run_gpu("f64", x, w, f, args.steps, args.warmup)
+
+    sp_ms, sp_calls = r32["stages"]["spread"]
+    sp_avg_s = sp_ms / max(sp_calls, 1) / 1e3
+    alg = spread_algorithmic_bytes(N, Ms, D, "f32")
+    achieved = alg / sp_avg_s / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=traffic_record("spread"),
+                    kernel="spread_kernel<float,2,6>", avg_launch_us=round(sp_avg_s * 1e6, 3),
+                    algorithmic_bytes_per_launch=alg,
+                    alu_tflops=round(spread_flops(N, MW, D) / sp_avg_s / 1e12, 3),
+                    alu_frac_fp32=round(spread_flops(N, MW, D) / sp_avg_s / 1e12 / FP32_PEAK_TFLOPS, 5))
+    stage_us = {k: round(v[0] / max(v[1], 1) * 1e3, 3) for k, v in r32["stages"].items() if v[1]}
+    stage_us64 = {k: round(v[0] / max(v[1], 1) * 1e3, 3) for k, v in r64["stages"].items() if v[1]}
+
+    line = {
+        "metric": METRIC,
+        "value": N / (r32["ms_per_step"] / 1e3),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "polar R=T=512 (N=262144), d=2, M=256, sigma=2, KB m=6, "
+                               "area weights, 1 rhs complex64, weighted adjoint NFFT",
+                   "global_batch": 1, "nodes": N, "M": M, "sigma": SIGMA, "m": MW},
+        "latency_ms": {"p50": float(np.percentile(r32["lat"], 50)),
+                       "p99": float(np.percentile(r32["lat"], 99))},
+        "stage_us": stage_us,
+        "f64": {"value": N / (r64["ms_per_step"] / 1e3), "ms_per_step": r64["ms_per_step"],
+                "latency_ms": {"p50": float(np.percentile(r64["lat"], 50)),
+                               "p99": float(np.percentile(r64["lat"], 99))},
+                "stage_us": stage_us64},
+        "roofline": roofline,
+        "plan": r32["info"],
+        "paper_context": "Table 5.1, M=256 linogram N=524288: 6.6443e-02 s per reconstruction "
+                         "(7.89e6 points/s), hardware not stated",
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(x, w, f, r32["out"], r64["out"])
+        line["cpu_baseline"] = cb["baseline"]
+        line["rel_err"] = {"f32_vs_exact_sampled": cb["err32_vs_exact"],
+                           "f64_vs_exact_sampled": cb["err64_vs_exact"],
+                           "f32_vs_nfft_oracle": cb["err32_vs_nfft_oracle"],
+                           "f64_vs_nfft_oracle": cb["err64_vs_nfft_oracle"]}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

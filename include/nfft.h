@@ -122,8 +122,9 @@ int nfft_forward(nfft_plan_t plan, const void *fhat, void *f, int nrhs, void *st
 int nfft_destroy(nfft_plan_t plan);
 
 /*
- * nfft_footprint -- device bytes a plan with these parameters allocates
- * (independent of the node positions except through N). -1 on invalid arguments.
+ * nfft_footprint -- upper bound of the device bytes a plan with these
+ * parameters allocates (the exact figure depends on how the nodes fill the
+ * tiles; nfft_plan_info reports it). -1 on invalid arguments.
  */
 int64_t nfft_footprint(int d, int M, double sigma, int m, int64_t N, int precision, int max_rhs);
 
@@ -154,7 +155,7 @@ int nfft_permutation(nfft_plan_t plan, int32_t *perm_host);
  * them and returns, per stage, the accumulated milliseconds and the number of
  * calls since the last reset:
  *   out[2*s] = milliseconds, out[2*s+1] = calls, for s = 0..NFFT_STAGES-1
- * Stages: 0 spread (adjoint step 1), 1 FFT pass with tile merge (first pass of
+ * Stages: 0 spread with the sum of split tiles (adjoint step 1), 1 FFT pass with tile merge (first pass of
  * step 2), 2 remaining FFT passes with deconvolution (step 2 and 3),
  * 3 forward FFT passes with deconvolution (Algorithm 2.1 steps 1-2),
  * 4 forward window sums (Algorithm 2.1 step 3).

@@ -4,22 +4,37 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/nfft.h"
 #include "internal.hpp"
+#include "window.hpp"
 
 using nfft::cplx;
 using nfft::Geom;
 
 namespace {
 
-constexpr int kItemNodes = 256;  // nodes per spreading work item
+constexpr int kItemNodesDefault = 256;  // nodes per spreading work item
+
+// Tuning overrides (environment): NFFT_TILE_EDGE = tile edge in cells (a power
+// of two >= m, <= 256), NFFT_ITEM_NODES = nodes per spreading work item,
+// NFFT_FFT_MIN_WG = work-groups below which an FFT pass stops widening.
+int env_int(const char* name, int fallback) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return fallback;
+  char* end = nullptr;
+  long x = std::strtol(v, &end, 10);
+  return (end && *end == 0 && x > 0 && x < (1 << 20)) ? (int)x : fallback;
+}
+int item_nodes() { return env_int("NFFT_ITEM_NODES", kItemNodesDefault); }
 
 thread_local std::string g_noplan_error;
 
@@ -50,7 +65,15 @@ struct nfft_plan_s {
   int32_t* item_count = nullptr;
   int32_t* item_bin = nullptr;
   int32_t* item_first = nullptr;
-  void* sub = nullptr;
+  int32_t* item_slot = nullptr;    // itemp slot of an item of a split tile, else -1
+  int32_t* multi_bin = nullptr;    // split tiles
+  int32_t* multi_first = nullptr;  // first itemp slot of each split tile
+  int nmulti = 0;
+  int nslots = 0;                  // itemp slots
+  void* tilep = nullptr;           // tile partials [rhs][tile][P^d]
+  void* itemp = nullptr;           // item partials of split tiles [rhs][slot][P^d]
+  void* coef = nullptr;            // window polynomials [2m][deg + 1]
+  double poly_err = 0.0;           // verified max error / psi(0)
   void* bufA = nullptr;
   void* bufB = nullptr;
   void* grid = nullptr;
@@ -97,7 +120,9 @@ int oversampled(int M, double sigma) {
 
 int tile_edge(int d, int Ms) {
   // tile-local cells are packed into 8 bits per dimension, so T <= 256
-  const int t = d == 1 ? 256 : (d == 2 ? 32 : 8);
+  int t = d == 1 ? 256 : (d == 2 ? 16 : 8);
+  const int o = env_int("NFFT_TILE_EDGE", 0);
+  if (o >= 8 && o <= 256 && (o & (o - 1)) == 0) t = o;
   return std::min(t, Ms);
 }
 
@@ -129,10 +154,12 @@ int validate(int d, int M, double sigma, int m, int64_t N, int precision, int ma
     return fail(p, NFFT_EUNSUPPORTED, "M_sigma = %d: only powers of two in [8, 4096] are built",
                 Ms);
   const int T = tile_edge(d, Ms);
+  if (T < m) return fail(p, NFFT_EUNSUPPORTED, "tile edge %d < m = %d", T, m);
   const int P = T + 2 * m;
   size_t Ptot = 1;
   for (int t = 0; t < d; ++t) Ptot *= (size_t)P;
-  if (Ptot * cbytes(precision) > kMaxTileLds)
+  // the spreading tile accumulates in float64 for both precisions
+  if (Ptot * 16 > kMaxTileLds)
     return fail(p, NFFT_EUNSUPPORTED, "padded tile of %zu cells does not fit in LDS (d = %d, m = %d)",
                 Ptot, d, m);
   if (M > Ms) return fail(p, NFFT_EINVAL, "M_sigma < M");
@@ -194,10 +221,77 @@ struct ScopedFree {
   }
 };
 
+// psi(t) = e^{-b m} sinh(b z) / z, z = sqrt(m^2 - t^2): the window in grid
+// units scaled by pi e^{-b m} (the deconvolution factors undo the scale).
+long double psi_ld(long double t, long double b, long double m) {
+  const long double z2 = (m - t) * (m + t);
+  if (z2 <= 0.0L) return b * std::exp(-b * m);
+  const long double z = std::sqrt(z2);
+  // e^{b(z - m)} (1 - e^{-2bz}) / (2z), with z - m = -t^2 / (z + m)
+  return std::exp(-b * t * t / (z + m)) * (-std::expm1(-2.0L * b * z)) / (2.0L * z);
+}
+
+// Per-cell window polynomials in y = 2 frac - 1: Chebyshev interpolation of
+// degree DEG at the Chebyshev points, converted to monomial coefficients.
+// Returns the largest error on a fine grid relative to psi(0).
+template <typename R>
+double fit_window(int m, long double b, std::vector<R>& coef) {
+  constexpr int DEG = nfft::PolyDeg<R>::value;
+  constexpr int n = DEG + 1;
+  const long double pi = 3.14159265358979323846264338327950288L;
+  coef.assign((size_t)2 * m * n, (R)0);
+  double worst = 0.0;
+  const long double p0 = psi_ld(0.0L, b, m);
+  for (int i = 0; i < 2 * m; ++i) {
+    const long double shift = (long double)(m - 1 - i);
+    long double fv[n], ch[n];
+    for (int j = 0; j < n; ++j) {
+      const long double y = std::cos(pi * (j + 0.5L) / n);
+      fv[j] = psi_ld((y + 1.0L) / 2.0L + shift, b, m);
+    }
+    for (int k = 0; k < n; ++k) {
+      long double acc = 0.0L;
+      for (int j = 0; j < n; ++j) acc += fv[j] * std::cos(pi * k * (j + 0.5L) / n);
+      ch[k] = acc * 2.0L / n;
+    }
+    ch[0] *= 0.5L;
+    // monomial coefficients: T_0 = 1, T_1 = y, T_{k+1} = 2y T_k - T_{k-1}
+    long double Tm[n], Tc[n], Tn[n], mono[n];
+    for (int k = 0; k < n; ++k) Tm[k] = Tc[k] = mono[k] = 0.0L;
+    Tm[0] = 1.0L;
+    Tc[1] = 1.0L;
+    mono[0] += ch[0];
+    for (int k = 1; k < n; ++k) {
+      for (int q = 0; q < n; ++q) mono[q] += ch[k] * Tc[q];
+      for (int q = 0; q < n; ++q) Tn[q] = (q > 0 ? 2.0L * Tc[q - 1] : 0.0L) - Tm[q];
+      for (int q = 0; q < n; ++q) {
+        Tm[q] = Tc[q];
+        Tc[q] = Tn[q];
+      }
+    }
+    for (int q = 0; q < n; ++q) coef[(size_t)i * n + q] = (R)mono[q];
+    for (int s = 0; s <= 512; ++s) {
+      const long double y = -1.0L + 2.0L * s / 512.0L;
+      long double v = (long double)coef[(size_t)i * n + DEG];
+      for (int q = DEG - 1; q >= 0; --q) v = v * y + (long double)coef[(size_t)i * n + q];
+      const long double ex = psi_ld((y + 1.0L) / 2.0L + shift, b, m);
+      worst = std::max(worst, (double)(std::fabs(v - ex) / p0));
+    }
+  }
+  return worst;
+}
+
 template <typename R>
 int build_tables(nfft_plan_t p) {
   const int Ms = p->Ms, M = p->M, m = p->m;
   const long double b = (long double)p->b;
+  std::vector<R> coef;
+  p->poly_err = fit_window<R>(m, b, coef);
+  const double tol = std::is_same<R, double>::value ? 1e-13 : 1e-7;
+  if (!(p->poly_err <= tol))
+    return fail(p, NFFT_EUNSUPPORTED, "window polynomial error %.3g exceeds %.1g", p->poly_err, tol);
+  TRY(dalloc(p, &p->coef, coef.size() * sizeof(R)));
+  HIP_TRY(p, hipMemcpy(p->coef, coef.data(), coef.size() * sizeof(R), hipMemcpyHostToDevice));
   std::vector<R> fac(M);
   for (int kidx = 0; kidx < M; ++kidx) {
     const int k = kidx - M / 2;
@@ -261,24 +355,36 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
   HIP_TRY(p, hipStreamSynchronize(s));
   if (herr) return fail(p, NFFT_EINVAL, "nodes contain a non-finite coordinate");
 
-  // tile starts and work items (at most kItemNodes nodes of one tile each)
+  // tile starts and work items (at most kItem nodes of one tile each)
   std::vector<int32_t> hstart(g.nbins + 1);
   std::vector<int32_t> istart, icount, ibin, ifirst(g.nbins + 1);
+  const int kItem = item_nodes();
   int64_t acc = 0;
   p->maxpop = 0;
   for (int b = 0; b < g.nbins; ++b) {
     hstart[b] = (int32_t)acc;
     ifirst[b] = (int32_t)istart.size();
     p->maxpop = std::max(p->maxpop, hc[b]);
-    for (int k = 0; k < hc[b]; k += kItemNodes) {
+    for (int k = 0; k < hc[b]; k += kItem) {
       istart.push_back((int32_t)(acc + k));
-      icount.push_back(std::min(kItemNodes, hc[b] - k));
+      icount.push_back(std::min(kItem, hc[b] - k));
       ibin.push_back(b);
     }
     acc += hc[b];
   }
   hstart[g.nbins] = (int32_t)acc;
   ifirst[g.nbins] = (int32_t)istart.size();
+  // split tiles: their items write to their own slots and are summed later
+  std::vector<int32_t> islot(istart.size(), -1), mbin, mfirst;
+  for (int b = 0; b < g.nbins; ++b) {
+    const int n = ifirst[b + 1] - ifirst[b];
+    if (n <= 1) continue;
+    mbin.push_back(b);
+    mfirst.push_back(p->nslots);
+    for (int k = 0; k < n; ++k) islot[ifirst[b] + k] = p->nslots++;
+  }
+  mfirst.push_back(p->nslots);
+  p->nmulti = (int)mbin.size();
   g.nsub = (int)istart.size();
   HIP_TRY(p, hipMemcpyAsync(bstart, hstart.data(), (g.nbins + 1) * sizeof(int32_t),
                             hipMemcpyHostToDevice, s));
@@ -306,10 +412,22 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
     HIP_TRY(p, hipMemcpyAsync(p->item_bin, ibin.data(), ibin.size() * 4, hipMemcpyHostToDevice, s));
   }
   HIP_TRY(p, hipMemcpyAsync(p->item_first, ifirst.data(), (g.nbins + 1) * 4, hipMemcpyHostToDevice, s));
+  TRY(dalloc(p, &p->item_slot, ni * sizeof(int32_t)));
+  TRY(dalloc(p, &p->multi_bin, std::max<size_t>(1, mbin.size()) * sizeof(int32_t)));
+  TRY(dalloc(p, &p->multi_first, mfirst.size() * sizeof(int32_t)));
+  if (!islot.empty())
+    HIP_TRY(p, hipMemcpyAsync(p->item_slot, islot.data(), islot.size() * 4, hipMemcpyHostToDevice, s));
+  if (!mbin.empty())
+    HIP_TRY(p, hipMemcpyAsync(p->multi_bin, mbin.data(), mbin.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(p, hipMemcpyAsync(p->multi_first, mfirst.data(), mfirst.size() * 4, hipMemcpyHostToDevice, s));
 
   TRY(dalloc(p, &p->w, N * sizeof(cplx<R>)));
   const int64_t R_ = p->max_rhs;
-  TRY(dalloc(p, &p->sub, (size_t)R_ * g.nsub * g.Ptot * sizeof(cplx<R>)));
+  const size_t tile_bytes = (size_t)R_ * g.nbins * g.Ptot * sizeof(cplx<R>);
+  TRY(dalloc(p, &p->tilep, tile_bytes));
+  // tiles without nodes are never written: their partials stay zero
+  HIP_TRY(p, hipMemsetAsync(p->tilep, 0, tile_bytes, s));
+  TRY(dalloc(p, &p->itemp, (size_t)R_ * std::max(1, p->nslots) * g.Ptot * sizeof(cplx<R>)));
   const int64_t Ms = p->Ms, M = p->M;
   if (d >= 2) TRY(dalloc(p, &p->bufA, (size_t)R_ * ipow(Ms, d - 1) * M * sizeof(cplx<R>)));
   if (d == 3) TRY(dalloc(p, &p->bufB, (size_t)R_ * Ms * M * M * sizeof(cplx<R>)));
@@ -319,23 +437,34 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
   return NFFT_OK;
 }
 
+// Lines per work-group of an FFT pass: bounded by 64 KiB of LDS for the two
+// buffers and by 256 threads (L/8 butterflies per line), and lowered while
+// that leaves fewer than 256 work-groups.
 template <typename R>
-int lines_per_wg(int L, bool inner_major) {
-  const int budget = 64 * 1024;
-  int lmax = std::max(1, budget / (2 * L * (int)sizeof(cplx<R>)));
-  int want = inner_major ? 16 : std::max(1, 2048 / L);
-  return std::max(1, std::min(lmax, want));
+int lines_per_wg(int L, int64_t nlines) {
+  const int lds_cap = std::max(1, 65536 / (2 * (L + 1) * (int)sizeof(cplx<R>)));
+  int lpw = std::max(1, std::min(lds_cap, 2048 / L));  // L/8 threads per line
+  static const int min_wg = env_int("NFFT_FFT_MIN_WG", 256);
+  while (lpw > 1 && nlines / lpw < min_wg) lpw /= 2;
+  return lpw;
 }
 
 template <typename R>
-nfft::FftArgs<R> fft_args(nfft_plan_t p) {
+nfft::FftArgs<R> fft_args(nfft_plan_t p, int64_t nlines, const void* in, int64_t in_bs, int Lin,
+                          void* out, int64_t out_bs) {
   nfft::FftArgs<R> a{};
+  a.nlines = nlines;
+  a.in = (const cplx<R>*)in;
+  a.in_bs = in_bs;
+  a.Lin = Lin;
+  a.out = (cplx<R>*)out;
+  a.out_bs = out_bs;
   a.tw = (const cplx<R>*)p->tw;
   a.fac = (const R*)p->fac;
   a.g = p->g;
-  a.item_first = p->item_first;
-  a.sub = (const cplx<R>*)p->sub;
-  a.sub_bs = (int64_t)p->g.nsub * p->g.Ptot;
+  a.tilep = (const cplx<R>*)p->tilep;
+  a.tile_bs = (int64_t)p->g.nbins * p->g.Ptot;
+  a.lpw = lines_per_wg<R>(p->Ms, nlines);
   return a;
 }
 
@@ -365,60 +494,53 @@ int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t 
   sa.w = (const cplx<R>*)p->w;
   sa.perm = p->perm;
   sa.f = (const cplx<R>*)f;
-  sa.sub = (cplx<R>*)p->sub;
+  sa.tilep = (cplx<R>*)p->tilep;
+  sa.itemp = (cplx<R>*)p->itemp;
   sa.item_start = p->item_start;
   sa.item_count = p->item_count;
+  sa.item_bin = p->item_bin;
+  sa.item_slot = p->item_slot;
+  sa.coef = (const R*)p->coef;
   sa.f_rs = p->N;
-  sa.sub_rs = (int64_t)g.nsub * g.Ptot;
-  sa.b = (R)p->b;
-  sa.mr = (R)p->m;
+  sa.tile_rs = (int64_t)g.nbins * g.Ptot;
+  sa.item_rs = (int64_t)std::max(1, p->nslots) * g.Ptot;
   sa.edge = (R)(p->b * std::exp(-p->b * p->m));
   sa.g = g;
   HIP_TRY(p, nfft::launch_spread<R>(sa, nrhs, s));
+  nfft::ReduceArgs<R> ra{};
+  ra.tilep = (cplx<R>*)p->tilep;
+  ra.itemp = (const cplx<R>*)p->itemp;
+  ra.multi_bin = p->multi_bin;
+  ra.multi_first = p->multi_first;
+  ra.nmulti = p->nmulti;
+  ra.tile_rs = sa.tile_rs;
+  ra.item_rs = sa.item_rs;
+  ra.g = g;
+  HIP_TRY(p, nfft::launch_tile_reduce<R>(ra, nrhs, s));
   record(p, se, s);
 
   const int L = (int)Ms;
-  nfft::FftArgs<R> a = fft_args<R>(p);
-  cplx<R>* out = (cplx<R>*)fhat;
+  const auto fwd = nfft::kLoadMerge;
   if (p->d == 1) {
-    a.n_outer = 1; a.n_inner = 1;
-    a.out = out; a.out_bs = M; a.out_os = 0; a.out_is = 0; a.out_es = 1;
-    a.inner_major = 0; a.lpw = 1;
-    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, nfft::kLoadMerge, nfft::kStoreCropScaled, nrhs, s));
+    auto a = fft_args<R>(p, 1, nullptr, 0, L, fhat, M);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, fwd, nfft::kStoreCropScaled, nrhs, s));
     record(p, se, s);
   } else if (p->d == 2) {
-    cplx<R>* A = (cplx<R>*)p->bufA;
-    a.n_outer = Ms; a.n_inner = 1;
-    a.out = A; a.out_bs = Ms * M; a.out_os = M; a.out_is = 0; a.out_es = 1;
-    a.inner_major = 0; a.lpw = lines_per_wg<R>(L, false);
-    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, nfft::kLoadMerge, nfft::kStoreCropScaled, nrhs, s));
+    // [s1][s2] -> [k2][s1] -> [k1][k2]
+    auto a = fft_args<R>(p, Ms, nullptr, 0, L, p->bufA, M * Ms);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, fwd, nfft::kStoreCropScaled, nrhs, s));
     record(p, se, s);
-    nfft::FftArgs<R> c = fft_args<R>(p);
-    c.n_outer = 1; c.n_inner = M;
-    c.in = A; c.in_bs = Ms * M; c.in_os = 0; c.in_is = 1; c.in_es = M;
-    c.out = out; c.out_bs = M * M; c.out_os = 0; c.out_is = 1; c.out_es = M;
-    c.inner_major = 1; c.lpw = lines_per_wg<R>(L, true);
-    HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, false, nfft::kLoadStrided, nfft::kStoreCropScaled, nrhs, s));
+    auto c = fft_args<R>(p, M, p->bufA, M * Ms, L, fhat, M * M);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, false, nfft::kLoadLine, nfft::kStoreCropScaled, nrhs, s));
   } else {
-    cplx<R>* A = (cplx<R>*)p->bufA;
-    cplx<R>* B = (cplx<R>*)p->bufB;
-    a.n_outer = Ms * Ms; a.n_inner = 1;
-    a.out = A; a.out_bs = Ms * Ms * M; a.out_os = M; a.out_is = 0; a.out_es = 1;
-    a.inner_major = 0; a.lpw = lines_per_wg<R>(L, false);
-    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, nfft::kLoadMerge, nfft::kStoreCropScaled, nrhs, s));
+    // [s1][s2][s3] -> [k3][s1][s2] -> [k2][k3][s1] -> [k1][k2][k3]
+    auto a = fft_args<R>(p, Ms * Ms, nullptr, 0, L, p->bufA, M * Ms * Ms);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, fwd, nfft::kStoreCropScaled, nrhs, s));
     record(p, se, s);
-    nfft::FftArgs<R> c = fft_args<R>(p);
-    c.n_outer = Ms; c.n_inner = M;
-    c.in = A; c.in_bs = Ms * Ms * M; c.in_os = Ms * M; c.in_is = 1; c.in_es = M;
-    c.out = B; c.out_bs = Ms * M * M; c.out_os = M * M; c.out_is = 1; c.out_es = M;
-    c.inner_major = 1; c.lpw = lines_per_wg<R>(L, true);
-    HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, false, nfft::kLoadStrided, nfft::kStoreCropScaled, nrhs, s));
-    nfft::FftArgs<R> e = fft_args<R>(p);
-    e.n_outer = 1; e.n_inner = M * M;
-    e.in = B; e.in_bs = Ms * M * M; e.in_os = 0; e.in_is = 1; e.in_es = M * M;
-    e.out = out; e.out_bs = M * M * M; e.out_os = 0; e.out_is = 1; e.out_es = M * M;
-    e.inner_major = 1; e.lpw = lines_per_wg<R>(L, true);
-    HIP_TRY(p, nfft::launch_fft_pass<R>(e, L, false, nfft::kLoadStrided, nfft::kStoreCropScaled, nrhs, s));
+    auto c = fft_args<R>(p, M * Ms, p->bufA, M * Ms * Ms, L, p->bufB, M * M * Ms);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, false, nfft::kLoadLine, nfft::kStoreCropScaled, nrhs, s));
+    auto e = fft_args<R>(p, M * M, p->bufB, M * M * Ms, L, fhat, M * M * M);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(e, L, false, nfft::kLoadLine, nfft::kStoreCropScaled, nrhs, s));
   }
   record(p, se, s);
   if (p->profiling && se.n > 0) p->pending.push_back(se);
@@ -433,65 +555,39 @@ int run_forward(nfft_plan_t p, const void* fhat, void* f, int nrhs, hipStream_t 
   StageEvents se{};
   se.kind = 1;
   record(p, se, s);
-  const cplx<R>* in = (const cplx<R>*)fhat;
-  cplx<R>* G = (cplx<R>*)p->grid;
+  const auto ld = nfft::kLoadPadScaled;
+  const auto st = nfft::kStoreFull;
   if (p->d == 1) {
-    nfft::FftArgs<R> a = fft_args<R>(p);
-    a.n_outer = 1; a.n_inner = 1;
-    a.in = in; a.in_bs = M; a.in_os = 0; a.in_is = 0; a.in_es = 1;
-    a.out = G; a.out_bs = Ms; a.out_os = 0; a.out_is = 0; a.out_es = 1;
-    a.inner_major = 0; a.lpw = 1;
-    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, true, nfft::kLoadPadScaled, nfft::kStoreFull, nrhs, s));
+    auto a = fft_args<R>(p, 1, fhat, M, (int)M, p->grid, Ms);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, true, ld, st, nrhs, s));
   } else if (p->d == 2) {
-    cplx<R>* A = (cplx<R>*)p->bufA;
-    nfft::FftArgs<R> a = fft_args<R>(p);
-    a.n_outer = 1; a.n_inner = M;
-    a.in = in; a.in_bs = M * M; a.in_os = 0; a.in_is = 1; a.in_es = M;
-    a.out = A; a.out_bs = Ms * M; a.out_os = 0; a.out_is = 1; a.out_es = M;
-    a.inner_major = 1; a.lpw = lines_per_wg<R>(L, true);
-    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, true, nfft::kLoadPadScaled, nfft::kStoreFull, nrhs, s));
-    nfft::FftArgs<R> c = fft_args<R>(p);
-    c.n_outer = Ms; c.n_inner = 1;
-    c.in = A; c.in_bs = Ms * M; c.in_os = M; c.in_is = 0; c.in_es = 1;
-    c.out = G; c.out_bs = Ms * Ms; c.out_os = Ms; c.out_is = 0; c.out_es = 1;
-    c.inner_major = 0; c.lpw = lines_per_wg<R>(L, false);
-    HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, true, nfft::kLoadPadScaled, nfft::kStoreFull, nrhs, s));
+    // [k1][k2] -> [s2][k1] -> [s1][s2]
+    auto a = fft_args<R>(p, M, fhat, M * M, (int)M, p->bufA, Ms * M);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, true, ld, st, nrhs, s));
+    auto c = fft_args<R>(p, Ms, p->bufA, Ms * M, (int)M, p->grid, Ms * Ms);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, true, ld, st, nrhs, s));
   } else {
-    cplx<R>* A = (cplx<R>*)p->bufA;
-    cplx<R>* B = (cplx<R>*)p->bufB;
-    nfft::FftArgs<R> a = fft_args<R>(p);
-    a.n_outer = 1; a.n_inner = M * M;
-    a.in = in; a.in_bs = M * M * M; a.in_os = 0; a.in_is = 1; a.in_es = M * M;
-    a.out = B; a.out_bs = Ms * M * M; a.out_os = 0; a.out_is = 1; a.out_es = M * M;
-    a.inner_major = 1; a.lpw = lines_per_wg<R>(L, true);
-    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, true, nfft::kLoadPadScaled, nfft::kStoreFull, nrhs, s));
-    nfft::FftArgs<R> c = fft_args<R>(p);
-    c.n_outer = Ms; c.n_inner = M;
-    c.in = B; c.in_bs = Ms * M * M; c.in_os = M * M; c.in_is = 1; c.in_es = M;
-    c.out = A; c.out_bs = Ms * Ms * M; c.out_os = Ms * M; c.out_is = 1; c.out_es = M;
-    c.inner_major = 1; c.lpw = lines_per_wg<R>(L, true);
-    HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, true, nfft::kLoadPadScaled, nfft::kStoreFull, nrhs, s));
-    nfft::FftArgs<R> e = fft_args<R>(p);
-    e.n_outer = Ms * Ms; e.n_inner = 1;
-    e.in = A; e.in_bs = Ms * Ms * M; e.in_os = M; e.in_is = 0; e.in_es = 1;
-    e.out = G; e.out_bs = Ms * Ms * Ms; e.out_os = Ms; e.out_is = 0; e.out_es = 1;
-    e.inner_major = 0; e.lpw = lines_per_wg<R>(L, false);
-    HIP_TRY(p, nfft::launch_fft_pass<R>(e, L, true, nfft::kLoadPadScaled, nfft::kStoreFull, nrhs, s));
+    // [k1][k2][k3] -> [s3][k1][k2] -> [s2][s3][k1] -> [s1][s2][s3]
+    auto a = fft_args<R>(p, M * M, fhat, M * M * M, (int)M, p->bufB, Ms * M * M);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, true, ld, st, nrhs, s));
+    auto c = fft_args<R>(p, Ms * M, p->bufB, Ms * M * M, (int)M, p->bufA, Ms * Ms * M);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, true, ld, st, nrhs, s));
+    auto e = fft_args<R>(p, Ms * Ms, p->bufA, Ms * Ms * M, (int)M, p->grid, Ms * Ms * Ms);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(e, L, true, ld, st, nrhs, s));
   }
   record(p, se, s);
   nfft::InterpArgs<R> ia{};
   ia.loc = p->loc;
   ia.frac = (const R*)p->frac;
   ia.perm = p->perm;
-  ia.grid = G;
+  ia.grid = (const cplx<R>*)p->grid;
   ia.f = (cplx<R>*)f;
   ia.item_start = p->item_start;
   ia.item_count = p->item_count;
   ia.item_bin = p->item_bin;
+  ia.coef = (const R*)p->coef;
   ia.grid_rs = ipow(Ms, p->d);
   ia.f_rs = p->N;
-  ia.b = (R)p->b;
-  ia.mr = (R)p->m;
   ia.edge = (R)(p->b * std::exp(-p->b * p->m));
   ia.g = g;
   HIP_TRY(p, nfft::launch_interp<R>(ia, nrhs, s));
@@ -529,13 +625,14 @@ int64_t nfft_footprint(int d, int M, double sigma, int m, int64_t N, int precisi
   const int64_t P = T + 2 * m;
   const int64_t Ptot = ipow(P, d);
   const int64_t cb = (int64_t)cbytes(precision), rb = (int64_t)rbytes(precision);
-  const int64_t nsub_max = nbins + (N + kItemNodes - 1) / kItemNodes;
+  const int64_t nsub_max = nbins + (N + item_nodes() - 1) / item_nodes();
   const int64_t R_ = max_rhs;
   int64_t bytes = 0;
   bytes += N * 4 + N * 4 + N * d * rb;                     // perm, loc, frac
-  bytes += std::max<int64_t>(1, nsub_max) * 4 * 3 + (nbins + 1) * 4;  // item tables
+  bytes += std::max<int64_t>(1, nsub_max) * 4 * 3 + (nbins + 1) * 4 + nbins * 4;  // item tables
   bytes += N * cb;                                        // weights
-  bytes += R_ * nsub_max * Ptot * cb;                     // padded tile sums
+  bytes += R_ * (nbins + nsub_max) * Ptot * cb;           // tile and item partials
+  bytes += 2 * m * 17 * rb + nsub_max * 4;                // window polynomials, item slots
   if (d >= 2) bytes += R_ * ipow(Ms, d - 1) * M * cb;
   if (d == 3) bytes += R_ * Ms * M * M * cb;
   bytes += R_ * ipow(Ms, d) * cb;                         // forward grid
@@ -571,6 +668,10 @@ int nfft_plan(nfft_plan_t* out, int d, int M, double sigma, int m, int64_t N,
   g.P = g.T + 2 * m;
   g.Ptot = (int)ipow(g.P, d);
   g.nbins = (int)ipow(g.nb, d);
+  g.tshift = 0;
+  while ((1 << g.tshift) < g.T) ++g.tshift;
+  g.Ms_shift = 0;
+  while ((1 << g.Ms_shift) < g.Ms) ++g.Ms_shift;
   g.N = N;
   if (hipGetDevice(&p->device) != hipSuccess) {
     free_plan(p);

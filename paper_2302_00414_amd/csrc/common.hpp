@@ -51,6 +51,8 @@ struct Geom {
   int Ptot;     // P^d
   int nbins;    // nb^d
   int nsub;     // number of spreading work items (tile chunks)
+  int tshift;   // log2(T)
+  int Ms_shift; // log2(Ms)
   int64_t N;    // nodes
 };
 

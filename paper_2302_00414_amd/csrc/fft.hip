@@ -3,12 +3,14 @@
 //
 // One launch transforms every line of one dimension of a d-dimensional
 // array. A work-group holds `lpw` whole lines of length L in LDS (two
-// ping-pong buffers). Each pass is fused with its neighbours' elementwise
-// work:
-//   loaders : kLoadMerge      -- the first adjoint pass sums the padded tile
+// ping-pong buffers). Lines are read contiguously and the transformed axis
+// is written as the new slowest axis, so after d passes the array is back in
+// C order and every pass reads contiguous lines. Each pass is fused with its
+// neighbours' elementwise work:
+//   loaders : kLoadMerge      -- the first adjoint pass sums the tile
 //                                 partials of the spreading step into grid
 //                                 cells (fixed order, no atomics);
-//             kLoadStrided    -- plain strided read;
+//             kLoadLine       -- plain contiguous read;
 //             kLoadPadScaled  -- forward: read the M coefficients of a line,
 //                                 multiply by the deconvolution factor and
 //                                 zero-pad to L = M_sigma (D and the zero
@@ -72,14 +74,14 @@ __device__ __forceinline__ void dft8(cplx<R>* a) {
 
 // One Stockham pass of radix RAD over `lpw` lines of length L.
 template <typename R, int RAD, bool INV>
-__device__ __forceinline__ void stockham_pass(const cplx<R>* src, cplx<R>* dst, int L, int lpw,
-                                              int Ns, const cplx<R>* __restrict__ tw) {
+__device__ __forceinline__ void stockham_pass(const cplx<R>* src, cplx<R>* dst, int L, int LS,
+                                              int lpw, int Ns, const cplx<R>* __restrict__ tw) {
   const int nbf = L / RAD;
   for (int q = threadIdx.x; q < lpw * nbf; q += blockDim.x) {
     const int line = q / nbf;
     const int j = q - line * nbf;
-    const cplx<R>* s = src + line * L;
-    cplx<R>* o = dst + line * L;
+    const cplx<R>* s = src + line * LS;
+    cplx<R>* o = dst + line * LS;
     cplx<R> a[RAD];
 #pragma unroll
     for (int r = 0; r < RAD; ++r) a[r] = s[j + r * nbf];
@@ -106,61 +108,64 @@ __device__ __forceinline__ void stockham_pass(const cplx<R>* src, cplx<R>* dst, 
   }
 }
 
-// Sum of the padded tile partials that cover grid cell c (per dimension:
-// the own tile and, within m cells of its border, the neighbour tile whose
-// padding reaches over; tiles wrap periodically).
+// Sum of the tile partials that cover grid cell c: per dimension the own
+// tile and, within m cells of its border, the neighbour tile whose padding
+// reaches over (tiles wrap periodically). Tiles without nodes hold zeros.
 template <typename R, int D>
-__device__ __forceinline__ cplx<R> merge_cell(const cplx<R>* __restrict__ sub,
-                                              const int32_t* __restrict__ item_first,
-                                              const Geom& g, const int* c) {
-  int bq[3][3], pq[3][3], nq[3];
+__device__ __forceinline__ cplx<R> merge_cell(const cplx<R>* __restrict__ tilep, const Geom& g,
+                                              const int* c) {
+  // T and the tile count per dimension are powers of two: shifts and masks
+  double sx = 0.0, sy = 0.0;
+  const int tm = g.T - 1, nm = g.nb - 1, ts = g.tshift;
+  int r[3], b0[3];
 #pragma unroll
   for (int t = 0; t < D; ++t) {
-    const int r = c[t] % g.T;
-    const int b0 = c[t] / g.T;
-    int n = 0;
-#pragma unroll
-    for (int dl = -1; dl <= 1; ++dl) {
-      const int p = r + g.m - dl * g.T;
-      if (p >= 0 && p < g.P) {
-        bq[t][n] = (b0 + dl + g.nb) % g.nb;
-        pq[t][n] = p;
-        ++n;
-      }
-    }
-    nq[t] = n;
+    r[t] = c[t] & tm;
+    b0[t] = c[t] >> ts;
   }
-  R sx = 0, sy = 0;
-  const int n1 = D > 1 ? nq[1] : 1;
-  const int n2 = D > 2 ? nq[2] : 1;
-  for (int a0 = 0; a0 < nq[0]; ++a0)
-    for (int a1 = 0; a1 < n1; ++a1)
-      for (int a2 = 0; a2 < n2; ++a2) {
-        int bin = bq[0][a0];
-        int pl = pq[0][a0];
+#pragma unroll
+  for (int d0 = -1; d0 <= 1; ++d0) {
+    const int p0 = r[0] + g.m - d0 * g.T;
+    if (p0 < 0 || p0 >= g.P) continue;
+    const int q0 = (b0[0] + d0) & nm;
+#pragma unroll
+    for (int d1 = (D > 1 ? -1 : 0); d1 <= (D > 1 ? 1 : 0); ++d1) {
+      int p1 = 0, q1 = 0;
+      if (D > 1) {
+        p1 = r[1] + g.m - d1 * g.T;
+        if (p1 < 0 || p1 >= g.P) continue;
+        q1 = (b0[1] + d1) & nm;
+      }
+#pragma unroll
+      for (int d2 = (D > 2 ? -1 : 0); d2 <= (D > 2 ? 1 : 0); ++d2) {
+        int p2 = 0, q2 = 0;
+        if (D > 2) {
+          p2 = r[2] + g.m - d2 * g.T;
+          if (p2 < 0 || p2 >= g.P) continue;
+          q2 = (b0[2] + d2) & nm;
+        }
+        int bin = q0, pl = p0;
         if (D > 1) {
-          bin = bin * g.nb + bq[1][a1];
-          pl = pl * g.P + pq[1][a1];
+          bin = (bin << (g.Ms_shift - ts)) + q1;
+          pl = pl * g.P + p1;
         }
         if (D > 2) {
-          bin = bin * g.nb + bq[2][a2];
-          pl = pl * g.P + pq[2][a2];
+          bin = (bin << (g.Ms_shift - ts)) + q2;
+          pl = pl * g.P + p2;
         }
-        const int s0 = item_first[bin], s1 = item_first[bin + 1];
-        for (int s = s0; s < s1; ++s) {
-          const cplx<R> v = sub[(int64_t)s * g.Ptot + pl];
-          sx += v.x;
-          sy += v.y;
-        }
+        const cplx<R> v = tilep[(int64_t)bin * g.Ptot + pl];
+        sx += (double)v.x;
+        sy += (double)v.y;
       }
-  return mkc<R>(sx, sy);
+    }
+  }
+  return mkc<R>((R)sx, (R)sy);
 }
 
 template <typename R, int LD>
-__device__ __forceinline__ cplx<R> load_elem(const FftArgs<R>& a, int b, int64_t o, int64_t i,
-                                             int e, int L) {
-  if constexpr (LD == kLoadStrided) {
-    return a.in[b * a.in_bs + o * a.in_os + i * a.in_is + (int64_t)e * a.in_es];
+__device__ __forceinline__ cplx<R> load_elem(const FftArgs<R>& a, int b, int64_t q, int e, int L) {
+  if constexpr (LD == kLoadLine) {
+    return a.in[b * a.in_bs + q * L + e];
   } else if constexpr (LD == kLoadPadScaled) {
     const int M = a.g.M;
     int kidx;
@@ -170,30 +175,30 @@ __device__ __forceinline__ cplx<R> load_elem(const FftArgs<R>& a, int b, int64_t
       kidx = e - L + M / 2;
     else
       return mkc<R>(0, 0);
-    const cplx<R> v = a.in[b * a.in_bs + o * a.in_os + i * a.in_is + (int64_t)kidx * a.in_es];
+    const cplx<R> v = a.in[b * a.in_bs + q * M + kidx];
     return cscale<R>(v, a.fac[kidx]);
   } else {
-    // merge: the line index o enumerates the leading d-1 grid coordinates
-    int c[3] = {0, 0, 0};
+    // merge: the line index enumerates the leading d-1 grid coordinates
+    const cplx<R>* tp = a.tilep + b * a.tile_bs;
     const int d = a.g.d;
-    int64_t rem = o;
-    for (int t = d - 2; t >= 0; --t) {
-      c[t] = (int)(rem % a.g.Ms);
-      rem /= a.g.Ms;
+    if (d == 1) {
+      const int c[1] = {e};
+      return merge_cell<R, 1>(tp, a.g, c);
     }
-    c[d - 1] = e;
-    const cplx<R>* sub = a.sub + b * a.sub_bs;
-    if (d == 1) return merge_cell<R, 1>(sub, a.item_first, a.g, c);
-    if (d == 2) return merge_cell<R, 2>(sub, a.item_first, a.g, c);
-    return merge_cell<R, 3>(sub, a.item_first, a.g, c);
+    if (d == 2) {
+      const int c[2] = {(int)q, e};
+      return merge_cell<R, 2>(tp, a.g, c);
+    }
+    const int c[3] = {(int)(q >> a.g.Ms_shift), (int)(q & (a.g.Ms - 1)), e};
+    return merge_cell<R, 3>(tp, a.g, c);
   }
 }
 
 template <typename R, int ST>
-__device__ __forceinline__ void store_elem(const FftArgs<R>& a, int b, int64_t o, int64_t i,
-                                           int e, int L, cplx<R> v) {
+__device__ __forceinline__ void store_elem(const FftArgs<R>& a, int b, int64_t q, int e, int L,
+                                           cplx<R> v) {
   if constexpr (ST == kStoreFull) {
-    a.out[b * a.out_bs + o * a.out_os + i * a.out_is + (int64_t)e * a.out_es] = v;
+    a.out[b * a.out_bs + (int64_t)e * a.nlines + q] = v;
   } else {
     const int M = a.g.M;
     int kidx;
@@ -203,49 +208,52 @@ __device__ __forceinline__ void store_elem(const FftArgs<R>& a, int b, int64_t o
       kidx = e - L + M / 2;
     else
       return;
-    a.out[b * a.out_bs + o * a.out_os + i * a.out_is + (int64_t)kidx * a.out_es] =
-        cscale<R>(v, a.fac[kidx]);
+    a.out[b * a.out_bs + (int64_t)kidx * a.nlines + q] = cscale<R>(v, a.fac[kidx]);
   }
 }
 
 template <typename R, int LOG2L, bool INV, int LD, int ST>
-__global__ __launch_bounds__(256) void fft_pass_kernel(FftArgs<R> a) {
+__global__ __launch_bounds__(512) void fft_pass_kernel(FftArgs<R> a) {
   constexpr int L = 1 << LOG2L;
+  constexpr int TPL = L / 8;  // threads per line (one radix-8 butterfly each)
+  constexpr int LS = L + 1;   // padded LDS line stride (bank spread for the store phase)
   extern __shared__ unsigned char smem_raw[];
-  const int lpw = a.lpw;
+  const int lpw = a.lpw;      // blockDim.x == lpw * TPL
   cplx<R>* buf0 = reinterpret_cast<cplx<R>*>(smem_raw);
-  cplx<R>* buf1 = buf0 + lpw * L;
-  const int64_t nlines = a.n_outer * a.n_inner;
+  cplx<R>* buf1 = buf0 + lpw * LS;
+  const int64_t nlines = a.nlines;
   const int64_t q0 = (int64_t)blockIdx.x * lpw;
   const int b = blockIdx.y;
 
-  for (int idx = threadIdx.x; idx < lpw * L; idx += blockDim.x) {
-    int l, e;
-    if (a.inner_major) {
-      l = idx % lpw;
-      e = idx / lpw;
-    } else {
-      l = idx / L;
-      e = idx % L;
-    }
+  // first radix-8 pass (Ns = 1, no twiddles) on elements loaded straight
+  // into registers: thread j of a line takes elements j + r L/8
+  {
+    const int l = threadIdx.x / TPL;
+    const int j = threadIdx.x - l * TPL;
     const int64_t q = q0 + l;
-    cplx<R> v = mkc<R>(0, 0);
+    cplx<R> v[8];
     if (q < nlines) {
-      const int64_t o = q / a.n_inner, i = q % a.n_inner;
-      v = load_elem<R, LD>(a, b, o, i, e, L);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = load_elem<R, LD>(a, b, q, j + r * TPL, L);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = mkc<R>(0, 0);
     }
-    buf0[l * L + e] = v;
+    dft8<R, INV>(v);
+    cplx<R>* o = buf0 + l * LS + j * 8;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) o[r] = v[r];
   }
   __syncthreads();
 
   cplx<R>* src = buf0;
   cplx<R>* dst = buf1;
-  int Ns = 1;
+  int Ns = 8;
   constexpr int n8 = LOG2L / 3;
   constexpr int rem = LOG2L % 3;
 #pragma unroll 1
-  for (int p = 0; p < n8; ++p) {
-    stockham_pass<R, 8, INV>(src, dst, L, lpw, Ns, a.tw);
+  for (int p = 1; p < n8; ++p) {
+    stockham_pass<R, 8, INV>(src, dst, L, LS, lpw, Ns, a.tw);
     __syncthreads();
     cplx<R>* t = src;
     src = dst;
@@ -253,44 +261,32 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(FftArgs<R> a) {
     Ns *= 8;
   }
   if constexpr (rem == 2) {
-    stockham_pass<R, 4, INV>(src, dst, L, lpw, Ns, a.tw);
+    stockham_pass<R, 4, INV>(src, dst, L, LS, lpw, Ns, a.tw);
     __syncthreads();
-    cplx<R>* t = src;
     src = dst;
-    dst = t;
   } else if constexpr (rem == 1) {
-    stockham_pass<R, 2, INV>(src, dst, L, lpw, Ns, a.tw);
+    stockham_pass<R, 2, INV>(src, dst, L, LS, lpw, Ns, a.tw);
     __syncthreads();
-    cplx<R>* t = src;
     src = dst;
-    dst = t;
   }
 
+  // store: consecutive threads walk across lines (the output axis is rotated)
   for (int idx = threadIdx.x; idx < lpw * L; idx += blockDim.x) {
-    int l, e;
-    if (a.inner_major) {
-      l = idx % lpw;
-      e = idx / lpw;
-    } else {
-      l = idx / L;
-      e = idx % L;
-    }
+    const int l = idx % lpw;
+    const int e = idx / lpw;
     const int64_t q = q0 + l;
-    if (q < nlines) {
-      const int64_t o = q / a.n_inner, i = q % a.n_inner;
-      store_elem<R, ST>(a, b, o, i, e, L, src[l * L + e]);
-    }
+    if (q < nlines) store_elem<R, ST>(a, b, q, e, L, src[l * LS + e]);
   }
 }
 
 template <typename R, int LOG2L, bool INV, int LD, int ST>
 static hipError_t fft_launch(const FftArgs<R>& a, int nbatch, hipStream_t s) {
   constexpr int L = 1 << LOG2L;
-  const int64_t nlines = a.n_outer * a.n_inner;
-  const unsigned nblk = (unsigned)((nlines + a.lpw - 1) / a.lpw);
-  const size_t lds = 2 * (size_t)a.lpw * L * sizeof(cplx<R>);
-  hipLaunchKernelGGL((fft_pass_kernel<R, LOG2L, INV, LD, ST>), dim3(nblk, nbatch), dim3(256), lds,
-                     s, a);
+  const unsigned nblk = (unsigned)((a.nlines + a.lpw - 1) / a.lpw);
+  const size_t lds = 2 * (size_t)a.lpw * (L + 1) * sizeof(cplx<R>);
+  const int threads = a.lpw * (L / 8);
+  hipLaunchKernelGGL((fft_pass_kernel<R, LOG2L, INV, LD, ST>), dim3(nblk, nbatch), dim3(threads),
+                     lds, s, a);
   return hipGetLastError();
 }
 
@@ -299,8 +295,8 @@ static hipError_t fft_modes(const FftArgs<R>& a, bool inverse, LoadMode ld, Stor
                             int nbatch, hipStream_t s) {
   if (!inverse && ld == kLoadMerge && st == kStoreCropScaled)
     return fft_launch<R, LOG2L, false, kLoadMerge, kStoreCropScaled>(a, nbatch, s);
-  if (!inverse && ld == kLoadStrided && st == kStoreCropScaled)
-    return fft_launch<R, LOG2L, false, kLoadStrided, kStoreCropScaled>(a, nbatch, s);
+  if (!inverse && ld == kLoadLine && st == kStoreCropScaled)
+    return fft_launch<R, LOG2L, false, kLoadLine, kStoreCropScaled>(a, nbatch, s);
   if (inverse && ld == kLoadPadScaled && st == kStoreFull)
     return fft_launch<R, LOG2L, true, kLoadPadScaled, kStoreFull>(a, nbatch, s);
   return hipErrorInvalidValue;

@@ -30,6 +30,10 @@ hipError_t launch_permute_weights(const double* w, const int32_t* perm, int64_t 
                                   cplx<R>* w_sorted, hipStream_t s);
 
 // ------------------------------------------------------- spreading / sums
+// Tile partials: every tile owns a padded-tile slot in `tilep` ([rhs][tile]
+// [P^d], zero for tiles without nodes). A tile with a single work item is
+// spread straight into its slot; the items of a tile split into several work
+// items write to their own slots in `itemp` and tile_reduce sums them.
 template <typename R>
 struct SpreadArgs {
   const uint32_t* loc;       // packed tile-local cells, tile order
@@ -37,16 +41,34 @@ struct SpreadArgs {
   const cplx<R>* w;          // weights in tile order
   const int32_t* perm;       // tile order -> caller index
   const cplx<R>* f;          // samples, caller order, rhs stride f_rs
-  cplx<R>* sub;              // padded tile sums [rhs][item][P^d]
+  cplx<R>* tilep;            // tile partials [rhs][tile][P^d]
+  cplx<R>* itemp;            // item partials of split tiles [rhs][slot][P^d]
   const int32_t* item_start; // first node of each work item
   const int32_t* item_count; // nodes of each work item
-  int64_t f_rs;
-  int64_t sub_rs;
-  R b, mr, edge;
+  const int32_t* item_bin;   // tile of each work item
+  const int32_t* item_slot;  // slot in itemp, or -1 for the only item of a tile
+  const R* coef;             // window polynomials [2m][deg + 1]
+  int64_t f_rs, tile_rs, item_rs;
+  R edge;                    // window value at the closed edge |t| = m
   Geom g;
 };
 template <typename R>
 hipError_t launch_spread(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
+
+// Sum the item partials of every split tile into its tile slot, in item order
+// (deterministic; compensated summation).
+template <typename R>
+struct ReduceArgs {
+  cplx<R>* tilep;
+  const cplx<R>* itemp;
+  const int32_t* multi_bin;    // split tiles
+  const int32_t* multi_first;  // first itemp slot of each split tile (nmulti + 1)
+  int nmulti;
+  int64_t tile_rs, item_rs;
+  Geom g;
+};
+template <typename R>
+hipError_t launch_tile_reduce(const ReduceArgs<R>& a, int nrhs, hipStream_t s);
 
 template <typename R>
 struct InterpArgs {
@@ -58,38 +80,37 @@ struct InterpArgs {
   const int32_t* item_start;
   const int32_t* item_count;
   const int32_t* item_bin;
+  const R* coef;
   int64_t grid_rs;
   int64_t f_rs;
-  R b, mr, edge;
+  R edge;
   Geom g;
 };
 template <typename R>
 hipError_t launch_interp(const InterpArgs<R>& a, int nrhs, hipStream_t s);
 
 // ------------------------------------------------------------------- FFT
-enum LoadMode { kLoadMerge = 0, kLoadStrided = 1, kLoadPadScaled = 2 };
+enum LoadMode { kLoadMerge = 0, kLoadLine = 1, kLoadPadScaled = 2 };
 enum StoreMode { kStoreCropScaled = 0, kStoreFull = 1 };
 
+// Every pass reads whole lines that are contiguous in memory (line q at
+// in + q * Lin) and writes its transformed axis as the new slowest axis
+// (element k of line q at out + k * nlines + q). After d passes the axes are
+// back in C order.
 template <typename R>
 struct FftArgs {
-  // lines: q in [0, n_outer * n_inner), q = o * n_inner + i
-  int64_t n_outer, n_inner;
-  // input addressing (strided / padded loads)
-  const cplx<R>* in;
-  int64_t in_bs, in_os, in_is, in_es;
-  // output addressing
+  int64_t nlines;
+  const cplx<R>* in;   // strided / padded loads
+  int64_t in_bs;       // batch stride (elements)
+  int Lin;             // input line length (M_sigma, or M for padded loads)
   cplx<R>* out;
-  int64_t out_bs, out_os, out_is, out_es;
-  // merge loader: padded tile sums and tile -> first work item table
-  const cplx<R>* sub;
-  int64_t sub_bs;
-  const int32_t* item_first;
-  // twiddles e^{-2 pi i q / L}, q < L
-  const cplx<R>* tw;
-  // deconvolution factors over I_M (compressed index), length M
-  const R* fac;
-  int lpw;          // lines per work-group
-  int inner_major;  // 1: consecutive threads walk lines (strided passes)
+  int64_t out_bs;
+  // merge loader: tile partials [rhs][tile][P^d]
+  const cplx<R>* tilep;
+  int64_t tile_bs;
+  const cplx<R>* tw;   // twiddles e^{-2 pi i q / L}, q < L
+  const R* fac;        // deconvolution factors over I_M (compressed index)
+  int lpw;             // lines per work-group
   Geom g;
 };
 template <typename R>

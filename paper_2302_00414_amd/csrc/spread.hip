@@ -6,71 +6,83 @@
 // right-hand side. Its nodes touch only the padded tile of (T + 2m)^d cells
 // around the tile, which lives in LDS:
 //   spread : every thread takes nodes, forms c_j = w_j f_j and the d window
-//            factor vectors, and adds c_j * prod_t psi_t into the LDS tile;
-//            the finished padded tile is written out whole, and the tile
-//            sums are merged into grid cells by the first FFT pass.
+//            factor vectors, and adds c_j * prod_t psi_t into the LDS tile
+//            (float64 LDS atomics); the finished padded tile is written out
+//            whole. Tiles split into several work items are summed by
+//            tile_reduce, and the first FFT pass merges the tile partials
+//            into grid cells.
 //   sums   : the padded tile is gathered from the grid (periodically
 //            wrapped) into LDS, and every thread evaluates its nodes' sums.
 // Nodes exactly on a grid line (offset zero) get the extra closed-edge cell;
 // a wave takes the (2m+1)-wide loop only when one of its lanes needs it.
+#include <type_traits>
+
 #include "internal.hpp"
 #include "window.hpp"
 
 namespace nfft {
 
-template <typename R>
-__device__ __forceinline__ void lds_add(R* p, R v) {
+__device__ __forceinline__ void lds_add(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Window factors of one node in one dimension: psi[0] is the extra edge
-// cell (zero unless the node lies on a grid line), psi[1 + i] the value at
-// offset t = frac + m - 1 - i, i = 0..2m-1.
-template <typename R, int MW>
-__device__ __forceinline__ void node_window(R fr, bool edge, R b, R mr, R edge_val, R* psi) {
-  psi[0] = edge ? edge_val : (R)0;
-#pragma unroll
-  for (int i = 0; i < 2 * MW; ++i) psi[1 + i] = kb_psi(fr + (R)(MW - 1 - i), b, mr);
-}
+// Compensated (Neumaier) accumulation of one component.
+template <typename R>
+struct KSum {
+  R s = 0, c = 0;
+  __device__ __forceinline__ void add(R v) {
+    const R t = s + v;
+    if (fabs(s) >= fabs(v))
+      c += (s - t) + v;
+    else
+      c += (v - t) + s;
+    s = t;
+  }
+  __device__ __forceinline__ R value() const { return s + c; }
+};
 
-template <typename R, int D, int MW, bool EDGE>
-__device__ __forceinline__ void add_node(cplx<R>* tile, int P, const int* l, cplx<R> c,
-                                         const R (*psi)[2 * MW + 1]) {
+
+// Accumulate one node into the padded LDS tile (separate real and imaginary
+// planes of float64; float64 LDS atomics are the fast floating-point LDS
+// atomics on this target, float32 ones are not).
+template <int D, int MW, bool EDGE>
+__device__ __forceinline__ void add_node(double* re, double* im, int P, const int* l, double cx,
+                                         double cy, const double (*psi)[2 * MW + 1]) {
   constexpr int K0 = EDGE ? 0 : 1;
   constexpr int KE = 2 * MW + 1;
   if constexpr (D == 1) {
 #pragma unroll
     for (int i0 = K0; i0 < KE; ++i0) {
-      cplx<R>* p = tile + (l[0] + i0);
-      lds_add(&p->x, c.x * psi[0][i0]);
-      lds_add(&p->y, c.y * psi[0][i0]);
+      const int o = l[0] + i0;
+      lds_add(re + o, cx * psi[0][i0]);
+      lds_add(im + o, cy * psi[0][i0]);
     }
   } else if constexpr (D == 2) {
 #pragma unroll
     for (int i0 = K0; i0 < KE; ++i0) {
-      const R a = psi[0][i0];
-      const cplx<R> c0 = mkc<R>(c.x * a, c.y * a);
-      cplx<R>* row = tile + (l[0] + i0) * P + l[1];
+      const double a = psi[0][i0];
+      const double ax = cx * a, ay = cy * a;
+      const int row = (l[0] + i0) * P + l[1];
 #pragma unroll
       for (int i1 = K0; i1 < KE; ++i1) {
-        lds_add(&row[i1].x, c0.x * psi[1][i1]);
-        lds_add(&row[i1].y, c0.y * psi[1][i1]);
+        lds_add(re + row + i1, ax * psi[1][i1]);
+        lds_add(im + row + i1, ay * psi[1][i1]);
       }
     }
   } else {
 #pragma unroll
     for (int i0 = K0; i0 < KE; ++i0) {
-      const R a = psi[0][i0];
-      const cplx<R> c0 = mkc<R>(c.x * a, c.y * a);
+      const double a = psi[0][i0];
+      const double ax = cx * a, ay = cy * a;
 #pragma unroll
       for (int i1 = K0; i1 < KE; ++i1) {
-        const R a1 = psi[1][i1];
-        const cplx<R> c1 = mkc<R>(c0.x * a1, c0.y * a1);
-        cplx<R>* row = tile + ((l[0] + i0) * P + (l[1] + i1)) * P + l[2];
+        const double a1 = psi[1][i1];
+        const double bx = ax * a1, by = ay * a1;
+        const int row = ((l[0] + i0) * P + (l[1] + i1)) * P + l[2];
 #pragma unroll
         for (int i2 = K0; i2 < KE; ++i2) {
-          lds_add(&row[i2].x, c1.x * psi[2][i2]);
-          lds_add(&row[i2].y, c1.y * psi[2][i2]);
+          lds_add(re + row + i2, bx * psi[2][i2]);
+          lds_add(im + row + i2, by * psi[2][i2]);
         }
       }
     }
@@ -79,13 +91,14 @@ __device__ __forceinline__ void add_node(cplx<R>* tile, int P, const int* l, cpl
 
 template <typename R, int D, int MW>
 __global__ __launch_bounds__(256) void spread_kernel(SpreadArgs<R> a) {
-  extern __shared__ unsigned char smem_raw[];
-  cplx<R>* tile = reinterpret_cast<cplx<R>*>(smem_raw);
+  extern __shared__ double lds_d[];
   const int item = blockIdx.x;
   const int rhs = blockIdx.y;
   const int P = a.g.P;
   const int Ptot = a.g.Ptot;
-  for (int i = threadIdx.x; i < Ptot; i += blockDim.x) tile[i] = mkc<R>(0, 0);
+  double* re = lds_d;
+  double* im = lds_d + Ptot;
+  for (int i = threadIdx.x; i < 2 * Ptot; i += blockDim.x) lds_d[i] = 0.0;
   __syncthreads();
 
   const int64_t N = a.g.N;
@@ -96,25 +109,265 @@ __global__ __launch_bounds__(256) void spread_kernel(SpreadArgs<R> a) {
     const int i = start + k;
     const uint32_t L = a.loc[i];
     int l[D];
-    R psi[D][2 * MW + 1];
+    double psd[D][2 * MW + 1];
     bool any_edge = false;
 #pragma unroll
     for (int t = 0; t < D; ++t) {
       l[t] = (int)((L >> (kLocBits * t)) & kLocMask);
       const bool e = (L >> (kEdgeShift + t)) & 1u;
       any_edge |= e;
-      node_window<R, MW>(a.frac[t * N + i], e, a.b, a.mr, a.edge, psi[t]);
+      R psi[2 * MW + 1];
+      kb_poly<R, MW>(a.frac[t * N + i], e, a.edge, a.coef, psi);
+#pragma unroll
+      for (int q = 0; q < 2 * MW + 1; ++q) psd[t][q] = (double)psi[q];
     }
     const cplx<R> c = cmul<R>(a.w[i], f[a.perm[i]]);
     if (__any(any_edge))
-      add_node<R, D, MW, true>(tile, P, l, c, psi);
+      add_node<D, MW, true>(re, im, P, l, (double)c.x, (double)c.y, psd);
     else
-      add_node<R, D, MW, false>(tile, P, l, c, psi);
+      add_node<D, MW, false>(re, im, P, l, (double)c.x, (double)c.y, psd);
   }
   __syncthreads();
-  cplx<R>* out = a.sub + rhs * a.sub_rs + (int64_t)item * Ptot;
-  for (int i = threadIdx.x; i < Ptot; i += blockDim.x) out[i] = tile[i];
+  const int slot = a.item_slot[item];
+  cplx<R>* out = slot < 0 ? a.tilep + rhs * a.tile_rs + (int64_t)a.item_bin[item] * Ptot
+                          : a.itemp + rhs * a.item_rs + (int64_t)slot * Ptot;
+  for (int i = threadIdx.x; i < Ptot; i += blockDim.x) out[i] = mkc<R>((R)re[i], (R)im[i]);
 }
+
+
+// ----------------------------------------------------------------------------
+// Spreading for d <= 2 by lane groups. A group is one 16-lane DPP row; it
+// takes one node at a time and lane k owns footprint column k (the window
+// polynomial k, whose coefficients the lane keeps in registers). The row
+// factor of footprint row i is computed by lane i and broadcast to the group
+// with a DPP row broadcast, so every cell update is one multiply chain and
+// one LDS update of a row segment of consecutive cells.
+//   float32: every group accumulates into its own padded tile (plain
+//            read-modify-write, no atomics; float32 LDS atomics are slow on
+//            this target); the group tiles are summed with compensation at
+//            the end.
+//   float64: all groups accumulate into one padded tile with float64 LDS
+//            atomics.
+// A batch of nodes is first staged in LDS by the whole work-group (one node
+// per thread: offsets, c_j = w_j f_j and the packed cells).
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// Value of lane I of this lane's 16-lane row.
+template <int I>
+__device__ __forceinline__ float row_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + I, 0xf, 0xf, false));
+}
+template <int I>
+__device__ __forceinline__ double row_bcast(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x150 + I, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + I, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <typename R>
+__device__ __forceinline__ R horner(const R* c, R y) {
+  constexpr int DEG = PolyDeg<R>::value;
+  R v = c[DEG];
+#pragma unroll
+  for (int p = DEG - 1; p >= 0; --p) v = v * y + c[p];
+  return v;
+}
+
+template <typename R> struct GroupAcc;
+// float32: private padded tile per group, plain read-modify-write
+template <> struct GroupAcc<float> {
+  float2* tile;  // this group's tile
+  __device__ __forceinline__ void add(int cell, float x, float y) {
+    float2 v = tile[cell];
+    v.x += x;
+    v.y += y;
+    tile[cell] = v;
+  }
+};
+// float64: shared padded tile (real and imaginary planes), LDS atomics
+template <> struct GroupAcc<double> {
+  double* re;
+  double* im;
+  __device__ __forceinline__ void add(int cell, double x, double y) {
+    lds_add(re + cell, x);
+    lds_add(im + cell, y);
+  }
+};
+
+template <typename R, int D, int MW, int NT>
+__global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
+  static_assert(D <= 2 && 2 * MW <= 16, "group spreading covers d <= 2, m <= 8");
+  constexpr int DEG = PolyDeg<R>::value;
+  constexpr int NG = NT / 16;            // groups per work-group
+  constexpr int K2 = 2 * MW;             // footprint columns
+  constexpr bool PRIV = std::is_same<R, float>::value;
+  extern __shared__ double lds_d[];
+  const int item = blockIdx.x;
+  const int rhs = blockIdx.y;
+  const int P = a.g.P;
+  const int Ptot = a.g.Ptot;
+  const int tid = threadIdx.x;
+  const int grp = tid >> 4;
+  const int k = tid & 15;
+
+  // LDS layout: accumulation tile(s), then the node staging area
+  R* st_y0 = nullptr;
+  unsigned char* base = reinterpret_cast<unsigned char*>(lds_d);
+  size_t acc_bytes = PRIV ? (size_t)NG * Ptot * sizeof(float2) : (size_t)2 * Ptot * sizeof(double);
+  st_y0 = reinterpret_cast<R*>(base + acc_bytes);
+  R* st_y1 = st_y0 + NT;
+  R* st_cx = st_y1 + NT;
+  R* st_cy = st_cx + NT;
+  uint32_t* st_loc = reinterpret_cast<uint32_t*>(st_cy + NT);
+
+  for (int i = tid; i < (int)(acc_bytes / sizeof(double)); i += NT) lds_d[i] = 0.0;
+  GroupAcc<R> acc;
+  if constexpr (PRIV) {
+    acc.tile = reinterpret_cast<float2*>(lds_d) + (size_t)grp * Ptot;
+  } else {
+    acc.re = lds_d;
+    acc.im = lds_d + Ptot;
+  }
+
+  // this lane's window polynomial (column k; lanes past 2m keep polynomial 0)
+  R cf[DEG + 1];
+  {
+    const int kk = k < K2 ? k : 0;
+#pragma unroll
+    for (int p = 0; p <= DEG; ++p) cf[p] = a.coef[kk * (DEG + 1) + p];
+  }
+  const R edge = a.edge;
+  __syncthreads();
+
+  const int64_t N = a.g.N;
+  const int start = a.item_start[item];
+  const int cnt = a.item_count[item];
+  const cplx<R>* f = a.f + rhs * a.f_rs;
+  for (int b0 = 0; b0 < cnt; b0 += NT) {
+    const int nb = (cnt - b0) < NT ? (cnt - b0) : NT;
+    if (tid < nb) {
+      const int i = start + b0 + tid;
+      const cplx<R> c = cmul<R>(a.w[i], f[a.perm[i]]);
+      st_y0[tid] = (R)2 * a.frac[i] - (R)1;
+      st_y1[tid] = D > 1 ? (R)2 * a.frac[N + i] - (R)1 : (R)0;
+      st_cx[tid] = c.x;
+      st_cy[tid] = c.y;
+      st_loc[tid] = a.loc[i];
+    }
+    __syncthreads();
+    for (int n = grp; n < nb; n += NG) {
+      const R y0 = st_y0[n];
+      const R cx = st_cx[n], cy = st_cy[n];
+      const uint32_t L = st_loc[n];
+      const int l0 = (int)(L & kLocMask);
+      const bool e0 = (L >> kEdgeShift) & 1u;
+      const R p0 = horner<R>(cf, y0);  // row factor of footprint row k (d = 2) / column k (d = 1)
+      if constexpr (D == 1) {
+        if (k < K2) acc.add(l0 + 1 + k, cx * p0, cy * p0);
+        if (e0 && k == 0) acc.add(l0, cx * edge, cy * edge);
+      } else {
+        const R y1 = st_y1[n];
+        const int l1 = (int)((L >> kLocBits) & kLocMask);
+        const bool e1 = (L >> (kEdgeShift + 1)) & 1u;
+        const R p1 = horner<R>(cf, y1);  // column factor of column k
+        const R vx = cx * p1, vy = cy * p1;
+        const int col = l1 + 1 + k;
+        if constexpr (PRIV) {
+          // all 2m rows of this lane's column are distinct cells: read them
+          // all, then write them all (one LDS round trip per node)
+          float2 cur[K2];
+          float rw[K2];
+          static_for<0, K2>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            rw[I] = row_bcast<I>(p0);
+          });
+          if (k < K2) {
+            float2* t = acc.tile + (l0 + 1) * P + col;
+#pragma unroll
+            for (int i = 0; i < K2; ++i) cur[i] = t[i * P];
+#pragma unroll
+            for (int i = 0; i < K2; ++i) {
+              cur[i].x += vx * rw[i];
+              cur[i].y += vy * rw[i];
+            }
+#pragma unroll
+            for (int i = 0; i < K2; ++i) t[i * P] = cur[i];
+          }
+        } else {
+          static_for<0, K2>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            const R r = row_bcast<I>(p0);
+            if (k < K2) acc.add((l0 + 1 + I) * P + col, vx * r, vy * r);
+          });
+        }
+        if (e0 | e1) {
+          // closed-edge cells of a node on a grid line: row 0 and column 0
+          if (e0 && k < K2) acc.add(l0 * P + col, vx * edge, vy * edge);
+          if (e1 && k < K2) acc.add((l0 + 1 + k) * P + l1, cx * p0 * edge, cy * p0 * edge);
+          if (e0 && e1 && k == 0) acc.add(l0 * P + l1, cx * edge * edge, cy * edge * edge);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  const int slot = a.item_slot[item];
+  cplx<R>* out = slot < 0 ? a.tilep + rhs * a.tile_rs + (int64_t)a.item_bin[item] * Ptot
+                          : a.itemp + rhs * a.item_rs + (int64_t)slot * Ptot;
+  if constexpr (PRIV) {
+    const float2* t = reinterpret_cast<const float2*>(lds_d);
+    for (int i = tid; i < Ptot; i += NT) {
+      KSum<float> sx, sy;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const float2 v = t[(size_t)g * Ptot + i];
+        sx.add(v.x);
+        sy.add(v.y);
+      }
+      out[i] = mkc<R>(sx.value(), sy.value());
+    }
+  } else {
+    for (int i = tid; i < Ptot; i += NT) out[i] = mkc<R>((R)acc.re[i], (R)acc.im[i]);
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void tile_reduce_kernel(ReduceArgs<R> a) {
+  const int Ptot = a.g.Ptot;
+  const int chunks = (Ptot + blockDim.x - 1) / blockDim.x;
+  const int tix = blockIdx.x / chunks;
+  const int cell = (blockIdx.x - tix * chunks) * blockDim.x + threadIdx.x;
+  if (cell >= Ptot) return;
+  const int s0 = a.multi_first[tix], s1 = a.multi_first[tix + 1];
+  const cplx<R>* itemp = a.itemp + blockIdx.y * a.item_rs;
+  KSum<R> sx, sy;
+  for (int s = s0; s < s1; ++s) {
+    const cplx<R> v = itemp[(int64_t)s * Ptot + cell];
+    sx.add(v.x);
+    sy.add(v.y);
+  }
+  a.tilep[blockIdx.y * a.tile_rs + (int64_t)a.multi_bin[tix] * Ptot + cell] =
+      mkc<R>(sx.value(), sy.value());
+}
+
+template <typename R>
+hipError_t launch_tile_reduce(const ReduceArgs<R>& a, int nrhs, hipStream_t s) {
+  if (a.nmulti == 0) return hipSuccess;
+  const int chunks = (a.g.Ptot + 255) / 256;
+  hipLaunchKernelGGL(tile_reduce_kernel<R>, dim3(a.nmulti * chunks, nrhs), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_tile_reduce<float>(const ReduceArgs<float>&, int, hipStream_t);
+template hipError_t launch_tile_reduce<double>(const ReduceArgs<double>&, int, hipStream_t);
 
 template <typename R, int D, int MW, bool EDGE>
 __device__ __forceinline__ cplx<R> sum_node(const cplx<R>* tile, int P, const int* l,
@@ -219,7 +472,7 @@ __global__ __launch_bounds__(256) void interp_kernel(InterpArgs<R> a) {
       l[t] = (int)((L >> (kLocBits * t)) & kLocMask);
       const bool e = (L >> (kEdgeShift + t)) & 1u;
       any_edge |= e;
-      node_window<R, MW>(a.frac[t * N + i], e, a.b, a.mr, a.edge, psi[t]);
+      kb_poly<R, MW>(a.frac[t * N + i], e, a.edge, a.coef, psi[t]);
     }
     cplx<R> v;
     if (__any(any_edge))
@@ -232,8 +485,19 @@ __global__ __launch_bounds__(256) void interp_kernel(InterpArgs<R> a) {
 
 template <typename R, int D, int MW>
 static hipError_t spread_dm(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
-  size_t lds = (size_t)a.g.Ptot * sizeof(cplx<R>);
-  hipLaunchKernelGGL((spread_kernel<R, D, MW>), dim3(a.g.nsub, nrhs), dim3(256), lds, s, a);
+  if constexpr (D <= 2) {
+    // float32: 2 waves (8 private group tiles); float64: 4 waves, shared tile
+    constexpr int NT = std::is_same<R, float>::value ? 128 : 256;
+    constexpr int NG = NT / 16;
+    const size_t acc = std::is_same<R, float>::value ? (size_t)NG * a.g.Ptot * 8
+                                                     : (size_t)2 * a.g.Ptot * 8;
+    const size_t lds = acc + (size_t)NT * (4 * sizeof(R) + 4);
+    hipLaunchKernelGGL((spread_group_kernel<R, D, MW, NT>), dim3(a.g.nsub, nrhs), dim3(NT), lds, s,
+                       a);
+  } else {
+    size_t lds = (size_t)a.g.Ptot * 2 * sizeof(double);
+    hipLaunchKernelGGL((spread_kernel<R, D, MW>), dim3(a.g.nsub, nrhs), dim3(256), lds, s, a);
+  }
   return hipGetLastError();
 }
 

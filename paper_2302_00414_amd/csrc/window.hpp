@@ -35,10 +35,30 @@ __device__ __forceinline__ float kb_psi(float t, float b, float m) {
   return e1 * s;
 }
 
-// Window value at the closed edge |t| = m: psi(m) = b e^{-b m}.
-template <typename R>
-__device__ __forceinline__ R kb_edge(R b, R m) {
-  return b * exp(-b * m);
+// Degree of the per-cell window polynomials (see kb_poly).
+template <typename R> struct PolyDeg;
+template <> struct PolyDeg<double> { static constexpr int value = 16; };
+template <> struct PolyDeg<float> { static constexpr int value = 10; };
+
+// Window factors of one node in one dimension from per-cell polynomials:
+// for cell i = 0..2m-1 (offset t = frac + m - 1 - i) the host fits
+// psi(t) ~ sum_p coef[i][p] y^p with y = 2 frac - 1 in [-1, 1] (Chebyshev
+// interpolation, converted to monomials, error checked at plan time).
+// psi[0] is the extra closed-edge cell of a node on a grid line.
+template <typename R, int MW>
+__device__ __forceinline__ void kb_poly(R frac, bool edge, R edge_val,
+                                        const R* __restrict__ coef, R* psi) {
+  constexpr int DEG = PolyDeg<R>::value;
+  const R y = (R)2 * frac - (R)1;
+  psi[0] = edge ? edge_val : (R)0;
+#pragma unroll
+  for (int i = 0; i < 2 * MW; ++i) {
+    const R* c = coef + i * (DEG + 1);
+    R v = c[DEG];
+#pragma unroll
+    for (int p = DEG - 1; p >= 0; --p) v = v * y + c[p];
+    psi[1 + i] = v;
+  }
 }
 
 }  // namespace nfft

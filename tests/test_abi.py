@@ -47,7 +47,8 @@ def test_strerror_texts():
     ((2, 4, 2.0, 4), _lib.NFFT_EINVAL),        # M_sigma = 8 < 2m + 2
     ((2, 32, 2.0, 9), _lib.NFFT_EUNSUPPORTED),  # m > 8
     ((2, 30, 2.0, 4), _lib.NFFT_EUNSUPPORTED),  # M_sigma = 60 not a power of two
-    ((3, 64, 2.0, 8), _lib.NFFT_OK),           # valid in float32 ...
+    ((3, 64, 2.0, 8), _lib.NFFT_EUNSUPPORTED),  # padded 3-D tile of m = 8 exceeds LDS
+    ((3, 64, 2.0, 6), _lib.NFFT_OK),           # valid
 ])
 def test_plan_validation_before_device(args, status):
     lib = _lib.load()
@@ -66,7 +67,7 @@ def test_plan_validation_before_device(args, status):
 
 
 def test_f64_3d_large_m_unsupported():
-    """The padded tile of a 3-D float64 plan with m = 8 does not fit in LDS."""
+    """The padded float64 accumulation tile of a 3-D plan with m = 8 does not fit in LDS."""
     lib = _lib.load()
     x = np.zeros((4, 3))
     h = ctypes.c_void_p()
