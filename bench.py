@@ -154,6 +154,11 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["both", "f32", "f64"], default="both",
+                    help="profiling runs: time one path only (the JSON line needs both)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="profiling runs: also launch one device-to-device copy of this size, "
+                         "a known-size reference for the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the reconstruction of one request runs on one "
@@ -172,19 +177,39 @@ def main():
     N = x.shape[0]
     Ms = 2 * M
 
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"calibration copy: {n * 4} bytes read, {n * 4} bytes written", file=sys.stderr)
+    if args.precision != "both":
+        r = run_gpu(args.precision, x, w, f, args.steps, args.warmup)
+        print(json.dumps({"precision": args.precision, "ms_per_step": r["ms_per_step"],
+                          "points_per_s": N / (r["ms_per_step"] / 1e3),
+                          "stage_us": {k: v[0] / max(v[1], 1) * 1e3 for k, v in r["stages"].items()
+                                       if v[1]}}), flush=True)
+        return
     r32 = run_gpu("f32", x, w, f, args.steps, args.warmup)
     r64 = run_gpu("f64", x, w, f, args.steps, args.warmup)
 
     sp_ms, sp_calls = r32["stages"]["spread"]
     sp_avg_s = sp_ms / max(sp_calls, 1) / 1e3
     alg = spread_algorithmic_bytes(N, Ms, D, "f32")
-    achieved = alg / sp_avg_s / 1e9
-    roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=traffic_record("spread"),
-                    kernel="spread_kernel<float,2,6>", avg_launch_us=round(sp_avg_s * 1e6, 3),
+    flops = spread_flops(N, MW, D)
+    achieved = flops / sp_avg_s / 1e12
+    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_PEAK_TFLOPS,
+                    unit="TFLOP/s", frac=round(achieved / FP32_PEAK_TFLOPS, 5),
+                    traffic=traffic_record("spread"),
+                    kernel="spread_group_kernel<float,2,6,128>",
+                    avg_launch_us=round(sp_avg_s * 1e6, 3),
+                    algorithmic_flops_per_launch=flops,
                     algorithmic_bytes_per_launch=alg,
-                    alu_tflops=round(spread_flops(N, MW, D) / sp_avg_s / 1e12, 3),
-                    alu_frac_fp32=round(spread_flops(N, MW, D) / sp_avg_s / 1e12 / FP32_PEAK_TFLOPS, 5))
+                    hbm_view_gbs=round(alg / sp_avg_s / 1e9, 2),
+                    hbm_view_frac=round(alg / sp_avg_s / 1e9 / HBM_PEAK_GBS, 5),
+                    cell_updates_per_s=(2 * MW) ** D * N / sp_avg_s)
     stage_us = {k: round(v[0] / max(v[1], 1) * 1e3, 3) for k, v in r32["stages"].items() if v[1]}
     stage_us64 = {k: round(v[0] / max(v[1], 1) * 1e3, 3) for k, v in r64["stages"].items() if v[1]}
 

@@ -155,12 +155,13 @@ int nfft_permutation(nfft_plan_t plan, int32_t *perm_host);
  * them and returns, per stage, the accumulated milliseconds and the number of
  * calls since the last reset:
  *   out[2*s] = milliseconds, out[2*s+1] = calls, for s = 0..NFFT_STAGES-1
- * Stages: 0 spread with the sum of split tiles (adjoint step 1), 1 FFT pass with tile merge (first pass of
- * step 2), 2 remaining FFT passes with deconvolution (step 2 and 3),
- * 3 forward FFT passes with deconvolution (Algorithm 2.1 steps 1-2),
- * 4 forward window sums (Algorithm 2.1 step 3).
+ * Stages: 0 spreading (adjoint step 1), 1 sum of tiles split into several
+ * work items, 2 first FFT pass with the merge of tile partials into grid
+ * cells, 3 remaining FFT passes with deconvolution and crop (adjoint steps 2
+ * and 3), 4 forward deconvolution, zero padding and FFT passes (Algorithm 2.1
+ * steps 1-2), 5 forward window sums (Algorithm 2.1 step 3).
  */
-#define NFFT_STAGES 5
+#define NFFT_STAGES 6
 int nfft_set_profiling(nfft_plan_t plan, int enable);
 int nfft_stage_times(nfft_plan_t plan, double *out, int n, int reset);
 

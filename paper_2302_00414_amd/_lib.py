@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libnfft_mi355x.so")
 
 NFFT_OK, NFFT_EINVAL, NFFT_ENOMEM, NFFT_EDEVICE, NFFT_ESTATE, NFFT_EUNSUPPORTED = range(6)
 NFFT_F64, NFFT_F32 = 0, 1
-NFFT_STAGES = 5
+NFFT_STAGES = 6
 
 EXPORTS = (
     "nfft_plan", "nfft_set_weights", "nfft_adjoint", "nfft_forward", "nfft_destroy",

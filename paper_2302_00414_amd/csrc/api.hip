@@ -39,7 +39,7 @@ int item_nodes() { return env_int("NFFT_ITEM_NODES", kItemNodesDefault); }
 thread_local std::string g_noplan_error;
 
 struct StageEvents {
-  hipEvent_t ev[4];
+  hipEvent_t ev[5];
   int n;       // events used
   int kind;    // 0 adjoint, 1 forward
 };
@@ -442,7 +442,7 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
 // that leaves fewer than 256 work-groups.
 template <typename R>
 int lines_per_wg(int L, int64_t nlines) {
-  const int lds_cap = std::max(1, 65536 / (2 * (L + 1) * (int)sizeof(cplx<R>)));
+  const int lds_cap = std::max(1, 65536 / (2 * (L + L / 8 + 1) * (int)sizeof(cplx<R>)));
   int lpw = std::max(1, std::min(lds_cap, 2048 / L));  // L/8 threads per line
   static const int min_wg = env_int("NFFT_FFT_MIN_WG", 256);
   while (lpw > 1 && nlines / lpw < min_wg) lpw /= 2;
@@ -507,6 +507,7 @@ int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t 
   sa.edge = (R)(p->b * std::exp(-p->b * p->m));
   sa.g = g;
   HIP_TRY(p, nfft::launch_spread<R>(sa, nrhs, s));
+  record(p, se, s);
   nfft::ReduceArgs<R> ra{};
   ra.tilep = (cplx<R>*)p->tilep;
   ra.itemp = (const cplx<R>*)p->itemp;
@@ -766,19 +767,18 @@ int nfft_stage_times(nfft_plan_t p, double* out, int n, int reset) {
     HIP_TRY(p, hipEventSynchronize(se.ev[se.n - 1]));
     float ms = 0.f;
     if (se.kind == 0) {
-      // adjoint: start, after spread, after first FFT pass, end
-      const int map[3] = {0, 1, 2};
-      for (int i = 0; i + 1 < se.n && i < 3; ++i) {
+      // adjoint: start, after spread, after split-tile reduce, after first FFT pass, end
+      for (int i = 0; i + 1 < se.n && i < 4; ++i) {
         HIP_TRY(p, hipEventElapsedTime(&ms, se.ev[i], se.ev[i + 1]));
-        p->stage_ms[map[i]] += ms;
-        p->stage_calls[map[i]] += 1;
+        p->stage_ms[i] += ms;
+        p->stage_calls[i] += 1;
       }
     } else {
-      const int map[2] = {3, 4};
+      // forward: start, after FFT passes, after window sums
       for (int i = 0; i + 1 < se.n && i < 2; ++i) {
         HIP_TRY(p, hipEventElapsedTime(&ms, se.ev[i], se.ev[i + 1]));
-        p->stage_ms[map[i]] += ms;
-        p->stage_calls[map[i]] += 1;
+        p->stage_ms[4 + i] += ms;
+        p->stage_calls[4 + i] += 1;
       }
     }
     for (int i = 0; i < se.n; ++i) p->event_pool.push_back(se.ev[i]);

@@ -72,6 +72,10 @@ __device__ __forceinline__ void dft8(cplx<R>* a) {
   a[7] = csub<R>(e3, w3);
 }
 
+// LDS position of element i of a line: one pad slot per 8 elements breaks the
+// power-of-two strides of the Stockham passes across the LDS banks.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 3); }
+
 // One Stockham pass of radix RAD over `lpw` lines of length L.
 template <typename R, int RAD, bool INV>
 __device__ __forceinline__ void stockham_pass(const cplx<R>* src, cplx<R>* dst, int L, int LS,
@@ -84,7 +88,7 @@ __device__ __forceinline__ void stockham_pass(const cplx<R>* src, cplx<R>* dst, 
     cplx<R>* o = dst + line * LS;
     cplx<R> a[RAD];
 #pragma unroll
-    for (int r = 0; r < RAD; ++r) a[r] = s[j + r * nbf];
+    for (int r = 0; r < RAD; ++r) a[r] = s[lpad(j + r * nbf)];
     const int jm = j & (Ns - 1);
     if (Ns > 1) {
       const int step = jm * (L / (Ns * RAD));
@@ -104,7 +108,7 @@ __device__ __forceinline__ void stockham_pass(const cplx<R>* src, cplx<R>* dst, 
     }
     const int idx = (j - jm) * RAD + jm;
 #pragma unroll
-    for (int r = 0; r < RAD; ++r) o[idx + r * Ns] = a[r];
+    for (int r = 0; r < RAD; ++r) o[lpad(idx + r * Ns)] = a[r];
   }
 }
 
@@ -216,7 +220,7 @@ template <typename R, int LOG2L, bool INV, int LD, int ST>
 __global__ __launch_bounds__(512) void fft_pass_kernel(FftArgs<R> a) {
   constexpr int L = 1 << LOG2L;
   constexpr int TPL = L / 8;  // threads per line (one radix-8 butterfly each)
-  constexpr int LS = L + 1;   // padded LDS line stride (bank spread for the store phase)
+  constexpr int LS = L + L / 8 + 1;  // LDS line stride: padded line plus one slot
   extern __shared__ unsigned char smem_raw[];
   const int lpw = a.lpw;      // blockDim.x == lpw * TPL
   cplx<R>* buf0 = reinterpret_cast<cplx<R>*>(smem_raw);
@@ -240,9 +244,9 @@ __global__ __launch_bounds__(512) void fft_pass_kernel(FftArgs<R> a) {
       for (int r = 0; r < 8; ++r) v[r] = mkc<R>(0, 0);
     }
     dft8<R, INV>(v);
-    cplx<R>* o = buf0 + l * LS + j * 8;
+    cplx<R>* o = buf0 + l * LS;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) o[r] = v[r];
+    for (int r = 0; r < 8; ++r) o[lpad(j * 8 + r)] = v[r];
   }
   __syncthreads();
 
@@ -275,7 +279,7 @@ __global__ __launch_bounds__(512) void fft_pass_kernel(FftArgs<R> a) {
     const int l = idx % lpw;
     const int e = idx / lpw;
     const int64_t q = q0 + l;
-    if (q < nlines) store_elem<R, ST>(a, b, q, e, L, src[l * LS + e]);
+    if (q < nlines) store_elem<R, ST>(a, b, q, e, L, src[l * LS + lpad(e)]);
   }
 }
 
@@ -283,7 +287,7 @@ template <typename R, int LOG2L, bool INV, int LD, int ST>
 static hipError_t fft_launch(const FftArgs<R>& a, int nbatch, hipStream_t s) {
   constexpr int L = 1 << LOG2L;
   const unsigned nblk = (unsigned)((a.nlines + a.lpw - 1) / a.lpw);
-  const size_t lds = 2 * (size_t)a.lpw * (L + 1) * sizeof(cplx<R>);
+  const size_t lds = 2 * (size_t)a.lpw * (L + L / 8 + 1) * sizeof(cplx<R>);
   const int threads = a.lpw * (L / 8);
   hipLaunchKernelGGL((fft_pass_kernel<R, LOG2L, INV, LD, ST>), dim3(nblk, nbatch), dim3(threads),
                      lds, s, a);

@@ -106,7 +106,8 @@ def nfft_set_profiling(plan, enable: bool) -> None:
     check(_lib.load().nfft_set_profiling(plan, int(bool(enable))), plan)
 
 
-STAGE_NAMES = ("spread", "fft_merge", "fft_rest_deconv", "fwd_fft_deconv", "fwd_sums")
+STAGE_NAMES = ("spread", "split_tile_reduce", "fft_merge", "fft_rest_deconv", "fwd_fft_deconv",
+               "fwd_sums")
 
 
 def nfft_stage_times(plan, reset: bool = False) -> dict:
