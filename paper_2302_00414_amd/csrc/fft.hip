@@ -166,6 +166,53 @@ __device__ __forceinline__ cplx<R> merge_cell(const cplx<R>* __restrict__ tilep,
   return mkc<R>((R)sx, (R)sy);
 }
 
+// Tiles at least 2m wide: a cell lies within m of at most one border per
+// dimension, so at most two tiles cover it per dimension (its own and one
+// neighbour). All 2^d candidate loads are issued without branches; a missing
+// neighbour is replaced by the own tile with weight zero.
+template <typename R, int D>
+__device__ __forceinline__ cplx<R> merge_cell2(const cplx<R>* __restrict__ tilep, const Geom& g,
+                                               const int* c) {
+  const int tm = g.T - 1, nm = g.nb - 1, ts = g.tshift;
+  int qb[3][2], pp[3][2];
+  float wt[3];
+#pragma unroll
+  for (int t = 0; t < D; ++t) {
+    const int r = c[t] & tm;
+    const int b0 = c[t] >> ts;
+    qb[t][0] = b0;
+    pp[t][0] = r + g.m;
+    const bool lo = r < g.m, hi = r >= g.T - g.m;
+    qb[t][1] = lo ? ((b0 - 1) & nm) : (hi ? ((b0 + 1) & nm) : b0);
+    pp[t][1] = lo ? r + g.m + g.T : (hi ? r + g.m - g.T : r + g.m);
+    wt[t] = (lo || hi) ? 1.0f : 0.0f;
+  }
+  const int bs = g.Ms_shift - ts;
+  cplx<R> v[1 << D];
+  float w[1 << D];
+#pragma unroll
+  for (int s = 0; s < (1 << D); ++s) {
+    int bin = 0, pl = 0;
+    float ws = 1.0f;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+      const int o = (s >> (D - 1 - t)) & 1;
+      bin = (bin << bs) + qb[t][o];
+      pl = pl * g.P + pp[t][o];
+      ws = o ? ws * wt[t] : ws;
+    }
+    v[s] = tilep[(int64_t)bin * g.Ptot + pl];
+    w[s] = ws;
+  }
+  double sx = 0.0, sy = 0.0;
+#pragma unroll
+  for (int s = 0; s < (1 << D); ++s) {
+    sx += (double)w[s] * (double)v[s].x;
+    sy += (double)w[s] * (double)v[s].y;
+  }
+  return mkc<R>((R)sx, (R)sy);
+}
+
 template <typename R, int LD>
 __device__ __forceinline__ cplx<R> load_elem(const FftArgs<R>& a, int b, int64_t q, int e, int L) {
   if constexpr (LD == kLoadLine) {
@@ -185,16 +232,17 @@ __device__ __forceinline__ cplx<R> load_elem(const FftArgs<R>& a, int b, int64_t
     // merge: the line index enumerates the leading d-1 grid coordinates
     const cplx<R>* tp = a.tilep + b * a.tile_bs;
     const int d = a.g.d;
+    const bool two = a.g.T >= 2 * a.g.m;
     if (d == 1) {
       const int c[1] = {e};
-      return merge_cell<R, 1>(tp, a.g, c);
+      return two ? merge_cell2<R, 1>(tp, a.g, c) : merge_cell<R, 1>(tp, a.g, c);
     }
     if (d == 2) {
       const int c[2] = {(int)q, e};
-      return merge_cell<R, 2>(tp, a.g, c);
+      return two ? merge_cell2<R, 2>(tp, a.g, c) : merge_cell<R, 2>(tp, a.g, c);
     }
     const int c[3] = {(int)(q >> a.g.Ms_shift), (int)(q & (a.g.Ms - 1)), e};
-    return merge_cell<R, 3>(tp, a.g, c);
+    return two ? merge_cell2<R, 3>(tp, a.g, c) : merge_cell<R, 3>(tp, a.g, c);
   }
 }
 

@@ -162,13 +162,15 @@ __device__ __forceinline__ void static_for(F&& f) {
 // Value of lane I of this lane's 16-lane row.
 template <int I>
 __device__ __forceinline__ float row_bcast(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + I, 0xf, 0xf, false));
+  const int b = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x150 + I, 0xf, 0xf, false));
 }
 template <int I>
 __device__ __forceinline__ double row_bcast(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x150 + I, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + I, 0xf, 0xf, false);
+  const int l = (int)(b & 0xffffffffLL), u = (int)(b >> 32);
+  const int lo = __builtin_amdgcn_update_dpp(l, l, 0x150 + I, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(u, u, 0x150 + I, 0xf, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
@@ -202,7 +204,44 @@ template <> struct GroupAcc<double> {
   }
 };
 
-template <typename R, int D, int MW, int NT>
+// Per-node values a group needs for one node: the column factor times c_j
+// (vx, vy, lane k), the 2m row factors (rw, broadcast to every lane), the
+// node's tile-local cell and its on-grid-line flags.
+template <typename R, int K2>
+struct NodePrep {
+  R vx, vy, p0, cx, cy;
+  R rw[K2];
+  int l0, l1;
+  bool e0, e1;
+};
+
+template <typename R, int D, int K2>
+__device__ __forceinline__ void prep_node(NodePrep<R, K2>& h, R y0, R y1, R cx, R cy, uint32_t L,
+                                          const R* cf) {
+  h.cx = cx;
+  h.cy = cy;
+  h.l0 = (int)(L & kLocMask);
+  h.e0 = (L >> kEdgeShift) & 1u;
+  h.p0 = horner<R>(cf, y0);
+  if constexpr (D == 1) {
+    h.vx = cx * h.p0;
+    h.vy = cy * h.p0;
+    h.l1 = 0;
+    h.e1 = false;
+  } else {
+    h.l1 = (int)((L >> kLocBits) & kLocMask);
+    h.e1 = (L >> (kEdgeShift + 1)) & 1u;
+    const R p1 = horner<R>(cf, y1);
+    h.vx = cx * p1;
+    h.vy = cy * p1;
+    static_for<0, K2>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      h.rw[I] = row_bcast<I>(h.p0);
+    });
+  }
+}
+
+template <typename R, int D, int MW, int NT, int TT>
 __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
   static_assert(D <= 2 && 2 * MW <= 16, "group spreading covers d <= 2, m <= 8");
   constexpr int DEG = PolyDeg<R>::value;
@@ -212,17 +251,17 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
   extern __shared__ double lds_d[];
   const int item = blockIdx.x;
   const int rhs = blockIdx.y;
-  const int P = a.g.P;
+  // padded tile edge: a compile-time constant for the usual tile edge
+  const int P = TT > 0 ? TT + 2 * MW : a.g.P;
   const int Ptot = a.g.Ptot;
   const int tid = threadIdx.x;
   const int grp = tid >> 4;
   const int k = tid & 15;
 
   // LDS layout: accumulation tile(s), then the node staging area
-  R* st_y0 = nullptr;
   unsigned char* base = reinterpret_cast<unsigned char*>(lds_d);
-  size_t acc_bytes = PRIV ? (size_t)NG * Ptot * sizeof(float2) : (size_t)2 * Ptot * sizeof(double);
-  st_y0 = reinterpret_cast<R*>(base + acc_bytes);
+  const size_t acc_bytes = PRIV ? (size_t)NG * Ptot * sizeof(float2) : (size_t)2 * Ptot * sizeof(double);
+  R* st_y0 = reinterpret_cast<R*>(base + acc_bytes);
   R* st_y1 = st_y0 + NT;
   R* st_cx = st_y1 + NT;
   R* st_cy = st_cx + NT;
@@ -251,68 +290,88 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
   const int start = a.item_start[item];
   const int cnt = a.item_count[item];
   const cplx<R>* f = a.f + rhs * a.f_rs;
+  // one node per thread is loaded into registers one batch ahead, so the
+  // global-memory latency of batch b+1 overlaps the spreading of batch b
+  R pf0 = 0, pf1 = 0;
+  uint32_t pfl = 0;
+  cplx<R> pfw = mkc<R>(0, 0), pfs = mkc<R>(0, 0);
+  auto issue = [&](int b) {
+    if (b + tid < cnt) {
+      const int i = start + b + tid;
+      pf0 = a.frac[i];
+      pf1 = D > 1 ? a.frac[N + i] : (R)0;
+      pfl = a.loc[i];
+      pfw = a.w[i];
+      pfs = f[a.perm[i]];
+    }
+  };
+  issue(0);
   for (int b0 = 0; b0 < cnt; b0 += NT) {
     const int nb = (cnt - b0) < NT ? (cnt - b0) : NT;
     if (tid < nb) {
-      const int i = start + b0 + tid;
-      const cplx<R> c = cmul<R>(a.w[i], f[a.perm[i]]);
-      st_y0[tid] = (R)2 * a.frac[i] - (R)1;
-      st_y1[tid] = D > 1 ? (R)2 * a.frac[N + i] - (R)1 : (R)0;
+      const cplx<R> c = cmul<R>(pfw, pfs);
+      st_y0[tid] = (R)2 * pf0 - (R)1;
+      st_y1[tid] = (R)2 * pf1 - (R)1;
       st_cx[tid] = c.x;
       st_cy[tid] = c.y;
-      st_loc[tid] = a.loc[i];
+      st_loc[tid] = pfl;
     }
+    if (b0 + NT < cnt) issue(b0 + NT);
     __syncthreads();
-    for (int n = grp; n < nb; n += NG) {
-      const R y0 = st_y0[n];
-      const R cx = st_cx[n], cy = st_cy[n];
-      const uint32_t L = st_loc[n];
-      const int l0 = (int)(L & kLocMask);
-      const bool e0 = (L >> kEdgeShift) & 1u;
-      const R p0 = horner<R>(cf, y0);  // row factor of footprint row k (d = 2) / column k (d = 1)
+    // Software pipeline over this group's nodes n = grp, grp + NG, ...: the
+    // window factors of the next node are computed while the cell reads of
+    // the current node are in flight. LDS operations of a wave execute in
+    // order, so the next node's reads always see this node's writes.
+    int n = grp;
+    NodePrep<R, K2> h;
+    if (n < nb) prep_node<R, D, K2>(h, st_y0[n], st_y1[n], st_cx[n], st_cy[n], st_loc[n], cf);
+    for (; n < nb; n += NG) {
+      const int nn = n + NG;
       if constexpr (D == 1) {
-        if (k < K2) acc.add(l0 + 1 + k, cx * p0, cy * p0);
-        if (e0 && k == 0) acc.add(l0, cx * edge, cy * edge);
+        if (k < K2) acc.add(h.l0 + 1 + k, h.vx, h.vy);
+        if (h.e0 && k == 0) acc.add(h.l0, h.cx * edge, h.cy * edge);
+        if (nn < nb) prep_node<R, D, K2>(h, st_y0[nn], st_y1[nn], st_cx[nn], st_cy[nn], st_loc[nn], cf);
       } else {
-        const R y1 = st_y1[n];
-        const int l1 = (int)((L >> kLocBits) & kLocMask);
-        const bool e1 = (L >> (kEdgeShift + 1)) & 1u;
-        const R p1 = horner<R>(cf, y1);  // column factor of column k
-        const R vx = cx * p1, vy = cy * p1;
-        const int col = l1 + 1 + k;
+        const int col = h.l1 + 1 + k;
         if constexpr (PRIV) {
-          // all 2m rows of this lane's column are distinct cells: read them
-          // all, then write them all (one LDS round trip per node)
+          float2* t = acc.tile + (h.l0 + 1) * P + col;
           float2 cur[K2];
-          float rw[K2];
-          static_for<0, K2>([&](auto ic) {
-            constexpr int I = decltype(ic)::value;
-            rw[I] = row_bcast<I>(p0);
-          });
           if (k < K2) {
-            float2* t = acc.tile + (l0 + 1) * P + col;
 #pragma unroll
             for (int i = 0; i < K2; ++i) cur[i] = t[i * P];
+          }
+          NodePrep<R, K2> hn;
+          if (nn < nb)
+            prep_node<R, D, K2>(hn, st_y0[nn], st_y1[nn], st_cx[nn], st_cy[nn], st_loc[nn], cf);
+          if (k < K2) {
 #pragma unroll
             for (int i = 0; i < K2; ++i) {
-              cur[i].x += vx * rw[i];
-              cur[i].y += vy * rw[i];
+              cur[i].x += h.vx * h.rw[i];
+              cur[i].y += h.vy * h.rw[i];
             }
 #pragma unroll
             for (int i = 0; i < K2; ++i) t[i * P] = cur[i];
           }
+          if (h.e0 | h.e1) {
+            // closed-edge cells of a node on a grid line: row 0 and column 0
+            if (h.e0 && k < K2) acc.add(h.l0 * P + col, h.vx * edge, h.vy * edge);
+            if (h.e1 && k < K2)
+              acc.add((h.l0 + 1 + k) * P + h.l1, h.cx * h.p0 * edge, h.cy * h.p0 * edge);
+            if (h.e0 && h.e1 && k == 0) acc.add(h.l0 * P + h.l1, h.cx * edge * edge, h.cy * edge * edge);
+          }
+          h = hn;
         } else {
-          static_for<0, K2>([&](auto ic) {
-            constexpr int I = decltype(ic)::value;
-            const R r = row_bcast<I>(p0);
-            if (k < K2) acc.add((l0 + 1 + I) * P + col, vx * r, vy * r);
-          });
-        }
-        if (e0 | e1) {
-          // closed-edge cells of a node on a grid line: row 0 and column 0
-          if (e0 && k < K2) acc.add(l0 * P + col, vx * edge, vy * edge);
-          if (e1 && k < K2) acc.add((l0 + 1 + k) * P + l1, cx * p0 * edge, cy * p0 * edge);
-          if (e0 && e1 && k == 0) acc.add(l0 * P + l1, cx * edge * edge, cy * edge * edge);
+          if (k < K2) {
+#pragma unroll
+            for (int i = 0; i < K2; ++i) acc.add((h.l0 + 1 + i) * P + col, h.vx * h.rw[i], h.vy * h.rw[i]);
+          }
+          if (h.e0 | h.e1) {
+            if (h.e0 && k < K2) acc.add(h.l0 * P + col, h.vx * edge, h.vy * edge);
+            if (h.e1 && k < K2)
+              acc.add((h.l0 + 1 + k) * P + h.l1, h.cx * h.p0 * edge, h.cy * h.p0 * edge);
+            if (h.e0 && h.e1 && k == 0) acc.add(h.l0 * P + h.l1, h.cx * edge * edge, h.cy * edge * edge);
+          }
+          if (nn < nb) prep_node<R, D, K2>(h, st_y0[nn], st_y1[nn], st_cx[nn], st_cy[nn], st_loc[nn], cf);
         }
       }
     }
@@ -323,16 +382,24 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
   cplx<R>* out = slot < 0 ? a.tilep + rhs * a.tile_rs + (int64_t)a.item_bin[item] * Ptot
                           : a.itemp + rhs * a.item_rs + (int64_t)slot * Ptot;
   if constexpr (PRIV) {
+    // group tiles summed in a fixed pairwise order (in float64, rounded once)
     const float2* t = reinterpret_cast<const float2*>(lds_d);
     for (int i = tid; i < Ptot; i += NT) {
-      KSum<float> sx, sy;
+      double sx[NG], sy[NG];
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
         const float2 v = t[(size_t)g * Ptot + i];
-        sx.add(v.x);
-        sy.add(v.y);
+        sx[g] = v.x;
+        sy[g] = v.y;
       }
-      out[i] = mkc<R>(sx.value(), sy.value());
+#pragma unroll
+      for (int w = 1; w < NG; w *= 2)
+#pragma unroll
+        for (int g = 0; g + w < NG; g += 2 * w) {
+          sx[g] += sx[g + w];
+          sy[g] += sy[g + w];
+        }
+      out[i] = mkc<R>((R)sx[0], (R)sy[0]);
     }
   } else {
     for (int i = tid; i < Ptot; i += NT) out[i] = mkc<R>((R)acc.re[i], (R)acc.im[i]);
@@ -348,14 +415,38 @@ __global__ __launch_bounds__(256) void tile_reduce_kernel(ReduceArgs<R> a) {
   if (cell >= Ptot) return;
   const int s0 = a.multi_first[tix], s1 = a.multi_first[tix + 1];
   const cplx<R>* itemp = a.itemp + blockIdx.y * a.item_rs;
-  KSum<R> sx, sy;
-  for (int s = s0; s < s1; ++s) {
-    const cplx<R> v = itemp[(int64_t)s * Ptot + cell];
-    sx.add(v.x);
-    sy.add(v.y);
+  // four interleaved compensated sums keep four loads in flight; they are
+  // combined in a fixed order, so the result does not depend on timing
+  KSum<R> sx[4], sy[4];
+  int sidx = s0;
+  for (; sidx + 4 <= s1; sidx += 4) {
+    cplx<R> v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = itemp[(int64_t)(sidx + u) * Ptot + cell];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sx[u].add(v[u].x);
+      sy[u].add(v[u].y);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    if (sidx + u < s1) {
+      const cplx<R> v = itemp[(int64_t)(sidx + u) * Ptot + cell];
+      sx[u].add(v.x);
+      sy[u].add(v.y);
+    }
+  }
+  KSum<R> tx, ty;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    tx.add(sx[u].s);
+    tx.add(sx[u].c);
+    ty.add(sy[u].s);
+    ty.add(sy[u].c);
   }
   a.tilep[blockIdx.y * a.tile_rs + (int64_t)a.multi_bin[tix] * Ptot + cell] =
-      mkc<R>(sx.value(), sy.value());
+      mkc<R>(tx.value(), ty.value());
 }
 
 template <typename R>
@@ -492,8 +583,12 @@ static hipError_t spread_dm(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
     const size_t acc = std::is_same<R, float>::value ? (size_t)NG * a.g.Ptot * 8
                                                      : (size_t)2 * a.g.Ptot * 8;
     const size_t lds = acc + (size_t)NT * (4 * sizeof(R) + 4);
-    hipLaunchKernelGGL((spread_group_kernel<R, D, MW, NT>), dim3(a.g.nsub, nrhs), dim3(NT), lds, s,
-                       a);
+    if (D == 2 && a.g.T == 16)
+      hipLaunchKernelGGL((spread_group_kernel<R, D, MW, NT, 16>), dim3(a.g.nsub, nrhs), dim3(NT),
+                         lds, s, a);
+    else
+      hipLaunchKernelGGL((spread_group_kernel<R, D, MW, NT, 0>), dim3(a.g.nsub, nrhs), dim3(NT),
+                         lds, s, a);
   } else {
     size_t lds = (size_t)a.g.Ptot * 2 * sizeof(double);
     hipLaunchKernelGGL((spread_kernel<R, D, MW>), dim3(a.g.nsub, nrhs), dim3(256), lds, s, a);
