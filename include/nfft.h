@@ -91,6 +91,18 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
               const double *nodes, int precision, int max_rhs, void *stream);
 
 /*
+ * nfft_plan_clone -- a second handle on the same node set with its own
+ * workspace for max_rhs right-hand sides. The clone shares the source plan's
+ * sorted nodes, weights and tables (setting weights through either handle
+ * changes both) but not its workspace, so transforms through different
+ * handles may run concurrently on different streams. Each handle is
+ * destroyed separately; the shared data is freed with the last one.
+ *   out     receives the new handle (NULL on failure)
+ *   stream  hipStream_t for initialising the workspace; the call synchronises it
+ */
+int nfft_plan_clone(nfft_plan_t src, int max_rhs, nfft_plan_t *out, void *stream);
+
+/*
  * nfft_set_weights -- store W = diag(w) of eq. (3.6); the weights are complex in general.
  *   w  N complex128 values (host or device) in the caller's node order.
  * The plan keeps its own copy (permuted to its internal order, rounded to
@@ -136,10 +148,11 @@ const char *nfft_strerror(int status);
 const char *nfft_last_error(nfft_plan_t plan);
 
 /*
- * nfft_plan_info -- plan geometry, written to out[0..n-1] (n <= 12):
+ * nfft_plan_info -- plan geometry, written to out[0..n-1] (n <= 13):
  *   0 d, 1 M, 2 M_sigma, 3 m, 4 N, 5 precision, 6 max_rhs,
  *   7 tile edge (cells), 8 number of tiles, 9 number of spreading work items,
- *   10 largest tile population, 11 device bytes allocated.
+ *   10 largest tile population, 11 device bytes this handle keeps alive
+ *   (shared node data plus its workspace), 12 workspace bytes of this handle.
  */
 int nfft_plan_info(nfft_plan_t plan, int64_t *out, int n);
 

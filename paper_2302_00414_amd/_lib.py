@@ -16,7 +16,7 @@ NFFT_F64, NFFT_F32 = 0, 1
 NFFT_STAGES = 6
 
 EXPORTS = (
-    "nfft_plan", "nfft_set_weights", "nfft_adjoint", "nfft_forward", "nfft_destroy",
+    "nfft_plan", "nfft_plan_clone", "nfft_set_weights", "nfft_adjoint", "nfft_forward", "nfft_destroy",
     "nfft_footprint", "nfft_strerror", "nfft_last_error", "nfft_plan_info",
     "nfft_permutation", "nfft_set_profiling", "nfft_stage_times",
 )
@@ -45,6 +45,8 @@ def load() -> ctypes.CDLL:
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     lib.nfft_plan.argtypes = [ctypes.POINTER(vp), i32, i32, dbl, i32, i64, vp, i32, i32, vp]
     lib.nfft_plan.restype = i32
+    lib.nfft_plan_clone.argtypes = [vp, i32, ctypes.POINTER(vp), vp]
+    lib.nfft_plan_clone.restype = i32
     lib.nfft_set_weights.argtypes = [vp, vp, vp]
     lib.nfft_set_weights.restype = i32
     lib.nfft_adjoint.argtypes = [vp, vp, vp, i32, vp]

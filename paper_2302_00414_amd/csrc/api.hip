@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -44,6 +45,18 @@ struct StageEvents {
   int kind;    // 0 adjoint, 1 forward
 };
 
+// Device data that clones of a plan share: the sorted nodes, the weights, the
+// work-item tables and the window and deconvolution tables. Freed with the
+// last handle that refers to it.
+struct SharedData {
+  std::vector<void*> allocs;
+  int64_t bytes = 0;
+  bool has_weights = false;
+  ~SharedData() {
+    for (void* q : allocs) (void)hipFree(q);
+  }
+};
+
 }  // namespace
 
 struct nfft_plan_s {
@@ -53,8 +66,8 @@ struct nfft_plan_s {
   int64_t N = 0;
   Geom g{};
   int maxpop = 0;
-  int64_t bytes = 0;
-  bool has_weights = false;
+  int64_t bytes = 0;                 // workspace bytes owned by this handle
+  std::shared_ptr<SharedData> shared; // node data, weights and tables
   std::string last_error;
   // device buffers
   int32_t* perm = nullptr;
@@ -184,8 +197,10 @@ long double bessel_i0(long double z) {
   return sum;
 }
 
+// Device allocation owned by the plan's shared data (shared = true) or by
+// this handle's workspace.
 template <typename T>
-int dalloc(nfft_plan_t p, T** ptr, size_t bytes) {
+int dalloc(nfft_plan_t p, T** ptr, size_t bytes, bool shared = true) {
   *ptr = nullptr;
   if (bytes == 0) bytes = 16;
   void* q = nullptr;
@@ -193,8 +208,13 @@ int dalloc(nfft_plan_t p, T** ptr, size_t bytes) {
   if (e != hipSuccess)
     return fail(p, e == hipErrorOutOfMemory ? NFFT_ENOMEM : NFFT_EDEVICE,
                 "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
-  p->allocs.push_back(q);
-  p->bytes += (int64_t)bytes;
+  if (shared) {
+    p->shared->allocs.push_back(q);
+    p->shared->bytes += (int64_t)bytes;
+  } else {
+    p->allocs.push_back(q);
+    p->bytes += (int64_t)bytes;
+  }
   *ptr = static_cast<T*>(q);
   return NFFT_OK;
 }
@@ -314,6 +334,25 @@ int build_tables(nfft_plan_t p) {
   return NFFT_OK;
 }
 
+// Per-handle workspace for max_rhs right-hand sides: tile and item partials,
+// FFT buffers and the forward grid.
+template <typename R>
+int alloc_workspace(nfft_plan_t p, hipStream_t s) {
+  const Geom& g = p->g;
+  const int d = p->d;
+  const int64_t R_ = p->max_rhs;
+  const size_t tile_bytes = (size_t)R_ * g.nbins * g.Ptot * sizeof(cplx<R>);
+  TRY(dalloc(p, &p->tilep, tile_bytes, false));
+  // tiles without nodes are never written: their partials stay zero
+  HIP_TRY(p, hipMemsetAsync(p->tilep, 0, tile_bytes, s));
+  TRY(dalloc(p, &p->itemp, (size_t)R_ * std::max(1, p->nslots) * g.Ptot * sizeof(cplx<R>), false));
+  const int64_t Ms = p->Ms, M = p->M;
+  if (d >= 2) TRY(dalloc(p, &p->bufA, (size_t)R_ * ipow(Ms, d - 1) * M * sizeof(cplx<R>), false));
+  if (d == 3) TRY(dalloc(p, &p->bufB, (size_t)R_ * Ms * M * M * sizeof(cplx<R>), false));
+  TRY(dalloc(p, &p->grid, (size_t)R_ * ipow(Ms, d) * sizeof(cplx<R>), false));
+  return NFFT_OK;
+}
+
 template <typename R>
 int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
   const int64_t N = p->N;
@@ -422,16 +461,7 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
   HIP_TRY(p, hipMemcpyAsync(p->multi_first, mfirst.data(), mfirst.size() * 4, hipMemcpyHostToDevice, s));
 
   TRY(dalloc(p, &p->w, N * sizeof(cplx<R>)));
-  const int64_t R_ = p->max_rhs;
-  const size_t tile_bytes = (size_t)R_ * g.nbins * g.Ptot * sizeof(cplx<R>);
-  TRY(dalloc(p, &p->tilep, tile_bytes));
-  // tiles without nodes are never written: their partials stay zero
-  HIP_TRY(p, hipMemsetAsync(p->tilep, 0, tile_bytes, s));
-  TRY(dalloc(p, &p->itemp, (size_t)R_ * std::max(1, p->nslots) * g.Ptot * sizeof(cplx<R>)));
-  const int64_t Ms = p->Ms, M = p->M;
-  if (d >= 2) TRY(dalloc(p, &p->bufA, (size_t)R_ * ipow(Ms, d - 1) * M * sizeof(cplx<R>)));
-  if (d == 3) TRY(dalloc(p, &p->bufB, (size_t)R_ * Ms * M * M * sizeof(cplx<R>)));
-  TRY(dalloc(p, &p->grid, (size_t)R_ * ipow(Ms, d) * sizeof(cplx<R>)));
+  TRY(alloc_workspace<R>(p, s));
   TRY(build_tables<R>(p));
   HIP_TRY(p, hipStreamSynchronize(s));
   return NFFT_OK;
@@ -650,6 +680,7 @@ int nfft_plan(nfft_plan_t* out, int d, int M, double sigma, int m, int64_t N,
   if (!nodes) return fail(nullptr, NFFT_EINVAL, "nodes is NULL");
   nfft_plan_t p = new (std::nothrow) nfft_plan_s();
   if (!p) return fail(nullptr, NFFT_ENOMEM, "host allocation failed");
+  p->shared = std::make_shared<SharedData>();
   p->d = d;
   p->M = M;
   p->sigma = sigma;
@@ -690,6 +721,40 @@ int nfft_plan(nfft_plan_t* out, int d, int M, double sigma, int m, int64_t N,
   return NFFT_OK;
 }
 
+int nfft_plan_clone(nfft_plan_t src, int max_rhs, nfft_plan_t* out, void* stream) {
+  if (!out) return fail(src, NFFT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!src) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
+  if (max_rhs < 1 || max_rhs > 65535) return fail(src, NFFT_EINVAL, "max_rhs = %d, expected 1..65535", max_rhs);
+  nfft_plan_t p = new (std::nothrow) nfft_plan_s(*src);
+  if (!p) return fail(src, NFFT_ENOMEM, "host allocation failed");
+  // own workspace and bookkeeping; node data, weights and tables are shared
+  p->allocs.clear();
+  p->bytes = 0;
+  p->pending.clear();
+  p->event_pool.clear();
+  p->profiling = false;
+  for (int i = 0; i < NFFT_STAGES; ++i) {
+    p->stage_ms[i] = 0;
+    p->stage_calls[i] = 0;
+  }
+  p->last_error.clear();
+  p->max_rhs = max_rhs;
+  p->tilep = p->itemp = p->bufA = p->bufB = p->grid = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  int st = (hipSetDevice(p->device) == hipSuccess) ? NFFT_OK : NFFT_EDEVICE;
+  if (st == NFFT_OK)
+    st = p->prec == NFFT_F64 ? alloc_workspace<double>(p, s) : alloc_workspace<float>(p, s);
+  if (st == NFFT_OK && hipStreamSynchronize(s) != hipSuccess) st = NFFT_EDEVICE;
+  if (st != NFFT_OK) {
+    src->last_error = p->last_error.empty() ? "clone failed" : p->last_error;
+    free_plan(p);
+    return st;
+  }
+  *out = p;
+  return NFFT_OK;
+}
+
 int nfft_set_weights(nfft_plan_t p, const double* w, void* stream) {
   if (!p) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
   if (!w) return fail(p, NFFT_EINVAL, "w is NULL");
@@ -706,7 +771,7 @@ int nfft_set_weights(nfft_plan_t p, const double* w, void* stream) {
     HIP_TRY(p, nfft::launch_permute_weights<float>((const double*)dw, p->perm, p->N,
                                                    (cplx<float>*)p->w, s));
   HIP_TRY(p, hipStreamSynchronize(s));
-  p->has_weights = true;
+  p->shared->has_weights = true;
   return NFFT_OK;
 }
 
@@ -715,7 +780,7 @@ int nfft_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, void* strea
   if (!f || !fhat) return fail(p, NFFT_EINVAL, "f or fhat is NULL");
   if (nrhs < 1 || nrhs > p->max_rhs)
     return fail(p, NFFT_EINVAL, "nrhs = %d outside 1..max_rhs = %d", nrhs, p->max_rhs);
-  if (!p->has_weights) return fail(p, NFFT_ESTATE, "nfft_set_weights has not been called");
+  if (!p->shared->has_weights) return fail(p, NFFT_ESTATE, "nfft_set_weights has not been called");
   HIP_TRY(p, hipGetLastError());
   hipStream_t s = (hipStream_t)stream;
   return p->prec == NFFT_F64 ? run_adjoint<double>(p, f, fhat, nrhs, s)
@@ -743,9 +808,10 @@ int nfft_destroy(nfft_plan_t p) {
 
 int nfft_plan_info(nfft_plan_t p, int64_t* out, int n) {
   if (!p || !out || n < 0) return fail(p, NFFT_EINVAL, "bad arguments to nfft_plan_info");
-  const int64_t v[12] = {p->d, p->M, p->Ms, p->m, p->N, p->prec, p->max_rhs,
-                         p->g.T, p->g.nbins, p->g.nsub, p->maxpop, p->bytes};
-  for (int i = 0; i < n && i < 12; ++i) out[i] = v[i];
+  const int64_t v[13] = {p->d, p->M, p->Ms, p->m, p->N, p->prec, p->max_rhs,
+                         p->g.T, p->g.nbins, p->g.nsub, p->maxpop,
+                         p->bytes + p->shared->bytes, p->bytes};
+  for (int i = 0; i < n && i < 13; ++i) out[i] = v[i];
   return NFFT_OK;
 }
 

@@ -57,6 +57,12 @@ def nfft_plan(d: int, M: int, sigma: float, m: int, nodes: torch.Tensor, precisi
     return h
 
 
+def nfft_plan_clone(plan, max_rhs: int, stream=None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    check(_lib.load().nfft_plan_clone(plan, max_rhs, ctypes.byref(h), _stream_ptr(stream)), plan)
+    return h
+
+
 def nfft_set_weights(plan, w: torch.Tensor, stream=None) -> None:
     check(_lib.load().nfft_set_weights(plan, ctypes.c_void_p(w.data_ptr()), _stream_ptr(stream)), plan)
 
@@ -89,10 +95,10 @@ def nfft_last_error(plan=None) -> str:
 
 
 def nfft_plan_info(plan) -> dict:
-    out = (ctypes.c_int64 * 12)()
-    check(_lib.load().nfft_plan_info(plan, out, 12), plan)
+    out = (ctypes.c_int64 * 13)()
+    check(_lib.load().nfft_plan_info(plan, out, 13), plan)
     keys = ("d", "M", "Ms", "m", "N", "precision", "max_rhs", "tile", "tiles", "items",
-            "max_tile_nodes", "bytes")
+            "max_tile_nodes", "bytes", "workspace_bytes")
     return dict(zip(keys, (int(v) for v in out)))
 
 
@@ -138,6 +144,16 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def clone(self, max_rhs: int, stream=None) -> "Plan":
+        """A handle on the same node set and weights with its own workspace."""
+        c = Plan.__new__(Plan)
+        c.__dict__.update({k: v for k, v in self.__dict__.items() if k != "_h"})
+        c.max_rhs = max_rhs
+        c._h = None
+        with torch.cuda.device(self.device):
+            c._h = nfft_plan_clone(self._h, max_rhs, stream)
+        return c
 
     def set_weights(self, w, stream=None) -> None:
         if isinstance(w, np.ndarray):
