@@ -5,10 +5,10 @@
 // hundred nodes of one tile. A work-group owns one work item and one
 // right-hand side. Its nodes touch only the padded tile of (T + 2m)^d cells
 // around the tile, which lives in LDS:
-//   spread : every thread takes nodes, forms c_j = w_j f_j and the d window
-//            factor vectors, and adds c_j * prod_t psi_t into the LDS tile
-//            (float64 LDS atomics); the finished padded tile is written out
-//            whole. Tiles split into several work items are summed by
+//   spread : nodes are spread into the LDS tile by groups of lanes, each
+//            lane owning footprint cells (d <= 2: 16-lane groups per node,
+//            d = 3: one wave per node); the finished padded tile is written
+//            out whole. Tiles split into several work items are summed by
 //            tile_reduce, and the first FFT pass merges the tile partials
 //            into grid cells.
 //   sums   : the padded tile is gathered from the grid (periodically
@@ -40,100 +40,6 @@ struct KSum {
   }
   __device__ __forceinline__ R value() const { return s + c; }
 };
-
-
-// Accumulate one node into the padded LDS tile (separate real and imaginary
-// planes of float64; float64 LDS atomics are the fast floating-point LDS
-// atomics on this target, float32 ones are not).
-template <int D, int MW, bool EDGE>
-__device__ __forceinline__ void add_node(double* re, double* im, int P, const int* l, double cx,
-                                         double cy, const double (*psi)[2 * MW + 1]) {
-  constexpr int K0 = EDGE ? 0 : 1;
-  constexpr int KE = 2 * MW + 1;
-  if constexpr (D == 1) {
-#pragma unroll
-    for (int i0 = K0; i0 < KE; ++i0) {
-      const int o = l[0] + i0;
-      lds_add(re + o, cx * psi[0][i0]);
-      lds_add(im + o, cy * psi[0][i0]);
-    }
-  } else if constexpr (D == 2) {
-#pragma unroll
-    for (int i0 = K0; i0 < KE; ++i0) {
-      const double a = psi[0][i0];
-      const double ax = cx * a, ay = cy * a;
-      const int row = (l[0] + i0) * P + l[1];
-#pragma unroll
-      for (int i1 = K0; i1 < KE; ++i1) {
-        lds_add(re + row + i1, ax * psi[1][i1]);
-        lds_add(im + row + i1, ay * psi[1][i1]);
-      }
-    }
-  } else {
-#pragma unroll
-    for (int i0 = K0; i0 < KE; ++i0) {
-      const double a = psi[0][i0];
-      const double ax = cx * a, ay = cy * a;
-#pragma unroll
-      for (int i1 = K0; i1 < KE; ++i1) {
-        const double a1 = psi[1][i1];
-        const double bx = ax * a1, by = ay * a1;
-        const int row = ((l[0] + i0) * P + (l[1] + i1)) * P + l[2];
-#pragma unroll
-        for (int i2 = K0; i2 < KE; ++i2) {
-          lds_add(re + row + i2, bx * psi[2][i2]);
-          lds_add(im + row + i2, by * psi[2][i2]);
-        }
-      }
-    }
-  }
-}
-
-template <typename R, int D, int MW>
-__global__ __launch_bounds__(256) void spread_kernel(SpreadArgs<R> a) {
-  extern __shared__ double lds_d[];
-  const int item = blockIdx.x;
-  const int rhs = blockIdx.y;
-  const int P = a.g.P;
-  const int Ptot = a.g.Ptot;
-  double* re = lds_d;
-  double* im = lds_d + Ptot;
-  for (int i = threadIdx.x; i < 2 * Ptot; i += blockDim.x) lds_d[i] = 0.0;
-  __syncthreads();
-
-  const int64_t N = a.g.N;
-  const int start = a.item_start[item];
-  const int cnt = a.item_count[item];
-  const cplx<R>* f = a.f + rhs * a.f_rs;
-  for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
-    const int i = start + k;
-    const uint32_t L = a.loc[i];
-    int l[D];
-    double psd[D][2 * MW + 1];
-    bool any_edge = false;
-#pragma unroll
-    for (int t = 0; t < D; ++t) {
-      l[t] = (int)((L >> (kLocBits * t)) & kLocMask);
-      const bool e = (L >> (kEdgeShift + t)) & 1u;
-      any_edge |= e;
-      R psi[2 * MW + 1];
-      kb_poly<R, MW>(a.frac[t * N + i], e, a.edge, a.coef, psi);
-#pragma unroll
-      for (int q = 0; q < 2 * MW + 1; ++q) psd[t][q] = (double)psi[q];
-    }
-    const cplx<R> c = cmul<R>(a.w[i], f[a.perm[i]]);
-    if (__any(any_edge))
-      add_node<D, MW, true>(re, im, P, l, (double)c.x, (double)c.y, psd);
-    else
-      add_node<D, MW, false>(re, im, P, l, (double)c.x, (double)c.y, psd);
-  }
-  __syncthreads();
-  const int slot = a.item_slot[item];
-  cplx<R>* out = slot < 0 ? a.tilep + rhs * a.tile_rs + (int64_t)a.item_bin[item] * Ptot
-                          : a.itemp + rhs * a.item_rs + (int64_t)slot * Ptot;
-  for (int i = threadIdx.x; i < Ptot; i += blockDim.x) out[i] = mkc<R>((R)re[i], (R)im[i]);
-}
-
 
 // ----------------------------------------------------------------------------
 // Spreading for d <= 2 by lane groups. A group is one 16-lane DPP row; it
@@ -406,6 +312,198 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
   }
 }
 
+// ----------------------------------------------------------------------------
+// Spreading for d = 3, one wave per node. A batch of SB nodes is staged in LDS
+// (the 2m window factors of each dimension by Horner, c_j and the packed
+// cells), the jobs spread over the work-group. A wave then takes one node at a
+// time; its lanes own cells (i1, i2) of the footprint plane (64 at a time) and
+// walk the 2m footprint planes i0, whose factor every lane holds in registers.
+//   float32: two waves, one per component: each keeps a float32 plane of its
+//            own (real or imaginary part) and updates it by batched
+//            read-modify-write; no two lanes touch one cell, and float32 LDS
+//            atomics, far slower on this target, are not used.
+//   float64: four waves share one tile through float64 LDS atomics.
+// A node on a grid line (extra closed-edge cells) takes a slower path over
+// the full (2m+1)^3 footprint.
+template <typename R, int MW>
+struct Stage3 {
+  static constexpr int SB = 64;                   // nodes per staged batch
+  static constexpr int K2 = 2 * MW;
+  static constexpr int SW = 3 * K2 + 2;           // psi_0, psi_1, psi_2, cx, cy
+  static constexpr size_t bytes = (size_t)SB * (SW * sizeof(R) + sizeof(uint32_t));
+};
+
+template <typename R, int MW, int NW, int TT>
+__global__ __launch_bounds__(64 * NW) void spread3_kernel(SpreadArgs<R> a) {
+  constexpr int NT = 64 * NW;
+  constexpr int K2 = 2 * MW;
+  constexpr int KP = K2 * K2;                 // footprint cells of the (1,2) plane
+  constexpr int NPASS = (KP + 63) / 64;
+  constexpr int DEG = PolyDeg<R>::value;
+  constexpr int SB = Stage3<R, MW>::SB;
+  constexpr int SW = Stage3<R, MW>::SW;
+  constexpr bool SPLIT = std::is_same<R, float>::value;  // one component per wave
+  static_assert(!SPLIT || NW == 2, "float32: one wave per component");
+  extern __shared__ double lds_d[];
+  const int item = blockIdx.x;
+  const int rhs = blockIdx.y;
+  // padded tile edge: a compile-time constant for the usual tile edge
+  const int P = TT > 0 ? TT + 2 * MW : a.g.P;
+  const int PP = P * P;
+  const int Ptot = a.g.Ptot;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const size_t acc_bytes = (size_t)2 * Ptot * sizeof(R);
+  R* stage = reinterpret_cast<R*>(reinterpret_cast<unsigned char*>(lds_d) + acc_bytes);
+  uint32_t* sloc = reinterpret_cast<uint32_t*>(stage + SB * SW);
+  for (int i = tid; i < (int)(acc_bytes / sizeof(double)); i += NT) lds_d[i] = 0.0;
+
+  const int64_t N = a.g.N;
+  const int start = a.item_start[item];
+  const int cnt = a.item_count[item];
+  const cplx<R>* f = a.f + rhs * a.f_rs;
+  const R edge = a.edge;
+  // float32: this wave's component plane; float64: both planes, shared
+  R* plane = reinterpret_cast<R*>(lds_d) + (SPLIT ? (wave & 1) * Ptot : 0);
+  const int comp = SPLIT ? (wave & 1) : 0;
+  const int first = SPLIT ? 0 : wave;         // first node of this wave in a batch
+  constexpr int NS = SPLIT ? 1 : NW;          // node stride
+
+  // With a padded edge of 16 the 2m rows a wave touches would share LDS
+  // banks (a row is 16 elements; 32 banks of 4 bytes). The column index is
+  // XOR-ed with 8 on every other row, or pair of rows, so that the rows one
+  // LDS cycle serves fall on distinct banks: float64 planes (8-byte accesses,
+  // 16 lanes = 2 rows per cycle) flip on row bit 0, float32 planes (4-byte
+  // accesses, 32 lanes = 4 rows per cycle, two rows per 32 banks) on row
+  // bit 1.
+  const bool swz = P == 16;
+  constexpr int SWB = SPLIT ? 5 : 4;  // bit of the cell index that flips the column
+  auto sw = [swz](int c) { return swz ? c ^ (((c >> SWB) & 1) << 3) : c; };
+
+  // this lane's cell of the footprint plane in each pass
+  int q1[NPASS], q2[NPASS];
+#pragma unroll
+  for (int pass = 0; pass < NPASS; ++pass) {
+    const int q = lane + 64 * pass;
+    q1[pass] = q < KP ? q / K2 : 0;
+    q2[pass] = q < KP ? q % K2 : 0;
+  }
+
+  // per-node values a wave needs, read from the staging area one node ahead
+  struct Hdr {
+    uint32_t L;
+    R c0, c1;  // float32: this wave's component (c1 unused); float64: re, im
+    R w12[NPASS];
+    R p0[K2];
+  };
+  auto load_hdr = [&](int n) {
+    Hdr h;
+    const R* o = stage + n * SW;
+    h.L = sloc[n];
+    h.c0 = o[3 * K2 + comp];
+    h.c1 = SPLIT ? (R)0 : o[3 * K2 + 1];
+#pragma unroll
+    for (int pass = 0; pass < NPASS; ++pass) h.w12[pass] = o[K2 + q1[pass]] * o[2 * K2 + q2[pass]];
+#pragma unroll
+    for (int i0 = 0; i0 < K2; ++i0) h.p0[i0] = o[i0];
+    return h;
+  };
+
+  auto spread_node = [&](const Hdr& h, int n) {
+    const uint32_t L = h.L;
+    const int l0 = (int)(L & kLocMask);
+    const int l1 = (int)((L >> kLocBits) & kLocMask);
+    const int l2 = (int)((L >> (2 * kLocBits)) & kLocMask);
+    if (((L >> kEdgeShift) & 7u) == 0) {
+#pragma unroll
+      for (int pass = 0; pass < NPASS; ++pass) {
+        if (lane + 64 * pass >= KP) continue;
+        // the swizzle depends on the row only, not on the plane
+        const int cell0 = sw((l0 + 1) * PP + (l1 + 1 + q1[pass]) * P + (l2 + 1 + q2[pass]));
+        if constexpr (SPLIT) {
+          const R v = h.c0 * h.w12[pass];
+          R* t = plane + cell0;
+          R cur[K2];
+#pragma unroll
+          for (int i0 = 0; i0 < K2; ++i0) cur[i0] = t[i0 * PP];
+#pragma unroll
+          for (int i0 = 0; i0 < K2; ++i0) cur[i0] += v * h.p0[i0];
+#pragma unroll
+          for (int i0 = 0; i0 < K2; ++i0) t[i0 * PP] = cur[i0];
+        } else {
+          const R vx = h.c0 * h.w12[pass], vy = h.c1 * h.w12[pass];
+#pragma unroll
+          for (int i0 = 0; i0 < K2; ++i0) {
+            lds_add(lds_d + cell0 + i0 * PP, vx * h.p0[i0]);
+            lds_add(lds_d + Ptot + cell0 + i0 * PP, vy * h.p0[i0]);
+          }
+        }
+      }
+    } else {
+      // full closed footprint: index 0 of each dimension is the edge cell
+      const R* o = stage + n * SW;
+      const bool e0 = (L >> kEdgeShift) & 1u, e1 = (L >> (kEdgeShift + 1)) & 1u,
+                 e2 = (L >> (kEdgeShift + 2)) & 1u;
+      constexpr int KE = K2 + 1;
+      for (int q = lane; q < KE * KE * KE; q += 64) {
+        const int k0 = q / (KE * KE), k1 = (q / KE) % KE, k2 = q % KE;
+        const R w0 = k0 ? o[k0 - 1] : (e0 ? edge : (R)0);
+        const R w1 = k1 ? o[K2 + k1 - 1] : (e1 ? edge : (R)0);
+        const R w2 = k2 ? o[2 * K2 + k2 - 1] : (e2 ? edge : (R)0);
+        const R wv = w0 * w1 * w2;
+        const int cell = sw(((l0 + k0) * P + (l1 + k1)) * P + (l2 + k2));
+        if constexpr (SPLIT) {
+          plane[cell] += h.c0 * wv;
+        } else {
+          lds_add(lds_d + cell, h.c0 * wv);
+          lds_add(lds_d + Ptot + cell, h.c1 * wv);
+        }
+      }
+    }
+  };
+
+  for (int b0 = 0; b0 < cnt; b0 += SB) {
+    const int nb = (cnt - b0) < SB ? (cnt - b0) : SB;
+    __syncthreads();  // tile zeroed / previous batch consumed
+    for (int job = tid; job < 4 * SB; job += NT) {
+      const int n = job % SB, kind = job / SB;
+      if (n >= nb) continue;
+      const int i = start + b0 + n;
+      R* o = stage + n * SW;
+      if (kind < 3) {
+        const R y = (R)2 * a.frac[kind * N + i] - (R)1;
+#pragma unroll
+        for (int q = 0; q < K2; ++q) o[kind * K2 + q] = horner<R>(a.coef + q * (DEG + 1), y);
+      } else {
+        const cplx<R> c = cmul<R>(a.w[i], f[a.perm[i]]);
+        o[3 * K2] = c.x;
+        o[3 * K2 + 1] = c.y;
+        sloc[n] = a.loc[i];
+      }
+    }
+    __syncthreads();
+    // two nodes per trip with the header of the next one loaded ahead
+    if (first >= nb) continue;
+    Hdr h0 = load_hdr(first);
+    for (int n = first; n < nb; n += 2 * NS) {
+      const bool more = n + NS < nb;
+      Hdr h1 = h0;
+      if (more) h1 = load_hdr(n + NS);
+      spread_node(h0, n);
+      if (!more) break;
+      if (n + 2 * NS < nb) h0 = load_hdr(n + 2 * NS);
+      spread_node(h1, n + NS);
+    }
+  }
+  __syncthreads();
+  const int slot = a.item_slot[item];
+  cplx<R>* out = slot < 0 ? a.tilep + rhs * a.tile_rs + (int64_t)a.item_bin[item] * Ptot
+                          : a.itemp + rhs * a.item_rs + (int64_t)slot * Ptot;
+  const R* re = reinterpret_cast<const R*>(lds_d);
+  for (int i = tid; i < Ptot; i += NT) out[i] = mkc<R>(re[sw(i)], re[Ptot + sw(i)]);
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void tile_reduce_kernel(ReduceArgs<R> a) {
   const int Ptot = a.g.Ptot;
@@ -590,8 +688,14 @@ static hipError_t spread_dm(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
       hipLaunchKernelGGL((spread_group_kernel<R, D, MW, NT, 0>), dim3(a.g.nsub, nrhs), dim3(NT),
                          lds, s, a);
   } else {
-    size_t lds = (size_t)a.g.Ptot * 2 * sizeof(double);
-    hipLaunchKernelGGL((spread_kernel<R, D, MW>), dim3(a.g.nsub, nrhs), dim3(256), lds, s, a);
+    // d = 3: float32 two waves, one component plane each; float64 four
+    // waves sharing one tile
+    constexpr int NW = std::is_same<R, float>::value ? 2 : 4;
+    const size_t lds = (size_t)2 * a.g.Ptot * sizeof(R) + Stage3<R, MW>::bytes;
+    if (a.g.T == 8)
+      hipLaunchKernelGGL((spread3_kernel<R, MW, NW, 8>), dim3(a.g.nsub, nrhs), dim3(64 * NW), lds, s, a);
+    else
+      hipLaunchKernelGGL((spread3_kernel<R, MW, NW, 0>), dim3(a.g.nsub, nrhs), dim3(64 * NW), lds, s, a);
   }
   return hipGetLastError();
 }
