@@ -91,9 +91,85 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
               const double *nodes, int precision, int max_rhs, void *stream);
 
 /*
+ * Tuning. The spreading and FFT kernels take six launch parameters that
+ * change their speed, never their result beyond rounding order. An array
+ * tuning[NFFT_TUNE_*] selects them; an entry of 0, or an entry past
+ * ntuning, selects the library default:
+ *   NFFT_TUNE_TILE_EDGE       tile edge in cells: a power of two in [8, 256],
+ *                             >= m; clipped to M_sigma (default: d = 1: 256,
+ *                             d = 2: 16, d = 3: 8). Fixed at plan time.
+ *   NFFT_TUNE_ITEM_NODES      most nodes in one spreading work item,
+ *                             16..65536 (default 256). Fixed at plan time.
+ *   NFFT_TUNE_SPREAD_THREADS  threads of a spreading work-group for d <= 2,
+ *                             float32, one right-hand side per work-group:
+ *                             64, 128 or 256 (default 128).
+ *   NFFT_TUNE_RHS_PER_GROUP   right-hand sides that one spreading work-group
+ *                             takes when nrhs > 1 and d <= 2: 1, 2, 4 or 8
+ *                             (default 1). Above 1 the node data and window
+ *                             factors are read and evaluated once for them all.
+ *   NFFT_TUNE_FFT_MIN_WG      an FFT pass gives each work-group fewer lines
+ *                             while it would launch fewer work-groups than
+ *                             this, 1..65536 (default 256).
+ *   NFFT_TUNE_SPREAD_PLANES   layout of the private LDS tiles of that float32
+ *                             kernel: 1 = one complex tile per lane group,
+ *                             2 = two groups per node, one for the real and
+ *                             one for the imaginary plane (default 1).
+ * The environment variables NFFT_TILE_EDGE, NFFT_ITEM_NODES,
+ * NFFT_SPREAD_THREADS, NFFT_RHS_PER_GROUP, NFFT_FFT_MIN_WG and
+ * NFFT_SPREAD_PLANES replace the defaults. A combination whose spreading work-group does not fit in LDS is
+ * NFFT_EUNSUPPORTED.
+ */
+enum nfft_tune {
+  NFFT_TUNE_TILE_EDGE = 0,
+  NFFT_TUNE_ITEM_NODES = 1,
+  NFFT_TUNE_SPREAD_THREADS = 2,
+  NFFT_TUNE_RHS_PER_GROUP = 3,
+  NFFT_TUNE_FFT_MIN_WG = 4,
+  NFFT_TUNE_SPREAD_PLANES = 5,
+  NFFT_TUNE_COUNT = 6
+};
+
+/*
+ * nfft_plan_tuned -- nfft_plan with explicit tuning (see above); tuning may
+ * be NULL (ntuning ignored). Arguments and status codes as for nfft_plan.
+ */
+int nfft_plan_tuned(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
+                    const double *nodes, int precision, int max_rhs, const int *tuning,
+                    int ntuning, void *stream);
+
+/* nfft_get_tuning -- the plan's resolved tuning into out[0..n-1], n <= NFFT_TUNE_COUNT. */
+int nfft_get_tuning(nfft_plan_t plan, int *out, int n);
+
+/*
+ * nfft_set_tuning -- change a launch-time parameter of an existing plan
+ * (NFFT_TUNE_SPREAD_THREADS, NFFT_TUNE_RHS_PER_GROUP, NFFT_TUNE_FFT_MIN_WG,
+ * NFFT_TUNE_SPREAD_PLANES; value 0 restores the default). Tile edge and item size are fixed at plan
+ * time: NFFT_EINVAL for them. Takes effect for transforms enqueued later.
+ */
+int nfft_set_tuning(nfft_plan_t plan, int knob, int value);
+
+/*
+ * nfft_plan_autotune -- plan a node set with the tuning that runs the
+ * adjoint fastest on this device for nrhs right-hand sides. Candidate tile
+ * edges and work-item sizes each get a plan (the node sort is redone per
+ * candidate); on each, the launch-time parameters are swept; every candidate
+ * is timed with HIP events over several adjoint calls on zero data (the run
+ * time of the kernels does not depend on the values). The fastest plan is
+ * returned; the others are freed. Its tuning is read with nfft_get_tuning.
+ * Weights are not set: call nfft_set_weights before nfft_adjoint.
+ *   nrhs        right-hand sides per call to tune for, 1..max_rhs
+ *   best_ms     if not NULL, receives the winner's milliseconds per adjoint
+ *   other arguments as for nfft_plan; the call synchronises `stream` and
+ *   takes of the order of a second for a million nodes.
+ */
+int nfft_plan_autotune(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
+                       const double *nodes, int precision, int max_rhs, int nrhs,
+                       double *best_ms, void *stream);
+
+/*
  * nfft_plan_clone -- a second handle on the same node set with its own
  * workspace for max_rhs right-hand sides. The clone shares the source plan's
- * sorted nodes, weights and tables (setting weights through either handle
+ * sorted nodes, weights, tables and tuning (setting weights through either handle
  * changes both) but not its workspace, so transforms through different
  * handles may run concurrently on different streams. Each handle is
  * destroyed separately; the shared data is freed with the last one.

@@ -14,9 +14,14 @@ LIB_PATH = os.path.join(HERE, "libnfft_mi355x.so")
 NFFT_OK, NFFT_EINVAL, NFFT_ENOMEM, NFFT_EDEVICE, NFFT_ESTATE, NFFT_EUNSUPPORTED = range(6)
 NFFT_F64, NFFT_F32 = 0, 1
 NFFT_STAGES = 6
+(NFFT_TUNE_TILE_EDGE, NFFT_TUNE_ITEM_NODES, NFFT_TUNE_SPREAD_THREADS, NFFT_TUNE_RHS_PER_GROUP,
+ NFFT_TUNE_FFT_MIN_WG, NFFT_TUNE_SPREAD_PLANES) = range(6)
+NFFT_TUNE_COUNT = 6
 
 EXPORTS = (
-    "nfft_plan", "nfft_plan_clone", "nfft_set_weights", "nfft_adjoint", "nfft_forward", "nfft_destroy",
+    "nfft_plan", "nfft_plan_tuned", "nfft_plan_autotune", "nfft_get_tuning", "nfft_set_tuning",
+    "nfft_plan_clone",
+    "nfft_set_weights", "nfft_adjoint", "nfft_forward", "nfft_destroy",
     "nfft_footprint", "nfft_strerror", "nfft_last_error", "nfft_plan_info",
     "nfft_permutation", "nfft_set_profiling", "nfft_stage_times",
 )
@@ -45,6 +50,16 @@ def load() -> ctypes.CDLL:
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     lib.nfft_plan.argtypes = [ctypes.POINTER(vp), i32, i32, dbl, i32, i64, vp, i32, i32, vp]
     lib.nfft_plan.restype = i32
+    lib.nfft_plan_tuned.argtypes = [ctypes.POINTER(vp), i32, i32, dbl, i32, i64, vp, i32, i32,
+                                    ctypes.POINTER(i32), i32, vp]
+    lib.nfft_plan_tuned.restype = i32
+    lib.nfft_plan_autotune.argtypes = [ctypes.POINTER(vp), i32, i32, dbl, i32, i64, vp, i32, i32, i32,
+                                       ctypes.POINTER(dbl), vp]
+    lib.nfft_plan_autotune.restype = i32
+    lib.nfft_get_tuning.argtypes = [vp, ctypes.POINTER(i32), i32]
+    lib.nfft_get_tuning.restype = i32
+    lib.nfft_set_tuning.argtypes = [vp, i32, i32]
+    lib.nfft_set_tuning.restype = i32
     lib.nfft_plan_clone.argtypes = [vp, i32, ctypes.POINTER(vp), vp]
     lib.nfft_plan_clone.restype = i32
     lib.nfft_set_weights.argtypes = [vp, vp, vp]

@@ -23,11 +23,7 @@ using nfft::Geom;
 
 namespace {
 
-constexpr int kItemNodesDefault = 256;  // nodes per spreading work item
-
-// Tuning overrides (environment): NFFT_TILE_EDGE = tile edge in cells (a power
-// of two >= m, <= 256), NFFT_ITEM_NODES = nodes per spreading work item,
-// NFFT_FFT_MIN_WG = work-groups below which an FFT pass stops widening.
+// Environment replacements of the tuning defaults (positive integers only).
 int env_int(const char* name, int fallback) {
   const char* v = std::getenv(name);
   if (!v || !*v) return fallback;
@@ -35,7 +31,19 @@ int env_int(const char* name, int fallback) {
   long x = std::strtol(v, &end, 10);
   return (end && *end == 0 && x > 0 && x < (1 << 20)) ? (int)x : fallback;
 }
-int item_nodes() { return env_int("NFFT_ITEM_NODES", kItemNodesDefault); }
+
+// Library defaults of the tuning parameters (NFFT_TUNE_*), before clipping.
+int default_tuning(int knob, int d) {
+  switch (knob) {
+    case NFFT_TUNE_TILE_EDGE: return env_int("NFFT_TILE_EDGE", d == 1 ? 256 : (d == 2 ? 16 : 8));
+    case NFFT_TUNE_ITEM_NODES: return env_int("NFFT_ITEM_NODES", 256);
+    case NFFT_TUNE_SPREAD_THREADS: return env_int("NFFT_SPREAD_THREADS", 128);
+    case NFFT_TUNE_RHS_PER_GROUP: return env_int("NFFT_RHS_PER_GROUP", 1);
+    case NFFT_TUNE_FFT_MIN_WG: return env_int("NFFT_FFT_MIN_WG", 256);
+    case NFFT_TUNE_SPREAD_PLANES: return env_int("NFFT_SPREAD_PLANES", 1);
+    default: return 0;
+  }
+}
 
 thread_local std::string g_noplan_error;
 
@@ -66,6 +74,7 @@ struct nfft_plan_s {
   int64_t N = 0;
   Geom g{};
   int maxpop = 0;
+  int tune[NFFT_TUNE_COUNT] = {0};   // resolved tuning
   int64_t bytes = 0;                 // workspace bytes owned by this handle
   std::shared_ptr<SharedData> shared; // node data, weights and tables
   std::string last_error;
@@ -131,19 +140,11 @@ int oversampled(int M, double sigma) {
   return 2 * (int)std::ceil(a / 2.0);
 }
 
-int tile_edge(int d, int Ms) {
-  // tile-local cells are packed into 8 bits per dimension, so T <= 256
-  int t = d == 1 ? 256 : (d == 2 ? 16 : 8);
-  const int o = env_int("NFFT_TILE_EDGE", 0);
-  if (o >= 8 && o <= 256 && (o & (o - 1)) == 0) t = o;
-  return std::min(t, Ms);
-}
+// Largest LDS a work-group may use on gfx950.
+constexpr size_t kMaxLds = 160 * 1024;
 
 size_t cbytes(int prec) { return prec == NFFT_F64 ? 16 : 8; }
 size_t rbytes(int prec) { return prec == NFFT_F64 ? 8 : 4; }
-
-// Largest padded-tile LDS size a spreading work-group may use.
-constexpr size_t kMaxTileLds = 144 * 1024;
 
 int validate(int d, int M, double sigma, int m, int64_t N, int precision, int max_rhs,
              nfft_plan_t p) {
@@ -166,15 +167,6 @@ int validate(int d, int M, double sigma, int m, int64_t N, int precision, int ma
   if (!is_pow2(Ms) || Ms < 8 || Ms > 4096)
     return fail(p, NFFT_EUNSUPPORTED, "M_sigma = %d: only powers of two in [8, 4096] are built",
                 Ms);
-  const int T = tile_edge(d, Ms);
-  if (T < m) return fail(p, NFFT_EUNSUPPORTED, "tile edge %d < m = %d", T, m);
-  const int P = T + 2 * m;
-  size_t Ptot = 1;
-  for (int t = 0; t < d; ++t) Ptot *= (size_t)P;
-  // the spreading tile accumulates in float64 for both precisions
-  if (Ptot * 16 > kMaxTileLds)
-    return fail(p, NFFT_EUNSUPPORTED, "padded tile of %zu cells does not fit in LDS (d = %d, m = %d)",
-                Ptot, d, m);
   if (M > Ms) return fail(p, NFFT_EINVAL, "M_sigma < M");
   return NFFT_OK;
 }
@@ -183,6 +175,51 @@ int64_t ipow(int64_t a, int e) {
   int64_t r = 1;
   for (int i = 0; i < e; ++i) r *= a;
   return r;
+}
+
+// Resolve a tuning array (0 or missing = default) and check it against the
+// problem: tile edge a power of two in [8, 256] (tile-local cells are packed
+// into 8 bits per dimension), at least m, clipped to M_sigma; the spreading
+// work-groups of the chosen shape must fit in LDS.
+int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, int* out,
+                   nfft_plan_t p) {
+  for (int k = 0; k < NFFT_TUNE_COUNT; ++k) {
+    const int v = (in && k < n) ? in[k] : 0;
+    if (v < 0) return fail(p, NFFT_EINVAL, "tuning[%d] = %d is negative", k, v);
+    out[k] = v ? v : default_tuning(k, d);
+  }
+  int& T = out[NFFT_TUNE_TILE_EDGE];
+  if (!is_pow2(T) || T < 8 || T > 256)
+    return fail(p, NFFT_EINVAL, "tile edge %d: expected a power of two in [8, 256]", T);
+  T = std::min(T, Ms);
+  if (T < m) return fail(p, NFFT_EUNSUPPORTED, "tile edge %d < m = %d", T, m);
+  const int K = out[NFFT_TUNE_ITEM_NODES];
+  if (K < 16 || K > 65536) return fail(p, NFFT_EINVAL, "item nodes %d: expected 16..65536", K);
+  const int nt = out[NFFT_TUNE_SPREAD_THREADS];
+  if (nt != 64 && nt != 128 && nt != 256)
+    return fail(p, NFFT_EINVAL, "spread threads %d: expected 64, 128 or 256", nt);
+  const int nr = out[NFFT_TUNE_RHS_PER_GROUP];
+  if (nr != 1 && nr != 2 && nr != 4 && nr != 8)
+    return fail(p, NFFT_EINVAL, "rhs per group %d: expected 1, 2, 4 or 8", nr);
+  if (d == 3 && nr != 1) out[NFFT_TUNE_RHS_PER_GROUP] = 1;  // d = 3 has no multi-rhs kernel
+  const int planes = out[NFFT_TUNE_SPREAD_PLANES];
+  if (planes != 1 && planes != 2)
+    return fail(p, NFFT_EINVAL, "spread planes %d: expected 1 or 2", planes);
+  const int fw = out[NFFT_TUNE_FFT_MIN_WG];
+  if (fw < 1 || fw > 65536) return fail(p, NFFT_EINVAL, "fft min work-groups %d: expected 1..65536", fw);
+  const int P = T + 2 * m;
+  const int Ptot = (int)ipow(P, d);
+  const bool f64 = precision == NFFT_F64;
+  const size_t one = nfft::spread_lds_bytes(d, f64, m, T, Ptot, nt, 1, planes);
+  const size_t multi = out[NFFT_TUNE_RHS_PER_GROUP] > 1
+                           ? nfft::spread_lds_bytes(d, f64, m, T, Ptot, nt,
+                                                    out[NFFT_TUNE_RHS_PER_GROUP], planes)
+                           : 0;
+  if (one == 0 || one > kMaxLds || multi > kMaxLds)
+    return fail(p, NFFT_EUNSUPPORTED,
+                "padded tile of %d cells (d = %d, m = %d, tile edge %d) does not fit in LDS with "
+                "this work-group shape", Ptot, d, m, T);
+  return NFFT_OK;
 }
 
 // Modified Bessel function I_0 by its power series (all terms positive).
@@ -397,7 +434,7 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
   // tile starts and work items (at most kItem nodes of one tile each)
   std::vector<int32_t> hstart(g.nbins + 1);
   std::vector<int32_t> istart, icount, ibin, ifirst(g.nbins + 1);
-  const int kItem = item_nodes();
+  const int kItem = p->tune[NFFT_TUNE_ITEM_NODES];
   int64_t acc = 0;
   p->maxpop = 0;
   for (int b = 0; b < g.nbins; ++b) {
@@ -471,10 +508,9 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
 // buffers and by 256 threads (L/8 butterflies per line), and lowered while
 // that leaves fewer than 256 work-groups.
 template <typename R>
-int lines_per_wg(int L, int64_t nlines) {
+int lines_per_wg(int L, int64_t nlines, int min_wg) {
   const int lds_cap = std::max(1, 65536 / (2 * (L + L / 8 + 1) * (int)sizeof(cplx<R>)));
   int lpw = std::max(1, std::min(lds_cap, 2048 / L));  // L/8 threads per line
-  static const int min_wg = env_int("NFFT_FFT_MIN_WG", 256);
   while (lpw > 1 && nlines / lpw < min_wg) lpw /= 2;
   return lpw;
 }
@@ -494,7 +530,7 @@ nfft::FftArgs<R> fft_args(nfft_plan_t p, int64_t nlines, const void* in, int64_t
   a.g = p->g;
   a.tilep = (const cplx<R>*)p->tilep;
   a.tile_bs = (int64_t)p->g.nbins * p->g.Ptot;
-  a.lpw = lines_per_wg<R>(p->Ms, nlines);
+  a.lpw = lines_per_wg<R>(p->Ms, nlines, p->tune[NFFT_TUNE_FFT_MIN_WG]);
   return a;
 }
 
@@ -536,6 +572,9 @@ int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t 
   sa.item_rs = (int64_t)std::max(1, p->nslots) * g.Ptot;
   sa.edge = (R)(p->b * std::exp(-p->b * p->m));
   sa.g = g;
+  sa.nt = p->tune[NFFT_TUNE_SPREAD_THREADS];
+  sa.nr = nrhs > 1 ? p->tune[NFFT_TUNE_RHS_PER_GROUP] : 1;
+  sa.planes = p->tune[NFFT_TUNE_SPREAD_PLANES];
   HIP_TRY(p, nfft::launch_spread<R>(sa, nrhs, s));
   record(p, se, s);
   nfft::ReduceArgs<R> ra{};
@@ -627,6 +666,35 @@ int run_forward(nfft_plan_t p, const void* fhat, void* f, int nrhs, hipStream_t 
   return NFFT_OK;
 }
 
+// Milliseconds per adjoint of nrhs right-hand sides: two warm-up calls, then
+// the better of two rounds of `reps` calls between HIP events.
+double time_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t s) {
+  constexpr int reps = 5;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.0;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return -1.0;
+  }
+  auto call = [&]() {
+    return p->prec == NFFT_F64 ? run_adjoint<double>(p, f, fhat, nrhs, s)
+                               : run_adjoint<float>(p, f, fhat, nrhs, s);
+  };
+  double best = -1.0;
+  bool ok = call() == NFFT_OK && call() == NFFT_OK;
+  for (int round = 0; ok && round < 2; ++round) {
+    ok = hipEventRecord(e0, s) == hipSuccess;
+    for (int i = 0; ok && i < reps; ++i) ok = call() == NFFT_OK;
+    ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.f;
+    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    if (ok && (best < 0 || ms / reps < best)) best = ms / reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ok ? best : -1.0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -650,13 +718,16 @@ const char* nfft_last_error(nfft_plan_t plan) {
 int64_t nfft_footprint(int d, int M, double sigma, int m, int64_t N, int precision, int max_rhs) {
   if (validate(d, M, sigma, m, N, precision, max_rhs, nullptr) != NFFT_OK) return -1;
   const int64_t Ms = oversampled(M, sigma);
-  const int T = tile_edge(d, (int)Ms);
+  int tune[NFFT_TUNE_COUNT];
+  if (resolve_tuning(d, (int)Ms, m, precision, nullptr, 0, tune, nullptr) != NFFT_OK) return -1;
+  const int T = tune[NFFT_TUNE_TILE_EDGE];
+  const int K = tune[NFFT_TUNE_ITEM_NODES];
   const int64_t nb = Ms / T;
   const int64_t nbins = ipow(nb, d);
   const int64_t P = T + 2 * m;
   const int64_t Ptot = ipow(P, d);
   const int64_t cb = (int64_t)cbytes(precision), rb = (int64_t)rbytes(precision);
-  const int64_t nsub_max = nbins + (N + item_nodes() - 1) / item_nodes();
+  const int64_t nsub_max = nbins + (N + K - 1) / K;
   const int64_t R_ = max_rhs;
   int64_t bytes = 0;
   bytes += N * 4 + N * 4 + N * d * rb;                     // perm, loc, frac
@@ -673,9 +744,18 @@ int64_t nfft_footprint(int d, int M, double sigma, int m, int64_t N, int precisi
 
 int nfft_plan(nfft_plan_t* out, int d, int M, double sigma, int m, int64_t N,
               const double* nodes, int precision, int max_rhs, void* stream) {
+  return nfft_plan_tuned(out, d, M, sigma, m, N, nodes, precision, max_rhs, nullptr, 0, stream);
+}
+
+int nfft_plan_tuned(nfft_plan_t* out, int d, int M, double sigma, int m, int64_t N,
+                    const double* nodes, int precision, int max_rhs, const int* tuning,
+                    int ntuning, void* stream) {
   if (!out) return fail(nullptr, NFFT_EINVAL, "out is NULL");
   *out = nullptr;
   int st = validate(d, M, sigma, m, N, precision, max_rhs, nullptr);
+  if (st != NFFT_OK) return st;
+  int tune[NFFT_TUNE_COUNT];
+  st = resolve_tuning(d, oversampled(M, sigma), m, precision, tuning, ntuning, tune, nullptr);
   if (st != NFFT_OK) return st;
   if (!nodes) return fail(nullptr, NFFT_EINVAL, "nodes is NULL");
   nfft_plan_t p = new (std::nothrow) nfft_plan_s();
@@ -690,12 +770,13 @@ int nfft_plan(nfft_plan_t* out, int d, int M, double sigma, int m, int64_t N,
   p->max_rhs = max_rhs;
   p->Ms = oversampled(M, sigma);
   p->b = M_PI * (2.0 - 1.0 / sigma);
+  std::copy(tune, tune + NFFT_TUNE_COUNT, p->tune);
   Geom& g = p->g;
   g.d = d;
   g.Ms = p->Ms;
   g.M = M;
   g.m = m;
-  g.T = tile_edge(d, p->Ms);
+  g.T = p->tune[NFFT_TUNE_TILE_EDGE];
   g.nb = p->Ms / g.T;
   g.P = g.T + 2 * m;
   g.Ptot = (int)ipow(g.P, d);
@@ -752,6 +833,146 @@ int nfft_plan_clone(nfft_plan_t src, int max_rhs, nfft_plan_t* out, void* stream
     return st;
   }
   *out = p;
+  return NFFT_OK;
+}
+
+int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int64_t N,
+                       const double* nodes, int precision, int max_rhs, int nrhs,
+                       double* best_ms, void* stream) {
+  if (!out) return fail(nullptr, NFFT_EINVAL, "out is NULL");
+  *out = nullptr;
+  int st = validate(d, M, sigma, m, N, precision, max_rhs, nullptr);
+  if (st != NFFT_OK) return st;
+  if (!nodes) return fail(nullptr, NFFT_EINVAL, "nodes is NULL");
+  if (nrhs < 1 || nrhs > max_rhs)
+    return fail(nullptr, NFFT_EINVAL, "nrhs = %d outside 1..max_rhs = %d", nrhs, max_rhs);
+  hipStream_t s = (hipStream_t)stream;
+  const int Ms = oversampled(M, sigma);
+  const bool f32 = precision == NFFT_F32;
+  // zero right-hand sides and an output buffer for the timing runs
+  const size_t cb = cbytes(precision);
+  void* f = nullptr;
+  void* fhat = nullptr;
+  if (hipMalloc(&f, (size_t)nrhs * N * cb) != hipSuccess ||
+      hipMalloc(&fhat, (size_t)nrhs * ipow(M, d) * cb) != hipSuccess) {
+    (void)hipFree(f);
+    return fail(nullptr, NFFT_ENOMEM, "no device memory for the timing buffers");
+  }
+  ScopedFree bufs;
+  bufs.ptrs = {f, fhat};
+  if (hipMemsetAsync(f, 0, (size_t)nrhs * N * cb, s) != hipSuccess)
+    return fail(nullptr, NFFT_EDEVICE, "hipMemsetAsync failed");
+
+  std::vector<int> tiles, items = {128, 256, 512};
+  if (d == 1) tiles = {64, 128, 256};
+  else if (d == 2) tiles = {8, 16, 32};
+  else tiles = {8, 16};
+  std::vector<int> threads = {0}, planes = {0}, rpg = {0};
+  if (d <= 2 && f32) {
+    threads = {64, 128, 256};
+    planes = {1, 2};
+  }
+  if (d <= 2 && nrhs > 1) rpg = {1, 2, 4, 8};
+
+  nfft_plan_t best = nullptr;
+  double best_t = -1.0;
+  int best_tune[NFFT_TUNE_COUNT] = {0};
+  for (int T : tiles) {
+    if (T > Ms) continue;
+    for (int K : items) {
+      int tune[NFFT_TUNE_COUNT] = {T, K, 0, 0, 0, 0};
+      int resolved[NFFT_TUNE_COUNT];
+      if (resolve_tuning(d, Ms, m, precision, tune, NFFT_TUNE_COUNT, resolved, nullptr) != NFFT_OK)
+        continue;
+      nfft_plan_t p = nullptr;
+      st = nfft_plan_tuned(&p, d, M, sigma, m, N, nodes, precision, max_rhs, tune,
+                           NFFT_TUNE_COUNT, stream);
+      if (st == NFFT_ENOMEM || st == NFFT_EUNSUPPORTED) continue;
+      if (st != NFFT_OK) {
+        if (best) free_plan(best);
+        return st;
+      }
+      if (hipMemsetAsync(p->w, 0, (size_t)N * cb, s) != hipSuccess) {
+        free_plan(p);
+        if (best) free_plan(best);
+        return fail(nullptr, NFFT_EDEVICE, "hipMemsetAsync failed");
+      }
+      bool mine = false;  // p is (or became) the best plan
+      for (int nt : threads)
+        for (int pl : planes)
+          for (int nr : rpg) {
+            int in[NFFT_TUNE_COUNT];
+            std::copy(p->tune, p->tune + NFFT_TUNE_COUNT, in);
+            if (nt) in[NFFT_TUNE_SPREAD_THREADS] = nt;
+            if (pl) in[NFFT_TUNE_SPREAD_PLANES] = pl;
+            if (nr) in[NFFT_TUNE_RHS_PER_GROUP] = nr;
+            // the single-rhs kernel's shape does not matter when groups take several rhs
+            if (nr > 1 && (nt != threads[0] || pl != planes[0])) continue;
+            int res[NFFT_TUNE_COUNT];
+            if (resolve_tuning(d, Ms, m, precision, in, NFFT_TUNE_COUNT, res, nullptr) != NFFT_OK)
+              continue;
+            std::copy(res, res + NFFT_TUNE_COUNT, p->tune);
+            const double t = time_adjoint(p, f, fhat, nrhs, s);
+            if (t < 0) continue;
+            if (best_t < 0 || t < best_t) {
+              best_t = t;
+              std::copy(res, res + NFFT_TUNE_COUNT, best_tune);
+              if (best && best != p) free_plan(best);
+              best = p;
+              mine = true;
+            }
+          }
+      if (mine) {
+        std::copy(best_tune, best_tune + NFFT_TUNE_COUNT, p->tune);
+      } else {
+        free_plan(p);
+      }
+    }
+  }
+  if (!best) return fail(nullptr, NFFT_EUNSUPPORTED, "no candidate tuning could be planned and timed");
+  // FFT work-group width on the winner
+  for (int fw : {64, 1024}) {
+    int in[NFFT_TUNE_COUNT], res[NFFT_TUNE_COUNT];
+    std::copy(best_tune, best_tune + NFFT_TUNE_COUNT, in);
+    in[NFFT_TUNE_FFT_MIN_WG] = fw;
+    if (resolve_tuning(d, Ms, m, precision, in, NFFT_TUNE_COUNT, res, nullptr) != NFFT_OK) continue;
+    std::copy(res, res + NFFT_TUNE_COUNT, best->tune);
+    const double t = time_adjoint(best, f, fhat, nrhs, s);
+    if (t >= 0 && t < best_t) {
+      best_t = t;
+      std::copy(res, res + NFFT_TUNE_COUNT, best_tune);
+    }
+  }
+  std::copy(best_tune, best_tune + NFFT_TUNE_COUNT, best->tune);
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    free_plan(best);
+    return fail(nullptr, NFFT_EDEVICE, "device failure while timing candidates");
+  }
+  best->shared->has_weights = false;
+  if (best_ms) *best_ms = best_t;
+  *out = best;
+  return NFFT_OK;
+}
+
+int nfft_get_tuning(nfft_plan_t p, int* out, int n) {
+  if (!p) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
+  if (!out || n < 0 || n > NFFT_TUNE_COUNT)
+    return fail(p, NFFT_EINVAL, "out is NULL or n = %d outside 0..%d", n, NFFT_TUNE_COUNT);
+  for (int k = 0; k < n; ++k) out[k] = p->tune[k];
+  return NFFT_OK;
+}
+
+int nfft_set_tuning(nfft_plan_t p, int knob, int value) {
+  if (!p) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
+  if (knob != NFFT_TUNE_SPREAD_THREADS && knob != NFFT_TUNE_RHS_PER_GROUP &&
+      knob != NFFT_TUNE_FFT_MIN_WG && knob != NFFT_TUNE_SPREAD_PLANES)
+    return fail(p, NFFT_EINVAL, "tuning knob %d cannot change after planning", knob);
+  int in[NFFT_TUNE_COUNT], out[NFFT_TUNE_COUNT];
+  std::copy(p->tune, p->tune + NFFT_TUNE_COUNT, in);
+  in[knob] = value;
+  const int st = resolve_tuning(p->d, p->Ms, p->m, p->prec, in, NFFT_TUNE_COUNT, out, p);
+  if (st != NFFT_OK) return st;
+  std::copy(out, out + NFFT_TUNE_COUNT, p->tune);
   return NFFT_OK;
 }
 

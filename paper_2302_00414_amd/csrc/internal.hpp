@@ -51,9 +51,18 @@ struct SpreadArgs {
   int64_t f_rs, tile_rs, item_rs;
   R edge;                    // window value at the closed edge |t| = m
   Geom g;
+  int nt;                    // threads per work-group, d <= 2 float32 single-rhs kernel
+  int nr;                    // right-hand sides per work-group (1, 2, 4 or 8; d <= 2)
+  int planes;                // 2: float32 real and imaginary planes in separate groups
 };
 template <typename R>
 hipError_t launch_spread(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
+// Several right-hand sides per work-group (d <= 2, nr > 1).
+template <typename R>
+hipError_t launch_spread_multi(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
+// LDS bytes one spreading work-group needs for these launch parameters, or 0
+// if the combination is not built.
+size_t spread_lds_bytes(int d, bool f64, int m, int T, int Ptot, int nt, int nr, int planes);
 
 // Sum the item partials of every split tile into its tile slot, in item order
 // (deterministic; compensated summation).

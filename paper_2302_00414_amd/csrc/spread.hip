@@ -17,29 +17,9 @@
 // a wave takes the (2m+1)-wide loop only when one of its lanes needs it.
 #include <type_traits>
 
-#include "internal.hpp"
-#include "window.hpp"
+#include "spread_common.hpp"
 
 namespace nfft {
-
-__device__ __forceinline__ void lds_add(double* p, double v) {
-  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// Compensated (Neumaier) accumulation of one component.
-template <typename R>
-struct KSum {
-  R s = 0, c = 0;
-  __device__ __forceinline__ void add(R v) {
-    const R t = s + v;
-    if (fabs(s) >= fabs(v))
-      c += (s - t) + v;
-    else
-      c += (v - t) + s;
-    s = t;
-  }
-  __device__ __forceinline__ R value() const { return s + c; }
-};
 
 // ----------------------------------------------------------------------------
 // Spreading for d <= 2 by lane groups. A group is one 16-lane DPP row; it
@@ -57,103 +37,18 @@ struct KSum {
 // A batch of nodes is first staged in LDS by the whole work-group (one node
 // per thread: offsets, c_j = w_j f_j and the packed cells).
 
-template <int I, int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (I < N) {
-    f(std::integral_constant<int, I>{});
-    static_for<I + 1, N>(f);
-  }
-}
-
-// Value of lane I of this lane's 16-lane row.
-template <int I>
-__device__ __forceinline__ float row_bcast(float v) {
-  const int b = __float_as_int(v);
-  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x150 + I, 0xf, 0xf, false));
-}
-template <int I>
-__device__ __forceinline__ double row_bcast(double v) {
-  const long long b = __double_as_longlong(v);
-  const int l = (int)(b & 0xffffffffLL), u = (int)(b >> 32);
-  const int lo = __builtin_amdgcn_update_dpp(l, l, 0x150 + I, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(u, u, 0x150 + I, 0xf, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-template <typename R>
-__device__ __forceinline__ R horner(const R* c, R y) {
-  constexpr int DEG = PolyDeg<R>::value;
-  R v = c[DEG];
-#pragma unroll
-  for (int p = DEG - 1; p >= 0; --p) v = v * y + c[p];
-  return v;
-}
-
-template <typename R> struct GroupAcc;
-// float32: private padded tile per group, plain read-modify-write
-template <> struct GroupAcc<float> {
-  float2* tile;  // this group's tile
-  __device__ __forceinline__ void add(int cell, float x, float y) {
-    float2 v = tile[cell];
-    v.x += x;
-    v.y += y;
-    tile[cell] = v;
-  }
-};
-// float64: shared padded tile (real and imaginary planes), LDS atomics
-template <> struct GroupAcc<double> {
-  double* re;
-  double* im;
-  __device__ __forceinline__ void add(int cell, double x, double y) {
-    lds_add(re + cell, x);
-    lds_add(im + cell, y);
-  }
-};
-
-// Per-node values a group needs for one node: the column factor times c_j
-// (vx, vy, lane k), the 2m row factors (rw, broadcast to every lane), the
-// node's tile-local cell and its on-grid-line flags.
-template <typename R, int K2>
-struct NodePrep {
-  R vx, vy, p0, cx, cy;
-  R rw[K2];
-  int l0, l1;
-  bool e0, e1;
-};
-
-template <typename R, int D, int K2>
-__device__ __forceinline__ void prep_node(NodePrep<R, K2>& h, R y0, R y1, R cx, R cy, uint32_t L,
-                                          const R* cf) {
-  h.cx = cx;
-  h.cy = cy;
-  h.l0 = (int)(L & kLocMask);
-  h.e0 = (L >> kEdgeShift) & 1u;
-  h.p0 = horner<R>(cf, y0);
-  if constexpr (D == 1) {
-    h.vx = cx * h.p0;
-    h.vy = cy * h.p0;
-    h.l1 = 0;
-    h.e1 = false;
-  } else {
-    h.l1 = (int)((L >> kLocBits) & kLocMask);
-    h.e1 = (L >> (kEdgeShift + 1)) & 1u;
-    const R p1 = horner<R>(cf, y1);
-    h.vx = cx * p1;
-    h.vy = cy * p1;
-    static_for<0, K2>([&](auto ic) {
-      constexpr int I = decltype(ic)::value;
-      h.rw[I] = row_bcast<I>(h.p0);
-    });
-  }
-}
-
-template <typename R, int D, int MW, int NT, int TT>
+template <typename R, int D, int MW, int NT, int TT, bool CS>
 __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
   static_assert(D <= 2 && 2 * MW <= 16, "group spreading covers d <= 2, m <= 8");
+  static_assert(!CS || std::is_same<R, float>::value, "component split is a float32 layout");
   constexpr int DEG = PolyDeg<R>::value;
   constexpr int NG = NT / 16;            // groups per work-group
   constexpr int K2 = 2 * MW;             // footprint columns
   constexpr bool PRIV = std::is_same<R, float>::value;
+  // CS: groups 2q and 2q+1 take the same nodes, for the real and the
+  // imaginary part, each into a float32 plane of its own (half the LDS of a
+  // complex tile per group, so twice the groups fit).
+  constexpr int NODE_GROUPS = CS ? NG / 2 : NG;
   extern __shared__ double lds_d[];
   const int item = blockIdx.x;
   const int rhs = blockIdx.y;
@@ -163,24 +58,40 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
   const int tid = threadIdx.x;
   const int grp = tid >> 4;
   const int k = tid & 15;
+  const int comp = CS ? (grp & 1) : 0;
+  const int ngrp = CS ? (grp >> 1) : grp;  // node group
 
   // LDS layout: accumulation tile(s), then the node staging area
   unsigned char* base = reinterpret_cast<unsigned char*>(lds_d);
-  const size_t acc_bytes = PRIV ? (size_t)NG * Ptot * sizeof(float2) : (size_t)2 * Ptot * sizeof(double);
+  const size_t acc_bytes = CS     ? (size_t)NG * Ptot * sizeof(float)
+                           : PRIV ? (size_t)NG * Ptot * sizeof(float2)
+                                  : (size_t)2 * Ptot * sizeof(double);
   R* st_y0 = reinterpret_cast<R*>(base + acc_bytes);
   R* st_y1 = st_y0 + NT;
   R* st_cx = st_y1 + NT;
   R* st_cy = st_cx + NT;
   uint32_t* st_loc = reinterpret_cast<uint32_t*>(st_cy + NT);
+  // CS: this group's component of c_j stands in for cx (cy unused)
+  const R* st_c0 = (CS && comp) ? st_cy : st_cx;
 
   for (int i = tid; i < (int)(acc_bytes / sizeof(double)); i += NT) lds_d[i] = 0.0;
   GroupAcc<R> acc;
-  if constexpr (PRIV) {
+  float* ptile = nullptr;  // CS: this group's float32 plane
+  if constexpr (CS) {
+    ptile = reinterpret_cast<float*>(lds_d) + (size_t)grp * Ptot;
+  } else if constexpr (PRIV) {
     acc.tile = reinterpret_cast<float2*>(lds_d) + (size_t)grp * Ptot;
   } else {
     acc.re = lds_d;
     acc.im = lds_d + Ptot;
   }
+  auto add1 = [&](int cell, R x, R y) {
+    if constexpr (CS) {
+      ptile[cell] += x;
+    } else {
+      acc.add(cell, x, y);
+    }
+  };
 
   // this lane's window polynomial (column k; lanes past 2m keep polynomial 0)
   R cf[DEG + 1];
@@ -211,6 +122,9 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
       pfs = f[a.perm[i]];
     }
   };
+  auto prep = [&](NodePrep<R, K2>& h, int n) {
+    prep_node<R, D, K2>(h, st_y0[n], st_y1[n], st_c0[n], CS ? (R)0 : st_cy[n], st_loc[n], cf);
+  };
   issue(0);
   for (int b0 = 0; b0 < cnt; b0 += NT) {
     const int nb = (cnt - b0) < NT ? (cnt - b0) : NT;
@@ -224,46 +138,62 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
     }
     if (b0 + NT < cnt) issue(b0 + NT);
     __syncthreads();
-    // Software pipeline over this group's nodes n = grp, grp + NG, ...: the
-    // window factors of the next node are computed while the cell reads of
-    // the current node are in flight. LDS operations of a wave execute in
-    // order, so the next node's reads always see this node's writes.
-    int n = grp;
+    // Software pipeline over this group's nodes n = ngrp, ngrp + NODE_GROUPS,
+    // ...: the window factors of the next node are computed while the cell
+    // reads of the current node are in flight. LDS operations of a wave
+    // execute in order, so the next node's reads always see this node's
+    // writes.
+    int n = ngrp;
     NodePrep<R, K2> h;
-    if (n < nb) prep_node<R, D, K2>(h, st_y0[n], st_y1[n], st_cx[n], st_cy[n], st_loc[n], cf);
-    for (; n < nb; n += NG) {
-      const int nn = n + NG;
+    if (n < nb) prep(h, n);
+    for (; n < nb; n += NODE_GROUPS) {
+      const int nn = n + NODE_GROUPS;
       if constexpr (D == 1) {
-        if (k < K2) acc.add(h.l0 + 1 + k, h.vx, h.vy);
-        if (h.e0 && k == 0) acc.add(h.l0, h.cx * edge, h.cy * edge);
-        if (nn < nb) prep_node<R, D, K2>(h, st_y0[nn], st_y1[nn], st_cx[nn], st_cy[nn], st_loc[nn], cf);
+        if (k < K2) add1(h.l0 + 1 + k, h.vx, h.vy);
+        if (h.e0 && k == 0) add1(h.l0, h.cx * edge, h.cy * edge);
+        if (nn < nb) prep(h, nn);
       } else {
         const int col = h.l1 + 1 + k;
         if constexpr (PRIV) {
-          float2* t = acc.tile + (h.l0 + 1) * P + col;
-          float2 cur[K2];
-          if (k < K2) {
-#pragma unroll
-            for (int i = 0; i < K2; ++i) cur[i] = t[i * P];
-          }
           NodePrep<R, K2> hn;
-          if (nn < nb)
-            prep_node<R, D, K2>(hn, st_y0[nn], st_y1[nn], st_cx[nn], st_cy[nn], st_loc[nn], cf);
-          if (k < K2) {
+          if constexpr (CS) {
+            float* t = ptile + (h.l0 + 1) * P + col;
+            float cur[K2];
+            if (k < K2) {
 #pragma unroll
-            for (int i = 0; i < K2; ++i) {
-              cur[i].x += h.vx * h.rw[i];
-              cur[i].y += h.vy * h.rw[i];
+              for (int i = 0; i < K2; ++i) cur[i] = t[i * P];
             }
+            if (nn < nb) prep(hn, nn);
+            if (k < K2) {
 #pragma unroll
-            for (int i = 0; i < K2; ++i) t[i * P] = cur[i];
+              for (int i = 0; i < K2; ++i) cur[i] += h.vx * h.rw[i];
+#pragma unroll
+              for (int i = 0; i < K2; ++i) t[i * P] = cur[i];
+            }
+          } else {
+            float2* t = acc.tile + (h.l0 + 1) * P + col;
+            float2 cur[K2];
+            if (k < K2) {
+#pragma unroll
+              for (int i = 0; i < K2; ++i) cur[i] = t[i * P];
+            }
+            if (nn < nb) prep(hn, nn);
+            if (k < K2) {
+#pragma unroll
+              for (int i = 0; i < K2; ++i) {
+                cur[i].x += h.vx * h.rw[i];
+                cur[i].y += h.vy * h.rw[i];
+              }
+#pragma unroll
+              for (int i = 0; i < K2; ++i) t[i * P] = cur[i];
+            }
           }
           if (h.e0 | h.e1) {
             // closed-edge cells of a node on a grid line: row 0 and column 0
-            if (h.e0 && k < K2) acc.add(h.l0 * P + col, h.vx * edge, h.vy * edge);
+            if (h.e0 && k < K2) add1(h.l0 * P + col, h.vx * edge, h.vy * edge);
             if (h.e1 && k < K2)
-              acc.add((h.l0 + 1 + k) * P + h.l1, h.cx * h.p0 * edge, h.cy * h.p0 * edge);
-            if (h.e0 && h.e1 && k == 0) acc.add(h.l0 * P + h.l1, h.cx * edge * edge, h.cy * edge * edge);
+              add1((h.l0 + 1 + k) * P + h.l1, h.cx * h.p0 * edge, h.cy * h.p0 * edge);
+            if (h.e0 && h.e1 && k == 0) add1(h.l0 * P + h.l1, h.cx * edge * edge, h.cy * edge * edge);
           }
           h = hn;
         } else {
@@ -277,7 +207,7 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
               acc.add((h.l0 + 1 + k) * P + h.l1, h.cx * h.p0 * edge, h.cy * h.p0 * edge);
             if (h.e0 && h.e1 && k == 0) acc.add(h.l0 * P + h.l1, h.cx * edge * edge, h.cy * edge * edge);
           }
-          if (nn < nb) prep_node<R, D, K2>(h, st_y0[nn], st_y1[nn], st_cx[nn], st_cy[nn], st_loc[nn], cf);
+          if (nn < nb) prep(h, nn);
         }
       }
     }
@@ -287,7 +217,26 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
   const int slot = a.item_slot[item];
   cplx<R>* out = slot < 0 ? a.tilep + rhs * a.tile_rs + (int64_t)a.item_bin[item] * Ptot
                           : a.itemp + rhs * a.item_rs + (int64_t)slot * Ptot;
-  if constexpr (PRIV) {
+  if constexpr (CS) {
+    // planes of one component summed in a fixed pairwise order (float64)
+    const float* t = reinterpret_cast<const float*>(lds_d);
+    for (int i = tid; i < Ptot; i += NT) {
+      double sx[NODE_GROUPS], sy[NODE_GROUPS];
+#pragma unroll
+      for (int g = 0; g < NODE_GROUPS; ++g) {
+        sx[g] = t[(size_t)(2 * g) * Ptot + i];
+        sy[g] = t[(size_t)(2 * g + 1) * Ptot + i];
+      }
+#pragma unroll
+      for (int w = 1; w < NODE_GROUPS; w *= 2)
+#pragma unroll
+        for (int g = 0; g + w < NODE_GROUPS; g += 2 * w) {
+          sx[g] += sx[g + w];
+          sy[g] += sy[g + w];
+        }
+      out[i] = mkc<R>((R)sx[0], (R)sy[0]);
+    }
+  } else if constexpr (PRIV) {
     // group tiles summed in a fixed pairwise order (in float64, rounded once)
     const float2* t = reinterpret_cast<const float2*>(lds_d);
     for (int i = tid; i < Ptot; i += NT) {
@@ -672,21 +621,46 @@ __global__ __launch_bounds__(256) void interp_kernel(InterpArgs<R> a) {
   }
 }
 
+// d <= 2 single right-hand side: float32 private group tiles, nt threads
+template <typename R, int D, int MW, int NT, bool CS>
+static hipError_t spread_group_nt(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
+  constexpr int NG = NT / 16;
+  const size_t acc = CS ? (size_t)NG * a.g.Ptot * 4
+                        : std::is_same<R, float>::value ? (size_t)NG * a.g.Ptot * 8
+                                                        : (size_t)2 * a.g.Ptot * 8;
+  const size_t lds = acc + (size_t)NT * (4 * sizeof(R) + 4);
+  const dim3 grid(a.g.nsub, nrhs);
+  if constexpr (D == 2) {
+    if (a.g.T == 16) {
+      hipLaunchKernelGGL((spread_group_kernel<R, D, MW, NT, 16, CS>), grid, dim3(NT), lds, s, a);
+      return hipGetLastError();
+    }
+    if (a.g.T == 8) {
+      hipLaunchKernelGGL((spread_group_kernel<R, D, MW, NT, 8, CS>), grid, dim3(NT), lds, s, a);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((spread_group_kernel<R, D, MW, NT, 0, CS>), grid, dim3(NT), lds, s, a);
+  return hipGetLastError();
+}
+
 template <typename R, int D, int MW>
 static hipError_t spread_dm(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
   if constexpr (D <= 2) {
-    // float32: 2 waves (8 private group tiles); float64: 4 waves, shared tile
-    constexpr int NT = std::is_same<R, float>::value ? 128 : 256;
-    constexpr int NG = NT / 16;
-    const size_t acc = std::is_same<R, float>::value ? (size_t)NG * a.g.Ptot * 8
-                                                     : (size_t)2 * a.g.Ptot * 8;
-    const size_t lds = acc + (size_t)NT * (4 * sizeof(R) + 4);
-    if (D == 2 && a.g.T == 16)
-      hipLaunchKernelGGL((spread_group_kernel<R, D, MW, NT, 16>), dim3(a.g.nsub, nrhs), dim3(NT),
-                         lds, s, a);
-    else
-      hipLaunchKernelGGL((spread_group_kernel<R, D, MW, NT, 0>), dim3(a.g.nsub, nrhs), dim3(NT),
-                         lds, s, a);
+    // float32: private group tiles, 64 / 128 / 256 threads; float64: 256
+    // threads sharing one tile
+    if constexpr (std::is_same<R, float>::value) {
+      if (a.planes == 2) {
+        if (a.nt == 64) return spread_group_nt<R, D, MW, 64, true>(a, nrhs, s);
+        if (a.nt == 256) return spread_group_nt<R, D, MW, 256, true>(a, nrhs, s);
+        return spread_group_nt<R, D, MW, 128, true>(a, nrhs, s);
+      }
+      if (a.nt == 64) return spread_group_nt<R, D, MW, 64, false>(a, nrhs, s);
+      if (a.nt == 256) return spread_group_nt<R, D, MW, 256, false>(a, nrhs, s);
+      return spread_group_nt<R, D, MW, 128, false>(a, nrhs, s);
+    } else {
+      return spread_group_nt<R, D, MW, 256, false>(a, nrhs, s);
+    }
   } else {
     // d = 3: float32 two waves, one component plane each; float64 four
     // waves sharing one tile
@@ -720,9 +694,28 @@ static hipError_t interp_dm(const InterpArgs<R>& a, int nrhs, hipStream_t s) {
     default: return hipErrorInvalidValue;          \
   }
 
+size_t spread_multi_lds_bytes(bool f64, int Ptot, int nr);
+
+size_t spread_lds_bytes(int d, bool f64, int m, int T, int Ptot, int nt, int nr, int planes) {
+  (void)T;
+  const size_t rb = f64 ? 8 : 4;
+  if (d <= 2) {
+    if (nr > 1) return spread_multi_lds_bytes(f64, Ptot, nr);
+    if (nr != 1) return 0;
+    if (f64) return (size_t)2 * Ptot * 8 + (size_t)256 * (4 * rb + 4);
+    if (nt != 64 && nt != 128 && nt != 256) return 0;
+    // float32 private tiles: complex (8 bytes a cell) or one plane (4 bytes)
+    return (size_t)(nt / 16) * Ptot * (planes == 2 ? 4 : 8) + (size_t)nt * (4 * rb + 4);
+  }
+  if (nr != 1) return 0;
+  // Stage3: 64 nodes of 3 * 2m + 2 reals and one packed cell word
+  return (size_t)2 * Ptot * rb + (size_t)64 * ((3 * 2 * m + 2) * rb + 4);
+}
+
 template <typename R>
 hipError_t launch_spread(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
   if (a.g.nsub == 0) return hipSuccess;
+  if (a.nr > 1 && a.g.d <= 2) return launch_spread_multi<R>(a, nrhs, s);
   switch (a.g.d) {
     case 1: NFFT_DISPATCH_M(spread_dm, R, 1, a, nrhs, s)
     case 2: NFFT_DISPATCH_M(spread_dm, R, 2, a, nrhs, s)

@@ -1,0 +1,122 @@
+// Device helpers shared by the spreading kernels: float64 LDS atomics,
+// compensated sums, DPP row broadcasts, Horner evaluation of the window
+// polynomials and the per-node preparation of the lane-group kernels.
+#pragma once
+
+#include <type_traits>
+
+#include "internal.hpp"
+#include "window.hpp"
+
+namespace nfft {
+
+__device__ __forceinline__ void lds_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Compensated (Neumaier) accumulation of one component.
+template <typename R>
+struct KSum {
+  R s = 0, c = 0;
+  __device__ __forceinline__ void add(R v) {
+    const R t = s + v;
+    if (fabs(s) >= fabs(v))
+      c += (s - t) + v;
+    else
+      c += (v - t) + s;
+    s = t;
+  }
+  __device__ __forceinline__ R value() const { return s + c; }
+};
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// Value of lane I of this lane's 16-lane row.
+template <int I>
+__device__ __forceinline__ float row_bcast(float v) {
+  const int b = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x150 + I, 0xf, 0xf, false));
+}
+template <int I>
+__device__ __forceinline__ double row_bcast(double v) {
+  const long long b = __double_as_longlong(v);
+  const int l = (int)(b & 0xffffffffLL), u = (int)(b >> 32);
+  const int lo = __builtin_amdgcn_update_dpp(l, l, 0x150 + I, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(u, u, 0x150 + I, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <typename R>
+__device__ __forceinline__ R horner(const R* c, R y) {
+  constexpr int DEG = PolyDeg<R>::value;
+  R v = c[DEG];
+#pragma unroll
+  for (int p = DEG - 1; p >= 0; --p) v = v * y + c[p];
+  return v;
+}
+
+template <typename R> struct GroupAcc;
+// float32: private padded tile per group, plain read-modify-write
+template <> struct GroupAcc<float> {
+  float2* tile;  // this group's tile
+  __device__ __forceinline__ void add(int cell, float x, float y) {
+    float2 v = tile[cell];
+    v.x += x;
+    v.y += y;
+    tile[cell] = v;
+  }
+};
+// float64: shared padded tile (real and imaginary planes), LDS atomics
+template <> struct GroupAcc<double> {
+  double* re;
+  double* im;
+  __device__ __forceinline__ void add(int cell, double x, double y) {
+    lds_add(re + cell, x);
+    lds_add(im + cell, y);
+  }
+};
+
+// Per-node values a group needs for one node: the column factor times c_j
+// (vx, vy, lane k), the 2m row factors (rw, broadcast to every lane), the
+// node's tile-local cell and its on-grid-line flags.
+template <typename R, int K2>
+struct NodePrep {
+  R vx, vy, p0, cx, cy;
+  R rw[K2];
+  int l0, l1;
+  bool e0, e1;
+};
+
+template <typename R, int D, int K2>
+__device__ __forceinline__ void prep_node(NodePrep<R, K2>& h, R y0, R y1, R cx, R cy, uint32_t L,
+                                          const R* cf) {
+  h.cx = cx;
+  h.cy = cy;
+  h.l0 = (int)(L & kLocMask);
+  h.e0 = (L >> kEdgeShift) & 1u;
+  h.p0 = horner<R>(cf, y0);
+  if constexpr (D == 1) {
+    h.vx = cx * h.p0;
+    h.vy = cy * h.p0;
+    h.l1 = 0;
+    h.e1 = false;
+  } else {
+    h.l1 = (int)((L >> kLocBits) & kLocMask);
+    h.e1 = (L >> (kEdgeShift + 1)) & 1u;
+    const R p1 = horner<R>(cf, y1);
+    h.vx = cx * p1;
+    h.vy = cy * p1;
+    static_for<0, K2>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      h.rw[I] = row_bcast<I>(h.p0);
+    });
+  }
+}
+
+}  // namespace nfft

@@ -57,6 +57,60 @@ def nfft_plan(d: int, M: int, sigma: float, m: int, nodes: torch.Tensor, precisi
     return h
 
 
+TUNING_KEYS = ("tile_edge", "item_nodes", "spread_threads", "rhs_per_group", "fft_min_wg",
+               "spread_planes")
+
+
+def _tuning_array(tuning) -> Optional[ctypes.Array]:
+    """dict (keys of TUNING_KEYS) or sequence -> int32 array; None = defaults."""
+    if tuning is None:
+        return None
+    if isinstance(tuning, dict):
+        unknown = set(tuning) - set(TUNING_KEYS)
+        if unknown:
+            raise ValueError(f"unknown tuning keys {sorted(unknown)}")
+        vals = [int(tuning.get(k, 0) or 0) for k in TUNING_KEYS]
+    else:
+        vals = [int(v) for v in tuning]
+    return (ctypes.c_int32 * len(vals))(*vals)
+
+
+def nfft_plan_tuned(d: int, M: int, sigma: float, m: int, nodes: torch.Tensor, precision=NFFT_F64,
+                    max_rhs: int = 1, tuning=None, stream=None) -> ctypes.c_void_p:
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    arr = _tuning_array(tuning)
+    st = lib.nfft_plan_tuned(ctypes.byref(h), d, M, float(sigma), m, nodes.shape[0],
+                             ctypes.c_void_p(nodes.data_ptr()), _PREC[precision], max_rhs,
+                             arr, len(arr) if arr is not None else 0, _stream_ptr(stream))
+    check(st, None)
+    return h
+
+
+def nfft_plan_autotune(d: int, M: int, sigma: float, m: int, nodes: torch.Tensor, precision=NFFT_F64,
+                       max_rhs: int = 1, nrhs: int = 1, stream=None):
+    """-> (handle, milliseconds per adjoint of the winner)."""
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    best = ctypes.c_double(0.0)
+    st = lib.nfft_plan_autotune(ctypes.byref(h), d, M, float(sigma), m, nodes.shape[0],
+                                ctypes.c_void_p(nodes.data_ptr()), _PREC[precision], max_rhs, nrhs,
+                                ctypes.byref(best), _stream_ptr(stream))
+    check(st, None)
+    return h, best.value
+
+
+def nfft_get_tuning(plan) -> dict:
+    out = (ctypes.c_int32 * _lib.NFFT_TUNE_COUNT)()
+    check(_lib.load().nfft_get_tuning(plan, out, _lib.NFFT_TUNE_COUNT), plan)
+    return dict(zip(TUNING_KEYS, (int(v) for v in out)))
+
+
+def nfft_set_tuning(plan, knob, value: int) -> None:
+    k = TUNING_KEYS.index(knob) if isinstance(knob, str) else int(knob)
+    check(_lib.load().nfft_set_tuning(plan, k, int(value)), plan)
+
+
 def nfft_plan_clone(plan, max_rhs: int, stream=None) -> ctypes.c_void_p:
     h = ctypes.c_void_p()
     check(_lib.load().nfft_plan_clone(plan, max_rhs, ctypes.byref(h), _stream_ptr(stream)), plan)
@@ -128,7 +182,11 @@ class Plan:
     """One node set on one device (nodes wrapped onto [-1/2, 1/2)^d)."""
 
     def __init__(self, nodes, M: int, sigma: float = 2.0, m: int = 6, precision="f64",
-                 max_rhs: int = 1, device: Optional[torch.device] = None, stream=None):
+                 max_rhs: int = 1, device: Optional[torch.device] = None, stream=None,
+                 tuning=None):
+        """tuning: None (defaults), a dict of TUNING_KEYS, or "auto" (the
+        library times candidate tunings for max_rhs right-hand sides and keeps
+        the fastest; see nfft_plan_autotune)."""
         self.device = torch.device(device or "cuda")
         x = _as_f64_nodes(nodes).to(self.device)
         self.N, self.d = x.shape
@@ -139,7 +197,15 @@ class Plan:
         self.Ms = oversampled_size(M, sigma)
         self._h = None
         with torch.cuda.device(self.device):
-            self._h = nfft_plan(self.d, M, sigma, m, x, self.prec, max_rhs, stream)
+            self.tuned_ms = None
+            if isinstance(tuning, str):
+                if tuning != "auto":
+                    raise ValueError(f"tuning={tuning!r}: expected None, a dict or 'auto'")
+                self._h, self.tuned_ms = nfft_plan_autotune(self.d, M, sigma, m, x, self.prec,
+                                                            max_rhs, max_rhs, stream)
+            else:
+                self._h = nfft_plan_tuned(self.d, M, sigma, m, x, self.prec, max_rhs, tuning,
+                                          stream)
 
     @property
     def handle(self):
@@ -193,8 +259,38 @@ class Plan:
         nfft_forward(self._h, fhat, out, nrhs, stream)
         return out.reshape(self.N) if single else out
 
+    def _graph(self, fn, src: torch.Tensor, out: torch.Tensor):
+        """Capture fn(src, out=out) (every kernel of one transform) into a HIP
+        graph on a side stream; replaying it reruns the transform on whatever
+        src holds then. The transform allocates nothing and clears nothing
+        with memset, so the captured launches are exactly the eager ones."""
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(side):
+            fn(src, out=out)  # warm-up outside the capture
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            fn(src, out=out)
+        return g
+
+    def graph_adjoint(self, f: torch.Tensor, out: torch.Tensor):
+        """HIP graph of self.adjoint(f, out=out); f and out stay bound to it."""
+        return self._graph(self.adjoint, f, out)
+
+    def graph_forward(self, fhat: torch.Tensor, out: torch.Tensor):
+        """HIP graph of self.forward(fhat, out=out)."""
+        return self._graph(self.forward, fhat, out)
+
     def info(self) -> dict:
         return nfft_plan_info(self._h)
+
+    def tuning(self) -> dict:
+        return nfft_get_tuning(self._h)
+
+    def set_tuning(self, knob, value: int) -> None:
+        """Change a launch-time knob (spread_threads, rhs_per_group, fft_min_wg, spread_planes)."""
+        nfft_set_tuning(self._h, knob, value)
 
     def permutation(self) -> np.ndarray:
         return nfft_permutation(self._h, self.N)

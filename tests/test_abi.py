@@ -47,7 +47,7 @@ def test_strerror_texts():
     ((2, 4, 2.0, 4), _lib.NFFT_EINVAL),        # M_sigma = 8 < 2m + 2
     ((2, 32, 2.0, 9), _lib.NFFT_EUNSUPPORTED),  # m > 8
     ((2, 30, 2.0, 4), _lib.NFFT_EUNSUPPORTED),  # M_sigma = 60 not a power of two
-    ((3, 64, 2.0, 8), _lib.NFFT_EUNSUPPORTED),  # padded 3-D tile of m = 8 exceeds LDS
+    ((3, 64, 2.0, 8), _lib.NFFT_OK),           # float32 3-D, m = 8: two float32 planes fit in LDS
     ((3, 64, 2.0, 6), _lib.NFFT_OK),           # valid
 ])
 def test_plan_validation_before_device(args, status):
@@ -73,6 +73,47 @@ def test_f64_3d_large_m_unsupported():
     h = ctypes.c_void_p()
     st = lib.nfft_plan(ctypes.byref(h), 3, 64, 2.0, 8, 4, x.ctypes.data, _lib.NFFT_F64, 1, None)
     assert st == _lib.NFFT_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("d,m,prec,tuning,status", [
+    (2, 6, _lib.NFFT_F32, [12], _lib.NFFT_EINVAL),                # tile edge not a power of two
+    (2, 6, _lib.NFFT_F32, [4], _lib.NFFT_EINVAL),                 # tile edge below 8
+    (2, 6, _lib.NFFT_F32, [512], _lib.NFFT_EINVAL),               # tile edge above 256
+    (2, 6, _lib.NFFT_F32, [0, 8], _lib.NFFT_EINVAL),              # work item below 16 nodes
+    (2, 6, _lib.NFFT_F32, [0, 0, 96], _lib.NFFT_EINVAL),          # spread threads not 64/128/256
+    (2, 6, _lib.NFFT_F32, [0, 0, 0, 3], _lib.NFFT_EINVAL),        # rhs per group not 1/2/4/8
+    (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 70000], _lib.NFFT_EINVAL),  # fft min work-groups
+    (2, 6, _lib.NFFT_F32, [-1], _lib.NFFT_EINVAL),                # negative entry
+    (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 3], _lib.NFFT_EINVAL),  # spread planes not 1/2
+    (2, 8, _lib.NFFT_F32, [32, 0, 256, 0, 0, 2], _lib.NFFT_OK),   # 16 float32 48^2 planes fit
+    (3, 4, _lib.NFFT_F32, [32], _lib.NFFT_EUNSUPPORTED),          # 40^3 padded tile exceeds LDS
+    (2, 8, _lib.NFFT_F32, [64, 0, 256], _lib.NFFT_EUNSUPPORTED),  # 16 private 80^2 tiles exceed LDS
+    (2, 8, _lib.NFFT_F64, [32, 0, 0, 8], _lib.NFFT_EUNSUPPORTED),  # 8 float64 48^2 tiles exceed LDS
+    (2, 6, _lib.NFFT_F32, [32, 512, 64, 4, 128], _lib.NFFT_OK),
+    (2, 6, _lib.NFFT_F32, None, _lib.NFFT_OK),
+])
+def test_tuning_validation_before_device(d, m, prec, tuning, status):
+    lib = _lib.load()
+    x = np.zeros((4, d))
+    h = ctypes.c_void_p(123)
+    arr = (ctypes.c_int32 * len(tuning))(*tuning) if tuning is not None else None
+    st = lib.nfft_plan_tuned(ctypes.byref(h), d, 128, 2.0, m, 4, x.ctypes.data, prec, 4, arr,
+                             len(tuning) if tuning else 0, None)
+    if status == _lib.NFFT_OK:
+        assert st in (_lib.NFFT_OK, _lib.NFFT_EDEVICE)
+        if st == _lib.NFFT_OK:
+            lib.nfft_destroy(h)
+    else:
+        assert st == status, lib.nfft_last_error(None)
+        assert h.value is None
+        assert lib.nfft_last_error(None)
+
+
+def test_tuning_knobs_need_a_plan():
+    lib = _lib.load()
+    out = (ctypes.c_int32 * 6)()
+    assert lib.nfft_get_tuning(None, out, 6) == _lib.NFFT_EINVAL
+    assert lib.nfft_set_tuning(None, _lib.NFFT_TUNE_SPREAD_THREADS, 64) == _lib.NFFT_EINVAL
 
 
 def test_bad_counts_and_pointers():

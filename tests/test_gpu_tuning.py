@@ -1,0 +1,138 @@
+"""Launch tuning and the fused multi-right-hand-side spreading, through the C ABI.
+
+Every tuning changes only how the work is cut (tile edge, work-item size,
+work-group shape, right-hand sides per work-group, FFT work-group width),
+so every tuned plan must reproduce the FP64 oracle (O2) to the parity
+tolerance and the default plan up to rounding order.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import nfft as onfft, metrics, window
+from paper_2302_00414_amd import workloads as wl
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+TOL_O2 = {"f64": 1e-12, "f32": 1e-5}
+# two launches of the same plan arithmetic in a different order
+TOL_ORDER = {"f64": 1e-13, "f32": 2e-6}
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _plan(x, M, m, prec, max_rhs=1, tuning=None):
+    from paper_2302_00414_amd.nfft import Plan
+    print(f"[case] N={x.shape[0]} d={x.shape[1]} M={M} m={m} {prec} rhs={max_rhs} tuning={tuning}",
+          flush=True)
+    return Plan(x, M, 2.0, m, precision=prec, max_rhs=max_rhs, device="cuda:0", tuning=tuning)
+
+
+def _nodes(d, M, seed):
+    """Uniform nodes plus grid-aligned nodes (closed edge) and a crowded
+    cluster whose tile splits into several work items."""
+    Ms = window.oversampled_size(M, 2.0)
+    rng = np.random.default_rng(seed)
+    return np.concatenate([wl.uniform_nodes(1500, d, seed),
+                           rng.integers(-Ms // 2, Ms // 2, size=(200, d)) / Ms,
+                           0.004 * rng.standard_normal((700, d))])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("d,M", [(1, 128), (2, 32)])
+@pytest.mark.parametrize("nr,nrhs", [(2, 5), (4, 11), (8, 5), (8, 16)])
+def test_fused_rhs_matches_oracle(d, M, nr, nrhs, prec):
+    m = 5
+    x = _nodes(d, M, 40 + d)
+    N = x.shape[0]
+    w = (1.0 + 0.3 * wl.complex_normal(N, 41)) / N
+    F = wl.complex_normal((nrhs, N), 42)
+    p = _plan(x, M, m, prec, max_rhs=nrhs, tuning={"rhs_per_group": nr})
+    assert p.tuning()["rhs_per_group"] == nr
+    p.set_weights(w)
+    got = _np(p.adjoint(torch.from_numpy(F)))
+    ref = onfft.adjoint(x, w[None, :] * F, M, 2.0, m)
+    for r in range(nrhs):
+        assert metrics.rel_err(got[r], ref[r]) <= TOL_O2[prec], r
+    # the same plan with one right-hand side per work-group
+    p.set_tuning("rhs_per_group", 1)
+    sep = _np(p.adjoint(torch.from_numpy(F)))
+    assert metrics.rel_err(got, sep) <= TOL_ORDER[prec]
+    p.close()
+
+
+TUNINGS = [
+    {"tile_edge": 8},
+    {"tile_edge": 32, "item_nodes": 64},
+    {"item_nodes": 1024, "spread_threads": 64},
+    {"spread_threads": 256, "fft_min_wg": 1},
+    {"fft_min_wg": 65536},
+    {"spread_planes": 2},
+    {"tile_edge": 8, "spread_planes": 2, "spread_threads": 256},
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("tuning", TUNINGS)
+def test_tunings_agree(tuning, prec):
+    M, m = 64, 6
+    x = _nodes(2, M, 50)
+    N = x.shape[0]
+    w = (1.0 + 0.3 * wl.complex_normal(N, 51)) / N
+    f = wl.complex_normal(N, 52)
+    fh = wl.complex_normal(M * M, 53)
+    base = _plan(x, M, m, prec)
+    base.set_weights(w)
+    a0 = _np(base.adjoint(torch.from_numpy(f)))
+    b0 = _np(base.forward(torch.from_numpy(fh)))
+    p = _plan(x, M, m, prec, tuning=tuning)
+    got_t = p.tuning()
+    for k, v in tuning.items():
+        assert got_t[k] == v, (k, got_t)
+    p.set_weights(w)
+    a = _np(p.adjoint(torch.from_numpy(f)))
+    b = _np(p.forward(torch.from_numpy(fh)))
+    assert metrics.rel_err(a, onfft.adjoint(x, w * f, M, 2.0, m)) <= TOL_O2[prec]
+    assert metrics.rel_err(a, a0) <= TOL_ORDER[prec]
+    assert metrics.rel_err(b, b0) <= TOL_ORDER[prec]
+    base.close()
+    p.close()
+
+
+def test_set_tuning_rules():
+    from paper_2302_00414_amd.nfft import NfftError
+    x = wl.uniform_nodes(500, 2, 60)
+    p = _plan(x, 32, 4, "f32")
+    t = p.tuning()
+    assert t == {"tile_edge": 16, "item_nodes": 256, "spread_threads": 128, "rhs_per_group": 1,
+                 "fft_min_wg": 256, "spread_planes": 1}
+    p.set_tuning("spread_threads", 64)
+    assert p.tuning()["spread_threads"] == 64
+    p.set_tuning("spread_threads", 0)          # back to the default
+    assert p.tuning()["spread_threads"] == 128
+    with pytest.raises(NfftError):
+        p.set_tuning("tile_edge", 32)         # fixed at plan time
+    with pytest.raises(NfftError):
+        p.set_tuning("rhs_per_group", 3)
+    assert p.tuning() == t
+    p.close()
+
+
+def test_3d_m8_float32():
+    """d = 3 with m = 8 (float32 only: two float32 planes of 24^3 cells fit in LDS)."""
+    x = _nodes(3, 16, 70)
+    N = x.shape[0]
+    w = np.full(N, 1.0 / N)
+    f = wl.complex_normal(N, 71)
+    p = _plan(x, 16, 8, "f32")
+    p.set_weights(w)
+    got = _np(p.adjoint(torch.from_numpy(f)))
+    assert metrics.rel_err(got, onfft.adjoint(x, w * f, 16, 2.0, 8)) <= TOL_O2["f32"]
+    fh = wl.complex_normal(16 ** 3, 72)
+    assert metrics.rel_err(_np(p.forward(torch.from_numpy(fh))),
+                           onfft.forward(x, fh, 16, 2.0, 8)) <= TOL_O2["f32"]
+    p.close()
