@@ -7,12 +7,16 @@ right-hand side of complex samples per step. A step is one reconstruction
 fhat = D^* F^* B^* W f (spreading, FFT, deconvolution and crop) with the plan,
 the weights and the samples already resident in device memory.
 
-Prints one JSON line: points/s of the float32 path (value), per-step latency
-percentiles, the float64 path's figures, the roofline position of the
-spreading kernel (timed with HIP events on the library's stream inside the
-timed region) and the FP64 CPU oracle timed on a bounded sample.
+Plans are made by the library's autotuner (plan-time work, outside the timed
+region). Prints one JSON line: points/s of the float32 path (value), per-step
+latency percentiles, the float64 path's figures, per-stage times with their
+HBM rates from algorithmic bytes, the roofline position of the spreading
+kernel (timed with HIP events on the library's stream inside the timed
+region), the batched form (spiral, 131072 nodes, 32 right-hand sides, one
+fused float32 call against 32 float64 calls) and the FP64 CPU oracle timed
+on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
 """
 import argparse
 import hashlib
@@ -49,12 +53,27 @@ def spread_flops(N, m, d):
     return 4 * (2 * m) ** d * N
 
 
-def run_gpu(prec, x, w, f, steps, warmup):
+def stage_bytes(N, Ms, Mb, d, prec, nrhs=1):
+    """Algorithmic HBM bytes of each adjoint stage (the least each stage must
+    move): spreading reads the encoded nodes, weights and samples and writes
+    the M_sigma^d grid of cell sums once; the first FFT pass reads that grid
+    (the tile partials hold it spread over padded tiles) and writes
+    M_sigma^(d-1) M values after the crop of its dimension; the remaining
+    passes read that and write the M^d result."""
+    rb = 8 if prec == "f64" else 4
+    cb = 2 * rb
+    spread = N * (d * rb + 4 + cb) + nrhs * (N * cb + Ms ** d * cb)
+    merge = nrhs * (Ms ** d + Ms ** (d - 1) * Mb) * cb
+    rest = nrhs * (Ms ** (d - 1) * Mb + Mb ** d) * cb
+    return {"spread": spread, "fft_merge": merge, "fft_rest_deconv": rest}
+
+
+def run_gpu(prec, x, w, f, steps, warmup, tuning="auto"):
     import torch
     from paper_2302_00414_amd.nfft import Plan
 
     dev = torch.device("cuda:0")
-    plan = Plan(x, M, SIGMA, MW, precision=prec, device=dev)
+    plan = Plan(x, M, SIGMA, MW, precision=prec, device=dev, tuning=tuning)
     plan.set_weights(w)
     cdt = torch.complex64 if prec == "f32" else torch.complex128
     fd = torch.from_numpy(f).to(device=dev, dtype=cdt)
@@ -92,10 +111,49 @@ def run_gpu(prec, x, w, f, steps, warmup):
         lat.append(a.elapsed_time(b))
     res = out.cpu().numpy().astype(np.complex128)
     info = plan.info()
+    tuning = plan.tuning()
     plan.close()
     ms_per_step = max(gpu_ms, wall * 1e3) / steps
     return dict(ms_per_step=ms_per_step, gpu_ms=gpu_ms, wall_s=wall, stages=stages,
-                lat=np.array(lat), out=res, info=info)
+                lat=np.array(lat), out=res, info=info, tuning=tuning)
+
+
+def run_batched(steps):
+    """Spiral trajectory, N = 131072, 32 right-hand sides, M = 256, m = 6: one
+    fused float32 adjoint of all 32 against 32 float64 single calls."""
+    import torch
+    from paper_2302_00414_amd import workloads as wl
+    from paper_2302_00414_amd.nfft import Plan
+
+    N, R = 131072, 32
+    x = wl.spiral_nodes(N, M)
+    w = wl.spiral_area_weights(N, M)
+    F = wl.complex_normal((R, N), 5)
+    res = {}
+    for prec, nrhs in (("f32", R), ("f64", 1)):
+        cdt = torch.complex64 if prec == "f32" else torch.complex128
+        plan = Plan(x, M, SIGMA, MW, precision=prec, max_rhs=nrhs, tuning="auto")
+        plan.set_weights(w)
+        fd = torch.from_numpy(F).to("cuda", cdt)
+        out = torch.empty((nrhs, M * M), dtype=cdt, device="cuda")
+        calls = (lambda: plan.adjoint(fd, out=out)) if nrhs == R else \
+                (lambda: [plan.adjoint(fd[r:r + 1], out=out) for r in range(R)])
+        for _ in range(3):
+            calls()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            calls()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[prec] = dict(ms_per_32_rhs=ms, points_per_s=N * R / (ms / 1e3), tuning=plan.tuning())
+        plan.close()
+    return dict(workload="spiral N=131072, d=2, M=256, sigma=2, m=6, 32 rhs, area weights",
+                f32_fused=res["f32"], f64_separate_calls=res["f64"],
+                speedup=res["f64"]["ms_per_32_rhs"] / res["f32"]["ms_per_32_rhs"])
 
 
 def cpu_baseline(x, w, f, gpu_out32, gpu_out64, budget_s=12.0):
@@ -134,18 +192,25 @@ def cpu_baseline(x, w, f, gpu_out32, gpu_out64, budget_s=12.0):
     )
 
 
-def traffic_record(kernel_prefix):
+def traffic_record(kernel):
     """HBM bytes per launch from committed counter summaries, if they were taken
-    on the current kernel source (sha256 of csrc/spread.hip recorded with them)."""
+    on this kernel and the current kernel source (sha256 of the spreading
+    sources recorded with them)."""
     path = os.path.join(ROOT, "profiles", "spread_traffic_polar512.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_2302_00414_amd", "csrc", "spread.hip")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("source_sha256") != h:
+    if rec.get("source_sha256") != spread_source_sha() or rec.get("kernel", "").replace(" ", "") \
+            != ("nfft::" + kernel).replace(" ", ""):
         return None
     return rec.get("bytes_per_launch")
+
+
+def spread_source_sha():
+    h = hashlib.sha256()
+    for name in ("spread.hip", "spread_common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2302_00414_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
 
 
 def main():
@@ -154,6 +219,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 32-rhs spiral figures")
+    ap.add_argument("--tuning", default="auto",
+                    help='profiling runs: "auto" (autotuner) or a JSON object of tuning keys')
     ap.add_argument("--precision", choices=["both", "f32", "f64"], default="both",
                     help="profiling runs: time one path only (the JSON line needs both)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -185,25 +253,31 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(f"calibration copy: {n * 4} bytes read, {n * 4} bytes written", file=sys.stderr)
+    tuning = args.tuning if args.tuning == "auto" else json.loads(args.tuning)
     if args.precision != "both":
-        r = run_gpu(args.precision, x, w, f, args.steps, args.warmup)
+        r = run_gpu(args.precision, x, w, f, args.steps, args.warmup, tuning)
         print(json.dumps({"precision": args.precision, "ms_per_step": r["ms_per_step"],
+                          "tuning": r["tuning"],
                           "points_per_s": N / (r["ms_per_step"] / 1e3),
                           "stage_us": {k: v[0] / max(v[1], 1) * 1e3 for k, v in r["stages"].items()
                                        if v[1]}}), flush=True)
         return
-    r32 = run_gpu("f32", x, w, f, args.steps, args.warmup)
-    r64 = run_gpu("f64", x, w, f, args.steps, args.warmup)
+    r32 = run_gpu("f32", x, w, f, args.steps, args.warmup, tuning)
+    r64 = run_gpu("f64", x, w, f, args.steps, args.warmup, tuning)
 
     sp_ms, sp_calls = r32["stages"]["spread"]
     sp_avg_s = sp_ms / max(sp_calls, 1) / 1e3
     alg = spread_algorithmic_bytes(N, Ms, D, "f32")
     flops = spread_flops(N, MW, D)
     achieved = flops / sp_avg_s / 1e12
+    t = r32["tuning"]
+    kname = (f"spread_group_kernel<float, 2, 6, {t['spread_threads']}, "
+             f"{t['tile_edge'] if t['tile_edge'] in (8, 16) else 0}, "
+             f"{'true' if t['spread_planes'] == 2 else 'false'}>")
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_PEAK_TFLOPS,
                     unit="TFLOP/s", frac=round(achieved / FP32_PEAK_TFLOPS, 5),
-                    traffic=traffic_record("spread"),
-                    kernel="spread_group_kernel<float,2,6,128>",
+                    traffic=traffic_record(kname),
+                    kernel=kname,
                     avg_launch_us=round(sp_avg_s * 1e6, 3),
                     algorithmic_flops_per_launch=flops,
                     algorithmic_bytes_per_launch=alg,
@@ -212,6 +286,12 @@ def main():
                     cell_updates_per_s=(2 * MW) ** D * N / sp_avg_s)
     stage_us = {k: round(v[0] / max(v[1], 1) * 1e3, 3) for k, v in r32["stages"].items() if v[1]}
     stage_us64 = {k: round(v[0] / max(v[1], 1) * 1e3, 3) for k, v in r64["stages"].items() if v[1]}
+
+    def hbm(stage_times, prec):
+        b = stage_bytes(N, Ms, M, D, prec)
+        return {k: dict(alg_bytes=b[k], gbs=round(b[k] / (stage_times[k] * 1e-6) / 1e9, 1),
+                        frac=round(b[k] / (stage_times[k] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
+                for k in b if k in stage_times}
 
     line = {
         "metric": METRIC,
@@ -232,15 +312,20 @@ def main():
         "latency_ms": {"p50": float(np.percentile(r32["lat"], 50)),
                        "p99": float(np.percentile(r32["lat"], 99))},
         "stage_us": stage_us,
+        "stage_hbm": hbm(stage_us, "f32"),
+        "tuning": r32["tuning"],
         "f64": {"value": N / (r64["ms_per_step"] / 1e3), "ms_per_step": r64["ms_per_step"],
                 "latency_ms": {"p50": float(np.percentile(r64["lat"], 50)),
                                "p99": float(np.percentile(r64["lat"], 99))},
-                "stage_us": stage_us64},
+                "stage_us": stage_us64, "stage_hbm": hbm(stage_us64, "f64"),
+                "tuning": r64["tuning"]},
         "roofline": roofline,
         "plan": r32["info"],
         "paper_context": "Table 5.1, M=256 linogram N=524288: 6.6443e-02 s per reconstruction "
                          "(7.89e6 points/s), hardware not stated",
     }
+    if not args.no_batched:
+        line["batched"] = run_batched(max(10, min(args.steps // 10, 100)))
     if not args.no_cpu_baseline:
         cb = cpu_baseline(x, w, f, r32["out"], r64["out"])
         line["cpu_baseline"] = cb["baseline"]
