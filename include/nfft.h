@@ -91,7 +91,7 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
               const double *nodes, int precision, int max_rhs, void *stream);
 
 /*
- * Tuning. The spreading and FFT kernels take six launch parameters that
+ * Tuning. The spreading and FFT kernels take seven launch parameters that
  * change their speed, never their result beyond rounding order. An array
  * tuning[NFFT_TUNE_*] selects them; an entry of 0, or an entry past
  * ntuning, selects the library default:
@@ -114,10 +114,17 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
  *                             kernel: 1 = one complex tile per lane group,
  *                             2 = two groups per node, one for the real and
  *                             one for the imaginary plane (default 1).
+ *   NFFT_TUNE_SPREAD_MODE     single right-hand-side spreading for d = 2:
+ *                             1 = accumulation in LDS tiles, 2 = register
+ *                             row sweep (nodes of a tile taken row by row,
+ *                             the rows a node reaches kept in registers;
+ *                             needs T + 2m <= 32; resolved to 1 elsewhere).
+ *                             Default 1; the row sweep wins with many
+ *                             right-hand sides per call.
  * The environment variables NFFT_TILE_EDGE, NFFT_ITEM_NODES,
- * NFFT_SPREAD_THREADS, NFFT_RHS_PER_GROUP, NFFT_FFT_MIN_WG and
- * NFFT_SPREAD_PLANES replace the defaults. A combination whose spreading work-group does not fit in LDS is
- * NFFT_EUNSUPPORTED.
+ * NFFT_SPREAD_THREADS, NFFT_RHS_PER_GROUP, NFFT_FFT_MIN_WG, NFFT_SPREAD_PLANES
+ * and NFFT_SPREAD_MODE replace the defaults. A combination whose spreading
+ * work-group does not fit in LDS is NFFT_EUNSUPPORTED.
  */
 enum nfft_tune {
   NFFT_TUNE_TILE_EDGE = 0,
@@ -126,7 +133,8 @@ enum nfft_tune {
   NFFT_TUNE_RHS_PER_GROUP = 3,
   NFFT_TUNE_FFT_MIN_WG = 4,
   NFFT_TUNE_SPREAD_PLANES = 5,
-  NFFT_TUNE_COUNT = 6
+  NFFT_TUNE_SPREAD_MODE = 6,
+  NFFT_TUNE_COUNT = 7
 };
 
 /*
@@ -143,7 +151,8 @@ int nfft_get_tuning(nfft_plan_t plan, int *out, int n);
 /*
  * nfft_set_tuning -- change a launch-time parameter of an existing plan
  * (NFFT_TUNE_SPREAD_THREADS, NFFT_TUNE_RHS_PER_GROUP, NFFT_TUNE_FFT_MIN_WG,
- * NFFT_TUNE_SPREAD_PLANES; value 0 restores the default). Tile edge and item size are fixed at plan
+ * NFFT_TUNE_SPREAD_PLANES, NFFT_TUNE_SPREAD_MODE; value 0 restores the
+ * default). Tile edge and item size are fixed at plan
  * time: NFFT_EINVAL for them. Takes effect for transforms enqueued later.
  */
 int nfft_set_tuning(nfft_plan_t plan, int knob, int value);

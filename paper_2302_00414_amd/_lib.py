@@ -15,8 +15,8 @@ NFFT_OK, NFFT_EINVAL, NFFT_ENOMEM, NFFT_EDEVICE, NFFT_ESTATE, NFFT_EUNSUPPORTED 
 NFFT_F64, NFFT_F32 = 0, 1
 NFFT_STAGES = 6
 (NFFT_TUNE_TILE_EDGE, NFFT_TUNE_ITEM_NODES, NFFT_TUNE_SPREAD_THREADS, NFFT_TUNE_RHS_PER_GROUP,
- NFFT_TUNE_FFT_MIN_WG, NFFT_TUNE_SPREAD_PLANES) = range(6)
-NFFT_TUNE_COUNT = 6
+ NFFT_TUNE_FFT_MIN_WG, NFFT_TUNE_SPREAD_PLANES, NFFT_TUNE_SPREAD_MODE) = range(7)
+NFFT_TUNE_COUNT = 7
 
 EXPORTS = (
     "nfft_plan", "nfft_plan_tuned", "nfft_plan_autotune", "nfft_get_tuning", "nfft_set_tuning",

@@ -41,6 +41,7 @@ int default_tuning(int knob, int d) {
     case NFFT_TUNE_RHS_PER_GROUP: return env_int("NFFT_RHS_PER_GROUP", 1);
     case NFFT_TUNE_FFT_MIN_WG: return env_int("NFFT_FFT_MIN_WG", 256);
     case NFFT_TUNE_SPREAD_PLANES: return env_int("NFFT_SPREAD_PLANES", 1);
+    case NFFT_TUNE_SPREAD_MODE: return env_int("NFFT_SPREAD_MODE", 1);
     default: return 0;
   }
 }
@@ -205,6 +206,9 @@ int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, in
   const int planes = out[NFFT_TUNE_SPREAD_PLANES];
   if (planes != 1 && planes != 2)
     return fail(p, NFFT_EINVAL, "spread planes %d: expected 1 or 2", planes);
+  int& mode = out[NFFT_TUNE_SPREAD_MODE];
+  if (mode != 1 && mode != 2) return fail(p, NFFT_EINVAL, "spread mode %d: expected 1 or 2", mode);
+  if (mode == 2 && !nfft::spread_rows_supported(d, T + 2 * m)) mode = 1;
   const int fw = out[NFFT_TUNE_FFT_MIN_WG];
   if (fw < 1 || fw > 65536) return fail(p, NFFT_EINVAL, "fft min work-groups %d: expected 1..65536", fw);
   const int P = T + 2 * m;
@@ -476,6 +480,20 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
                                      (const int32_t*)offsets, (const uint32_t*)loc_u,
                                      (const double*)frac_u, N, d, g.nbins, p->perm, p->loc,
                                      (R*)p->frac, s));
+  if (d == 2) {
+    // within each tile, nodes ordered by tile row (the register row-sweep
+    // spreading consumes them row by row)
+    void *perm2, *loc2, *frac2;
+    TRY(talloc(&perm2, N * sizeof(int32_t)));
+    TRY(talloc(&loc2, N * sizeof(uint32_t)));
+    TRY(talloc(&frac2, N * d * sizeof(R)));
+    HIP_TRY(p, nfft::launch_row_sort<R>((const int32_t*)bstart, g.nbins, g.T, N, d, p->perm,
+                                        p->loc, (const R*)p->frac, (int32_t*)perm2,
+                                        (uint32_t*)loc2, (R*)frac2, s));
+    HIP_TRY(p, hipMemcpyAsync(p->perm, perm2, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(p, hipMemcpyAsync(p->loc, loc2, N * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(p, hipMemcpyAsync(p->frac, frac2, N * d * sizeof(R), hipMemcpyDeviceToDevice, s));
+  }
 
   const size_t ni = std::max<size_t>(1, istart.size());
   TRY(dalloc(p, &p->item_start, ni * sizeof(int32_t)));
@@ -575,6 +593,7 @@ int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t 
   sa.nt = p->tune[NFFT_TUNE_SPREAD_THREADS];
   sa.nr = nrhs > 1 ? p->tune[NFFT_TUNE_RHS_PER_GROUP] : 1;
   sa.planes = p->tune[NFFT_TUNE_SPREAD_PLANES];
+  sa.mode = p->tune[NFFT_TUNE_SPREAD_MODE];
   HIP_TRY(p, nfft::launch_spread<R>(sa, nrhs, s));
   record(p, se, s);
   nfft::ReduceArgs<R> ra{};
@@ -867,12 +886,13 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
   if (d == 1) tiles = {64, 128, 256};
   else if (d == 2) tiles = {8, 16, 32};
   else tiles = {8, 16};
-  std::vector<int> threads = {0}, planes = {0}, rpg = {0};
+  std::vector<int> threads = {0}, planes = {0}, rpg = {0}, modes = {0};
   if (d <= 2 && f32) {
     threads = {64, 128, 256};
     planes = {1, 2};
   }
   if (d <= 2 && nrhs > 1) rpg = {1, 2, 4, 8};
+  if (d == 2) modes = {1, 2};
 
   nfft_plan_t best = nullptr;
   double best_t = -1.0;
@@ -880,7 +900,7 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
   for (int T : tiles) {
     if (T > Ms) continue;
     for (int K : items) {
-      int tune[NFFT_TUNE_COUNT] = {T, K, 0, 0, 0, 0};
+      int tune[NFFT_TUNE_COUNT] = {T, K, 0, 0, 0, 0, 0};
       int resolved[NFFT_TUNE_COUNT];
       if (resolve_tuning(d, Ms, m, precision, tune, NFFT_TUNE_COUNT, resolved, nullptr) != NFFT_OK)
         continue;
@@ -898,6 +918,7 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
         return fail(nullptr, NFFT_EDEVICE, "hipMemsetAsync failed");
       }
       bool mine = false;  // p is (or became) the best plan
+      for (int md : modes)
       for (int nt : threads)
         for (int pl : planes)
           for (int nr : rpg) {
@@ -906,8 +927,10 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
             if (nt) in[NFFT_TUNE_SPREAD_THREADS] = nt;
             if (pl) in[NFFT_TUNE_SPREAD_PLANES] = pl;
             if (nr) in[NFFT_TUNE_RHS_PER_GROUP] = nr;
-            // the single-rhs kernel's shape does not matter when groups take several rhs
-            if (nr > 1 && (nt != threads[0] || pl != planes[0])) continue;
+            if (md) in[NFFT_TUNE_SPREAD_MODE] = md;
+            // the LDS kernel's shape does not matter when another kernel spreads
+            if ((nr > 1 || md == 2) && (nt != threads[0] || pl != planes[0])) continue;
+            if (nr > 1 && md == 2) continue;  // several rhs per group: one kernel
             int res[NFFT_TUNE_COUNT];
             if (resolve_tuning(d, Ms, m, precision, in, NFFT_TUNE_COUNT, res, nullptr) != NFFT_OK)
               continue;
@@ -965,7 +988,8 @@ int nfft_get_tuning(nfft_plan_t p, int* out, int n) {
 int nfft_set_tuning(nfft_plan_t p, int knob, int value) {
   if (!p) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
   if (knob != NFFT_TUNE_SPREAD_THREADS && knob != NFFT_TUNE_RHS_PER_GROUP &&
-      knob != NFFT_TUNE_FFT_MIN_WG && knob != NFFT_TUNE_SPREAD_PLANES)
+      knob != NFFT_TUNE_FFT_MIN_WG && knob != NFFT_TUNE_SPREAD_PLANES &&
+      knob != NFFT_TUNE_SPREAD_MODE)
     return fail(p, NFFT_EINVAL, "tuning knob %d cannot change after planning", knob);
   int in[NFFT_TUNE_COUNT], out[NFFT_TUNE_COUNT];
   std::copy(p->tune, p->tune + NFFT_TUNE_COUNT, in);

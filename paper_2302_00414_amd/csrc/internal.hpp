@@ -25,6 +25,12 @@ template <typename R>
 hipError_t launch_scatter(const int32_t* bin, const int32_t* rank, const int32_t* offsets,
                           const uint32_t* loc_u, const double* frac_u, int64_t N, int d,
                           int nbins, int32_t* perm, uint32_t* loc, R* frac, hipStream_t s);
+// Stable in-tile sort of the tile-ordered node arrays by tile row (the
+// tile-local cell of dimension 0); results in perm2 / loc2 / frac2.
+template <typename R>
+hipError_t launch_row_sort(const int32_t* bstart, int nbins, int T, int64_t N, int d,
+                           const int32_t* perm, const uint32_t* loc, const R* frac, int32_t* perm2,
+                           uint32_t* loc2, R* frac2, hipStream_t s);
 template <typename R>
 hipError_t launch_permute_weights(const double* w, const int32_t* perm, int64_t N,
                                   cplx<R>* w_sorted, hipStream_t s);
@@ -54,9 +60,14 @@ struct SpreadArgs {
   int nt;                    // threads per work-group, d <= 2 float32 single-rhs kernel
   int nr;                    // right-hand sides per work-group (1, 2, 4 or 8; d <= 2)
   int planes;                // 2: float32 real and imaginary planes in separate groups
+  int mode;                  // d = 2 single rhs: 1 LDS tiles, 2 register row sweep
 };
 template <typename R>
 hipError_t launch_spread(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
+// Register row sweep (d = 2, padded tile edge <= 32, nodes row-sorted in tiles).
+bool spread_rows_supported(int d, int P);
+template <typename R>
+hipError_t launch_spread_rows(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
 // Several right-hand sides per work-group (d <= 2, nr > 1).
 template <typename R>
 hipError_t launch_spread_multi(const SpreadArgs<R>& a, int nrhs, hipStream_t s);

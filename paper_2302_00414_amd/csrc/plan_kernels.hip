@@ -111,6 +111,53 @@ __global__ void scatter_kernel(const int32_t* __restrict__ bin, const int32_t* _
   for (int t = 0; t < d; ++t) frac[t * N + dest] = round_frac<R>(frac_u[t * N + j]);
 }
 
+// Stable sort of every tile's nodes by their tile-local cell in dimension 0
+// (the tile row), one work-group per tile: row counts, their prefix sums,
+// then chunks of 256 nodes scattered with in-chunk ranks counted in order.
+template <typename R>
+__global__ __launch_bounds__(256) void row_sort_kernel(const int32_t* __restrict__ bstart, int T,
+                                                       int64_t N, int d,
+                                                       const int32_t* __restrict__ perm,
+                                                       const uint32_t* __restrict__ loc,
+                                                       const R* __restrict__ frac,
+                                                       int32_t* __restrict__ perm2,
+                                                       uint32_t* __restrict__ loc2,
+                                                       R* __restrict__ frac2) {
+  __shared__ int start[257];  // T <= 256
+  __shared__ int rows[256];
+  const int tid = threadIdx.x;
+  const int s = bstart[blockIdx.x], e = bstart[blockIdx.x + 1];
+  if (s == e) return;
+  for (int r = tid; r <= T; r += 256) start[r] = 0;
+  __syncthreads();
+  for (int i = s + tid; i < e; i += 256) atomicAdd(&start[(int)(loc[i] & kLocMask) + 1], 1);
+  __syncthreads();
+  if (tid == 0)
+    for (int r = 1; r <= T; ++r) start[r] += start[r - 1];
+  __syncthreads();
+  for (int c0 = s; c0 < e; c0 += 256) {
+    const int i = c0 + tid;
+    const int r = i < e ? (int)(loc[i] & kLocMask) : -1;
+    rows[tid] = r;
+    __syncthreads();
+    if (i < e) {
+      int rank = 0;
+      for (int t = 0; t < tid; ++t) rank += rows[t] == r;
+      const int dst = s + start[r] + rank;
+      perm2[dst] = perm[i];
+      loc2[dst] = loc[i];
+      for (int t = 0; t < d; ++t) frac2[t * N + dst] = frac[t * N + i];
+    }
+    __syncthreads();
+    if (tid < T) {
+      int c = 0;
+      for (int t = 0; t < 256; ++t) c += rows[t] == tid;
+      start[tid] += c;
+    }
+    __syncthreads();
+  }
+}
+
 template <typename R>
 __global__ void permute_weights_kernel(const double* __restrict__ w,
                                        const int32_t* __restrict__ perm, int64_t N,
@@ -159,6 +206,16 @@ hipError_t launch_scatter(const int32_t* bin, const int32_t* rank, const int32_t
 }
 
 template <typename R>
+hipError_t launch_row_sort(const int32_t* bstart, int nbins, int T, int64_t N, int d,
+                           const int32_t* perm, const uint32_t* loc, const R* frac, int32_t* perm2,
+                           uint32_t* loc2, R* frac2, hipStream_t s) {
+  if (T > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(row_sort_kernel<R>, dim3(nbins), dim3(256), 0, s, bstart, T, N, d, perm, loc,
+                     frac, perm2, loc2, frac2);
+  return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_permute_weights(const double* w, const int32_t* perm, int64_t N,
                                   cplx<R>* w_sorted, hipStream_t s) {
   hipLaunchKernelGGL(permute_weights_kernel<R>, dim3(grid1(N, 256)), dim3(256), 0, s, w, perm, N,
@@ -172,6 +229,12 @@ template hipError_t launch_scatter<float>(const int32_t*, const int32_t*, const 
 template hipError_t launch_scatter<double>(const int32_t*, const int32_t*, const int32_t*,
                                            const uint32_t*, const double*, int64_t, int, int,
                                            int32_t*, uint32_t*, double*, hipStream_t);
+template hipError_t launch_row_sort<float>(const int32_t*, int, int, int64_t, int, const int32_t*,
+                                           const uint32_t*, const float*, int32_t*, uint32_t*,
+                                           float*, hipStream_t);
+template hipError_t launch_row_sort<double>(const int32_t*, int, int, int64_t, int, const int32_t*,
+                                            const uint32_t*, const double*, int32_t*, uint32_t*,
+                                            double*, hipStream_t);
 template hipError_t launch_permute_weights<float>(const double*, const int32_t*, int64_t,
                                                   cplx<float>*, hipStream_t);
 template hipError_t launch_permute_weights<double>(const double*, const int32_t*, int64_t,

@@ -58,7 +58,7 @@ def nfft_plan(d: int, M: int, sigma: float, m: int, nodes: torch.Tensor, precisi
 
 
 TUNING_KEYS = ("tile_edge", "item_nodes", "spread_threads", "rhs_per_group", "fft_min_wg",
-               "spread_planes")
+               "spread_planes", "spread_mode")
 
 
 def _tuning_array(tuning) -> Optional[ctypes.Array]:
@@ -289,7 +289,8 @@ class Plan:
         return nfft_get_tuning(self._h)
 
     def set_tuning(self, knob, value: int) -> None:
-        """Change a launch-time knob (spread_threads, rhs_per_group, fft_min_wg, spread_planes)."""
+        """Change a launch-time knob (spread_threads, rhs_per_group, fft_min_wg, spread_planes,
+        spread_mode)."""
         nfft_set_tuning(self._h, knob, value)
 
     def permutation(self) -> np.ndarray:

@@ -85,6 +85,7 @@ def test_f64_3d_large_m_unsupported():
     (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 70000], _lib.NFFT_EINVAL),  # fft min work-groups
     (2, 6, _lib.NFFT_F32, [-1], _lib.NFFT_EINVAL),                # negative entry
     (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 3], _lib.NFFT_EINVAL),  # spread planes not 1/2
+    (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 3], _lib.NFFT_EINVAL),  # spread mode not 1/2
     (2, 8, _lib.NFFT_F32, [32, 0, 256, 0, 0, 2], _lib.NFFT_OK),   # 16 float32 48^2 planes fit
     (3, 4, _lib.NFFT_F32, [32], _lib.NFFT_EUNSUPPORTED),          # 40^3 padded tile exceeds LDS
     (2, 8, _lib.NFFT_F32, [64, 0, 256], _lib.NFFT_EUNSUPPORTED),  # 16 private 80^2 tiles exceed LDS
@@ -111,8 +112,8 @@ def test_tuning_validation_before_device(d, m, prec, tuning, status):
 
 def test_tuning_knobs_need_a_plan():
     lib = _lib.load()
-    out = (ctypes.c_int32 * 6)()
-    assert lib.nfft_get_tuning(None, out, 6) == _lib.NFFT_EINVAL
+    out = (ctypes.c_int32 * 7)()
+    assert lib.nfft_get_tuning(None, out, 7) == _lib.NFFT_EINVAL
     assert lib.nfft_set_tuning(None, _lib.NFFT_TUNE_SPREAD_THREADS, 64) == _lib.NFFT_EINVAL
 
 

@@ -71,8 +71,12 @@ TUNINGS = [
     {"item_nodes": 1024, "spread_threads": 64},
     {"spread_threads": 256, "fft_min_wg": 1},
     {"fft_min_wg": 65536},
-    {"spread_planes": 2},
-    {"tile_edge": 8, "spread_planes": 2, "spread_threads": 256},
+    {"spread_planes": 2, "spread_mode": 1},
+    {"tile_edge": 8, "spread_planes": 2, "spread_threads": 256, "spread_mode": 1},
+    {"spread_mode": 2},
+    {"spread_mode": 2, "tile_edge": 8, "item_nodes": 32},
+    {"spread_mode": 2, "item_nodes": 1000},
+    {"spread_mode": 2, "tile_edge": 32},   # padded edge 44 > 32: resolved to the LDS kernel
 ]
 
 
@@ -92,6 +96,9 @@ def test_tunings_agree(tuning, prec):
     p = _plan(x, M, m, prec, tuning=tuning)
     got_t = p.tuning()
     for k, v in tuning.items():
+        if k == "spread_mode" and tuning.get("tile_edge") == 32:
+            assert got_t[k] == 1
+            continue
         assert got_t[k] == v, (k, got_t)
     p.set_weights(w)
     a = _np(p.adjoint(torch.from_numpy(f)))
@@ -109,7 +116,7 @@ def test_set_tuning_rules():
     p = _plan(x, 32, 4, "f32")
     t = p.tuning()
     assert t == {"tile_edge": 16, "item_nodes": 256, "spread_threads": 128, "rhs_per_group": 1,
-                 "fft_min_wg": 256, "spread_planes": 1}
+                 "fft_min_wg": 256, "spread_planes": 1, "spread_mode": 1}
     p.set_tuning("spread_threads", 64)
     assert p.tuning()["spread_threads"] == 64
     p.set_tuning("spread_threads", 0)          # back to the default
@@ -135,4 +142,24 @@ def test_3d_m8_float32():
     fh = wl.complex_normal(16 ** 3, 72)
     assert metrics.rel_err(_np(p.forward(torch.from_numpy(fh))),
                            onfft.forward(x, fh, 16, 2.0, 8)) <= TOL_O2["f32"]
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("m", [2, 6, 8])
+def test_row_sweep_multi_rhs(prec, m):
+    """Register row sweep with several right-hand sides in one launch, at the
+    smallest and largest windows it covers (padded edge 16 + 2m <= 32)."""
+    M, nrhs = 32, 3
+    x = _nodes(2, M, 200 + m)
+    N = x.shape[0]
+    w = (1.0 + 0.3 * wl.complex_normal(N, 201)) / N
+    F = wl.complex_normal((nrhs, N), 202)
+    p = _plan(x, M, m, prec, max_rhs=nrhs, tuning={"spread_mode": 2})
+    assert p.tuning()["spread_mode"] == 2
+    p.set_weights(w)
+    got = _np(p.adjoint(torch.from_numpy(F)))
+    ref = onfft.adjoint(x, w[None, :] * F, M, 2.0, m)
+    for r in range(nrhs):
+        assert metrics.rel_err(got[r], ref[r]) <= TOL_O2[prec], r
     p.close()
