@@ -215,6 +215,31 @@ int nfft_adjoint(nfft_plan_t plan, const void *f, void *fhat, int nrhs, void *st
  */
 int nfft_forward(nfft_plan_t plan, const void *fhat, void *f, int nrhs, void *stream);
 
+/*
+ * nfft_weights -- density-compensation weights of Algorithm 3.6 for a node
+ * set, computed on the device in float64. The conditions (3.14),
+ * A_2M^T w = e_0 on I_2M, are solved by conjugate gradients from zero: on
+ * the normal equations of the second kind (3.15) when |I_2M| = (2M)^d <= N
+ * (then w = conj(A_2M) v), otherwise on those of the first kind (3.16). The
+ * products with A_2M^T and conj(A_2M) are this library's float64 NFFT at
+ * bandwidth 2M with window parameter m and oversampling sigma (so
+ * sigma * 2M must give a power-of-two M_sigma in [8, 4096]).
+ *   nodes   N*d float64 (host or device), as for nfft_plan
+ *   tol     stop once ||r|| <= tol ||b|| for the normal-equation residual r, > 0
+ *   maxit   iteration limit, >= 1
+ *   w       device, N complex128 in the caller's node order (output)
+ *   info    host, 4 doubles, or NULL: iterations, final relative residual,
+ *           branch (15 or 16 for (3.15) / (3.16)) and epsilon =
+ *           max_k |[A_2M^T w]_k - delta_{0,k}| over I_2M (the quantity of
+ *           (3.36)), evaluated with the same NFFT
+ *   stream  hipStream_t; the call synchronises it (convergence is tested on
+ *           the host after every iteration)
+ * Returns the nfft_plan status codes; NFFT_EINVAL for a NULL w, tol <= 0,
+ * maxit < 1 or an odd M (M is the bandwidth of the reconstruction).
+ */
+int nfft_weights(int d, int M, double sigma, int m, int64_t N, const double *nodes, double tol,
+                 int maxit, void *w, double *info, void *stream);
+
 /* nfft_destroy -- wait for the plan's outstanding work and free it. NULL is a no-op. */
 int nfft_destroy(nfft_plan_t plan);
 

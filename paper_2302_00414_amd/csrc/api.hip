@@ -977,6 +977,124 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
   return NFFT_OK;
 }
 
+int nfft_weights(int d, int M, double sigma, int m, int64_t N, const double* nodes, double tol,
+                 int maxit, void* w_out, double* info, void* stream) {
+  if (!w_out) return fail(nullptr, NFFT_EINVAL, "w is NULL");
+  if (!(tol > 0.0) || maxit < 1)
+    return fail(nullptr, NFFT_EINVAL, "tol = %g, maxit = %d: expected tol > 0, maxit >= 1", tol, maxit);
+  if (M < 2 || M > (1 << 20) || (M % 2) != 0)
+    return fail(nullptr, NFFT_EINVAL, "M = %d, expected an even M >= 2", M);
+  nfft_plan_t p = nullptr;
+  int st = nfft_plan(&p, d, 2 * M, sigma, m, N, nodes, NFFT_F64, 1, stream);
+  if (st != NFFT_OK) return st;
+  struct PlanGuard {
+    nfft_plan_t p;
+    ~PlanGuard() { free_plan(p); }
+  } guard{p};
+  hipStream_t s = (hipStream_t)stream;
+  using C = cplx<double>;
+  const int64_t K2 = ipow(2 * M, d);
+  const bool b15 = K2 <= N;           // Algorithm 3.6 step 2: which normal equations
+  const int64_t n = b15 ? K2 : N;     // length of the CG vectors
+  int64_t e_idx = 0;                  // index of k = 0 in I_2M (C order, k_t from -M)
+  for (int t = 0; t < d; ++t) e_idx = e_idx * (2 * M) + M;
+
+  ScopedFree bufs;
+  auto alloc = [&](C** q, int64_t count) -> int {
+    void* v = nullptr;
+    if (hipMalloc(&v, (size_t)std::max<int64_t>(1, count) * sizeof(C)) != hipSuccess)
+      return fail(nullptr, NFFT_ENOMEM, "no device memory for the CG vectors");
+    bufs.ptrs.push_back(v);
+    *q = (C*)v;
+    return NFFT_OK;
+  };
+  C *x, *r, *pv, *q, *tmp;
+  TRY(alloc(&x, n));
+  TRY(alloc(&r, n));
+  TRY(alloc(&pv, n));
+  TRY(alloc(&q, n));
+  TRY(alloc(&tmp, b15 ? N : K2));
+  double* scratch = nullptr;
+  if (hipMalloc((void**)&scratch, nfft::reduce_scratch_doubles() * sizeof(double)) != hipSuccess)
+    return fail(nullptr, NFFT_ENOMEM, "no device memory for the reductions");
+  bufs.ptrs.push_back(scratch);
+  const double* result = scratch + (nfft::reduce_scratch_doubles() - 1);
+
+  // unit weights on the internal plan: its adjoint is then A_2M^* itself
+  if (nfft::launch_fill((C*)p->w, N, 1.0, 0.0, s) != hipSuccess)
+    return fail(nullptr, NFFT_EDEVICE, "fill kernel failed");
+  p->shared->has_weights = true;
+
+  // CG on the conjugated systems. With A^T y = conj(adjoint(conj y)) and
+  // conj(A) v = conj(forward(conj v)), the operator A^T conj(A) of (3.15)
+  // maps q = conj(v) to conj(A^T conj(A) v) = adjoint(forward(q)), and
+  // conj(A) A^T of (3.16) becomes forward(adjoint(q)). The right-hand sides
+  // e_0 and 1_N are real and CG's step lengths are real, so these iterates
+  // are the conjugates of CG on the original systems.
+  auto apply = [&](const C* in, C* out) -> int {
+    if (b15) {
+      TRY(run_forward<double>(p, in, tmp, 1, s));
+      TRY(run_adjoint<double>(p, tmp, out, 1, s));
+    } else {
+      TRY(run_adjoint<double>(p, in, tmp, 1, s));
+      TRY(run_forward<double>(p, tmp, out, 1, s));
+    }
+    return NFFT_OK;
+  };
+  auto reduce = [&](const C* a, const C* b, int64_t len, int op, double* out) -> int {
+    if (nfft::launch_reduce(a, b, len, op, e_idx, scratch, s) != hipSuccess ||
+        hipMemcpyAsync(out, result, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(nullptr, NFFT_EDEVICE, "reduction failed");
+    return NFFT_OK;
+  };
+  HIP_TRY(nullptr, nfft::launch_fill(x, n, 0.0, 0.0, s));
+  if (b15) {
+    HIP_TRY(nullptr, nfft::launch_fill(r, n, 0.0, 0.0, s));
+    HIP_TRY(nullptr, nfft::launch_fill(r + e_idx, 1, 1.0, 0.0, s));
+  } else {
+    HIP_TRY(nullptr, nfft::launch_fill(r, n, 1.0, 0.0, s));
+  }
+  HIP_TRY(nullptr, hipMemcpyAsync(pv, r, n * sizeof(C), hipMemcpyDeviceToDevice, s));
+  double rr = 0.0;
+  TRY(reduce(r, r, n, 0, &rr));
+  const double nb = std::sqrt(rr);
+  int it = 0;
+  while (it < maxit && std::sqrt(rr) > tol * nb) {
+    TRY(apply(pv, q));
+    double pAp = 0.0;
+    TRY(reduce(pv, q, n, 0, &pAp));
+    if (!(pAp > 0.0)) break;  // exact solution reached or breakdown
+    const double alpha = rr / pAp;
+    HIP_TRY(nullptr, nfft::launch_cg_update(x, r, pv, q, n, alpha, s));
+    double rr_new = 0.0;
+    TRY(reduce(r, r, n, 0, &rr_new));
+    HIP_TRY(nullptr, nfft::launch_cg_direction(pv, r, n, rr_new / rr, s));
+    rr = rr_new;
+    ++it;
+  }
+  // conj(w): (3.15) forward of the solution, (3.16) the solution itself
+  C* w = (C*)w_out;
+  if (b15)
+    TRY(run_forward<double>(p, x, w, 1, s));
+  else
+    HIP_TRY(nullptr, hipMemcpyAsync(w, x, N * sizeof(C), hipMemcpyDeviceToDevice, s));
+  // epsilon: A_2M^T w = conj(adjoint(conj w)), and e_0 is real
+  C* at = b15 ? q : tmp;
+  TRY(run_adjoint<double>(p, w, at, 1, s));
+  double eps = 0.0;
+  TRY(reduce(at, at, K2, 1, &eps));
+  HIP_TRY(nullptr, nfft::launch_conj(w, N, s));
+  HIP_TRY(nullptr, hipStreamSynchronize(s));
+  if (info) {
+    info[0] = it;
+    info[1] = nb > 0 ? std::sqrt(rr) / nb : 0.0;
+    info[2] = b15 ? 15 : 16;
+    info[3] = eps;
+  }
+  return NFFT_OK;
+}
+
 int nfft_get_tuning(nfft_plan_t p, int* out, int n) {
   if (!p) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
   if (!out || n < 0 || n > NFFT_TUNE_COUNT)

@@ -137,4 +137,15 @@ template <typename R>
 hipError_t launch_fft_pass(const FftArgs<R>& a, int L, bool inverse, LoadMode ld, StoreMode st,
                            int nbatch, hipStream_t s);
 
+// ------------------------------------------------ float64 vector kernels
+size_t reduce_scratch_doubles();
+hipError_t launch_fill(cplx<double>* v, int64_t n, double re, double im, hipStream_t s);
+hipError_t launch_conj(cplx<double>* v, int64_t n, hipStream_t s);
+hipError_t launch_reduce(const cplx<double>* a, const cplx<double>* b, int64_t n, int op,
+                         int64_t e_idx, double* scratch, hipStream_t s);
+hipError_t launch_cg_update(cplx<double>* x, cplx<double>* r, const cplx<double>* p,
+                            const cplx<double>* q, int64_t n, double alpha, hipStream_t s);
+hipError_t launch_cg_direction(cplx<double>* p, const cplx<double>* r, int64_t n, double beta,
+                               hipStream_t s);
+
 }  // namespace nfft

@@ -1,0 +1,130 @@
+// Float64 vector kernels for the conjugate-gradient solve of the weight
+// conditions (Algorithm 3.6): fills, dot products and norms reduced in a fixed
+// order (deterministic), fused vector updates and the residual maximum.
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace nfft {
+
+namespace {
+
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocks = 1024;  // partial sums of the first pass
+
+__global__ void fill_kernel(cplx<double>* v, int64_t n, double re, double im) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) v[i] = mkc<double>(re, im);
+}
+
+__global__ void conj_kernel(cplx<double>* v, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) v[i].y = -v[i].y;
+}
+
+// block sums of Re(conj(a_i) b_i) (op 0) or of max |a_i - e_i| with e the
+// unit vector at index e_idx (op 1), grid-stride in a fixed order
+__global__ __launch_bounds__(kRedThreads) void reduce_pass1(const cplx<double>* a,
+                                                            const cplx<double>* b, int64_t n,
+                                                            int op, int64_t e_idx,
+                                                            double* partial) {
+  __shared__ double sh[kRedThreads];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    if (op == 0) {
+      acc += a[i].x * b[i].x + a[i].y * b[i].y;
+    } else {
+      const double dx = a[i].x - (i == e_idx ? 1.0 : 0.0);
+      acc = fmax(acc, sqrt(dx * dx + a[i].y * a[i].y));
+    }
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w /= 2) {
+    if (threadIdx.x < w)
+      sh[threadIdx.x] = op == 0 ? sh[threadIdx.x] + sh[threadIdx.x + w]
+                                : fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kRedThreads) void reduce_pass2(const double* partial, int n, int op,
+                                                            double* out) {
+  __shared__ double sh[kRedThreads];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += kRedThreads)
+    acc = op == 0 ? acc + partial[i] : fmax(acc, partial[i]);
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w /= 2) {
+    if (threadIdx.x < w)
+      sh[threadIdx.x] = op == 0 ? sh[threadIdx.x] + sh[threadIdx.x + w]
+                                : fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+// x += alpha p, r -= alpha q
+__global__ void cg_update_kernel(cplx<double>* x, cplx<double>* r, const cplx<double>* p,
+                                 const cplx<double>* q, int64_t n, double alpha) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  x[i].x += alpha * p[i].x;
+  x[i].y += alpha * p[i].y;
+  r[i].x -= alpha * q[i].x;
+  r[i].y -= alpha * q[i].y;
+}
+
+// p = r + beta p
+__global__ void cg_direction_kernel(cplx<double>* p, const cplx<double>* r, int64_t n, double beta) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  p[i].x = r[i].x + beta * p[i].x;
+  p[i].y = r[i].y + beta * p[i].y;
+}
+
+unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+size_t reduce_scratch_doubles() { return kRedBlocks + 1; }
+
+hipError_t launch_fill(cplx<double>* v, int64_t n, double re, double im, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks(n)), dim3(256), 0, s, v, n, re, im);
+  return hipGetLastError();
+}
+
+hipError_t launch_conj(cplx<double>* v, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(conj_kernel, dim3(blocks(n)), dim3(256), 0, s, v, n);
+  return hipGetLastError();
+}
+
+// op 0: Re <a, b>; op 1: max_i |a_i - delta_{i, e_idx}|. The result lands in
+// scratch[kRedBlocks] (device); scratch holds reduce_scratch_doubles() values.
+hipError_t launch_reduce(const cplx<double>* a, const cplx<double>* b, int64_t n, int op,
+                         int64_t e_idx, double* scratch, hipStream_t s) {
+  const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (n + kRedThreads - 1) / kRedThreads));
+  hipLaunchKernelGGL(reduce_pass1, dim3(nb), dim3(kRedThreads), 0, s, a, b, n, op, e_idx, scratch);
+  hipLaunchKernelGGL(reduce_pass2, dim3(1), dim3(kRedThreads), 0, s, scratch, nb, op,
+                     scratch + kRedBlocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(cplx<double>* x, cplx<double>* r, const cplx<double>* p,
+                            const cplx<double>* q, int64_t n, double alpha, hipStream_t s) {
+  hipLaunchKernelGGL(cg_update_kernel, dim3(blocks(n)), dim3(256), 0, s, x, r, p, q, n, alpha);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_direction(cplx<double>* p, const cplx<double>* r, int64_t n, double beta,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(cg_direction_kernel, dim3(blocks(n)), dim3(256), 0, s, p, r, n, beta);
+  return hipGetLastError();
+}
+
+}  // namespace nfft

@@ -131,6 +131,32 @@ def nfft_forward(plan, fhat: torch.Tensor, f: torch.Tensor, nrhs: int, stream=No
                                    ctypes.c_void_p(f.data_ptr()), nrhs, _stream_ptr(stream)), plan)
 
 
+def nfft_weights(d: int, M: int, sigma: float, m: int, nodes: torch.Tensor, tol: float,
+                 maxit: int, w: torch.Tensor, stream=None) -> dict:
+    """Algorithm 3.6 on the device (float64); w: complex128 device tensor of N."""
+    info = (ctypes.c_double * 4)()
+    check(_lib.load().nfft_weights(d, M, float(sigma), m, nodes.shape[0],
+                                   ctypes.c_void_p(nodes.data_ptr()), float(tol), int(maxit),
+                                   ctypes.c_void_p(w.data_ptr()), info, _stream_ptr(stream)), None)
+    return {"iterations": int(info[0]), "rel_residual": float(info[1]),
+            "branch": "3.15" if int(info[2]) == 15 else "3.16", "epsilon": float(info[3])}
+
+
+def compute_weights(nodes, M: int, sigma: float = 2.0, m: int = 8, tol: float = 1e-13,
+                    maxit: int = 1000, device=None, stream=None):
+    """Density-compensation weights of Algorithm 3.6 for a node set, computed
+    on the GPU in float64. Returns (w, info): w complex128 on the device in
+    the caller's node order, info with iterations, relative residual, branch
+    and epsilon."""
+    dev = torch.device(device or "cuda")
+    x = _as_f64_nodes(nodes).to(dev)
+    N, d = x.shape
+    w = torch.empty(N, dtype=torch.complex128, device=dev)
+    with torch.cuda.device(dev):
+        info = nfft_weights(d, M, sigma, m, x, tol, maxit, w, stream)
+    return w, info
+
+
 def nfft_destroy(plan) -> None:
     check(_lib.load().nfft_destroy(plan), None)
 

@@ -110,6 +110,18 @@ def test_tuning_validation_before_device(d, m, prec, tuning, status):
         assert lib.nfft_last_error(None)
 
 
+def test_weights_argument_checks():
+    lib = _lib.load()
+    x = np.zeros((8, 2))
+    info = (ctypes.c_double * 4)()
+    buf = ctypes.c_void_p(1)
+    assert lib.nfft_weights(2, 16, 2.0, 8, 8, x.ctypes.data, 1e-13, 100, None, info, None) == _lib.NFFT_EINVAL
+    assert lib.nfft_weights(2, 16, 2.0, 8, 8, x.ctypes.data, 0.0, 100, buf, info, None) == _lib.NFFT_EINVAL
+    assert lib.nfft_weights(2, 16, 2.0, 8, 8, x.ctypes.data, 1e-13, 0, buf, info, None) == _lib.NFFT_EINVAL
+    assert lib.nfft_weights(2, 15, 2.0, 8, 8, x.ctypes.data, 1e-13, 10, buf, info, None) == _lib.NFFT_EINVAL
+    assert lib.nfft_last_error(None)
+
+
 def test_tuning_knobs_need_a_plan():
     lib = _lib.load()
     out = (ctypes.c_int32 * 7)()
