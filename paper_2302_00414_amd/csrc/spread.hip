@@ -143,72 +143,86 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
     // reads of the current node are in flight. LDS operations of a wave
     // execute in order, so the next node's reads always see this node's
     // writes.
-    int n = ngrp;
-    NodePrep<R, K2> h;
-    if (n < nb) prep(h, n);
-    for (; n < nb; n += NODE_GROUPS) {
-      const int nn = n + NODE_GROUPS;
-      if constexpr (D == 1) {
-        if (k < K2) add1(h.l0 + 1 + k, h.vx, h.vy);
-        if (h.e0 && k == 0) add1(h.l0, h.cx * edge, h.cy * edge);
-        if (nn < nb) prep(h, nn);
-      } else {
+    if constexpr (PRIV && D == 2) {
+      // two headers in turn, so the next node's window is prepared into the
+      // other one and nothing is copied between trips
+      auto step = [&](const NodePrep<R, K2>& h, NodePrep<R, K2>& hn, int nn) {
         const int col = h.l1 + 1 + k;
-        if constexpr (PRIV) {
-          NodePrep<R, K2> hn;
-          if constexpr (CS) {
-            float* t = ptile + (h.l0 + 1) * P + col;
-            float cur[K2];
-            if (k < K2) {
+        if constexpr (CS) {
+          float* t = ptile + (h.l0 + 1) * P + col;
+          float cur[K2];
+          if (k < K2) {
 #pragma unroll
-              for (int i = 0; i < K2; ++i) cur[i] = t[i * P];
+            for (int i = 0; i < K2; ++i) cur[i] = t[i * P];
+          }
+          if (nn < nb) prep(hn, nn);
+          if (k < K2) {
+#pragma unroll
+            for (int i = 0; i < K2; ++i) cur[i] += h.vx * h.rw[i];
+#pragma unroll
+            for (int i = 0; i < K2; ++i) t[i * P] = cur[i];
+          }
+        } else {
+          float2* t = acc.tile + (h.l0 + 1) * P + col;
+          float2 cur[K2];
+          if (k < K2) {
+#pragma unroll
+            for (int i = 0; i < K2; ++i) cur[i] = t[i * P];
+          }
+          if (nn < nb) prep(hn, nn);
+          if (k < K2) {
+#pragma unroll
+            for (int i = 0; i < K2; ++i) {
+              cur[i].x += h.vx * h.rw[i];
+              cur[i].y += h.vy * h.rw[i];
             }
-            if (nn < nb) prep(hn, nn);
-            if (k < K2) {
 #pragma unroll
-              for (int i = 0; i < K2; ++i) cur[i] += h.vx * h.rw[i];
+            for (int i = 0; i < K2; ++i) t[i * P] = cur[i];
+          }
+        }
+        if (h.e0 | h.e1) {
+          // closed-edge cells of a node on a grid line: row 0 and column 0
+          if (h.e0 && k < K2) add1(h.l0 * P + col, h.vx * edge, h.vy * edge);
+          if (h.e1 && k < K2)
+            add1((h.l0 + 1 + k) * P + h.l1, h.cx * h.p0 * edge, h.cy * h.p0 * edge);
+          if (h.e0 && h.e1 && k == 0) add1(h.l0 * P + h.l1, h.cx * edge * edge, h.cy * edge * edge);
+        }
+      };
+      NodePrep<R, K2> h0, h1;
+      int n = ngrp;
+      if (n < nb) prep(h0, n);
+      while (n < nb) {
+        step(h0, h1, n + NODE_GROUPS);
+        n += NODE_GROUPS;
+        if (n >= nb) break;
+        step(h1, h0, n + NODE_GROUPS);
+        n += NODE_GROUPS;
+      }
+    } else {
+      // d = 1, and float64 (shared tile, atomics): the next header is
+      // prepared into the same registers after this node's updates
+      int n = ngrp;
+      NodePrep<R, K2> h;
+      if (n < nb) prep(h, n);
+      for (; n < nb; n += NODE_GROUPS) {
+        const int nn = n + NODE_GROUPS;
+        if constexpr (D == 1) {
+          if (k < K2) add1(h.l0 + 1 + k, h.vx, h.vy);
+          if (h.e0 && k == 0) add1(h.l0, h.cx * edge, h.cy * edge);
+        } else {
+          const int col = h.l1 + 1 + k;
+          if (k < K2) {
 #pragma unroll
-              for (int i = 0; i < K2; ++i) t[i * P] = cur[i];
-            }
-          } else {
-            float2* t = acc.tile + (h.l0 + 1) * P + col;
-            float2 cur[K2];
-            if (k < K2) {
-#pragma unroll
-              for (int i = 0; i < K2; ++i) cur[i] = t[i * P];
-            }
-            if (nn < nb) prep(hn, nn);
-            if (k < K2) {
-#pragma unroll
-              for (int i = 0; i < K2; ++i) {
-                cur[i].x += h.vx * h.rw[i];
-                cur[i].y += h.vy * h.rw[i];
-              }
-#pragma unroll
-              for (int i = 0; i < K2; ++i) t[i * P] = cur[i];
-            }
+            for (int i = 0; i < K2; ++i) add1((h.l0 + 1 + i) * P + col, h.vx * h.rw[i], h.vy * h.rw[i]);
           }
           if (h.e0 | h.e1) {
-            // closed-edge cells of a node on a grid line: row 0 and column 0
             if (h.e0 && k < K2) add1(h.l0 * P + col, h.vx * edge, h.vy * edge);
             if (h.e1 && k < K2)
               add1((h.l0 + 1 + k) * P + h.l1, h.cx * h.p0 * edge, h.cy * h.p0 * edge);
             if (h.e0 && h.e1 && k == 0) add1(h.l0 * P + h.l1, h.cx * edge * edge, h.cy * edge * edge);
           }
-          h = hn;
-        } else {
-          if (k < K2) {
-#pragma unroll
-            for (int i = 0; i < K2; ++i) acc.add((h.l0 + 1 + i) * P + col, h.vx * h.rw[i], h.vy * h.rw[i]);
-          }
-          if (h.e0 | h.e1) {
-            if (h.e0 && k < K2) acc.add(h.l0 * P + col, h.vx * edge, h.vy * edge);
-            if (h.e1 && k < K2)
-              acc.add((h.l0 + 1 + k) * P + h.l1, h.cx * h.p0 * edge, h.cy * h.p0 * edge);
-            if (h.e0 && h.e1 && k == 0) acc.add(h.l0 * P + h.l1, h.cx * edge * edge, h.cy * edge * edge);
-          }
-          if (nn < nb) prep(h, nn);
         }
+        if (nn < nb) prep(h, nn);
       }
     }
     __syncthreads();

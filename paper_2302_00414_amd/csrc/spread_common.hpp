@@ -37,11 +37,12 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-// Value of lane I of this lane's 16-lane row.
+// Value of lane I of this lane's 16-lane row (DPP row broadcast; every lane
+// of the row reads an existing lane, so no lane keeps an old value and the
+// move writes a fresh register).
 template <int I>
 __device__ __forceinline__ float row_bcast(float v) {
-  const int b = __float_as_int(v);
-  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x150 + I, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + I, 0xf, 0xf, false));
 }
 template <int I>
 __device__ __forceinline__ double row_bcast(double v) {
