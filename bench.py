@@ -118,6 +118,56 @@ def run_gpu(prec, x, w, f, steps, warmup, tuning="auto"):
                 lat=np.array(lat), out=res, info=info, tuning=tuning)
 
 
+def run_forward(prec, x, steps):
+    """Forward NFFT f = B F D fhat (Algorithm 2.1) on the same plan shape:
+    milliseconds per call and per stage."""
+    import torch
+    from paper_2302_00414_amd import workloads as wl
+    from paper_2302_00414_amd.nfft import Plan
+
+    cdt = torch.complex64 if prec == "f32" else torch.complex128
+    plan = Plan(x, M, SIGMA, MW, precision=prec, tuning="auto")
+    fh = torch.from_numpy(wl.complex_normal(M ** D, 7)).to("cuda", cdt)
+    out = torch.empty(x.shape[0], dtype=cdt, device="cuda")
+    for _ in range(5):
+        plan.forward(fh, out=out)
+    torch.cuda.synchronize()
+    plan.stage_times(reset=True)
+    plan.set_profiling(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.forward(fh, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    plan.set_profiling(False)
+    st = plan.stage_times(reset=True)
+    plan.close()
+    ms = e0.elapsed_time(e1) / steps
+    return dict(ms_per_call=ms, points_per_s=x.shape[0] / (ms / 1e3),
+                stage_us={k: round(v[0] / max(v[1], 1) * 1e3, 3) for k, v in st.items() if v[1]})
+
+
+def run_weights():
+    """Algorithm 3.6 on the GPU (float64 CG with the library NFFT at 2M):
+    d = 2, M = 32, N = 16384 uniform nodes (the setting of Example 5.2,
+    |I_2M| = 4096 < N, branch (3.15))."""
+    import torch
+    from paper_2302_00414_amd import workloads as wl
+    from paper_2302_00414_amd.nfft import compute_weights
+
+    x = wl.uniform_nodes(16384, 2, 11)
+    compute_weights(x, 32, 2.0, 8)  # warm-up (plan kernels, first launches)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w, info = compute_weights(x, 32, 2.0, 8)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dict(workload="d=2, M=32, N=16384 uniform (Example 5.2 setting), m=8, tol 1e-13",
+                seconds=dt, **info)
+
+
 def run_batched(steps):
     """Spiral trajectory, N = 131072, 32 right-hand sides, M = 256, m = 6: one
     fused float32 adjoint of all 32 against 32 float64 single calls."""
@@ -326,6 +376,9 @@ def main():
     }
     if not args.no_batched:
         line["batched"] = run_batched(max(10, min(args.steps // 10, 100)))
+        line["forward"] = {"f32": run_forward("f32", x, max(10, args.steps // 5)),
+                           "f64": run_forward("f64", x, max(10, args.steps // 5))}
+        line["weights_gpu"] = run_weights()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(x, w, f, r32["out"], r64["out"])
         line["cpu_baseline"] = cb["baseline"]

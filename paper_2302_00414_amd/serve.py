@@ -49,6 +49,7 @@ class Request:
     future: cf.Future = field(default_factory=cf.Future)
     t_start: float = 0.0
     t_done: float = 0.0
+    batch: int = -1             # index of the batch that ran it
 
 
 @dataclass
@@ -82,13 +83,14 @@ class ServerError(RuntimeError):
 class DeviceExecutor:
     """HIP library on one device; one PyTorch stream per slot."""
 
-    def __init__(self, device: str = "cuda:0", precision: str = "f32"):
+    def __init__(self, device: str = "cuda:0", precision: str = "f32", tuning=None):
         import torch
         from . import nfft as _nfft
         self.torch = torch
         self.nfft = _nfft
         self.device = torch.device(device)
         self.precision = precision
+        self.tuning = tuning  # None (library defaults), a dict, or "auto" (timed per node set)
         self.cdtype = torch.complex64 if precision == "f32" else torch.complex128
         self.streams: Dict[int, Any] = {}
 
@@ -100,7 +102,7 @@ class DeviceExecutor:
 
     def create(self, nodes, M, sigma, m, weights):
         plan = self.nfft.Plan(nodes, M, sigma, m, precision=self.precision, max_rhs=1,
-                              device=self.device)
+                              device=self.device, tuning=self.tuning)
         plan.set_weights(weights)
         info = plan.info()
         return plan, info["bytes"]
@@ -195,10 +197,11 @@ class Server:
     """
 
     def __init__(self, hbm_budget: int, max_slots: int = 4, max_batch_rhs: int = 16,
-                 executor=None, poll_s: float = 20e-6):
+                 executor=None, poll_s: float = 20e-6, batching: bool = True):
         self.budget = int(hbm_budget)
         self.max_slots = max_slots
         self.max_batch_rhs = max_batch_rhs
+        self.batching = batching  # False: every request is a batch of its own
         self.ex = executor if executor is not None else DeviceExecutor()
         self.poll_s = poll_s
         self.sets: Dict[Any, NodeSet] = {}
@@ -329,6 +332,8 @@ class Server:
                 if r.key == head.key and rhs + r.nrhs <= self.max_batch_rhs:
                     group.append(r)
                     rhs += r.nrhs
+                    if not self.batching:
+                        break
             io = self.ex.io_bytes(ns.N, ns.M, ns.d, rhs)
             if self.used + io > self.budget:
                 break
@@ -349,6 +354,7 @@ class Server:
             t = time.perf_counter()
             for r in group:
                 r.t_start = t
+                r.batch = self.batches
             token = self.ex.launch(ws, group, slot)
             self.batches += 1
             self.used += io
@@ -391,7 +397,7 @@ class Server:
         return dict(requests=len(done), p50_ms=float(np.percentile(lat, 50)),
                     p99_ms=float(np.percentile(lat, 99)), mean_ms=float(lat.mean()),
                     points_per_s=pts / span if span > 0 else float("nan"),
-                    rejected=self.rejected, batches=self.batches)
+                    rejected=self.rejected, batches=len({r.batch for r in done}))
 
 
 # -------------------------------------------------------------- workload
@@ -428,14 +434,26 @@ def main():
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--budget-gib", type=float, default=32.0)
     ap.add_argument("--m", type=int, default=6)
+    ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--max-batch-rhs", type=int, default=16,
+                    help="right-hand sides one batch may gather")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="every request runs as a batch of its own")
+    ap.add_argument("--tuning", choices=["default", "auto"], default="default",
+                    help="auto: the library autotuner picks each node set's tuning")
     args = ap.parse_args()
     rng = np.random.default_rng(1)
-    srv = Server(int(args.budget_gib * (1 << 30)), max_slots=args.slots, max_batch_rhs=16).start()
+    ex = DeviceExecutor(precision=args.precision,
+                        tuning="auto" if args.tuning == "auto" else None)
+    srv = Server(int(args.budget_gib * (1 << 30)), max_slots=args.slots,
+                 max_batch_rhs=args.max_batch_rhs, executor=ex,
+                 batching=not args.no_batching).start()
     sets = make_served_stream(args.sets_per_M, tuple(args.Ms))
     for s in sets:
         srv.register(s["key"], s["nodes"], s["M"], 2.0, args.m, s["weights"])
     dev = torch.device("cuda:0")
-    pools = {s["key"]: torch.randn(16, s["nodes"].shape[0], dtype=torch.complex64, device=dev)
+    cdt = torch.complex64 if args.precision == "f32" else torch.complex128
+    pools = {s["key"]: torch.randn(16, s["nodes"].shape[0], dtype=cdt, device=dev)
              for s in sets}
     keys = [s["key"] for s in sets]
     out = []
@@ -447,14 +465,24 @@ def main():
         t_next = t0
         for i in range(n):
             t_next += gaps[i]
-            while time.perf_counter() < t_next:
-                pass
+            # sleep (releasing the interpreter lock for the scheduler thread)
+            # until shortly before the arrival time, then spin
+            while True:
+                left = t_next - time.perf_counter()
+                if left <= 0:
+                    break
+                if left > 3e-4:
+                    time.sleep(left - 2e-4)
             key = keys[rng.integers(len(keys))]
             nrhs = int(rng.integers(1, 17))
             srv.submit(key, pools[key][:nrhs])
         srv.drain()
         st = srv.stats(mark)
         st["qps"] = qps
+        st["precision"] = args.precision
+        st["max_batch_rhs"] = args.max_batch_rhs
+        st["batching"] = not args.no_batching
+        st["slots"] = args.slots
         out.append(st)
         print(json.dumps(st), flush=True)
     srv.close()

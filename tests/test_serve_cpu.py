@@ -133,3 +133,16 @@ def test_unknown_node_set_and_oversized_request():
         srv.submit("zz", None, nrhs=1)
     with pytest.raises(ServerError):
         srv.submit("a", None, nrhs=5)
+
+
+def test_no_batching_runs_each_request_alone():
+    srv, ex = _server(slots=1, max_rhs=16, duration=lambda N, r: 0.02)
+    srv = Server(10**9, max_slots=1, max_batch_rhs=16, executor=ex, batching=False)
+    srv.register("a", _nodes(100), 8, 2.0, 4, None)
+    srv.start()
+    futs = [srv.submit("a", None, nrhs=2) for _ in range(6)]
+    for fu in futs:
+        fu.result(timeout=5)
+    srv.drain()
+    assert srv.batches == 6
+    srv.close()
