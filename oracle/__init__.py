@@ -18,10 +18,13 @@ Levels (Kircheis & Potts, arXiv 2302.00414):
 * ``weights`` -- O3, Algorithm 3.6: density-compensation factors from the
                  augmented system (3.14) on I_2M, via the normal equations
                  (3.15) (underdetermined) or (3.16) (overdetermined).
+* ``bopt``    -- O4, the optimized sparse matrix B_opt of Algorithm 4.3
+                 (column-wise least squares with (4.13)/(4.14)) and the
+                 reconstruction D^* F^* B_opt^* f of Algorithm 4.4.
 * ``window``  -- the Kaiser-Bessel window pair (phi, phi_hat) used by O2.
 * ``metrics`` -- the relative errors (5.6).
 
 Everything is float64 / complex128. Every function is pinned by CPU tests
 against closed forms, invariants, hand-derived values or brute force.
 """
-from . import window, ndft, nfft, weights, metrics  # noqa: F401
+from . import window, ndft, nfft, weights, bopt, metrics  # noqa: F401
