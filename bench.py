@@ -168,6 +168,40 @@ def run_weights():
                 seconds=dt, **info)
 
 
+def run_bopt(steps):
+    """Optimized sparse matrix (Algorithms 4.3 / 4.4): jittered 384 x 384 grid
+    (N = 147456), d = 2, M = 256, sigma = 2, m = 4, float32 plan. Times the
+    float64 device precompute of B_opt and the reconstruction D^* F^* B_opt^* f."""
+    import torch
+    from paper_2302_00414_amd import workloads as wl
+    from paper_2302_00414_amd.nfft import Plan
+
+    x = wl.jittered_nodes((384, 384), 12)
+    N = x.shape[0]
+    plan = Plan(x, M, SIGMA, 4, precision="f32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = plan.build_bopt(x)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    f = torch.from_numpy(wl.complex_normal(N, 13)).to("cuda", torch.complex64)
+    out = torch.empty(M * M, dtype=torch.complex64, device="cuda")
+    for _ in range(5):
+        plan.bopt_adjoint(f, out=out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.bopt_adjoint(f, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    plan.close()
+    return dict(workload="jittered 384x384 (N=147456), d=2, M=256, sigma=2, m=4, float32",
+                build_s=t_build, ms_per_reconstruction=ms, points_per_s=N / (ms / 1e3), **info)
+
+
 def run_batched(steps):
     """Spiral trajectory, N = 131072, 32 right-hand sides, M = 256, m = 6: one
     fused float32 adjoint of all 32 against 32 float64 single calls."""
@@ -379,6 +413,7 @@ def main():
         line["forward"] = {"f32": run_forward("f32", x, max(10, args.steps // 5)),
                            "f64": run_forward("f64", x, max(10, args.steps // 5))}
         line["weights_gpu"] = run_weights()
+        line["bopt"] = run_bopt(max(10, args.steps // 5))
     if not args.no_cpu_baseline:
         cb = cpu_baseline(x, w, f, r32["out"], r64["out"])
         line["cpu_baseline"] = cb["baseline"]

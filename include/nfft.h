@@ -240,6 +240,43 @@ int nfft_forward(nfft_plan_t plan, const void *fhat, void *f, int nrhs, void *st
 int nfft_weights(int d, int M, double sigma, int m, int64_t N, const double *nodes, double tol,
                  int maxit, void *w, double *info, void *stream);
 
+/*
+ * Optimized sparse matrix (Section 4): Algorithm 4.3 on the device in float64
+ * and the reconstruction of Algorithm 4.4, h_opt = D^* F^* B_opt^* f
+ * (eq. (4.12)), a modified adjoint NFFT that needs no weights.
+ *
+ * nfft_bopt_build -- compute B_opt for the plan's node set and keep it with
+ * the plan (shared with its clones). B_opt is real and has the nonzero
+ * pattern of B (2.15): grid column l holds the nodes whose closed window
+ * support reaches l periodically. Its values minimise
+ * ||H_l b - |I_Ms|^{-1} D^{-1} f_l||_2 over real b (H_l of (4.11)), i.e.
+ * solve Re(H_l^* H_l) b = Re(v_l) with (4.13) and (4.14); the values are kept
+ * in the plan's precision. A node whose Cholesky pivot falls below 1e-13
+ * |I_M| (a duplicate, or numerically dependent) gets the value zero.
+ *   nodes  the plan's nodes again, N*d float64 (host or device), same order
+ *   info   host, 3 doubles, or NULL: largest column set, number of nonzeros,
+ *          number of columns with a dropped node
+ * NFFT_EUNSUPPORTED if some column holds more nodes than one work-group's
+ * LDS can factor (about 190); NFFT_ESTATE if already built. Synchronises
+ * `stream`.
+ */
+int nfft_bopt_build(nfft_plan_t plan, const double *nodes, double *info, void *stream);
+
+/*
+ * nfft_bopt_adjoint -- h_opt = D^* F^* B_opt^* f for nrhs right-hand sides
+ * (Algorithm 4.4 step 1); f and fhat as for nfft_adjoint. NFFT_ESTATE before
+ * nfft_bopt_build.
+ */
+int nfft_bopt_adjoint(nfft_plan_t plan, const void *f, void *fhat, int nrhs, void *stream);
+
+/*
+ * nfft_bopt_get -- copy B_opt to host memory by grid columns (C order of
+ * s_t = l_t + M_sigma/2): nnz receives the number of nonzeros; col_ptr
+ * (M_sigma^d + 1 entries), nodes and vals (nnz entries each, vals as float64)
+ * are filled where not NULL. Synchronous.
+ */
+int nfft_bopt_get(nfft_plan_t plan, int64_t *nnz, int64_t *col_ptr, int32_t *nodes, double *vals);
+
 /* nfft_destroy -- wait for the plan's outstanding work and free it. NULL is a no-op. */
 int nfft_destroy(nfft_plan_t plan);
 

@@ -61,6 +61,13 @@ struct SharedData {
   std::vector<void*> allocs;
   int64_t bytes = 0;
   bool has_weights = false;
+  // optimized sparse matrix (Algorithm 4.3), by grid columns
+  bool has_bopt = false;
+  int64_t* bopt_ptr = nullptr;    // column starts, M_sigma^d + 1
+  int32_t* bopt_node = nullptr;   // node ids (caller order), by column
+  void* bopt_val = nullptr;       // values (plan precision), by column
+  int64_t bopt_nnz = 0;
+  int bopt_nmax = 0;
   ~SharedData() {
     for (void* q : allocs) (void)hipFree(q);
   }
@@ -357,7 +364,9 @@ int build_tables(nfft_plan_t p) {
   for (int kidx = 0; kidx < M; ++kidx) {
     const int k = kidx - M / 2;
     const long double a = 2.0L * 3.14159265358979323846264338327950288L * k / Ms;
-    const long double arg = (long double)m * std::sqrt(b * b - a * a);
+    // at sigma = 1 and k = -M/2 the radicand is zero up to rounding (b = pi
+    // was formed in double precision): clamp it
+    const long double arg = (long double)m * std::sqrt(std::max(b * b - a * a, 0.0L));
     const long double val = std::exp(b * m) /
                             (3.14159265358979323846264338327950288L * bessel_i0(arg));
     fac[kidx] = (R)((k % 2 == 0) ? val : -val);
@@ -633,6 +642,42 @@ int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t 
   }
   record(p, se, s);
   if (p->profiling && se.n > 0) p->pending.push_back(se);
+  return NFFT_OK;
+}
+
+// Algorithm 4.4 step 1: h_opt = D^* F^* B_opt^* f. The grid of B_opt^* f is
+// formed by columns (no tiles), then the FFT passes of the adjoint NFFT run
+// with their first pass reading that grid.
+template <typename R>
+int run_bopt_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t s) {
+  const int64_t Ms = p->Ms, M = p->M;
+  const int64_t ncols = ipow(Ms, p->d);
+  SharedData& sd = *p->shared;
+  // the deconvolution table divides by the window scaled by pi e^{-b m} in
+  // every dimension
+  const double scale = std::pow(M_PI * std::exp(-p->b * p->m), p->d);
+  HIP_TRY(p, nfft::launch_bopt_apply<R>(sd.bopt_ptr, sd.bopt_node, (const R*)sd.bopt_val,
+                                        (const cplx<R>*)f, p->N, (cplx<R>*)p->grid, ncols,
+                                        ncols, nrhs, scale, s));
+  const int L = (int)Ms;
+  const auto ld = nfft::kLoadLine;
+  const auto st = nfft::kStoreCropScaled;
+  if (p->d == 1) {
+    auto a = fft_args<R>(p, 1, p->grid, Ms, L, fhat, M);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, ld, st, nrhs, s));
+  } else if (p->d == 2) {
+    auto a = fft_args<R>(p, Ms, p->grid, Ms * Ms, L, p->bufA, M * Ms);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, ld, st, nrhs, s));
+    auto c = fft_args<R>(p, M, p->bufA, M * Ms, L, fhat, M * M);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, false, ld, st, nrhs, s));
+  } else {
+    auto a = fft_args<R>(p, Ms * Ms, p->grid, Ms * Ms * Ms, L, p->bufA, M * Ms * Ms);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, ld, st, nrhs, s));
+    auto c = fft_args<R>(p, M * Ms, p->bufA, M * Ms * Ms, L, p->bufB, M * M * Ms);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, false, ld, st, nrhs, s));
+    auto e = fft_args<R>(p, M * M, p->bufB, M * M * Ms, L, fhat, M * M * M);
+    HIP_TRY(p, nfft::launch_fft_pass<R>(e, L, false, ld, st, nrhs, s));
+  }
   return NFFT_OK;
 }
 
@@ -1091,6 +1136,128 @@ int nfft_weights(int d, int M, double sigma, int m, int64_t N, const double* nod
     info[1] = nb > 0 ? std::sqrt(rr) / nb : 0.0;
     info[2] = b15 ? 15 : 16;
     info[3] = eps;
+  }
+  return NFFT_OK;
+}
+
+int nfft_bopt_build(nfft_plan_t p, const double* nodes, double* info, void* stream) {
+  if (!p) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
+  if (!nodes) return fail(p, NFFT_EINVAL, "nodes is NULL");
+  SharedData& sd = *p->shared;
+  if (sd.has_bopt) return fail(p, NFFT_ESTATE, "B_opt is already built for this node set");
+  hipStream_t s = (hipStream_t)stream;
+  const int d = p->d, Ms = p->Ms, M = p->M, m = p->m;
+  const int64_t N = p->N;
+  const int64_t ncols = ipow(Ms, d);
+  ScopedFree tmp;
+  auto talloc = [&](void** q, size_t bytes) -> int {
+    if (hipMalloc(q, bytes ? bytes : 16) != hipSuccess)
+      return fail(p, NFFT_ENOMEM, "hipMalloc(%zu) failed", bytes);
+    tmp.ptrs.push_back(*q);
+    return NFFT_OK;
+  };
+  void *d_nodes, *count, *fill, *wh, *dropped;
+  TRY(talloc(&d_nodes, N * d * sizeof(double)));
+  TRY(talloc(&count, ncols * sizeof(int)));
+  TRY(talloc(&fill, ncols * sizeof(int)));
+  TRY(talloc(&wh, M * sizeof(double)));
+  TRY(talloc(&dropped, sizeof(int)));
+  HIP_TRY(p, hipMemcpyAsync(d_nodes, nodes, N * d * sizeof(double), hipMemcpyDefault, s));
+  HIP_TRY(p, hipMemsetAsync(count, 0, ncols * sizeof(int), s));
+  HIP_TRY(p, hipMemsetAsync(fill, 0, ncols * sizeof(int), s));
+  HIP_TRY(p, hipMemsetAsync(dropped, 0, sizeof(int), s));
+  HIP_TRY(p, nfft::launch_bopt_pattern((const double*)d_nodes, N, d, Ms, m, 0, (int*)count,
+                                       nullptr, nullptr, nullptr, s));
+  std::vector<int> hc(ncols);
+  HIP_TRY(p, hipMemcpyAsync(hc.data(), count, ncols * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipStreamSynchronize(s));
+  std::vector<int64_t> hp(ncols + 1, 0);
+  int nmax = 0;
+  for (int64_t c = 0; c < ncols; ++c) {
+    hp[c + 1] = hp[c] + hc[c];
+    nmax = std::max(nmax, hc[c]);
+  }
+  // the packed Gram matrix of the largest column must fit in LDS
+  if (nfft::bopt_solve_lds(nmax) > kMaxLds)
+    return fail(p, NFFT_EUNSUPPORTED,
+                "a grid column is reached by %d nodes; the column solve holds at most %d in LDS",
+                nmax, [] {
+                  int n = 1;
+                  while (nfft::bopt_solve_lds(n + 1) <= kMaxLds) ++n;
+                  return n;
+                }());
+  const int64_t nnz = hp[ncols];
+  const size_t rb = rbytes(p->prec);
+  TRY(dalloc(p, &sd.bopt_ptr, (ncols + 1) * sizeof(int64_t)));
+  TRY(dalloc(p, &sd.bopt_node, std::max<int64_t>(1, nnz) * sizeof(int32_t)));
+  TRY(dalloc(p, &sd.bopt_val, std::max<int64_t>(1, nnz) * rb));
+  HIP_TRY(p, hipMemcpyAsync(sd.bopt_ptr, hp.data(), (ncols + 1) * sizeof(int64_t),
+                            hipMemcpyHostToDevice, s));
+  HIP_TRY(p, nfft::launch_bopt_pattern((const double*)d_nodes, N, d, Ms, m, 1, nullptr,
+                                       sd.bopt_ptr, (int*)fill, sd.bopt_node, s));
+  // w^(k) = I_0(m sqrt(b^2 - (2 pi k / M_s)^2)) / M_s, k = -M/2 .. M/2-1
+  std::vector<double> hw(M);
+  for (int i = 0; i < M; ++i) {
+    const long double k = (long double)(i - M / 2);
+    const long double arg = (long double)p->b * p->b -
+                            (2.0L * M_PI * k / Ms) * (2.0L * M_PI * k / Ms);
+    hw[i] = (double)(bessel_i0((long double)m * std::sqrt(std::max(arg, 0.0L))) / Ms);
+  }
+  HIP_TRY(p, hipMemcpyAsync(wh, hw.data(), M * sizeof(double), hipMemcpyHostToDevice, s));
+  constexpr double kPivotRel = 1e-13;
+  if (p->prec == NFFT_F64)
+    HIP_TRY(p, nfft::launch_bopt_solve<double>((const double*)d_nodes, d, M, Ms, (const double*)wh,
+                                               sd.bopt_ptr, sd.bopt_node, (double*)sd.bopt_val,
+                                               ncols, std::max(1, nmax), kPivotRel, (int*)dropped, s));
+  else
+    HIP_TRY(p, nfft::launch_bopt_solve<float>((const double*)d_nodes, d, M, Ms, (const double*)wh,
+                                              sd.bopt_ptr, sd.bopt_node, (float*)sd.bopt_val,
+                                              ncols, std::max(1, nmax), kPivotRel, (int*)dropped, s));
+  int hd = 0;
+  HIP_TRY(p, hipMemcpyAsync(&hd, dropped, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipStreamSynchronize(s));
+  sd.has_bopt = true;
+  sd.bopt_nnz = nnz;
+  sd.bopt_nmax = nmax;
+  if (info) {
+    info[0] = nmax;
+    info[1] = (double)nnz;
+    info[2] = hd;
+  }
+  return NFFT_OK;
+}
+
+int nfft_bopt_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, void* stream) {
+  if (!p) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
+  if (!f || !fhat) return fail(p, NFFT_EINVAL, "f or fhat is NULL");
+  if (nrhs < 1 || nrhs > p->max_rhs)
+    return fail(p, NFFT_EINVAL, "nrhs = %d outside 1..max_rhs = %d", nrhs, p->max_rhs);
+  if (!p->shared->has_bopt) return fail(p, NFFT_ESTATE, "nfft_bopt_build has not been called");
+  HIP_TRY(p, hipGetLastError());
+  hipStream_t s = (hipStream_t)stream;
+  return p->prec == NFFT_F64 ? run_bopt_adjoint<double>(p, f, fhat, nrhs, s)
+                             : run_bopt_adjoint<float>(p, f, fhat, nrhs, s);
+}
+
+int nfft_bopt_get(nfft_plan_t p, int64_t* nnz, int64_t* col_ptr, int32_t* nodes, double* vals) {
+  if (!p) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
+  SharedData& sd = *p->shared;
+  if (!sd.has_bopt) return fail(p, NFFT_ESTATE, "nfft_bopt_build has not been called");
+  if (nnz) *nnz = sd.bopt_nnz;
+  const int64_t ncols = ipow(p->Ms, p->d);
+  if (col_ptr)
+    HIP_TRY(p, hipMemcpy(col_ptr, sd.bopt_ptr, (ncols + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (nodes)
+    HIP_TRY(p, hipMemcpy(nodes, sd.bopt_node, sd.bopt_nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (vals) {
+    if (p->prec == NFFT_F64) {
+      HIP_TRY(p, hipMemcpy(vals, sd.bopt_val, sd.bopt_nnz * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+      std::vector<float> tmpv(sd.bopt_nnz);
+      HIP_TRY(p, hipMemcpy(tmpv.data(), sd.bopt_val, sd.bopt_nnz * sizeof(float),
+                           hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < sd.bopt_nnz; ++i) vals[i] = tmpv[i];
+    }
   }
   return NFFT_OK;
 }

@@ -1,0 +1,314 @@
+// Optimized sparse matrix B_opt (Algorithm 4.3) and its adjoint spreading
+// (Algorithm 4.4 step 1, B_opt^* f), float64 precompute.
+//
+// B_opt has the nonzero pattern of B: column l (a cell of the oversampled
+// grid, numbered in C order of s_t = l_t + M_s/2) holds the nodes whose
+// closed window support reaches l periodically. Per column the values
+// minimise ||H_l b - |I_Ms|^{-1} D^{-1} f_l||_2 over real b, i.e. solve the
+// real normal equations Re(H_l^* H_l) b = Re(v_l) with
+//   [H_l^* H_l]_{hj} = prod_t (D_{M/2-1}(x_ht - x_jt) + e^{-M pi i (x_ht - x_jt)})   (4.13),
+//   v_j = prod_t sum_{k=-M/2}^{M/2-1} w^(k) e^{2 pi i k (x_jt - l_t/M_s)}            (4.14),
+// D_{M/2-1}(s) = sin((M-1) pi s)/sin(pi s). One work-group per column builds
+// the packed lower triangle of the Gram matrix in LDS, factors it by Cholesky
+// (a pivot below a relative threshold marks a dependent node, which gets the
+// value zero: duplicate nodes share nothing, the residual is unchanged) and
+// solves by forward and back substitution.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.hpp"
+
+namespace nfft {
+
+namespace {
+
+__device__ __forceinline__ double wrap_half(double x) {
+  double y = x - floor(x + 0.5);
+  return y >= 0.5 ? y - 1.0 : y;
+}
+
+// Each node visits the (2m+1)^d candidate cells of its closed support; op 0
+// counts nodes per column, op 1 writes node ids at col_ptr[c] + fill[c]++.
+__global__ void bopt_pattern_kernel(const double* __restrict__ nodes, int64_t N, int d, int Ms,
+                                    int m, int op, int* __restrict__ count,
+                                    const int64_t* __restrict__ col_ptr,
+                                    int* __restrict__ fill, int32_t* __restrict__ col_node) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  double u[3];
+  int lo[3];
+  for (int t = 0; t < d; ++t) {
+    u[t] = wrap_half(nodes[j * d + t]) * Ms + 0.5 * Ms;
+    lo[t] = (int)ceil(u[t] - m);
+  }
+  const int K = 2 * m + 1;
+  int total = 1;
+  for (int t = 0; t < d; ++t) total *= K;
+  for (int q = 0; q < total; ++q) {
+    int rem = q;
+    int64_t c = 0;
+    bool ok = true;
+    for (int t = 0; t < d; ++t) {
+      const int o = rem % K;
+      rem /= K;
+      const int l = lo[t] + o;
+      ok = ok && fabs(u[t] - (double)l) <= (double)m;
+      c = c * Ms + (int64_t)(((l % Ms) + Ms) % Ms);
+    }
+    if (!ok) continue;
+    if (op == 0) {
+      atomicAdd(count + c, 1);
+    } else {
+      const int pos = atomicAdd(fill + c, 1);
+      col_node[col_ptr[c] + pos] = (int32_t)j;
+    }
+  }
+}
+
+// sum_{k=-M/2}^{M/2-1} w^(k) e^{2 pi i k s} for an even table w^ (entry
+// k + M/2): the cosine series by Clenshaw's recurrence plus the unpaired
+// term k = -M/2
+__device__ __forceinline__ void window_series(const double* __restrict__ wh, int M, double s,
+                                              double* re, double* im) {
+  const int H = M / 2;
+  double c, sn;
+  sincospi(2.0 * s, &sn, &c);
+  double b1 = 0.0, b2 = 0.0;
+  for (int k = H - 1; k >= 1; --k) {
+    const double b0 = 2.0 * wh[H + k] + 2.0 * c * b1 - b2;
+    b2 = b1;
+    b1 = b0;
+  }
+  // sum_{k=1}^{H-1} 2 w^(k) cos(2 pi k s) = b1 cos - b2 (with a_0 = 0)
+  double cm, sm;
+  sincospi((double)M * s, &sm, &cm);
+  *re = wh[H] + b1 * c - b2 + wh[0] * cm;
+  *im = -wh[0] * sm;
+}
+
+__device__ __forceinline__ void dirichlet_term(int M, double s, double* re, double* im) {
+  double sn, cs;
+  sincospi(s, &sn, &cs);
+  double dk;
+  if (fabs(sn) < 1e-12) {
+    double s2, c2;
+    sincospi((double)(M - 1) * s, &s2, &c2);
+    dk = (double)(M - 1) * c2 / cs;
+  } else {
+    double s2, c2;
+    sincospi((double)(M - 1) * s, &s2, &c2);
+    dk = s2 / sn;
+  }
+  double sm, cm;
+  sincospi((double)M * s, &sm, &cm);
+  *re = dk + cm;
+  *im = -sm;
+}
+
+__device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // i >= j
+
+template <typename R>
+__global__ __launch_bounds__(256) void bopt_solve_kernel(
+    const double* __restrict__ nodes, int d, int M, int Ms, const double* __restrict__ wh,
+    const int64_t* __restrict__ col_ptr, int32_t* __restrict__ col_node, R* __restrict__ col_val,
+    int nmax, double piv_rel, int* __restrict__ dropped) {
+  extern __shared__ double sm[];
+  const int64_t c = blockIdx.x;
+  const int64_t start = col_ptr[c];
+  const int n = (int)(col_ptr[c + 1] - start);
+  if (n == 0) return;
+  const int tid = threadIdx.x;
+  const int NT = blockDim.x;
+  double* A = sm;                                     // packed lower triangle, n(n+1)/2
+  double* xs = A + (size_t)nmax * (nmax + 1) / 2;     // n x d coordinates
+  double* v = xs + (size_t)nmax * 3;                  // right side, then solution
+  int* ids = reinterpret_cast<int*>(v + nmax);        // sorted node ids
+  int* idr = ids + nmax;                              // unsorted
+  __shared__ int ndrop;
+  if (tid == 0) ndrop = 0;
+  for (int i = tid; i < n; i += NT) idr[i] = col_node[start + i];
+  __syncthreads();
+  // rank sort (ids are distinct): deterministic order by node id
+  for (int i = tid; i < n; i += NT) {
+    const int me = idr[i];
+    int r = 0;
+    for (int q = 0; q < n; ++q) r += idr[q] < me;
+    ids[r] = me;
+  }
+  __syncthreads();
+  // grid index of this column: l_t = s_t - M_s/2
+  int64_t cc = c;
+  double lt[3] = {0, 0, 0};
+  for (int t = d - 1; t >= 0; --t) {
+    lt[t] = (double)(cc % Ms) - 0.5 * Ms;
+    cc /= Ms;
+  }
+  for (int i = tid; i < n; i += NT)
+    for (int t = 0; t < d; ++t) xs[i * 3 + t] = wrap_half(nodes[(int64_t)ids[i] * d + t]);
+  __syncthreads();
+  // right side (4.14), real part
+  for (int i = tid; i < n; i += NT) {
+    double pr = 1.0, pi = 0.0;
+    for (int t = 0; t < d; ++t) {
+      double re, im;
+      window_series(wh, M, xs[i * 3 + t] - lt[t] / Ms, &re, &im);
+      const double nr = pr * re - pi * im;
+      pi = pr * im + pi * re;
+      pr = nr;
+    }
+    v[i] = pr;
+  }
+  // Gram matrix (4.13), real part, lower triangle
+  const int npairs = n * (n + 1) / 2;
+  for (int q = tid; q < npairs; q += NT) {
+    int i = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+    while (tri(i, 0) > q) --i;
+    while (tri(i + 1, 0) <= q) ++i;
+    const int j = q - tri(i, 0);
+    double pr = 1.0, pi = 0.0;
+    for (int t = 0; t < d; ++t) {
+      double re, im;
+      dirichlet_term(M, xs[i * 3 + t] - xs[j * 3 + t], &re, &im);
+      const double nr = pr * re - pi * im;
+      pi = pr * im + pi * re;
+      pr = nr;
+    }
+    A[q] = pr;
+  }
+  __syncthreads();
+  // Cholesky, right-looking; a pivot below piv_rel * |I_M| (the diagonal of
+  // H^* H) drops the node: its column of L is zero and its value is zero
+  double tol = piv_rel;
+  for (int t = 0; t < d; ++t) tol *= (double)M;
+  for (int k = 0; k < n; ++k) {
+    const double akk = A[tri(k, k)];
+    const bool keep = akk > tol;
+    const double lkk = keep ? sqrt(akk) : 0.0;
+    __syncthreads();
+    if (tid == 0) {
+      A[tri(k, k)] = lkk;
+      if (!keep) ++ndrop;
+    }
+    for (int i = k + 1 + tid; i < n; i += NT) A[tri(i, k)] = keep ? A[tri(i, k)] / lkk : 0.0;
+    __syncthreads();
+    if (keep) {
+      const int rest = n - k - 1;
+      const int nup = rest * (rest + 1) / 2;
+      for (int q = tid; q < nup; q += NT) {
+        int i = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+        while (tri(i, 0) > q) --i;
+        while (tri(i + 1, 0) <= q) ++i;
+        const int j = q - tri(i, 0);
+        const int ii = k + 1 + i, jj = k + 1 + j;
+        A[tri(ii, jj)] -= A[tri(ii, k)] * A[tri(jj, k)];
+      }
+    }
+    __syncthreads();
+  }
+  // forward substitution L y = v
+  for (int k = 0; k < n; ++k) {
+    const double lkk = A[tri(k, k)];
+    __syncthreads();
+    if (tid == 0) v[k] = lkk > 0.0 ? v[k] / lkk : 0.0;
+    __syncthreads();
+    const double yk = v[k];
+    for (int i = k + 1 + tid; i < n; i += NT) v[i] -= A[tri(i, k)] * yk;
+    __syncthreads();
+  }
+  // back substitution L^T b = y
+  for (int k = n - 1; k >= 0; --k) {
+    const double lkk = A[tri(k, k)];
+    if (tid == 0) v[k] = lkk > 0.0 ? v[k] / lkk : 0.0;
+    __syncthreads();
+    const double bk = v[k];
+    for (int i = tid; i < k; i += NT) v[i] -= A[tri(k, i)] * bk;
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += NT) {
+    col_node[start + i] = ids[i];
+    col_val[start + i] = (R)v[i];
+  }
+  if (tid == 0 && ndrop) atomicAdd(dropped, 1);
+}
+
+// g_c = scale * sum over the column's nodes of b_cj f_j (one wave per
+// column); scale converts to the units of the library's normalised window,
+// which the deconvolution table of the FFT passes expects
+template <typename R>
+__global__ __launch_bounds__(256) void bopt_apply_kernel(const int64_t* __restrict__ col_ptr,
+                                                         const int32_t* __restrict__ col_node,
+                                                         const R* __restrict__ col_val,
+                                                         const cplx<R>* __restrict__ f,
+                                                         int64_t f_rs, cplx<R>* __restrict__ grid,
+                                                         int64_t g_rs, int64_t ncols, double scale) {
+  const int64_t c = blockIdx.x * (int64_t)(blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= ncols) return;
+  const cplx<R>* fr = f + blockIdx.y * f_rs;
+  double sx = 0.0, sy = 0.0;
+  for (int64_t e = col_ptr[c] + lane; e < col_ptr[c + 1]; e += 64) {
+    const cplx<R> v = fr[col_node[e]];
+    const double b = (double)col_val[e];
+    sx += b * (double)v.x;
+    sy += b * (double)v.y;
+  }
+  for (int w = 32; w > 0; w >>= 1) {
+    sx += __shfl_xor(sx, w);
+    sy += __shfl_xor(sy, w);
+  }
+  if (lane == 0) grid[blockIdx.y * g_rs + c] = mkc<R>((R)(sx * scale), (R)(sy * scale));
+}
+
+unsigned grid1(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_bopt_pattern(const double* nodes, int64_t N, int d, int Ms, int m, int op,
+                               int* count, const int64_t* col_ptr, int* fill, int32_t* col_node,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(bopt_pattern_kernel, dim3(grid1(N, 256)), dim3(256), 0, s, nodes, N, d, Ms, m,
+                     op, count, col_ptr, fill, col_node);
+  return hipGetLastError();
+}
+
+// dynamic LDS of the column solve for columns of up to nmax nodes (plus 64
+// bytes of headroom for the kernel's static LDS)
+size_t bopt_solve_lds(int nmax) {
+  return ((size_t)nmax * (nmax + 1) / 2 + (size_t)nmax * 4) * sizeof(double) +
+         (size_t)2 * nmax * sizeof(int) + 64;
+}
+
+template <typename R>
+hipError_t launch_bopt_solve(const double* nodes, int d, int M, int Ms, const double* wh,
+                             const int64_t* col_ptr, int32_t* col_node, R* col_val, int64_t ncols,
+                             int nmax, double piv_rel, int* dropped, hipStream_t s) {
+  if (ncols == 0) return hipSuccess;
+  hipLaunchKernelGGL(bopt_solve_kernel<R>, dim3((unsigned)ncols), dim3(256), bopt_solve_lds(nmax),
+                     s, nodes, d, M, Ms, wh, col_ptr, col_node, col_val, nmax, piv_rel, dropped);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_bopt_apply(const int64_t* col_ptr, const int32_t* col_node, const R* col_val,
+                             const cplx<R>* f, int64_t f_rs, cplx<R>* grid, int64_t g_rs,
+                             int64_t ncols, int nrhs, double scale, hipStream_t s) {
+  hipLaunchKernelGGL(bopt_apply_kernel<R>, dim3(grid1(ncols, 4), nrhs), dim3(256), 0, s, col_ptr,
+                     col_node, col_val, f, f_rs, grid, g_rs, ncols, scale);
+  return hipGetLastError();
+}
+
+template hipError_t launch_bopt_solve<float>(const double*, int, int, int, const double*,
+                                             const int64_t*, int32_t*, float*, int64_t, int,
+                                             double, int*, hipStream_t);
+template hipError_t launch_bopt_solve<double>(const double*, int, int, int, const double*,
+                                              const int64_t*, int32_t*, double*, int64_t, int,
+                                              double, int*, hipStream_t);
+template hipError_t launch_bopt_apply<float>(const int64_t*, const int32_t*, const float*,
+                                             const cplx<float>*, int64_t, cplx<float>*, int64_t,
+                                             int64_t, int, double, hipStream_t);
+template hipError_t launch_bopt_apply<double>(const int64_t*, const int32_t*, const double*,
+                                              const cplx<double>*, int64_t, cplx<double>*, int64_t,
+                                              int64_t, int, double, hipStream_t);
+
+}  // namespace nfft

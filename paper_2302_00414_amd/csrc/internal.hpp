@@ -137,6 +137,21 @@ template <typename R>
 hipError_t launch_fft_pass(const FftArgs<R>& a, int L, bool inverse, LoadMode ld, StoreMode st,
                            int nbatch, hipStream_t s);
 
+// ------------------------------------------------ optimized sparse matrix
+// op 0: nodes per grid column; op 1: node ids into the column lists
+hipError_t launch_bopt_pattern(const double* nodes, int64_t N, int d, int Ms, int m, int op,
+                               int* count, const int64_t* col_ptr, int* fill, int32_t* col_node,
+                               hipStream_t s);
+size_t bopt_solve_lds(int nmax);
+template <typename R>
+hipError_t launch_bopt_solve(const double* nodes, int d, int M, int Ms, const double* wh,
+                             const int64_t* col_ptr, int32_t* col_node, R* col_val, int64_t ncols,
+                             int nmax, double piv_rel, int* dropped, hipStream_t s);
+template <typename R>
+hipError_t launch_bopt_apply(const int64_t* col_ptr, const int32_t* col_node, const R* col_val,
+                             const cplx<R>* f, int64_t f_rs, cplx<R>* grid, int64_t g_rs,
+                             int64_t ncols, int nrhs, double scale, hipStream_t s);
+
 // ------------------------------------------------ float64 vector kernels
 size_t reduce_scratch_doubles();
 hipError_t launch_fill(cplx<double>* v, int64_t n, double re, double im, hipStream_t s);

@@ -157,6 +157,33 @@ def compute_weights(nodes, M: int, sigma: float = 2.0, m: int = 8, tol: float = 
     return w, info
 
 
+def nfft_bopt_build(plan, nodes: torch.Tensor, stream=None) -> dict:
+    info = (ctypes.c_double * 3)()
+    check(_lib.load().nfft_bopt_build(plan, ctypes.c_void_p(nodes.data_ptr()), info,
+                                      _stream_ptr(stream)), plan)
+    return {"max_column": int(info[0]), "nnz": int(info[1]), "columns_with_dropped_node": int(info[2])}
+
+
+def nfft_bopt_adjoint(plan, f: torch.Tensor, fhat: torch.Tensor, nrhs: int, stream=None) -> None:
+    check(_lib.load().nfft_bopt_adjoint(plan, ctypes.c_void_p(f.data_ptr()),
+                                        ctypes.c_void_p(fhat.data_ptr()), nrhs,
+                                        _stream_ptr(stream)), plan)
+
+
+def nfft_bopt_get(plan, ncols: int):
+    """-> (col_ptr int64[ncols+1], nodes int32[nnz], vals float64[nnz]) on the host."""
+    lib = _lib.load()
+    nnz = ctypes.c_int64(0)
+    check(lib.nfft_bopt_get(plan, ctypes.byref(nnz), None, None, None), plan)
+    ptr = np.empty(ncols + 1, dtype=np.int64)
+    nodes = np.empty(max(1, nnz.value), dtype=np.int32)
+    vals = np.empty(max(1, nnz.value), dtype=np.float64)
+    check(lib.nfft_bopt_get(plan, None, ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                            vals.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), plan)
+    return ptr, nodes[:nnz.value], vals[:nnz.value]
+
+
 def nfft_destroy(plan) -> None:
     check(_lib.load().nfft_destroy(plan), None)
 
@@ -307,6 +334,28 @@ class Plan:
     def graph_forward(self, fhat: torch.Tensor, out: torch.Tensor):
         """HIP graph of self.forward(fhat, out=out)."""
         return self._graph(self.forward, fhat, out)
+
+    def build_bopt(self, nodes, stream=None) -> dict:
+        """Algorithm 4.3 on the device for this node set (pass the same nodes
+        again, float64); afterwards bopt_adjoint is available."""
+        x = _as_f64_nodes(nodes).to(self.device)
+        with torch.cuda.device(self.device):
+            return nfft_bopt_build(self._h, x, stream)
+
+    def bopt_adjoint(self, f, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """h_opt = D^* F^* B_opt^* f (Algorithm 4.4); f is (N,) or (nrhs, N)."""
+        single = f.dim() == 1 if isinstance(f, torch.Tensor) else np.ndim(f) == 1
+        f = self._coerce(f, self.N)
+        nrhs = f.numel() // self.N
+        K = self.M ** self.d
+        if out is None:
+            out = torch.empty((nrhs, K), dtype=self.cdtype, device=self.device)
+        nfft_bopt_adjoint(self._h, f, out, nrhs, stream)
+        return out.reshape(K) if single else out
+
+    def bopt_matrix(self):
+        """B_opt on the host: (col_ptr, nodes, vals) by grid columns."""
+        return nfft_bopt_get(self._h, self.Ms ** self.d)
 
     def info(self) -> dict:
         return nfft_plan_info(self._h)

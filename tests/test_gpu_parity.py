@@ -42,6 +42,8 @@ SMALL = [
     (2, 48, 4.0 / 3.0, 5, 2500),  # M_sigma = 64, sigma != 2
     (2, 64, 2.0, 7, 7001),       # ragged N
     (2, 8, 2.0, 3, 50),          # single tile (16 <= 32), periodic self-neighbour
+    (2, 32, 1.0, 4, 2000),       # sigma = 1: M_sigma = M, k = -M/2 at the edge of hat w's support
+    (1, 64, 1.0, 3, 300),
     (3, 16, 2.0, 4, 4000),       # 4^3 tiles of 8
     (3, 8, 2.0, 2, 777),         # 2^3 tiles
 ]
