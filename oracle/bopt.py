@@ -188,3 +188,24 @@ def reconstruct(x, f, B, M, sigma, m):
         flat = flat * Ms + np.mod(K[:, t], Ms)
     h = ghat[:, flat] / window.phi_hat_d(K, m, sigma, Ms)[None, :]
     return h[0] if np.ndim(f) == 1 else h
+
+
+def inverse_adjoint(x, h, B, M, sigma, m):
+    """Remark 4.6: an approximate solution of A^* f = h (the inverse adjoint
+    NFFT), f = B_opt F D h: Algorithm 2.1 steps 1 and 2 (deconvolution, zero
+    padding, inverse DFT) followed by B_opt in place of the window matrix B."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    N, d = x.shape
+    Ms = window.oversampled_size(M, sigma)
+    H = np.asarray(h, dtype=np.complex128).reshape(-1, M ** d)
+    K = index_set(M, d)
+    flat = np.zeros(K.shape[0], dtype=np.int64)
+    for t in range(d):
+        flat = flat * Ms + np.mod(K[:, t], Ms)
+    ghat = np.zeros((H.shape[0], Ms ** d), dtype=np.complex128)
+    ghat[:, flat] = H / window.phi_hat_d(K, m, sigma, Ms)[None, :]
+    g = np.fft.ifftn(ghat.reshape((H.shape[0],) + (Ms,) * d), axes=tuple(range(1, d + 1)))
+    # storage at l mod M_s -> centred C order (index l + M_s/2)
+    g = np.fft.fftshift(g, axes=tuple(range(1, d + 1))).reshape(H.shape[0], -1)
+    f = (B @ g.T).T
+    return f[0] if np.ndim(h) == 1 else f

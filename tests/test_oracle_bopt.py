@@ -142,3 +142,31 @@ def test_planted_mistakes_fail_the_pins(monkeypatch):
     vref = H.conj().T @ np.linalg.inv(D) @ F.conj().T[:, c] / Ms
     bad = np.conj(bopt.rhs(x, -L[c], M, 2.0, 2))
     assert np.max(np.abs(bad - vref)) > 1e-3 * np.max(np.abs(vref))
+
+
+@pytest.mark.parametrize("d,N,M,sigma,m", [(1, 96, 32, 2.0, 2), (2, 300, 16, 1.0, 2)])
+def test_inverse_adjoint_fft_route(d, N, M, sigma, m):
+    """Remark 4.6: f = B_opt F D h by the FFT route equals the dense product."""
+    x = wl.uniform_nodes(N, d, 80 + d)
+    B = bopt.bopt(x, M, sigma, m)
+    h = wl.complex_normal(M ** d, 81)
+    D, F, _ = nfft.dense_matrices(x, M, sigma, m)
+    f = bopt.inverse_adjoint(x, h, B, M, sigma, m)
+    assert metrics.rel_err(f, B.toarray() @ (F @ (D @ h))) <= 1e-12
+
+
+def test_inverse_adjoint_solves_the_adjoint_system():
+    """Remark 4.6 with |I_M| <= N: A^* f ~ h for f = B_opt F D h (jittered
+    grid, sigma = 2), far closer than with the window matrix B scaled by the
+    best constant."""
+    x = wl.jittered_nodes((24, 24), 82)
+    M, sigma, m = 16, 2.0, 4
+    B = bopt.bopt(x, M, sigma, m)
+    h = wl.complex_normal(M * M, 83)
+    f = bopt.inverse_adjoint(x, h, B, M, sigma, m)
+    e_opt = metrics.rel_err(ndft.adjoint(x, f, M), h)
+    fb = nfft.forward(x, h, M, sigma, m)                  # B F D h with the window matrix
+    r = ndft.adjoint(x, fb, M)
+    c = np.vdot(r, h) / np.vdot(r, r)
+    e_plain = metrics.rel_err(c * r, h)
+    assert e_opt < 0.05 and e_opt < 0.2 * e_plain
