@@ -120,7 +120,9 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
  *                             the rows a node reaches kept in registers;
  *                             needs T + 2m <= 32; resolved to 1 elsewhere).
  *                             Default 1; the row sweep wins with many
- *                             right-hand sides per call.
+ *                             right-hand sides per call, and in float32
+ *                             takes two of them per wave when
+ *                             NFFT_TUNE_RHS_PER_GROUP >= 2.
  * The environment variables NFFT_TILE_EDGE, NFFT_ITEM_NODES,
  * NFFT_SPREAD_THREADS, NFFT_RHS_PER_GROUP, NFFT_FFT_MIN_WG, NFFT_SPREAD_PLANES
  * and NFFT_SPREAD_MODE replace the defaults. A combination whose spreading
@@ -268,6 +270,16 @@ int nfft_bopt_build(nfft_plan_t plan, const double *nodes, double *info, void *s
  * nfft_bopt_build.
  */
 int nfft_bopt_adjoint(nfft_plan_t plan, const void *f, void *fhat, int nrhs, void *stream);
+
+/*
+ * nfft_bopt_inverse_adjoint -- Remark 4.6: an approximate solution of
+ * A^* f = h (the inverse adjoint NFFT) by f = B_opt F D h, i.e. Algorithm
+ * 2.1 with B_opt in place of B, for nrhs right-hand sides.
+ *   h  device, nrhs*M^d complex (plan precision), C order of I_M
+ *   f  device, nrhs*N complex (plan precision), caller's node order (output)
+ * NFFT_ESTATE before nfft_bopt_build.
+ */
+int nfft_bopt_inverse_adjoint(nfft_plan_t plan, const void *h, void *f, int nrhs, void *stream);
 
 /*
  * nfft_bopt_get -- copy B_opt to host memory by grid columns (C order of

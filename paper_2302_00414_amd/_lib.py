@@ -22,7 +22,7 @@ EXPORTS = (
     "nfft_plan", "nfft_plan_tuned", "nfft_plan_autotune", "nfft_get_tuning", "nfft_set_tuning",
     "nfft_plan_clone",
     "nfft_set_weights", "nfft_adjoint", "nfft_forward", "nfft_weights", "nfft_bopt_build",
-    "nfft_bopt_adjoint", "nfft_bopt_get", "nfft_destroy",
+    "nfft_bopt_adjoint", "nfft_bopt_inverse_adjoint", "nfft_bopt_get", "nfft_destroy",
     "nfft_footprint", "nfft_strerror", "nfft_last_error", "nfft_plan_info",
     "nfft_permutation", "nfft_set_profiling", "nfft_stage_times",
 )
@@ -75,6 +75,8 @@ def load() -> ctypes.CDLL:
     lib.nfft_bopt_build.restype = i32
     lib.nfft_bopt_adjoint.argtypes = [vp, vp, vp, i32, vp]
     lib.nfft_bopt_adjoint.restype = i32
+    lib.nfft_bopt_inverse_adjoint.argtypes = [vp, vp, vp, i32, vp]
+    lib.nfft_bopt_inverse_adjoint.restype = i32
     lib.nfft_bopt_get.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(dbl)]
     lib.nfft_bopt_get.restype = i32

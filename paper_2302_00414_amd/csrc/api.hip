@@ -68,6 +68,8 @@ struct SharedData {
   void* bopt_val = nullptr;       // values (plan precision), by column
   int64_t bopt_nnz = 0;
   int bopt_nmax = 0;
+  int32_t* bopt_lo = nullptr;     // first support cell per node and dimension (caller order)
+  void* bopt_rows = nullptr;      // values by rows: N x (2m+1)^d in footprint order
   ~SharedData() {
     for (void* q : allocs) (void)hipFree(q);
   }
@@ -681,14 +683,12 @@ int run_bopt_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStre
   return NFFT_OK;
 }
 
+// Algorithm 2.1 steps 1 and 2: deconvolution and zero padding of fhat, then
+// the inverse FFT passes, into the plan's grid ([s_1]...[s_d], C order).
 template <typename R>
-int run_forward(nfft_plan_t p, const void* fhat, void* f, int nrhs, hipStream_t s) {
-  const Geom& g = p->g;
+int forward_grid(nfft_plan_t p, const void* fhat, int nrhs, hipStream_t s) {
   const int64_t Ms = p->Ms, M = p->M;
   const int L = (int)Ms;
-  StageEvents se{};
-  se.kind = 1;
-  record(p, se, s);
   const auto ld = nfft::kLoadPadScaled;
   const auto st = nfft::kStoreFull;
   if (p->d == 1) {
@@ -709,6 +709,30 @@ int run_forward(nfft_plan_t p, const void* fhat, void* f, int nrhs, hipStream_t 
     auto e = fft_args<R>(p, Ms * Ms, p->bufA, Ms * Ms * M, (int)M, p->grid, Ms * Ms * Ms);
     HIP_TRY(p, nfft::launch_fft_pass<R>(e, L, true, ld, st, nrhs, s));
   }
+  return NFFT_OK;
+}
+
+// Remark 4.6: f = B_opt F D h, the forward's grid gathered with the stored
+// values of B_opt instead of window evaluations.
+template <typename R>
+int run_bopt_inverse_adjoint(nfft_plan_t p, const void* h, void* f, int nrhs, hipStream_t s) {
+  TRY(forward_grid<R>(p, h, nrhs, s));
+  const SharedData& sd = *p->shared;
+  const double scale = std::pow(M_PI * std::exp(-p->b * p->m), p->d);
+  HIP_TRY(p, nfft::launch_bopt_gather<R>(sd.bopt_lo, (const R*)sd.bopt_rows,
+                                         (const cplx<R>*)p->grid, ipow(p->Ms, p->d), p->N, p->d,
+                                         p->Ms, p->m, (cplx<R>*)f, p->N, nrhs, scale, s));
+  return NFFT_OK;
+}
+
+template <typename R>
+int run_forward(nfft_plan_t p, const void* fhat, void* f, int nrhs, hipStream_t s) {
+  const Geom& g = p->g;
+  const int64_t Ms = p->Ms;
+  StageEvents se{};
+  se.kind = 1;
+  record(p, se, s);
+  TRY(forward_grid<R>(p, fhat, nrhs, s));
   record(p, se, s);
   nfft::InterpArgs<R> ia{};
   ia.loc = p->loc;
@@ -975,7 +999,7 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
             if (md) in[NFFT_TUNE_SPREAD_MODE] = md;
             // the LDS kernel's shape does not matter when another kernel spreads
             if ((nr > 1 || md == 2) && (nt != threads[0] || pl != planes[0])) continue;
-            if (nr > 1 && md == 2) continue;  // several rhs per group: one kernel
+            if (nr > 2 && md == 2) continue;  // the row sweep takes at most two rhs per wave
             int res[NFFT_TUNE_COUNT];
             if (resolve_tuning(d, Ms, m, precision, in, NFFT_TUNE_COUNT, res, nullptr) != NFFT_OK)
               continue;
@@ -1213,6 +1237,18 @@ int nfft_bopt_build(nfft_plan_t p, const double* nodes, double* info, void* stre
     HIP_TRY(p, nfft::launch_bopt_solve<float>((const double*)d_nodes, d, M, Ms, (const double*)wh,
                                               sd.bopt_ptr, sd.bopt_node, (float*)sd.bopt_val,
                                               ncols, std::max(1, nmax), kPivotRel, (int*)dropped, s));
+  // the same values by rows, for the inverse adjoint of Remark 4.6
+  const int64_t F = ipow(2 * m + 1, d);
+  TRY(dalloc(p, &sd.bopt_lo, N * d * sizeof(int32_t)));
+  TRY(dalloc(p, &sd.bopt_rows, N * F * rb));
+  HIP_TRY(p, hipMemsetAsync(sd.bopt_rows, 0, N * F * rb, s));
+  HIP_TRY(p, nfft::launch_bopt_lo((const double*)d_nodes, N, d, Ms, m, sd.bopt_lo, s));
+  if (p->prec == NFFT_F64)
+    HIP_TRY(p, nfft::launch_bopt_rows<double>(sd.bopt_ptr, sd.bopt_node, (const double*)sd.bopt_val,
+                                              ncols, d, Ms, m, sd.bopt_lo, (double*)sd.bopt_rows, s));
+  else
+    HIP_TRY(p, nfft::launch_bopt_rows<float>(sd.bopt_ptr, sd.bopt_node, (const float*)sd.bopt_val,
+                                             ncols, d, Ms, m, sd.bopt_lo, (float*)sd.bopt_rows, s));
   int hd = 0;
   HIP_TRY(p, hipMemcpyAsync(&hd, dropped, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(p, hipStreamSynchronize(s));
@@ -1237,6 +1273,18 @@ int nfft_bopt_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, void* 
   hipStream_t s = (hipStream_t)stream;
   return p->prec == NFFT_F64 ? run_bopt_adjoint<double>(p, f, fhat, nrhs, s)
                              : run_bopt_adjoint<float>(p, f, fhat, nrhs, s);
+}
+
+int nfft_bopt_inverse_adjoint(nfft_plan_t p, const void* h, void* f, int nrhs, void* stream) {
+  if (!p) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
+  if (!f || !h) return fail(p, NFFT_EINVAL, "h or f is NULL");
+  if (nrhs < 1 || nrhs > p->max_rhs)
+    return fail(p, NFFT_EINVAL, "nrhs = %d outside 1..max_rhs = %d", nrhs, p->max_rhs);
+  if (!p->shared->has_bopt) return fail(p, NFFT_ESTATE, "nfft_bopt_build has not been called");
+  HIP_TRY(p, hipGetLastError());
+  hipStream_t s = (hipStream_t)stream;
+  return p->prec == NFFT_F64 ? run_bopt_inverse_adjoint<double>(p, h, f, nrhs, s)
+                             : run_bopt_inverse_adjoint<float>(p, h, f, nrhs, s);
 }
 
 int nfft_bopt_get(nfft_plan_t p, int64_t* nnz, int64_t* col_ptr, int32_t* nodes, double* vals) {

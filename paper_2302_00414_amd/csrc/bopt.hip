@@ -260,9 +260,115 @@ __global__ __launch_bounds__(256) void bopt_apply_kernel(const int64_t* __restri
   if (lane == 0) grid[blockIdx.y * g_rs + c] = mkc<R>((R)(sx * scale), (R)(sy * scale));
 }
 
+// First cell of every node's closed support, per dimension (caller order).
+__global__ void bopt_lo_kernel(const double* __restrict__ nodes, int64_t N, int d, int Ms, int m,
+                               int32_t* __restrict__ lo) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  for (int t = 0; t < d; ++t)
+    lo[j * d + t] = (int32_t)ceil(wrap_half(nodes[j * d + t]) * Ms + 0.5 * Ms - m);
+}
+
+// B_opt by rows: the value of node j in its footprint cell q (offsets
+// q_t = s_t - lo_t in [0, 2m], q = sum q_t (2m+1)^(d-1-t)); cells outside the
+// support stay zero. One thread per column; every (node, cell) pair is
+// written once.
+template <typename R>
+__global__ void bopt_rows_kernel(const int64_t* __restrict__ col_ptr,
+                                 const int32_t* __restrict__ col_node,
+                                 const R* __restrict__ col_val, int64_t ncols, int d, int Ms,
+                                 int m, const int32_t* __restrict__ lo, R* __restrict__ rows) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  const int K = 2 * m + 1;
+  int F = 1;
+  for (int t = 0; t < d; ++t) F *= K;
+  int s[3];
+  int64_t cc = c;
+  for (int t = d - 1; t >= 0; --t) {
+    s[t] = (int)(cc % Ms);
+    cc /= Ms;
+  }
+  for (int64_t e = col_ptr[c]; e < col_ptr[c + 1]; ++e) {
+    const int j = col_node[e];
+    int q = 0;
+    for (int t = 0; t < d; ++t) q = q * K + (((s[t] - lo[(int64_t)j * d + t]) % Ms) + Ms) % Ms;
+    rows[(int64_t)j * F + q] = col_val[e];
+  }
+}
+
+// f_j = scale * sum over the node's support of b_jl g_l (Remark 4.6's
+// f = B_opt F D h, with g = F D h from the forward FFT passes)
+template <typename R>
+__global__ void bopt_gather_kernel(const int32_t* __restrict__ lo, const R* __restrict__ rows,
+                                   const cplx<R>* __restrict__ grid, int64_t g_rs, int64_t N,
+                                   int d, int Ms, int m, cplx<R>* __restrict__ f, int64_t f_rs,
+                                   double scale) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const cplx<R>* g = grid + blockIdx.y * g_rs;
+  const int K = 2 * m + 1;
+  int F = 1;
+  for (int t = 0; t < d; ++t) F *= K;
+  int l[3] = {0, 0, 0};
+  for (int t = 0; t < d; ++t) l[t] = lo[j * d + t];
+  double sx = 0.0, sy = 0.0;
+  for (int q = 0; q < F; ++q) {
+    const R b = rows[j * F + q];
+    if (b == (R)0) continue;
+    int rem = q;
+    int64_t cell = 0;
+    int o[3];
+    for (int t = d - 1; t >= 0; --t) {
+      o[t] = rem % K;
+      rem /= K;
+    }
+    for (int t = 0; t < d; ++t) cell = cell * Ms + (((l[t] + o[t]) % Ms) + Ms) % Ms;
+    const cplx<R> v = g[cell];
+    sx += (double)b * (double)v.x;
+    sy += (double)b * (double)v.y;
+  }
+  f[blockIdx.y * f_rs + j] = mkc<R>((R)(sx * scale), (R)(sy * scale));
+}
+
 unsigned grid1(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
+
+hipError_t launch_bopt_lo(const double* nodes, int64_t N, int d, int Ms, int m, int32_t* lo,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(bopt_lo_kernel, dim3(grid1(N, 256)), dim3(256), 0, s, nodes, N, d, Ms, m, lo);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_bopt_rows(const int64_t* col_ptr, const int32_t* col_node, const R* col_val,
+                            int64_t ncols, int d, int Ms, int m, const int32_t* lo, R* rows,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(bopt_rows_kernel<R>, dim3(grid1(ncols, 256)), dim3(256), 0, s, col_ptr,
+                     col_node, col_val, ncols, d, Ms, m, lo, rows);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_bopt_gather(const int32_t* lo, const R* rows, const cplx<R>* grid, int64_t g_rs,
+                              int64_t N, int d, int Ms, int m, cplx<R>* f, int64_t f_rs, int nrhs,
+                              double scale, hipStream_t s) {
+  hipLaunchKernelGGL(bopt_gather_kernel<R>, dim3(grid1(N, 256), nrhs), dim3(256), 0, s, lo, rows,
+                     grid, g_rs, N, d, Ms, m, f, f_rs, scale);
+  return hipGetLastError();
+}
+
+template hipError_t launch_bopt_rows<float>(const int64_t*, const int32_t*, const float*, int64_t,
+                                            int, int, int, const int32_t*, float*, hipStream_t);
+template hipError_t launch_bopt_rows<double>(const int64_t*, const int32_t*, const double*, int64_t,
+                                             int, int, int, const int32_t*, double*, hipStream_t);
+template hipError_t launch_bopt_gather<float>(const int32_t*, const float*, const cplx<float>*,
+                                              int64_t, int64_t, int, int, int, cplx<float>*,
+                                              int64_t, int, double, hipStream_t);
+template hipError_t launch_bopt_gather<double>(const int32_t*, const double*, const cplx<double>*,
+                                               int64_t, int64_t, int, int, int, cplx<double>*,
+                                               int64_t, int, double, hipStream_t);
 
 hipError_t launch_bopt_pattern(const double* nodes, int64_t N, int d, int Ms, int m, int op,
                                int* count, const int64_t* col_ptr, int* fill, int32_t* col_node,

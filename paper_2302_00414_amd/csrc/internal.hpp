@@ -152,6 +152,17 @@ hipError_t launch_bopt_apply(const int64_t* col_ptr, const int32_t* col_node, co
                              const cplx<R>* f, int64_t f_rs, cplx<R>* grid, int64_t g_rs,
                              int64_t ncols, int nrhs, double scale, hipStream_t s);
 
+hipError_t launch_bopt_lo(const double* nodes, int64_t N, int d, int Ms, int m, int32_t* lo,
+                          hipStream_t s);
+template <typename R>
+hipError_t launch_bopt_rows(const int64_t* col_ptr, const int32_t* col_node, const R* col_val,
+                            int64_t ncols, int d, int Ms, int m, const int32_t* lo, R* rows,
+                            hipStream_t s);
+template <typename R>
+hipError_t launch_bopt_gather(const int32_t* lo, const R* rows, const cplx<R>* grid, int64_t g_rs,
+                              int64_t N, int d, int Ms, int m, cplx<R>* f, int64_t f_rs, int nrhs,
+                              double scale, hipStream_t s);
+
 // ------------------------------------------------ float64 vector kernels
 size_t reduce_scratch_doubles();
 hipError_t launch_fill(cplx<double>* v, int64_t n, double re, double im, hipStream_t s);

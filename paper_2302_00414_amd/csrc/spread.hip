@@ -729,8 +729,8 @@ size_t spread_lds_bytes(int d, bool f64, int m, int T, int Ptot, int nt, int nr,
 template <typename R>
 hipError_t launch_spread(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
   if (a.g.nsub == 0) return hipSuccess;
-  if (a.nr > 1 && a.g.d <= 2) return launch_spread_multi<R>(a, nrhs, s);
   if (a.mode == 2 && spread_rows_supported(a.g.d, a.g.P)) return launch_spread_rows<R>(a, nrhs, s);
+  if (a.nr > 1 && a.g.d <= 2) return launch_spread_multi<R>(a, nrhs, s);
   switch (a.g.d) {
     case 1: NFFT_DISPATCH_M(spread_dm, R, 1, a, nrhs, s)
     case 2: NFFT_DISPATCH_M(spread_dm, R, 2, a, nrhs, s)

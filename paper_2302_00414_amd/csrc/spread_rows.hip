@@ -43,17 +43,19 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
-template <typename R, int MW, int TT>
-__global__ __launch_bounds__(64) void spread_rows_kernel(SpreadArgs<R> a) {
+template <typename R, int MW, int TT, int NR>
+__global__ __launch_bounds__(64) void spread_rows_kernel(SpreadArgs<R> a, int nrhs) {
   constexpr int DEG = PolyDeg<R>::value;
   constexpr int K2 = 2 * MW;
   constexpr int W = K2 + 1;  // window rows
   constexpr int C = 2;       // columns per lane: padded edge <= 32
   constexpr int SB = 64;     // nodes staged per batch
-  __shared__ R st_y0[SB], st_y1[SB], st_cx[SB], st_cy[SB];
+  __shared__ R st_y0[SB], st_y1[SB], st_cx[NR][SB], st_cy[NR][SB];
   __shared__ uint32_t st_loc[SB];
   const int item = blockIdx.x;
-  const int rhs = blockIdx.y;
+  // NR right-hand sides per wave share every node's window factors
+  const int r0 = blockIdx.y * NR;
+  const int nr = (nrhs - r0) < NR ? (nrhs - r0) : NR;
   const int P = TT > 0 ? TT + K2 : a.g.P;
   const int lane = threadIdx.x;
   const int g = lane >> 4;
@@ -69,16 +71,22 @@ __global__ __launch_bounds__(64) void spread_rows_kernel(SpreadArgs<R> a) {
   const int64_t N = a.g.N;
   const int start = a.item_start[item];
   const int cnt = a.item_count[item];
-  const cplx<R>* f = a.f + rhs * a.f_rs;
   const int slot = a.item_slot[item];
-  cplx<R>* out = slot < 0 ? a.tilep + rhs * a.tile_rs + (int64_t)a.item_bin[item] * a.g.Ptot
-                          : a.itemp + rhs * a.item_rs + (int64_t)slot * a.g.Ptot;
+  cplx<R>* outs[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int rhs = r0 + (q < nr ? q : 0);
+    outs[q] = slot < 0 ? a.tilep + rhs * a.tile_rs + (int64_t)a.item_bin[item] * a.g.Ptot
+                       : a.itemp + rhs * a.item_rs + (int64_t)slot * a.g.Ptot;
+  }
 
-  R ax[W][C], ay[W][C];
+  R ax[NR][W][C], ay[NR][W][C];
 #pragma unroll
-  for (int r = 0; r < W; ++r)
+  for (int q = 0; q < NR; ++q)
 #pragma unroll
-    for (int s = 0; s < C; ++s) ax[r][s] = ay[r][s] = (R)0;
+    for (int r = 0; r < W; ++r)
+#pragma unroll
+      for (int s = 0; s < C; ++s) ax[q][r][s] = ay[q][r][s] = (R)0;
   int row = 0;      // padded row held in window slot 0
   int maxrow = -1;  // last padded row any node has reached
 
@@ -88,28 +96,35 @@ __global__ __launch_bounds__(64) void spread_rows_kernel(SpreadArgs<R> a) {
       // no node reached this row: the whole window is zero
       if (g == 0) {
 #pragma unroll
-        for (int s = 0; s < C; ++s) {
-          const int col = k + 16 * s;
-          if (col < P) out[row * P + col] = mkc<R>((R)0, (R)0);
+        for (int q = 0; q < NR; ++q) {
+          if (q >= nr) break;
+#pragma unroll
+          for (int s = 0; s < C; ++s) {
+            const int col = k + 16 * s;
+            if (col < P) outs[q][row * P + col] = mkc<R>((R)0, (R)0);
+          }
         }
       }
     } else {
 #pragma unroll
-      for (int s = 0; s < C; ++s) {
-        const R x = group_sum(ax[0][s]);
-        const R y = group_sum(ay[0][s]);
-        const int col = k + 16 * s;
-        if (g == 0 && col < P) out[row * P + col] = mkc<R>(x, y);
-      }
-#pragma unroll
-      for (int r = 0; r + 1 < W; ++r)
+      for (int q = 0; q < NR; ++q) {
 #pragma unroll
         for (int s = 0; s < C; ++s) {
-          ax[r][s] = ax[r + 1][s];
-          ay[r][s] = ay[r + 1][s];
+          const R x = group_sum(ax[q][0][s]);
+          const R y = group_sum(ay[q][0][s]);
+          const int col = k + 16 * s;
+          if (q < nr && g == 0 && col < P) outs[q][row * P + col] = mkc<R>(x, y);
         }
 #pragma unroll
-      for (int s = 0; s < C; ++s) ax[W - 1][s] = ay[W - 1][s] = (R)0;
+        for (int r = 0; r + 1 < W; ++r)
+#pragma unroll
+          for (int s = 0; s < C; ++s) {
+            ax[q][r][s] = ax[q][r + 1][s];
+            ay[q][r][s] = ay[q][r + 1][s];
+          }
+#pragma unroll
+        for (int s = 0; s < C; ++s) ax[q][W - 1][s] = ay[q][W - 1][s] = (R)0;
+      }
     }
     ++row;
   };
@@ -117,7 +132,9 @@ __global__ __launch_bounds__(64) void spread_rows_kernel(SpreadArgs<R> a) {
   // node data of the next batch, one node per lane, loaded a batch ahead
   R pf0 = 0, pf1 = 0;
   uint32_t pfl = 0;
-  cplx<R> pfw = mkc<R>(0, 0), pfs = mkc<R>(0, 0);
+  cplx<R> pfw = mkc<R>(0, 0), pfs[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) pfs[q] = mkc<R>(0, 0);
   auto issue = [&](int b) {
     if (b + lane < cnt) {
       const int i = start + b + lane;
@@ -125,7 +142,10 @@ __global__ __launch_bounds__(64) void spread_rows_kernel(SpreadArgs<R> a) {
       pf1 = a.frac[N + i];
       pfl = a.loc[i];
       pfw = a.w[i];
-      pfs = f[a.perm[i]];
+      const int jj = a.perm[i];
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (q < nr) pfs[q] = a.f[(int64_t)(r0 + q) * a.f_rs + jj];
     }
   };
   issue(0);
@@ -133,12 +153,15 @@ __global__ __launch_bounds__(64) void spread_rows_kernel(SpreadArgs<R> a) {
     const int nb = (cnt - b0) < SB ? (cnt - b0) : SB;
     __syncthreads();  // previous batch consumed
     if (lane < nb) {
-      const cplx<R> c = cmul<R>(pfw, pfs);
       st_y0[lane] = (R)2 * pf0 - (R)1;
       st_y1[lane] = (R)2 * pf1 - (R)1;
-      st_cx[lane] = c.x;
-      st_cy[lane] = c.y;
       st_loc[lane] = pfl;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        const cplx<R> c = cmul<R>(pfw, pfs[q]);
+        st_cx[q][lane] = c.x;
+        st_cy[q][lane] = c.y;
+      }
     }
     if (b0 + SB < cnt) issue(b0 + SB);
     __syncthreads();
@@ -158,36 +181,47 @@ __global__ __launch_bounds__(64) void spread_rows_kernel(SpreadArgs<R> a) {
       if (take) {
         const R p0 = horner<R>(cf, st_y0[j]);
         const R p1 = horner<R>(cf, st_y1[j]);
-        const R cx = st_cx[j], cy = st_cy[j];
         const int l1 = (int)((L >> kLocBits) & kLocMask);
         const bool e0 = (L >> kEdgeShift) & 1u;
         const bool e1 = (L >> (kEdgeShift + 1)) & 1u;
         // column factors of this lane's columns (footprint column jc = col - l1 - 1;
         // jc = -1 is the closed-edge column)
-        R vx[C], vy[C];
+        R cw[C];
 #pragma unroll
         for (int s = 0; s < C; ++s) {
           const int jc = k + 16 * s - l1 - 1;
           const R v = lane_read<R>(p1, (g << 4) | (jc & 15));
-          const R cw = (jc >= 0 && jc < K2) ? v : ((jc == -1 && e1) ? edge : (R)0);
-          vx[s] = cx * cw;
-          vy[s] = cy * cw;
+          cw[s] = (jc >= 0 && jc < K2) ? v : ((jc == -1 && e1) ? edge : (R)0);
+        }
+        R vx[NR][C], vy[NR][C];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+          const R cx = st_cx[q][j], cy = st_cy[q][j];
+#pragma unroll
+          for (int s = 0; s < C; ++s) {
+            vx[q][s] = cx * cw[s];
+            vy[q][s] = cy * cw[s];
+          }
         }
         // window slot 0: closed-edge row; slot 1 + i: footprint row i
         const R w0 = e0 ? edge : (R)0;
 #pragma unroll
-        for (int s = 0; s < C; ++s) {
-          ax[0][s] += vx[s] * w0;
-          ay[0][s] += vy[s] * w0;
-        }
+        for (int q = 0; q < NR; ++q)
+#pragma unroll
+          for (int s = 0; s < C; ++s) {
+            ax[q][0][s] += vx[q][s] * w0;
+            ay[q][0][s] += vy[q][s] * w0;
+          }
         static_for<0, K2>([&](auto ic) {
           constexpr int I = decltype(ic)::value;
           const R rw = row_bcast<I>(p0);
 #pragma unroll
-          for (int s = 0; s < C; ++s) {
-            ax[1 + I][s] += vx[s] * rw;
-            ay[1 + I][s] += vy[s] * rw;
-          }
+          for (int q = 0; q < NR; ++q)
+#pragma unroll
+            for (int s = 0; s < C; ++s) {
+              ax[q][1 + I][s] += vx[q][s] * rw;
+              ay[q][1 + I][s] += vy[q][s] * rw;
+            }
         });
       }
       i += used;
@@ -198,14 +232,24 @@ __global__ __launch_bounds__(64) void spread_rows_kernel(SpreadArgs<R> a) {
 
 namespace {
 
+template <typename R, int MW, int NR>
+hipError_t rows_nr(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
+  const dim3 grid(a.g.nsub, (nrhs + NR - 1) / NR);
+  if (a.g.T == 16)
+    hipLaunchKernelGGL((spread_rows_kernel<R, MW, 16, NR>), grid, dim3(64), 0, s, a, nrhs);
+  else
+    hipLaunchKernelGGL((spread_rows_kernel<R, MW, 0, NR>), grid, dim3(64), 0, s, a, nrhs);
+  return hipGetLastError();
+}
+
+// float32: two right-hand sides per wave when a call has several (the
+// window work is shared); float64 keeps one (register budget)
 template <typename R, int MW>
 hipError_t rows_m(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
-  const dim3 grid(a.g.nsub, nrhs);
-  if (a.g.T == 16)
-    hipLaunchKernelGGL((spread_rows_kernel<R, MW, 16>), grid, dim3(64), 0, s, a);
-  else
-    hipLaunchKernelGGL((spread_rows_kernel<R, MW, 0>), grid, dim3(64), 0, s, a);
-  return hipGetLastError();
+  if constexpr (std::is_same<R, float>::value) {
+    if (nrhs > 1 && a.nr >= 2) return rows_nr<R, MW, 2>(a, nrhs, s);
+  }
+  return rows_nr<R, MW, 1>(a, nrhs, s);
 }
 
 }  // namespace

@@ -170,6 +170,12 @@ def nfft_bopt_adjoint(plan, f: torch.Tensor, fhat: torch.Tensor, nrhs: int, stre
                                         _stream_ptr(stream)), plan)
 
 
+def nfft_bopt_inverse_adjoint(plan, h: torch.Tensor, f: torch.Tensor, nrhs: int, stream=None) -> None:
+    check(_lib.load().nfft_bopt_inverse_adjoint(plan, ctypes.c_void_p(h.data_ptr()),
+                                                ctypes.c_void_p(f.data_ptr()), nrhs,
+                                                _stream_ptr(stream)), plan)
+
+
 def nfft_bopt_get(plan, ncols: int):
     """-> (col_ptr int64[ncols+1], nodes int32[nnz], vals float64[nnz]) on the host."""
     lib = _lib.load()
@@ -352,6 +358,18 @@ class Plan:
             out = torch.empty((nrhs, K), dtype=self.cdtype, device=self.device)
         nfft_bopt_adjoint(self._h, f, out, nrhs, stream)
         return out.reshape(K) if single else out
+
+    def bopt_inverse_adjoint(self, h, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """f = B_opt F D h, an approximate solution of A^* f = h (Remark 4.6);
+        h is (M^d,) or (nrhs, M^d)."""
+        K = self.M ** self.d
+        single = h.dim() == 1 if isinstance(h, torch.Tensor) else np.ndim(h) == 1
+        h = self._coerce(h, K)
+        nrhs = h.numel() // K
+        if out is None:
+            out = torch.empty((nrhs, self.N), dtype=self.cdtype, device=self.device)
+        nfft_bopt_inverse_adjoint(self._h, h, out, nrhs, stream)
+        return out.reshape(self.N) if single else out
 
     def bopt_matrix(self):
         """B_opt on the host: (col_ptr, nodes, vals) by grid columns."""

@@ -123,3 +123,43 @@ def test_jittered_reconstruction_beats_plain_density():
     assert metrics.rel_err(got, ref) <= 1e-7
     assert e_gpu < 0.02 and e_gpu < 0.2 * e_dens
     p.close()
+
+
+JITTERED = [((96,), 64, 2.0, 2), ((20, 20), 16, 2.0, 2), ((24, 24), 16, 2.0, 4)]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape,M,sigma,m", JITTERED)
+def test_inverse_adjoint_matches_oracle(shape, M, sigma, m, prec):
+    """Remark 4.6 on the GPU: f = B_opt F D h against the oracle, on jittered
+    nodes (well separated, so every column problem is well conditioned and
+    B_opt is determined to rounding)."""
+    x = wl.jittered_nodes(shape, 90)
+    d = x.shape[1]
+    h = wl.complex_normal((2, M ** d), 91)
+    p = _plan(x, M, sigma, m, prec, max_rhs=2)
+    p.build_bopt(x)
+    got = p.bopt_inverse_adjoint(torch.from_numpy(h)).cpu().numpy()
+    ref = ob.inverse_adjoint(x, h, ob.bopt(x, M, sigma, m), M, sigma, m)
+    tol = 1e-8 if prec == "f64" else 1e-5
+    for r in range(2):
+        assert metrics.rel_err(got[r], ref[r]) <= tol, r
+    p.close()
+
+
+def test_inverse_adjoint_on_random_nodes_solves_as_well():
+    """Uniform random nodes can nearly coincide, which leaves a column of B_opt
+    ill determined: solvers may differ there while fitting equally well. The
+    GPU result solves A^* f = h as well as the oracle's."""
+    d, N, M, sigma, m = 1, 96, 64, 2.0, 2
+    x = wl.uniform_nodes(N, d, 91)
+    h = wl.complex_normal(M, 92)
+    p = _plan(x, M, sigma, m, "f64")
+    p.build_bopt(x)
+    got = p.bopt_inverse_adjoint(torch.from_numpy(h)).cpu().numpy()
+    ref = ob.inverse_adjoint(x, h, ob.bopt(x, M, sigma, m), M, sigma, m)
+    r_gpu = metrics.rel_err(ndft.adjoint(x, got, M), h)
+    r_ref = metrics.rel_err(ndft.adjoint(x, ref, M), h)
+    print(f"[bopt] residual of A^* f = h: gpu {r_gpu:.3e} oracle {r_ref:.3e}", flush=True)
+    assert r_gpu <= 1.1 * r_ref + 1e-12
+    p.close()

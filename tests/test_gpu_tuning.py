@@ -147,7 +147,8 @@ def test_3d_m8_float32():
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("m", [2, 6, 8])
-def test_row_sweep_multi_rhs(prec, m):
+@pytest.mark.parametrize("rpg", [1, 2])
+def test_row_sweep_multi_rhs(prec, m, rpg):
     """Register row sweep with several right-hand sides in one launch, at the
     smallest and largest windows it covers (padded edge 16 + 2m <= 32)."""
     M, nrhs = 32, 3
@@ -155,7 +156,7 @@ def test_row_sweep_multi_rhs(prec, m):
     N = x.shape[0]
     w = (1.0 + 0.3 * wl.complex_normal(N, 201)) / N
     F = wl.complex_normal((nrhs, N), 202)
-    p = _plan(x, M, m, prec, max_rhs=nrhs, tuning={"spread_mode": 2})
+    p = _plan(x, M, m, prec, max_rhs=nrhs, tuning={"spread_mode": 2, "rhs_per_group": rpg})
     assert p.tuning()["spread_mode"] == 2
     p.set_weights(w)
     got = _np(p.adjoint(torch.from_numpy(F)))
