@@ -22,6 +22,11 @@ reference for small problems.
 
 ``residual`` is epsilon = max_k |[A_2M^T w]_k - delta_{0,k}| over I_2M, the
 quantity of (3.36) that enters the bounds (3.37) and (3.46).
+
+Two weight choices from the literature that Section 3.4 compares with:
+``weights_pcf`` (3.62), the minimiser of the Frobenius problem (3.61), and
+``weights_relaxed``, the solution of the summed conditions A A^* w = 1_N
+(3.63), both from the dense A A^* of (3.60).
 """
 from __future__ import annotations
 
@@ -103,3 +108,27 @@ def residual(x, w, M) -> float:
     M2 = 2 * M
     r = np.conj(ndft.adjoint(x, np.conj(w), M2)) - _e0(M2, x.shape[1])
     return float(np.max(np.abs(r)))
+
+
+# ------------------------------------------------ weights from the literature
+def gram_nodes(x, M) -> np.ndarray:
+    """[A A^*]_{j,h} = sum_{k in I_M} e^{2 pi i k.(x_j - x_h)} (3.60), from the
+    Fourier matrix (2.7) itself (dense, small N)."""
+    A = fourier_matrix(np.atleast_2d(np.asarray(x, dtype=np.float64)), M)
+    return A @ A.conj().T
+
+
+def weights_pcf(x, M) -> np.ndarray:
+    """(3.62): the minimiser of ||A A^* W - I_N||_F over diagonal W,
+    w_j = |I_M| / sum_h |[A A^*]_{j,h}|^2."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    H = gram_nodes(x, M)
+    return (M ** x.shape[1]) / np.sum(np.abs(H) ** 2, axis=1) + 0j
+
+
+def weights_relaxed(x, M) -> np.ndarray:
+    """(3.63): A A^* w = 1_N, the minimum-norm least-squares solution (dense)."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    H = gram_nodes(x, M)
+    w, *_ = np.linalg.lstsq(H, np.ones(x.shape[0], dtype=np.complex128), rcond=None)
+    return w

@@ -110,3 +110,39 @@ def test_planted_unaugmented_system_is_caught(monkeypatch):
     fh = wl.uniform_coefficients(32, 81)
     f = ndft.forward(x, fh, 32)
     assert metrics.rel_err(ndft.adjoint(x, w * f, 32), fh) > 1e-3
+
+
+def test_pcf_weights_minimise_the_frobenius_problem():
+    """(3.62) against a numerical minimisation of (3.61) over diagonal W on a
+    tiny problem, and 1/N on an equispaced grid with n = M."""
+    from scipy.optimize import minimize
+    x = wl.uniform_nodes(6, 1, 900)
+    M = 4
+    H = weights.gram_nodes(x, M)
+    w = weights.weights_pcf(x, M)
+
+    def obj(v):
+        W = np.diag(v[:6] + 1j * v[6:])
+        return np.linalg.norm(H @ W - np.eye(6)) ** 2
+
+    best = minimize(obj, np.concatenate([np.full(6, 0.1), np.zeros(6)]), method="BFGS",
+                    options={"gtol": 1e-12}).x
+    assert np.allclose(best[:6] + 1j * best[6:], w, atol=1e-6)
+    assert obj(np.concatenate([w.real, w.imag])) <= obj(best) + 1e-12
+    xe = wl.equispaced_nodes(8, 2)
+    np.testing.assert_allclose(weights.weights_pcf(xe, 8), 1.0 / 64, rtol=1e-12)
+
+
+def test_relaxed_weights_solve_the_summed_conditions():
+    """(3.63): A A^* w = 1_N; 1/N on an equispaced grid with n = M; and the
+    conjugate of Algorithm 3.6's weights (conditions (3.14) hold on I_M) solves
+    the same consistent system."""
+    x = wl.uniform_nodes(500, 1, 901)
+    M = 12
+    w = weights.weights_relaxed(x, M)
+    H = weights.gram_nodes(x, M)
+    np.testing.assert_allclose(H @ w, np.ones(500), atol=1e-9)
+    xe = wl.equispaced_nodes(16, 1)
+    np.testing.assert_allclose(weights.weights_relaxed(xe, 16), 1.0 / 16, rtol=1e-12)
+    v = np.conj(weights.weights_lstsq(x, M // 2))
+    np.testing.assert_allclose(H @ v, np.ones(500), atol=1e-9)
