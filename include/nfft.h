@@ -243,6 +243,22 @@ int nfft_weights(int d, int M, double sigma, int m, int64_t N, const double *nod
                  int maxit, void *w, double *info, void *stream);
 
 /*
+ * nfft_weights_ex -- nfft_weights with a choice of scheme:
+ *   NFFT_WEIGHTS_ALG36    Algorithm 3.6 as above (info[2] = 15 or 16);
+ *   NFFT_WEIGHTS_RELAXED  the summed conditions A A^* w = 1_N of (3.63),
+ *                         float64 CG with the NFFT at bandwidth M; info[2] = 63
+ *                         and info[3] = max_j |[A A^* w]_j - 1|;
+ *   NFFT_WEIGHTS_PCF      (3.62), the minimiser of ||A A^* W - I_N||_F over
+ *                         diagonal W: w_j = |I_M| / sum_h |[A A^*]_{j,h}|^2,
+ *                         evaluated directly over all N^2 pairs in float64
+ *                         with the Dirichlet-kernel form of the entries
+ *                         (sigma, m, tol, maxit unused); info[2] = 62.
+ */
+enum nfft_weight_scheme { NFFT_WEIGHTS_ALG36 = 0, NFFT_WEIGHTS_RELAXED = 1, NFFT_WEIGHTS_PCF = 2 };
+int nfft_weights_ex(int d, int M, double sigma, int m, int64_t N, const double *nodes, int scheme,
+                    double tol, int maxit, void *w, double *info, void *stream);
+
+/*
  * Optimized sparse matrix (Section 4): Algorithm 4.3 on the device in float64
  * and the reconstruction of Algorithm 4.4, h_opt = D^* F^* B_opt^* f
  * (eq. (4.12)), a modified adjoint NFFT that needs no weights.

@@ -1048,13 +1048,44 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
 
 int nfft_weights(int d, int M, double sigma, int m, int64_t N, const double* nodes, double tol,
                  int maxit, void* w_out, double* info, void* stream) {
+  return nfft_weights_ex(d, M, sigma, m, N, nodes, NFFT_WEIGHTS_ALG36, tol, maxit, w_out, info,
+                         stream);
+}
+
+int nfft_weights_ex(int d, int M, double sigma, int m, int64_t N, const double* nodes, int scheme,
+                    double tol, int maxit, void* w_out, double* info, void* stream) {
   if (!w_out) return fail(nullptr, NFFT_EINVAL, "w is NULL");
+  if (scheme != NFFT_WEIGHTS_ALG36 && scheme != NFFT_WEIGHTS_RELAXED && scheme != NFFT_WEIGHTS_PCF)
+    return fail(nullptr, NFFT_EINVAL, "weight scheme %d unknown", scheme);
   if (!(tol > 0.0) || maxit < 1)
     return fail(nullptr, NFFT_EINVAL, "tol = %g, maxit = %d: expected tol > 0, maxit >= 1", tol, maxit);
   if (M < 2 || M > (1 << 20) || (M % 2) != 0)
     return fail(nullptr, NFFT_EINVAL, "M = %d, expected an even M >= 2", M);
+  if (scheme == NFFT_WEIGHTS_PCF) {
+    // (3.62) directly: O(N^2) pairs
+    if (d < 1 || d > 3) return fail(nullptr, NFFT_EINVAL, "d = %d, expected 1, 2 or 3", d);
+    if (N < 1 || N > 0x7fffffffLL) return fail(nullptr, NFFT_EINVAL, "N out of range");
+    if (!nodes) return fail(nullptr, NFFT_EINVAL, "nodes is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    void* dx = nullptr;
+    if (hipMalloc(&dx, N * d * sizeof(double)) != hipSuccess)
+      return fail(nullptr, NFFT_ENOMEM, "no device memory for the nodes");
+    ScopedFree keep;
+    keep.ptrs.push_back(dx);
+    HIP_TRY(nullptr, hipMemcpyAsync(dx, nodes, N * d * sizeof(double), hipMemcpyDefault, s));
+    HIP_TRY(nullptr, nfft::launch_pcf((const double*)dx, N, d, M, (cplx<double>*)w_out, s));
+    HIP_TRY(nullptr, hipStreamSynchronize(s));
+    if (info) {
+      info[0] = 0;
+      info[1] = 0;
+      info[2] = 62;
+      info[3] = 0;
+    }
+    return NFFT_OK;
+  }
+  const bool relaxed = scheme == NFFT_WEIGHTS_RELAXED;
   nfft_plan_t p = nullptr;
-  int st = nfft_plan(&p, d, 2 * M, sigma, m, N, nodes, NFFT_F64, 1, stream);
+  int st = nfft_plan(&p, d, relaxed ? M : 2 * M, sigma, m, N, nodes, NFFT_F64, 1, stream);
   if (st != NFFT_OK) return st;
   struct PlanGuard {
     nfft_plan_t p;
@@ -1062,8 +1093,9 @@ int nfft_weights(int d, int M, double sigma, int m, int64_t N, const double* nod
   } guard{p};
   hipStream_t s = (hipStream_t)stream;
   using C = cplx<double>;
-  const int64_t K2 = ipow(2 * M, d);
-  const bool b15 = K2 <= N;           // Algorithm 3.6 step 2: which normal equations
+  const int64_t K2 = ipow(relaxed ? M : 2 * M, d);
+  // Algorithm 3.6 step 2: which normal equations; (3.63) is always a system in C^N
+  const bool b15 = !relaxed && K2 <= N;
   const int64_t n = b15 ? K2 : N;     // length of the CG vectors
   int64_t e_idx = 0;                  // index of k = 0 in I_2M (C order, k_t from -M)
   for (int t = 0; t < d; ++t) e_idx = e_idx * (2 * M) + M;
@@ -1142,23 +1174,30 @@ int nfft_weights(int d, int M, double sigma, int m, int64_t N, const double* nod
     rr = rr_new;
     ++it;
   }
-  // conj(w): (3.15) forward of the solution, (3.16) the solution itself
+  // conj(w): (3.15) forward of the solution, (3.16) the solution itself;
+  // (3.63): w itself (A A^* is the operator, no conjugation)
   C* w = (C*)w_out;
   if (b15)
     TRY(run_forward<double>(p, x, w, 1, s));
   else
     HIP_TRY(nullptr, hipMemcpyAsync(w, x, N * sizeof(C), hipMemcpyDeviceToDevice, s));
-  // epsilon: A_2M^T w = conj(adjoint(conj w)), and e_0 is real
-  C* at = b15 ? q : tmp;
-  TRY(run_adjoint<double>(p, w, at, 1, s));
   double eps = 0.0;
-  TRY(reduce(at, at, K2, 1, &eps));
-  HIP_TRY(nullptr, nfft::launch_conj(w, N, s));
+  if (relaxed) {
+    // max_j |[A A^* w]_j - 1|
+    TRY(apply(w, q));
+    TRY(reduce(q, q, N, 2, &eps));
+  } else {
+    // epsilon: A_2M^T w = conj(adjoint(conj w)), and e_0 is real
+    C* at = b15 ? q : tmp;
+    TRY(run_adjoint<double>(p, w, at, 1, s));
+    TRY(reduce(at, at, K2, 1, &eps));
+    HIP_TRY(nullptr, nfft::launch_conj(w, N, s));
+  }
   HIP_TRY(nullptr, hipStreamSynchronize(s));
   if (info) {
     info[0] = it;
     info[1] = nb > 0 ? std::sqrt(rr) / nb : 0.0;
-    info[2] = b15 ? 15 : 16;
+    info[2] = relaxed ? 63 : (b15 ? 15 : 16);
     info[3] = eps;
   }
   return NFFT_OK;

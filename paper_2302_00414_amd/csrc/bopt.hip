@@ -17,6 +17,7 @@
 
 #include <cstdint>
 
+#include "dirichlet.hpp"
 #include "internal.hpp"
 
 namespace nfft {
@@ -85,25 +86,6 @@ __device__ __forceinline__ void window_series(const double* __restrict__ wh, int
   sincospi((double)M * s, &sm, &cm);
   *re = wh[H] + b1 * c - b2 + wh[0] * cm;
   *im = -wh[0] * sm;
-}
-
-__device__ __forceinline__ void dirichlet_term(int M, double s, double* re, double* im) {
-  double sn, cs;
-  sincospi(s, &sn, &cs);
-  double dk;
-  if (fabs(sn) < 1e-12) {
-    double s2, c2;
-    sincospi((double)(M - 1) * s, &s2, &c2);
-    dk = (double)(M - 1) * c2 / cs;
-  } else {
-    double s2, c2;
-    sincospi((double)(M - 1) * s, &s2, &c2);
-    dk = s2 / sn;
-  }
-  double sm, cm;
-  sincospi((double)M * s, &sm, &cm);
-  *re = dk + cm;
-  *im = -sm;
 }
 
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // i >= j

@@ -167,6 +167,7 @@ hipError_t launch_bopt_gather(const int32_t* lo, const R* rows, const cplx<R>* g
 size_t reduce_scratch_doubles();
 hipError_t launch_fill(cplx<double>* v, int64_t n, double re, double im, hipStream_t s);
 hipError_t launch_conj(cplx<double>* v, int64_t n, hipStream_t s);
+hipError_t launch_pcf(const double* x, int64_t N, int d, int M, cplx<double>* w, hipStream_t s);
 hipError_t launch_reduce(const cplx<double>* a, const cplx<double>* b, int64_t n, int op,
                          int64_t e_idx, double* scratch, hipStream_t s);
 hipError_t launch_cg_update(cplx<double>* x, cplx<double>* r, const cplx<double>* p,

@@ -3,6 +3,7 @@
 // order (deterministic), fused vector updates and the residual maximum.
 #include <algorithm>
 
+#include "dirichlet.hpp"
 #include "internal.hpp"
 
 namespace nfft {
@@ -35,7 +36,8 @@ __global__ __launch_bounds__(kRedThreads) void reduce_pass1(const cplx<double>* 
     if (op == 0) {
       acc += a[i].x * b[i].x + a[i].y * b[i].y;
     } else {
-      const double dx = a[i].x - (i == e_idx ? 1.0 : 0.0);
+      // op 1: distance to the unit vector at e_idx; op 2: to the all-ones vector
+      const double dx = a[i].x - ((op == 2 || i == e_idx) ? 1.0 : 0.0);
       acc = fmax(acc, sqrt(dx * dx + a[i].y * a[i].y));
     }
   }
@@ -86,6 +88,43 @@ __global__ void cg_direction_kernel(cplx<double>* p, const cplx<double>* r, int6
   p[i].y = r[i].y + beta * p[i].y;
 }
 
+// (3.62): w_j = |I_M| / sum_h |[A A^*]_{j,h}|^2 with
+// [A A^*]_{j,h} = prod_t (D_{M/2-1} + e^{-M pi i .})(x_jt - x_ht); every
+// thread sums over all h in a fixed order, the coordinates staged in LDS
+__global__ __launch_bounds__(256) void pcf_kernel(const double* __restrict__ x, int64_t N, int d,
+                                                  int M, cplx<double>* __restrict__ w) {
+  __shared__ double xs[256 * 3];
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double xj[3] = {0, 0, 0};
+  if (j < N)
+    for (int t = 0; t < d; ++t) xj[t] = x[j * d + t];
+  double sum = 0.0;
+  for (int64_t h0 = 0; h0 < N; h0 += 256) {
+    __syncthreads();
+    const int64_t hh = h0 + threadIdx.x;
+    if (hh < N)
+      for (int t = 0; t < d; ++t) xs[threadIdx.x * 3 + t] = x[hh * d + t];
+    __syncthreads();
+    const int nh = (int)((N - h0) < 256 ? (N - h0) : 256);
+    for (int q = 0; q < nh; ++q) {
+      double pr = 1.0, pi = 0.0;
+      for (int t = 0; t < d; ++t) {
+        double re, im;
+        dirichlet_term(M, xj[t] - xs[q * 3 + t], &re, &im);
+        const double nr = pr * re - pi * im;
+        pi = pr * im + pi * re;
+        pr = nr;
+      }
+      sum += pr * pr + pi * pi;
+    }
+  }
+  if (j < N) {
+    double md = 1.0;
+    for (int t = 0; t < d; ++t) md *= (double)M;
+    w[j] = mkc<double>(md / sum, 0.0);
+  }
+}
+
 unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -98,13 +137,18 @@ hipError_t launch_fill(cplx<double>* v, int64_t n, double re, double im, hipStre
   return hipGetLastError();
 }
 
+hipError_t launch_pcf(const double* x, int64_t N, int d, int M, cplx<double>* w, hipStream_t s) {
+  hipLaunchKernelGGL(pcf_kernel, dim3(blocks(N)), dim3(256), 0, s, x, N, d, M, w);
+  return hipGetLastError();
+}
+
 hipError_t launch_conj(cplx<double>* v, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(conj_kernel, dim3(blocks(n)), dim3(256), 0, s, v, n);
   return hipGetLastError();
 }
 
-// op 0: Re <a, b>; op 1: max_i |a_i - delta_{i, e_idx}|. The result lands in
+// op 0: Re <a, b>; op 1: max_i |a_i - delta_{i, e_idx}|; op 2: max_i |a_i - 1|. The result lands in
 // scratch[kRedBlocks] (device); scratch holds reduce_scratch_doubles() values.
 hipError_t launch_reduce(const cplx<double>* a, const cplx<double>* b, int64_t n, int op,
                          int64_t e_idx, double* scratch, hipStream_t s) {

@@ -142,18 +142,35 @@ def nfft_weights(d: int, M: int, sigma: float, m: int, nodes: torch.Tensor, tol:
             "branch": "3.15" if int(info[2]) == 15 else "3.16", "epsilon": float(info[3])}
 
 
+WEIGHT_SCHEMES = {"alg3.6": 0, "relaxed": 1, "pcf": 2}
+_BRANCH = {15: "3.15", 16: "3.16", 62: "3.62", 63: "3.63"}
+
+
+def nfft_weights_ex(d: int, M: int, sigma: float, m: int, nodes: torch.Tensor, scheme, tol: float,
+                    maxit: int, w: torch.Tensor, stream=None) -> dict:
+    info = (ctypes.c_double * 4)()
+    sch = WEIGHT_SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+    check(_lib.load().nfft_weights_ex(d, M, float(sigma), m, nodes.shape[0],
+                                      ctypes.c_void_p(nodes.data_ptr()), sch, float(tol), int(maxit),
+                                      ctypes.c_void_p(w.data_ptr()), info, _stream_ptr(stream)), None)
+    return {"iterations": int(info[0]), "rel_residual": float(info[1]),
+            "branch": _BRANCH.get(int(info[2]), str(int(info[2]))), "epsilon": float(info[3])}
+
+
 def compute_weights(nodes, M: int, sigma: float = 2.0, m: int = 8, tol: float = 1e-13,
-                    maxit: int = 1000, device=None, stream=None):
-    """Density-compensation weights of Algorithm 3.6 for a node set, computed
-    on the GPU in float64. Returns (w, info): w complex128 on the device in
-    the caller's node order, info with iterations, relative residual, branch
-    and epsilon."""
+                    maxit: int = 1000, device=None, stream=None, scheme: str = "alg3.6"):
+    """Density-compensation weights for a node set, computed on the GPU in
+    float64: Algorithm 3.6 (scheme "alg3.6", the default), the relaxed
+    conditions A A^* w = 1 of (3.63) ("relaxed") or the PCF weights (3.62)
+    ("pcf"). Returns (w, info): w complex128 on the device in the caller's
+    node order, info with iterations, relative residual, branch and epsilon
+    (for "relaxed": max |A A^* w - 1|)."""
     dev = torch.device(device or "cuda")
     x = _as_f64_nodes(nodes).to(dev)
     N, d = x.shape
     w = torch.empty(N, dtype=torch.complex128, device=dev)
     with torch.cuda.device(dev):
-        info = nfft_weights(d, M, sigma, m, x, tol, maxit, w, stream)
+        info = nfft_weights_ex(d, M, sigma, m, x, scheme, tol, maxit, w, stream)
     return w, info
 
 
