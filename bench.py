@@ -12,7 +12,7 @@ region). Prints one JSON line: points/s of the float32 path (value), per-step
 latency percentiles, the float64 path's figures, per-stage times with their
 HBM rates from algorithmic bytes, the roofline position of the spreading
 kernel (timed with HIP events on the library's stream inside the timed
-region), the batched form (spiral, 131072 nodes, 32 right-hand sides, one
+region, on every PROFILE_EVERY-th step), the batched form (spiral, 131072 nodes, 32 right-hand sides, one
 fused float32 call against 32 float64 calls) and the FP64 CPU oracle timed
 on a bounded sample.
 
@@ -34,6 +34,8 @@ METRIC = "nonuniform points/s for weighted adjoint NFFT (2D M=256, rel err<=1e-5
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
+# stage events are recorded on every PROFILE_EVERY-th step of a timed region
+PROFILE_EVERY = 8
 R_POLAR = T_POLAR = 512
 M, SIGMA, MW, D = 256, 2.0, 6, 2
 
@@ -82,15 +84,24 @@ def run_gpu(prec, x, w, f, steps, warmup, tuning="auto"):
         plan.adjoint(fd, out=out)
     torch.cuda.synchronize()
 
-    # timed region: K back-to-back steps, stage events recorded by the library
-    plan.stage_times(reset=True)
+    # one untimed profiled pass fills the library's event pool, so the timed
+    # region records stage events without creating any
     plan.set_profiling(True)
+    for _ in range(steps // PROFILE_EVERY + 1):
+        plan.adjoint(fd, out=out)
+    torch.cuda.synchronize()
+    plan.stage_times(reset=True)
+
+    # timed region: K back-to-back steps; the library records its stage events
+    # (HIP events on its stream around every kernel) on every PROFILE_EVERY-th
+    # step, so that the events cost little of the measured throughput
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record()
-    for _ in range(steps):
+    for i in range(steps):
+        plan.set_profiling(i % PROFILE_EVERY == 0)
         plan.adjoint(fd, out=out)
     ev1.record()
     torch.cuda.synchronize()
@@ -131,13 +142,16 @@ def run_forward(prec, x, steps):
     out = torch.empty(x.shape[0], dtype=cdt, device="cuda")
     for _ in range(5):
         plan.forward(fh, out=out)
+    plan.set_profiling(True)
+    for _ in range(steps // PROFILE_EVERY + 1):
+        plan.forward(fh, out=out)
     torch.cuda.synchronize()
     plan.stage_times(reset=True)
-    plan.set_profiling(True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(steps):
+    for i in range(steps):
+        plan.set_profiling(i % PROFILE_EVERY == 0)
         plan.forward(fh, out=out)
     e1.record()
     torch.cuda.synchronize()
@@ -290,9 +304,25 @@ def traffic_record(kernel):
     return rec.get("bytes_per_launch")
 
 
+# sources of the d = 2 single-rhs spreading kernels
+SPREAD_SOURCES = ("spread.hip", "spread_common.hpp", "spread_group.hpp", "spread_pre.hip",
+                  "spread_rows.hip")
+
+
+def spread_kernel_name(t):
+    """Name of the spreading kernel the library launches for this tuning
+    (d = 2, m = 6, float32, one right-hand side), as the profiler prints it."""
+    T, mode = t["tile_edge"], t["spread_mode"]
+    if mode == 2 and T + 2 * MW <= 32:
+        return f"spread_rows_kernel<float, {MW}, {T if T == 16 else 0}, 1>"
+    return (f"spread_group_kernel<float, 2, {MW}, {t['spread_threads']}, "
+            f"{T if T in (8, 16) else 0}, {'true' if t['spread_planes'] == 2 else 'false'}, "
+            f"{'true' if mode == 3 else 'false'}>")
+
+
 def spread_source_sha():
     h = hashlib.sha256()
-    for name in ("spread.hip", "spread_common.hpp"):
+    for name in SPREAD_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_2302_00414_amd", "csrc", name), "rb").read())
     return h.hexdigest()
 
@@ -355,9 +385,7 @@ def main():
     flops = spread_flops(N, MW, D)
     achieved = flops / sp_avg_s / 1e12
     t = r32["tuning"]
-    kname = (f"spread_group_kernel<float, 2, 6, {t['spread_threads']}, "
-             f"{t['tile_edge'] if t['tile_edge'] in (8, 16) else 0}, "
-             f"{'true' if t['spread_planes'] == 2 else 'false'}>")
+    kname = spread_kernel_name(t)
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_PEAK_TFLOPS,
                     unit="TFLOP/s", frac=round(achieved / FP32_PEAK_TFLOPS, 5),
                     traffic=traffic_record(kname),
@@ -396,6 +424,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(r32["lat"], 50)),
                        "p99": float(np.percentile(r32["lat"], 99))},
         "stage_us": stage_us,
+        "stage_events": f"HIP events on the library stream, every {PROFILE_EVERY}th timed step",
         "stage_hbm": hbm(stage_us, "f32"),
         "tuning": r32["tuning"],
         "f64": {"value": N / (r64["ms_per_step"] / 1e3), "ms_per_step": r64["ms_per_step"],

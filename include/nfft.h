@@ -119,6 +119,16 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
  *                             row sweep (nodes of a tile taken row by row,
  *                             the rows a node reaches kept in registers;
  *                             needs T + 2m <= 32; resolved to 1 elsewhere).
+ *                             3 = as 1, with the 2m window factors per
+ *                             dimension of every node read from a table
+ *                             computed once per node set (Algorithm 2.4
+ *                             step 1 with the values of the window
+ *                             precomputed, as the node set is fixed) instead
+ *                             of evaluated on every call; the plan keeps
+ *                             16 m (float32) or 32 m (float64) more bytes
+ *                             per node; resolved to 1 for d != 2, and a
+ *                             call with nrhs > 1 and NFFT_TUNE_RHS_PER_GROUP
+ *                             > 1 spreads as mode 1 does.
  *                             Default 1; the row sweep wins with many
  *                             right-hand sides per call, and in float32
  *                             takes two of them per wave when
@@ -156,6 +166,10 @@ int nfft_get_tuning(nfft_plan_t plan, int *out, int n);
  * NFFT_TUNE_SPREAD_PLANES, NFFT_TUNE_SPREAD_MODE; value 0 restores the
  * default). Tile edge and item size are fixed at plan
  * time: NFFT_EINVAL for them. Takes effect for transforms enqueued later.
+ * Switching a d = 2 plan to spread mode 3 the first time builds its window
+ * factor table: it allocates device memory (NFFT_ENOMEM if there is none;
+ * the tuning is then unchanged) and runs one kernel on the null stream,
+ * which the call waits for.
  */
 int nfft_set_tuning(nfft_plan_t plan, int knob, int value);
 
@@ -310,8 +324,10 @@ int nfft_destroy(nfft_plan_t plan);
 
 /*
  * nfft_footprint -- upper bound of the device bytes a plan with these
- * parameters allocates (the exact figure depends on how the nodes fill the
- * tiles; nfft_plan_info reports it). -1 on invalid arguments.
+ * parameters and the default tile edge and work-item size allocates, the
+ * window factor table of spread mode 3 included (the exact figure depends on
+ * how the nodes fill the tiles; nfft_plan_info reports it). -1 on invalid
+ * arguments.
  */
 int64_t nfft_footprint(int d, int M, double sigma, int m, int64_t N, int precision, int max_rhs);
 

@@ -70,6 +70,8 @@ struct SharedData {
   int bopt_nmax = 0;
   int32_t* bopt_lo = nullptr;     // first support cell per node and dimension (caller order)
   void* bopt_rows = nullptr;      // values by rows: N x (2m+1)^d in footprint order
+  // window factors of every node (d = 2, spread mode 3), [N][2][2m] in tile order
+  void* psi = nullptr;
   ~SharedData() {
     for (void* q : allocs) (void)hipFree(q);
   }
@@ -216,8 +218,10 @@ int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, in
   if (planes != 1 && planes != 2)
     return fail(p, NFFT_EINVAL, "spread planes %d: expected 1 or 2", planes);
   int& mode = out[NFFT_TUNE_SPREAD_MODE];
-  if (mode != 1 && mode != 2) return fail(p, NFFT_EINVAL, "spread mode %d: expected 1 or 2", mode);
+  if (mode < 1 || mode > 3)
+    return fail(p, NFFT_EINVAL, "spread mode %d: expected 1, 2 or 3", mode);
   if (mode == 2 && !nfft::spread_rows_supported(d, T + 2 * m)) mode = 1;
+  if (mode == 3 && d != 2) mode = 1;  // the factor table is laid out for d = 2
   const int fw = out[NFFT_TUNE_FFT_MIN_WG];
   if (fw < 1 || fw > 65536) return fail(p, NFFT_EINVAL, "fft min work-groups %d: expected 1..65536", fw);
   const int P = T + 2 * m;
@@ -405,6 +409,33 @@ int alloc_workspace(nfft_plan_t p, hipStream_t s) {
   return NFFT_OK;
 }
 
+// Window factor table of spread mode 3 (d = 2): computed once per node set
+// and shared by clones; 2 * 2m reals per node.
+template <typename R>
+int ensure_psi(nfft_plan_t p, hipStream_t s) {
+  if (p->d != 2 || p->shared->psi) return NFFT_OK;
+  R* q = nullptr;
+  TRY(dalloc(p, &q, (size_t)p->N * 4 * p->m * sizeof(R)));
+  HIP_TRY(p, nfft::launch_psi<R>((const R*)p->frac, p->N, p->m, (const R*)p->coef, q, s));
+  p->shared->psi = q;
+  return NFFT_OK;
+}
+
+// Free the factor table (nothing may still read it).
+void drop_psi(nfft_plan_t p) {
+  SharedData& sd = *p->shared;
+  if (!sd.psi) return;
+  auto it = std::find(sd.allocs.begin(), sd.allocs.end(), sd.psi);
+  if (it != sd.allocs.end()) sd.allocs.erase(it);
+  sd.bytes -= (int64_t)((size_t)p->N * 4 * p->m * (p->prec == NFFT_F64 ? 8 : 4));
+  (void)hipFree(sd.psi);
+  sd.psi = nullptr;
+}
+
+int ensure_psi_any(nfft_plan_t p, hipStream_t s) {
+  return p->prec == NFFT_F64 ? ensure_psi<double>(p, s) : ensure_psi<float>(p, s);
+}
+
 template <typename R>
 int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
   const int64_t N = p->N;
@@ -529,6 +560,7 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
   TRY(dalloc(p, &p->w, N * sizeof(cplx<R>)));
   TRY(alloc_workspace<R>(p, s));
   TRY(build_tables<R>(p));
+  if (p->tune[NFFT_TUNE_SPREAD_MODE] == 3) TRY(ensure_psi<R>(p, s));
   HIP_TRY(p, hipStreamSynchronize(s));
   return NFFT_OK;
 }
@@ -605,6 +637,7 @@ int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t 
   sa.nr = nrhs > 1 ? p->tune[NFFT_TUNE_RHS_PER_GROUP] : 1;
   sa.planes = p->tune[NFFT_TUNE_SPREAD_PLANES];
   sa.mode = p->tune[NFFT_TUNE_SPREAD_MODE];
+  sa.psi = sa.mode == 3 ? (const R*)p->shared->psi : nullptr;
   HIP_TRY(p, nfft::launch_spread<R>(sa, nrhs, s));
   record(p, se, s);
   nfft::ReduceArgs<R> ra{};
@@ -827,6 +860,7 @@ int64_t nfft_footprint(int d, int M, double sigma, int m, int64_t N, int precisi
   if (d == 3) bytes += R_ * Ms * M * M * cb;
   bytes += R_ * ipow(Ms, d) * cb;                         // forward grid
   bytes += M * rb + Ms * cb;                              // tables
+  if (d == 2) bytes += N * 4 * m * rb;                    // window factors (spread mode 3)
   return bytes;
 }
 
@@ -961,7 +995,7 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
     planes = {1, 2};
   }
   if (d <= 2 && nrhs > 1) rpg = {1, 2, 4, 8};
-  if (d == 2) modes = {1, 2};
+  if (d == 2) modes = {1, 2, 3};
 
   nfft_plan_t best = nullptr;
   double best_t = -1.0;
@@ -987,6 +1021,8 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
         return fail(nullptr, NFFT_EDEVICE, "hipMemsetAsync failed");
       }
       bool mine = false;  // p is (or became) the best plan
+      // the factor table of mode 3; without room for it mode 3 is skipped
+      const bool have_psi = d == 2 && ensure_psi_any(p, s) == NFFT_OK;
       for (int md : modes)
       for (int nt : threads)
         for (int pl : planes)
@@ -1000,6 +1036,7 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
             // the LDS kernel's shape does not matter when another kernel spreads
             if ((nr > 1 || md == 2) && (nt != threads[0] || pl != planes[0])) continue;
             if (nr > 2 && md == 2) continue;  // the row sweep takes at most two rhs per wave
+            if (md == 3 && (!have_psi || nr > 1)) continue;  // mode 3 is single-rhs only
             int res[NFFT_TUNE_COUNT];
             if (resolve_tuning(d, Ms, m, precision, in, NFFT_TUNE_COUNT, res, nullptr) != NFFT_OK)
               continue;
@@ -1040,6 +1077,7 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
     free_plan(best);
     return fail(nullptr, NFFT_EDEVICE, "device failure while timing candidates");
   }
+  if (best->tune[NFFT_TUNE_SPREAD_MODE] != 3) drop_psi(best);
   best->shared->has_weights = false;
   if (best_ms) *best_ms = best_t;
   *out = best;
@@ -1368,6 +1406,11 @@ int nfft_set_tuning(nfft_plan_t p, int knob, int value) {
   in[knob] = value;
   const int st = resolve_tuning(p->d, p->Ms, p->m, p->prec, in, NFFT_TUNE_COUNT, out, p);
   if (st != NFFT_OK) return st;
+  if (out[NFFT_TUNE_SPREAD_MODE] == 3 && !p->shared->psi) {
+    // the factor table is built once, on the null stream, before the switch
+    TRY(ensure_psi_any(p, nullptr));
+    HIP_TRY(p, hipStreamSynchronize(nullptr));
+  }
   std::copy(out, out + NFFT_TUNE_COUNT, p->tune);
   return NFFT_OK;
 }

@@ -60,7 +60,9 @@ struct SpreadArgs {
   int nt;                    // threads per work-group, d <= 2 float32 single-rhs kernel
   int nr;                    // right-hand sides per work-group (1, 2, 4 or 8; d <= 2)
   int planes;                // 2: float32 real and imaginary planes in separate groups
-  int mode;                  // d = 2 single rhs: 1 LDS tiles, 2 register row sweep
+  int mode;                  // d = 2 single rhs: 1 LDS tiles, 2 register row sweep,
+                             // 3 LDS tiles with precomputed window factors
+  const R* psi;              // d = 2: window factors [N][2][2m] in tile order (mode 3)
 };
 template <typename R>
 hipError_t launch_spread(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
@@ -68,6 +70,13 @@ hipError_t launch_spread(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
 bool spread_rows_supported(int d, int P);
 template <typename R>
 hipError_t launch_spread_rows(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
+// Group kernel reading the precomputed window factors (d = 2, a.psi set).
+template <typename R>
+hipError_t launch_spread_pre(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
+// Window factors of every node (tile order), [N][2][2m], from the same
+// per-cell polynomials the spreading kernels evaluate (d = 2).
+template <typename R>
+hipError_t launch_psi(const R* frac, int64_t N, int m, const R* coef, R* psi, hipStream_t s);
 // Several right-hand sides per work-group (d <= 2, nr > 1).
 template <typename R>
 hipError_t launch_spread_multi(const SpreadArgs<R>& a, int nrhs, hipStream_t s);

@@ -89,6 +89,7 @@ template <> struct GroupAcc<double> {
 template <typename R, int K2>
 struct NodePrep {
   R vx, vy, p0, cx, cy;
+  R q1;  // column factor of lane k, from the precomputed table
   R rw[K2];
   int l0, l1;
   bool e0, e1;
@@ -118,6 +119,34 @@ __device__ __forceinline__ void prep_node(NodePrep<R, K2>& h, R y0, R y1, R cx, 
       h.rw[I] = row_bcast<I>(h.p0);
     });
   }
+}
+
+// The same values from the table of window factors precomputed at plan time:
+// q holds the node's 2m factors of dimension 0, then the 2m of dimension 1.
+// Every lane of a group loads the row factors (one address per group), lane k
+// its column factor (q1; vx and vy are left to the caller).
+template <typename R, int K2>
+__device__ __forceinline__ void prep_node_pre(NodePrep<R, K2>& h, const R* q, R cx, R cy,
+                                              uint32_t L, int k) {
+  h.cx = cx;
+  h.cy = cy;
+  h.l0 = (int)(L & kLocMask);
+  h.e0 = (L >> kEdgeShift) & 1u;
+  h.l1 = (int)((L >> kLocBits) & kLocMask);
+  h.e1 = (L >> (kEdgeShift + 1)) & 1u;
+  // node rows start 16-byte aligned (2m factors of 4 or 8 bytes, twice)
+  constexpr int VW = (K2 * sizeof(R)) % 16 == 0 ? 16 / sizeof(R) : 8 / sizeof(R);
+  using V = typename std::conditional<VW * sizeof(R) == 16, float4, float2>::type;
+  static_for<0, K2 / VW>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    const V v = reinterpret_cast<const V*>(q)[I];
+    __builtin_memcpy(&h.rw[I * VW], &v, sizeof(V));
+  });
+  // the products with c_j are taken where they are used, so that nothing
+  // waits for these loads here
+  const int kk = k < K2 ? k : 0;
+  h.q1 = q[K2 + kk];
+  h.p0 = q[kk];
 }
 
 }  // namespace nfft

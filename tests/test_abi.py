@@ -85,7 +85,9 @@ def test_f64_3d_large_m_unsupported():
     (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 70000], _lib.NFFT_EINVAL),  # fft min work-groups
     (2, 6, _lib.NFFT_F32, [-1], _lib.NFFT_EINVAL),                # negative entry
     (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 3], _lib.NFFT_EINVAL),  # spread planes not 1/2
-    (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 3], _lib.NFFT_EINVAL),  # spread mode not 1/2
+    (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 4], _lib.NFFT_EINVAL),  # spread mode not 1/2/3
+    (2, 6, _lib.NFFT_F64, [0, 0, 0, 0, 0, 0, 3], _lib.NFFT_OK),   # precomputed window factors
+    (3, 4, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 3], _lib.NFFT_OK),   # mode 3 resolves to 1 for d = 3
     (2, 8, _lib.NFFT_F32, [32, 0, 256, 0, 0, 2], _lib.NFFT_OK),   # 16 float32 48^2 planes fit
     (3, 4, _lib.NFFT_F32, [32], _lib.NFFT_EUNSUPPORTED),          # 40^3 padded tile exceeds LDS
     (2, 8, _lib.NFFT_F32, [64, 0, 256], _lib.NFFT_EUNSUPPORTED),  # 16 private 80^2 tiles exceed LDS
@@ -149,5 +151,8 @@ def test_footprint_grows_with_inputs():
     a = lib.nfft_footprint(2, 256, 2.0, 6, 262144, _lib.NFFT_F32, 1)
     b = lib.nfft_footprint(2, 256, 2.0, 6, 262144, _lib.NFFT_F64, 1)
     c = lib.nfft_footprint(2, 256, 2.0, 6, 262144, _lib.NFFT_F32, 32)
-    assert 0 < a < b and c > 16 * a
+    assert 0 < a < b and c > 8 * a
+    # the per-node part: window factor table (4 m reals) among the node arrays
+    n2 = lib.nfft_footprint(2, 256, 2.0, 6, 2 * 262144, _lib.NFFT_F32, 1)
+    assert n2 - a >= 262144 * 4 * 6 * 4
     assert lib.nfft_footprint(2, 31, 2.0, 6, 10, 0, 1) == -1

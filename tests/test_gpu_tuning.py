@@ -77,6 +77,10 @@ TUNINGS = [
     {"spread_mode": 2, "tile_edge": 8, "item_nodes": 32},
     {"spread_mode": 2, "item_nodes": 1000},
     {"spread_mode": 2, "tile_edge": 32},   # padded edge 44 > 32: resolved to the LDS kernel
+    {"spread_mode": 3},
+    {"spread_mode": 3, "spread_planes": 2, "spread_threads": 64},
+    {"spread_mode": 3, "tile_edge": 8, "item_nodes": 32, "spread_threads": 256},
+    {"spread_mode": 3, "tile_edge": 32, "item_nodes": 1000},
 ]
 
 
@@ -96,7 +100,7 @@ def test_tunings_agree(tuning, prec):
     p = _plan(x, M, m, prec, tuning=tuning)
     got_t = p.tuning()
     for k, v in tuning.items():
-        if k == "spread_mode" and tuning.get("tile_edge") == 32:
+        if k == "spread_mode" and v == 2 and tuning.get("tile_edge") == 32:
             assert got_t[k] == 1
             continue
         assert got_t[k] == v, (k, got_t)
@@ -107,6 +111,45 @@ def test_tunings_agree(tuning, prec):
     assert metrics.rel_err(a, a0) <= TOL_ORDER[prec]
     assert metrics.rel_err(b, b0) <= TOL_ORDER[prec]
     base.close()
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("m", [1, 3, 4, 7, 8])
+def test_precomputed_window_factors(prec, m):
+    """Spread mode 3 reads the window factors from a table built once per node
+    set with the same polynomials and arithmetic as the lanes of mode 1: the
+    same plan switched between the two modes gives the same adjoint (float32
+    single-rhs kernels sum in a fixed order, so up to the last bit there; the
+    float64 kernels sum with LDS atomics), for one and for several
+    right-hand sides, and the table costs 4 m reals per node."""
+    M = 32
+    x = _nodes(2, M, 90 + m)
+    N = x.shape[0]
+    w = (1.0 + 0.3 * wl.complex_normal(N, 91)) / N
+    F = wl.complex_normal((3, N), 92)
+    p = _plan(x, M, m, prec, max_rhs=3)
+    p.set_weights(w)
+    bytes0 = p.info()["bytes"]
+    a1 = _np(p.adjoint(torch.from_numpy(F)))
+    p.set_tuning("spread_mode", 3)
+    assert p.tuning()["spread_mode"] == 3
+    rb = 8 if prec == "f64" else 4
+    assert p.info()["bytes"] - bytes0 == N * 4 * m * rb
+    a3 = _np(p.adjoint(torch.from_numpy(F)))
+    tol = {"f64": 1e-14, "f32": 1e-7}[prec]
+    for r in range(3):
+        assert metrics.rel_err(a3[r], a1[r]) <= tol, r
+    ref = onfft.adjoint(x, w[None, :] * F, M, 2.0, m)
+    for r in range(3):
+        assert metrics.rel_err(a3[r], ref[r]) <= TOL_O2[prec], r
+    # back to mode 1 and again to mode 3: the table is kept and reused
+    p.set_tuning("spread_mode", 1)
+    p.set_tuning("spread_mode", 3)
+    assert p.info()["bytes"] - bytes0 == N * 4 * m * rb
+    from paper_2302_00414_amd.nfft import nfft_footprint
+    assert nfft_footprint(2, M, 2.0, m, N, prec, 3) >= p.info()["bytes"]
+    assert metrics.rel_err(_np(p.adjoint(torch.from_numpy(F))), a3) <= tol
     p.close()
 
 
