@@ -213,6 +213,94 @@ __device__ __forceinline__ cplx<R> merge_cell2(const cplx<R>* __restrict__ tilep
   return mkc<R>((R)sx, (R)sy);
 }
 
+// The eight elements j + r L/8 (r = 0..7) of grid line q merged from the tile
+// partials, d = 2 or 3, tiles at least 2m wide whose edge divides L/8: the
+// line fixes the leading d - 1 coordinates, and the eight elements sit at the
+// same offset within their tiles, so the candidate tiles, offsets and weights
+// are worked out once for all eight. Same candidates, weights and summation
+// order as merge_cell2, so the same values.
+template <typename R, int D, int TPL>
+__device__ __forceinline__ void merge_line(const FftArgs<R>& a, int b, int64_t q, int j,
+                                           cplx<R> (&v)[8]) {
+  static_assert(D == 2 || D == 3, "lines of a 2-D or 3-D grid");
+  constexpr int NH = 1 << (D - 1);  // candidates over the leading coordinates
+  const Geom& g = a.g;
+  const cplx<R>* __restrict__ tp = a.tilep + b * a.tile_bs;
+  const int tm = g.T - 1, nm = g.nb - 1, ts = g.tshift, bs = g.Ms_shift - ts;
+  int c[2];
+  if constexpr (D == 2) {
+    c[0] = (int)q;
+  } else {
+    c[0] = (int)(q >> g.Ms_shift);
+    c[1] = (int)(q & (g.Ms - 1));
+  }
+  int qb[2][2], pp[2][2];
+  float wt[2];
+#pragma unroll
+  for (int t = 0; t < D - 1; ++t) {
+    const int r = c[t] & tm;
+    const int b0 = c[t] >> ts;
+    const bool lo = r < g.m, hi = r >= g.T - g.m;
+    qb[t][0] = b0;
+    qb[t][1] = lo ? ((b0 - 1) & nm) : (hi ? ((b0 + 1) & nm) : b0);
+    pp[t][0] = r + g.m;
+    pp[t][1] = lo ? r + g.m + g.T : (hi ? r + g.m - g.T : r + g.m);
+    wt[t] = (lo || hi) ? 1.0f : 0.0f;
+  }
+  // leading part of candidate s = (o_0 .. o_{d-2}, o_last): tile row, cell
+  // row offset and the running weight product
+  int bh[NH], ph[NH];
+  float wh[NH];
+#pragma unroll
+  for (int sh = 0; sh < NH; ++sh) {
+    int bin = 0, pl = 0;
+    float ws = 1.0f;
+#pragma unroll
+    for (int t = 0; t < D - 1; ++t) {
+      const int o = (sh >> (D - 2 - t)) & 1;
+      bin = (bin << bs) + qb[t][o];
+      pl = pl * g.P + pp[t][o];
+      ws = o ? ws * wt[t] : ws;
+    }
+    bh[sh] = bin << bs;
+    ph[sh] = pl * g.P;
+    wh[sh] = ws;
+  }
+  // last coordinate: offset within the tile shared by the eight elements
+  const int r1 = j & tm;
+  const bool lo1 = r1 < g.m, hi1 = r1 >= g.T - g.m;
+  const int dq1 = lo1 ? -1 : (hi1 ? 1 : 0);
+  const int pc = r1 + g.m;
+  const int pd = lo1 ? r1 + g.m + g.T : (hi1 ? r1 + g.m - g.T : r1 + g.m);
+  const float wt1 = (lo1 || hi1) ? 1.0f : 0.0f;
+  double w[2 * NH];
+#pragma unroll
+  for (int sh = 0; sh < NH; ++sh) {
+    w[2 * sh] = (double)wh[sh];
+    w[2 * sh + 1] = (double)(wh[sh] * wt1);
+  }
+  const int Ptot = g.Ptot;
+  const int tstep = TPL >> ts;  // tiles between consecutive elements
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int t1 = (j >> ts) + r * tstep;  // element < M_sigma: no wrap
+    const int t1n = (t1 + dq1) & nm;
+    cplx<R> u[2 * NH];
+#pragma unroll
+    for (int sh = 0; sh < NH; ++sh) {
+      u[2 * sh] = tp[(int64_t)(bh[sh] + t1) * Ptot + ph[sh] + pc];
+      u[2 * sh + 1] = tp[(int64_t)(bh[sh] + t1n) * Ptot + ph[sh] + pd];
+    }
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int s = 0; s < 2 * NH; ++s) {
+      sx += w[s] * (double)u[s].x;
+      sy += w[s] * (double)u[s].y;
+    }
+    v[r] = mkc<R>((R)sx, (R)sy);
+  }
+}
+
 template <typename R, int LD>
 __device__ __forceinline__ cplx<R> load_elem(const FftArgs<R>& a, int b, int64_t q, int e, int L) {
   if constexpr (LD == kLoadLine) {
@@ -284,7 +372,15 @@ __global__ __launch_bounds__(512) void fft_pass_kernel(FftArgs<R> a) {
     const int j = threadIdx.x - l * TPL;
     const int64_t q = q0 + l;
     cplx<R> v[8];
-    if (q < nlines) {
+    bool per_line = false;
+    if constexpr (LD == kLoadMerge)
+      per_line = a.g.d >= 2 && a.g.T >= 2 * a.g.m && (TPL & (a.g.T - 1)) == 0;
+    if (q < nlines && per_line) {
+      if (a.g.d == 2)
+        merge_line<R, 2, TPL>(a, b, q, j, v);
+      else
+        merge_line<R, 3, TPL>(a, b, q, j, v);
+    } else if (q < nlines) {
 #pragma unroll
       for (int r = 0; r < 8; ++r) v[r] = load_elem<R, LD>(a, b, q, j + r * TPL, L);
     } else {
