@@ -58,11 +58,14 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
   const size_t acc_bytes = CS     ? (size_t)NG * Ptot * sizeof(float)
                            : PRIV ? (size_t)NG * Ptot * sizeof(float2)
                                   : (size_t)2 * Ptot * sizeof(double);
-  R* st_y0 = reinterpret_cast<R*>(base + acc_bytes);
-  R* st_y1 = st_y0 + NT;
-  R* st_cx = st_y1 + NT;
+  // staged per node: c_j, and without the factor table also the offsets and
+  // the cell word (with it those come from device memory; the smaller
+  // staging area lets one more work-group share a compute unit)
+  R* st_cx = reinterpret_cast<R*>(base + acc_bytes);
   R* st_cy = st_cx + NT;
-  uint32_t* st_loc = reinterpret_cast<uint32_t*>(st_cy + NT);
+  R* st_y0 = st_cy + NT;
+  R* st_y1 = st_y0 + NT;
+  uint32_t* st_loc = reinterpret_cast<uint32_t*>(st_y1 + NT);
   // CS: this group's component of c_j stands in for cx (cy unused)
   const R* st_c0 = (CS && comp) ? st_cy : st_cx;
 
@@ -111,16 +114,20 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
         pf0 = a.frac[i];
         pf1 = D > 1 ? a.frac[N + i] : (R)0;
       }
-      pfl = a.loc[i];
+      if constexpr (!PRE) pfl = a.loc[i];
       pfw = a.w[i];
       pfs = f[a.perm[i]];
     }
   };
   int b0 = 0;  // first node of the staged batch (within the item)
   auto prep = [&](NodePrep<R, K2>& h, int n) {
-    if constexpr (PRE)
-      prep_node_pre<R, K2>(h, a.psi + (int64_t)(start + b0 + n) * (2 * K2), st_c0[n],
-                           CS ? (R)0 : st_cy[n], st_loc[n], k);
+    if constexpr (PRE) {
+      // the cell word from device memory, not the staging area: its wait is
+      // then on the vector-memory counter and does not also wait for this
+      // group's LDS writes issued since (LDS operations complete in order)
+      const int64_t i = start + b0 + n;
+      prep_node_pre<R, K2>(h, a.psi + i * (2 * K2), st_c0[n], CS ? (R)0 : st_cy[n], a.loc[i], k);
+    }
     else
       prep_node<R, D, K2>(h, st_y0[n], st_y1[n], st_c0[n], CS ? (R)0 : st_cy[n], st_loc[n], cf);
   };
@@ -143,7 +150,7 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
       }
       st_cx[tid] = c.x;
       st_cy[tid] = c.y;
-      st_loc[tid] = pfl;
+      if constexpr (!PRE) st_loc[tid] = pfl;
     }
     if (b0 + NT < cnt) issue(b0 + NT);
     __syncthreads();
@@ -158,9 +165,30 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
     // compiler wait for all loads in flight where the paths join.
     auto fetch = [&](NodePrep<R, K2>& hn, int nn) {
       if constexpr (PRE)
-        prep(hn, nn < nb ? nn : nn - NODE_GROUPS);
+        prep(hn, nn < nb ? nn : nb - 1);
       else if (nn < nb)
         prep(hn, nn);
+    };
+    // With the factor table the loads are issued two nodes ahead: three
+    // headers in turn, so a load has two steps of this group's LDS work to
+    // arrive in.
+    auto run3 = [&](auto&& step) {
+      NodePrep<R, K2> h0, h1, h2;
+      int n = ngrp;
+      if (n < nb) {
+        prep(h0, n);
+        fetch(h1, n + NODE_GROUPS);
+      }
+      while (n < nb) {
+        step(h0, h2, n + 2 * NODE_GROUPS);
+        n += NODE_GROUPS;
+        if (n >= nb) break;
+        step(h1, h0, n + 2 * NODE_GROUPS);
+        n += NODE_GROUPS;
+        if (n >= nb) break;
+        step(h2, h1, n + 2 * NODE_GROUPS);
+        n += NODE_GROUPS;
+      }
     };
     if constexpr (PRIV && D == 2) {
       // two headers in turn, so the next node's window is prepared into the
@@ -205,19 +233,23 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
         }
         edges(h, vx, vy, col);
       };
-      NodePrep<R, K2> h0, h1;
-      int n = ngrp;
-      if (n < nb) prep(h0, n);
-      while (n < nb) {
-        step(h0, h1, n + NODE_GROUPS);
-        n += NODE_GROUPS;
-        if (n >= nb) break;
-        step(h1, h0, n + NODE_GROUPS);
-        n += NODE_GROUPS;
+      if constexpr (PRE) {
+        run3(step);
+      } else {
+        NodePrep<R, K2> h0, h1;
+        int n = ngrp;
+        if (n < nb) prep(h0, n);
+        while (n < nb) {
+          step(h0, h1, n + NODE_GROUPS);
+          n += NODE_GROUPS;
+          if (n >= nb) break;
+          step(h1, h0, n + NODE_GROUPS);
+          n += NODE_GROUPS;
+        }
       }
     } else if constexpr (PRE) {
-      // float64 with the factor table: the next node's factors are loaded
-      // before this node's atomics are issued (two headers in turn)
+      // float64 with the factor table: the factors of the node two ahead are
+      // loaded before this node's atomics are issued
       auto step = [&](const NodePrep<R, K2>& h, NodePrep<R, K2>& hn, int nn) {
         fetch(hn, nn);
         const int col = h.l1 + 1 + k;
@@ -229,16 +261,7 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
         }
         edges(h, vx, vy, col);
       };
-      NodePrep<R, K2> h0, h1;
-      int n = ngrp;
-      if (n < nb) prep(h0, n);
-      while (n < nb) {
-        step(h0, h1, n + NODE_GROUPS);
-        n += NODE_GROUPS;
-        if (n >= nb) break;
-        step(h1, h0, n + NODE_GROUPS);
-        n += NODE_GROUPS;
-      }
+      run3(step);
     } else {
       // d = 1, and float64 (shared tile, atomics): the next header is
       // prepared into the same registers after this node's updates
@@ -318,7 +341,7 @@ static hipError_t spread_group_nt(const SpreadArgs<R>& a, int nrhs, hipStream_t 
   const size_t acc = CS ? (size_t)NG * a.g.Ptot * 4
                         : std::is_same<R, float>::value ? (size_t)NG * a.g.Ptot * 8
                                                         : (size_t)2 * a.g.Ptot * 8;
-  const size_t lds = acc + (size_t)NT * (4 * sizeof(R) + 4);
+  const size_t lds = acc + (size_t)NT * (PRE ? 2 * sizeof(R) : 4 * sizeof(R) + 4);
   const dim3 grid(a.g.nsub, nrhs);
   if constexpr (D == 2) {
     if (a.g.T == 16) {
