@@ -10,6 +10,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <numeric>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -98,7 +99,6 @@ struct nfft_plan_s {
   int32_t* item_start = nullptr;
   int32_t* item_count = nullptr;
   int32_t* item_bin = nullptr;
-  int32_t* item_first = nullptr;
   int32_t* item_slot = nullptr;    // itemp slot of an item of a split tile, else -1
   int32_t* multi_bin = nullptr;    // split tiles
   int32_t* multi_first = nullptr;  // first itemp slot of each split tile
@@ -479,7 +479,7 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
 
   // tile starts and work items (at most kItem nodes of one tile each)
   std::vector<int32_t> hstart(g.nbins + 1);
-  std::vector<int32_t> istart, icount, ibin, ifirst(g.nbins + 1);
+  std::vector<int32_t> istart, icount, ibin, ifirst(g.nbins + 1);  // ifirst: items of tile b
   const int kItem = p->tune[NFFT_TUNE_ITEM_NODES];
   int64_t acc = 0;
   p->maxpop = 0;
@@ -508,6 +508,24 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
   mfirst.push_back(p->nslots);
   p->nmulti = (int)mbin.size();
   g.nsub = (int)istart.size();
+  // launch order: largest work items first, so that the work-groups that
+  // start last are the small remainders of tiles (every item writes its own
+  // tile or slot, so the order changes no result)
+  {
+    std::vector<int32_t> order(istart.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t u, int32_t v) { return icount[u] > icount[v]; });
+    auto permute = [&](std::vector<int32_t>& a) {
+      std::vector<int32_t> t(a.size());
+      for (size_t i = 0; i < a.size(); ++i) t[i] = a[order[i]];
+      a.swap(t);
+    };
+    permute(istart);
+    permute(icount);
+    permute(ibin);
+    permute(islot);
+  }
   HIP_TRY(p, hipMemcpyAsync(bstart, hstart.data(), (g.nbins + 1) * sizeof(int32_t),
                             hipMemcpyHostToDevice, s));
 
@@ -541,13 +559,11 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
   TRY(dalloc(p, &p->item_start, ni * sizeof(int32_t)));
   TRY(dalloc(p, &p->item_count, ni * sizeof(int32_t)));
   TRY(dalloc(p, &p->item_bin, ni * sizeof(int32_t)));
-  TRY(dalloc(p, &p->item_first, (g.nbins + 1) * sizeof(int32_t)));
   if (!istart.empty()) {
     HIP_TRY(p, hipMemcpyAsync(p->item_start, istart.data(), istart.size() * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(p, hipMemcpyAsync(p->item_count, icount.data(), icount.size() * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(p, hipMemcpyAsync(p->item_bin, ibin.data(), ibin.size() * 4, hipMemcpyHostToDevice, s));
   }
-  HIP_TRY(p, hipMemcpyAsync(p->item_first, ifirst.data(), (g.nbins + 1) * 4, hipMemcpyHostToDevice, s));
   TRY(dalloc(p, &p->item_slot, ni * sizeof(int32_t)));
   TRY(dalloc(p, &p->multi_bin, std::max<size_t>(1, mbin.size()) * sizeof(int32_t)));
   TRY(dalloc(p, &p->multi_first, mfirst.size() * sizeof(int32_t)));
