@@ -793,6 +793,9 @@ int run_forward(nfft_plan_t p, const void* fhat, void* f, int nrhs, hipStream_t 
   ia.item_count = p->item_count;
   ia.item_bin = p->item_bin;
   ia.coef = (const R*)p->coef;
+  // the window factor table, where the plan has one (same values as the
+  // polynomials), saves the per-call evaluation
+  ia.psi = p->d == 2 ? (const R*)p->shared->psi : nullptr;
   ia.grid_rs = ipow(Ms, p->d);
   ia.f_rs = p->N;
   ia.edge = (R)(p->b * std::exp(-p->b * p->m));

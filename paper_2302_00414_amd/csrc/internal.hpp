@@ -110,6 +110,7 @@ struct InterpArgs {
   const int32_t* item_count;
   const int32_t* item_bin;
   const R* coef;
+  const R* psi;              // d = 2: window factor table [N][2][2m] in tile order, or null
   int64_t grid_rs;
   int64_t f_rs;
   R edge;

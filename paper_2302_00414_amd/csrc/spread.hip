@@ -371,6 +371,14 @@ __global__ __launch_bounds__(256) void interp_kernel(InterpArgs<R> a) {
       l[t] = (int)((L >> (kLocBits * t)) & kLocMask);
       const bool e = (L >> (kEdgeShift + t)) & 1u;
       any_edge |= e;
+      if constexpr (D == 2) {
+        if (a.psi) {
+          // the plan's window factor table holds the same values
+          psi[t][0] = e ? a.edge : (R)0;
+          load_factors<R, 2 * MW>(&psi[t][1], a.psi + (int64_t)i * (4 * MW) + t * (2 * MW));
+          continue;
+        }
+      }
       kb_poly<R, MW>(a.frac[t * N + i], e, a.edge, a.coef, psi[t]);
     }
     cplx<R> v;

@@ -121,6 +121,19 @@ __device__ __forceinline__ void prep_node(NodePrep<R, K2>& h, R y0, R y1, R cx, 
   }
 }
 
+// K2 consecutive reals of the window factor table into dst: a node's row of
+// 2 * K2 reals starts 16-byte aligned, so either half allows these loads.
+template <typename R, int K2>
+__device__ __forceinline__ void load_factors(R* dst, const R* q) {
+  constexpr int VW = (K2 * sizeof(R)) % 16 == 0 ? 16 / sizeof(R) : 8 / sizeof(R);
+  using V = typename std::conditional<VW * sizeof(R) == 16, float4, float2>::type;
+  static_for<0, K2 / VW>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    const V v = reinterpret_cast<const V*>(q)[I];
+    __builtin_memcpy(dst + I * VW, &v, sizeof(V));
+  });
+}
+
 // The same values from the table of window factors precomputed at plan time:
 // q holds the node's 2m factors of dimension 0, then the 2m of dimension 1.
 // Every lane of a group loads the row factors (one address per group), lane k
@@ -134,14 +147,7 @@ __device__ __forceinline__ void prep_node_pre(NodePrep<R, K2>& h, const R* q, R 
   h.e0 = (L >> kEdgeShift) & 1u;
   h.l1 = (int)((L >> kLocBits) & kLocMask);
   h.e1 = (L >> (kEdgeShift + 1)) & 1u;
-  // node rows start 16-byte aligned (2m factors of 4 or 8 bytes, twice)
-  constexpr int VW = (K2 * sizeof(R)) % 16 == 0 ? 16 / sizeof(R) : 8 / sizeof(R);
-  using V = typename std::conditional<VW * sizeof(R) == 16, float4, float2>::type;
-  static_for<0, K2 / VW>([&](auto ic) {
-    constexpr int I = decltype(ic)::value;
-    const V v = reinterpret_cast<const V*>(q)[I];
-    __builtin_memcpy(&h.rw[I * VW], &v, sizeof(V));
-  });
+  load_factors<R, K2>(h.rw, q);
   // the products with c_j are taken where they are used, so that nothing
   // waits for these loads here
   const int kk = k < K2 ? k : 0;

@@ -122,16 +122,19 @@ def test_precomputed_window_factors(prec, m):
     same plan switched between the two modes gives the same adjoint (float32
     single-rhs kernels sum in a fixed order, so up to the last bit there; the
     float64 kernels sum with LDS atomics), for one and for several
-    right-hand sides, and the table costs 4 m reals per node."""
+    right-hand sides; the forward's window sums use the table too once it
+    exists; and the table costs 4 m reals per node."""
     M = 32
     x = _nodes(2, M, 90 + m)
     N = x.shape[0]
     w = (1.0 + 0.3 * wl.complex_normal(N, 91)) / N
     F = wl.complex_normal((3, N), 92)
+    fh = wl.complex_normal((3, M * M), 93)
     p = _plan(x, M, m, prec, max_rhs=3)
     p.set_weights(w)
     bytes0 = p.info()["bytes"]
     a1 = _np(p.adjoint(torch.from_numpy(F)))
+    b1 = _np(p.forward(torch.from_numpy(fh)))
     p.set_tuning("spread_mode", 3)
     assert p.tuning()["spread_mode"] == 3
     rb = 8 if prec == "f64" else 4
@@ -143,6 +146,11 @@ def test_precomputed_window_factors(prec, m):
     ref = onfft.adjoint(x, w[None, :] * F, M, 2.0, m)
     for r in range(3):
         assert metrics.rel_err(a3[r], ref[r]) <= TOL_O2[prec], r
+    # the forward's window sums read the same table once it exists
+    b3 = _np(p.forward(torch.from_numpy(fh)))
+    for r in range(3):
+        assert metrics.rel_err(b3[r], b1[r]) <= tol, r
+        assert metrics.rel_err(b3[r], onfft.forward(x, fh[r], M, 2.0, m)) <= TOL_O2[prec], r
     # back to mode 1 and again to mode 3: the table is kept and reused
     p.set_tuning("spread_mode", 1)
     p.set_tuning("spread_mode", 3)
