@@ -52,6 +52,17 @@ class Request:
     batch: int = -1             # index of the batch that ran it
 
 
+@dataclass(frozen=True)
+class Done:
+    """What the statistics keep of a finished request (not its data or result,
+    which belong to the caller once the future is resolved)."""
+    key: Any
+    nrhs: int
+    t_submit: float
+    t_done: float
+    batch: int
+
+
 @dataclass
 class NodeSet:
     key: Any
@@ -210,7 +221,7 @@ class Server:
         self.free_slots = list(range(max_slots))
         self.used = 0
         self.lock = threading.Condition()
-        self.completed: List[Request] = []
+        self.completed: List[Done] = []
         self.points = 0
         self.rejected = 0
         self.batches = 0
@@ -284,7 +295,8 @@ class Server:
             for r, v in zip(b.reqs, res):
                 r.t_done = t
                 self.points += self.sets[r.key].N * r.nrhs
-                self.completed.append(r)
+                self.completed.append(Done(r.key, r.nrhs, r.t_submit, t, r.batch))
+                r.f = None                     # the samples are the caller's again
                 r.future.set_result(v)
             self.running.remove(b)
             self.free_slots.append(b.slot)

@@ -146,3 +146,32 @@ def test_no_batching_runs_each_request_alone():
     srv.drain()
     assert srv.batches == 6
     srv.close()
+
+
+def test_finished_requests_release_their_data():
+    """The server keeps statistics of finished requests, not their samples or
+    results: once the caller drops a future, its result can be freed (a long
+    request stream must not accumulate device memory)."""
+    import gc
+    import weakref
+
+    class Res:
+        pass
+
+    class Ex(FakeExecutor):
+        def results(self, token, reqs):
+            return [Res() for _ in reqs]
+
+    srv = Server(10**9, max_slots=2, max_batch_rhs=16, executor=Ex())
+    srv.register("a", _nodes(10), 8, 2.0, 4, None)
+    srv.start()
+    sample = Res()
+    fut = srv.submit("a", sample, nrhs=1)
+    res_ref, sample_ref = weakref.ref(fut.result(timeout=5)), weakref.ref(sample)
+    srv.drain()
+    del fut, sample
+    gc.collect()
+    assert res_ref() is None and sample_ref() is None
+    st = srv.stats()
+    assert st["requests"] == 1 and st["p50_ms"] > 0
+    srv.close()
