@@ -37,11 +37,25 @@ namespace nfft {
 // the full (2m+1)^3 footprint.
 template <typename R, int MW>
 struct Stage3 {
-  static constexpr int SB = 64;                   // nodes per staged batch
+  static constexpr int SB = 64;                   // nodes per staged batch (one per lane)
   static constexpr int K2 = 2 * MW;
-  static constexpr int SW = 3 * K2 + 2;           // psi_0, psi_1, psi_2, cx, cy
-  static constexpr size_t bytes = (size_t)SB * (SW * sizeof(R) + sizeof(uint32_t));
+  static constexpr int SW = 3 * K2;               // psi_0, psi_1, psi_2
+  static constexpr size_t bytes = (size_t)SB * SW * sizeof(R);
 };
+
+// Value of lane n (uniform n) of a wave-wide register.
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, int n) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, n);
+}
+__device__ __forceinline__ float lane_value(float v, int n) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), n));
+}
+__device__ __forceinline__ double lane_value(double v, int n) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), n);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), n);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
 template <typename R, int MW, int NW, int TT>
 __global__ __launch_bounds__(64 * NW) void spread3_kernel(SpreadArgs<R> a) {
@@ -66,7 +80,6 @@ __global__ __launch_bounds__(64 * NW) void spread3_kernel(SpreadArgs<R> a) {
   const int lane = tid & 63;
   const size_t acc_bytes = (size_t)2 * Ptot * sizeof(R);
   R* stage = reinterpret_cast<R*>(reinterpret_cast<unsigned char*>(lds_d) + acc_bytes);
-  uint32_t* sloc = reinterpret_cast<uint32_t*>(stage + SB * SW);
   for (int i = tid; i < (int)(acc_bytes / sizeof(double)); i += NT) lds_d[i] = 0.0;
 
   const int64_t N = a.g.N;
@@ -100,21 +113,31 @@ __global__ __launch_bounds__(64 * NW) void spread3_kernel(SpreadArgs<R> a) {
     q2[pass] = q < KP ? q % K2 : 0;
   }
 
-  // per-node values a wave needs, read from the staging area one node ahead
+  // Node data of the staged batch in registers: lane l holds node b0 + l
+  // (cell word and c_j). A wave reads node n's with readlane, so a node's
+  // addresses never wait on LDS, where they would queue behind the previous
+  // node's writes (LDS operations complete in order).
+  uint32_t myloc = 0;
+  R myc0 = 0, myc1 = 0;  // float32: this wave's component; float64: re, im
+
+  // per-node values a wave needs, read one node ahead
   struct Hdr {
     uint32_t L;
     R c0, c1;  // float32: this wave's component (c1 unused); float64: re, im
-    R w12[NPASS];
+    R w1[NPASS], w2[NPASS];  // psi_1, psi_2 at this lane's cells (product taken at use)
     R p0[K2];
   };
   auto load_hdr = [&](int n) {
     Hdr h;
     const R* o = stage + n * SW;
-    h.L = sloc[n];
-    h.c0 = o[3 * K2 + comp];
-    h.c1 = SPLIT ? (R)0 : o[3 * K2 + 1];
+    h.L = lane_value(myloc, n);
+    h.c0 = lane_value(myc0, n);
+    h.c1 = SPLIT ? (R)0 : lane_value(myc1, n);
 #pragma unroll
-    for (int pass = 0; pass < NPASS; ++pass) h.w12[pass] = o[K2 + q1[pass]] * o[2 * K2 + q2[pass]];
+    for (int pass = 0; pass < NPASS; ++pass) {
+      h.w1[pass] = o[K2 + q1[pass]];
+      h.w2[pass] = o[2 * K2 + q2[pass]];
+    }
 #pragma unroll
     for (int i0 = 0; i0 < K2; ++i0) h.p0[i0] = o[i0];
     return h;
@@ -132,7 +155,7 @@ __global__ __launch_bounds__(64 * NW) void spread3_kernel(SpreadArgs<R> a) {
         // the swizzle depends on the row only, not on the plane
         const int cell0 = sw((l0 + 1) * PP + (l1 + 1 + q1[pass]) * P + (l2 + 1 + q2[pass]));
         if constexpr (SPLIT) {
-          const R v = h.c0 * h.w12[pass];
+          const R v = h.c0 * (h.w1[pass] * h.w2[pass]);
           R* t = plane + cell0;
           R cur[K2];
 #pragma unroll
@@ -142,7 +165,8 @@ __global__ __launch_bounds__(64 * NW) void spread3_kernel(SpreadArgs<R> a) {
 #pragma unroll
           for (int i0 = 0; i0 < K2; ++i0) t[i0 * PP] = cur[i0];
         } else {
-          const R vx = h.c0 * h.w12[pass], vy = h.c1 * h.w12[pass];
+          const R w12 = h.w1[pass] * h.w2[pass];
+          const R vx = h.c0 * w12, vy = h.c1 * w12;
 #pragma unroll
           for (int i0 = 0; i0 < K2; ++i0) {
             lds_add(lds_d + cell0 + i0 * PP, vx * h.p0[i0]);
@@ -176,33 +200,34 @@ __global__ __launch_bounds__(64 * NW) void spread3_kernel(SpreadArgs<R> a) {
   for (int b0 = 0; b0 < cnt; b0 += SB) {
     const int nb = (cnt - b0) < SB ? (cnt - b0) : SB;
     __syncthreads();  // tile zeroed / previous batch consumed
-    for (int job = tid; job < 4 * SB; job += NT) {
+    for (int job = tid; job < 3 * SB; job += NT) {
       const int n = job % SB, kind = job / SB;
       if (n >= nb) continue;
       const int i = start + b0 + n;
       R* o = stage + n * SW;
-      if (kind < 3) {
-        const R y = (R)2 * a.frac[kind * N + i] - (R)1;
+      const R y = (R)2 * a.frac[kind * N + i] - (R)1;
 #pragma unroll
-        for (int q = 0; q < K2; ++q) o[kind * K2 + q] = horner<R>(a.coef + q * (DEG + 1), y);
-      } else {
-        const cplx<R> c = cmul<R>(a.w[i], f[a.perm[i]]);
-        o[3 * K2] = c.x;
-        o[3 * K2 + 1] = c.y;
-        sloc[n] = a.loc[i];
-      }
+      for (int q = 0; q < K2; ++q) o[kind * K2 + q] = horner<R>(a.coef + q * (DEG + 1), y);
+    }
+    if (lane < nb) {
+      const int i = start + b0 + lane;
+      myloc = a.loc[i];
+      const cplx<R> c = cmul<R>(a.w[i], f[a.perm[i]]);
+      myc0 = (SPLIT && comp) ? c.y : c.x;
+      myc1 = c.y;
     }
     __syncthreads();
-    // two nodes per trip with the header of the next one loaded ahead
+    // two nodes per trip with the header of the next one loaded ahead; the
+    // loads are issued on every trip (for the last node again past the end,
+    // then unused) and headers are never copied, so no wait for them joins
+    // paths or falls behind the previous node's LDS writes
     if (first >= nb) continue;
-    Hdr h0 = load_hdr(first);
+    Hdr h0 = load_hdr(first), h1;
     for (int n = first; n < nb; n += 2 * NS) {
-      const bool more = n + NS < nb;
-      Hdr h1 = h0;
-      if (more) h1 = load_hdr(n + NS);
+      h1 = load_hdr(n + NS < nb ? n + NS : nb - 1);
       spread_node(h0, n);
-      if (!more) break;
-      if (n + 2 * NS < nb) h0 = load_hdr(n + 2 * NS);
+      if (n + NS >= nb) break;
+      h0 = load_hdr(n + 2 * NS < nb ? n + 2 * NS : nb - 1);
       spread_node(h1, n + NS);
     }
   }
@@ -454,8 +479,8 @@ size_t spread_lds_bytes(int d, bool f64, int m, int T, int Ptot, int nt, int nr,
     return (size_t)(nt / 16) * Ptot * (planes == 2 ? 4 : 8) + (size_t)nt * (4 * rb + 4);
   }
   if (nr != 1) return 0;
-  // Stage3: 64 nodes of 3 * 2m + 2 reals and one packed cell word
-  return (size_t)2 * Ptot * rb + (size_t)64 * ((3 * 2 * m + 2) * rb + 4);
+  // Stage3: 64 nodes of 3 * 2m reals (cell words and c_j stay in registers)
+  return (size_t)2 * Ptot * rb + (size_t)64 * (3 * 2 * m) * rb;
 }
 
 template <typename R>
