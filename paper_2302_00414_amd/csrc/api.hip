@@ -71,7 +71,7 @@ struct SharedData {
   int bopt_nmax = 0;
   int32_t* bopt_lo = nullptr;     // first support cell per node and dimension (caller order)
   void* bopt_rows = nullptr;      // values by rows: N x (2m+1)^d in footprint order
-  // window factors of every node (d = 2, spread mode 3), [N][2][2m] in tile order
+  // window factors of every node (d = 2, spread mode 3), [N][2m][2] in tile order
   void* psi = nullptr;
   ~SharedData() {
     for (void* q : allocs) (void)hipFree(q);

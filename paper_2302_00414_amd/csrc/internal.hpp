@@ -62,7 +62,7 @@ struct SpreadArgs {
   int planes;                // 2: float32 real and imaginary planes in separate groups
   int mode;                  // d = 2 single rhs: 1 LDS tiles, 2 register row sweep,
                              // 3 LDS tiles with precomputed window factors
-  const R* psi;              // d = 2: window factors [N][2][2m] in tile order (mode 3)
+  const R* psi;              // d = 2: window factors [N][2m][2] in tile order (mode 3)
 };
 template <typename R>
 hipError_t launch_spread(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
@@ -73,7 +73,7 @@ hipError_t launch_spread_rows(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
 // Group kernel reading the precomputed window factors (d = 2, a.psi set).
 template <typename R>
 hipError_t launch_spread_pre(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
-// Window factors of every node (tile order), [N][2][2m], from the same
+// Window factors of every node (tile order), [N][2m][2], from the same
 // per-cell polynomials the spreading kernels evaluate (d = 2).
 template <typename R>
 hipError_t launch_psi(const R* frac, int64_t N, int m, const R* coef, R* psi, hipStream_t s);
@@ -110,7 +110,7 @@ struct InterpArgs {
   const int32_t* item_count;
   const int32_t* item_bin;
   const R* coef;
-  const R* psi;              // d = 2: window factor table [N][2][2m] in tile order, or null
+  const R* psi;              // d = 2: window factor table [N][2m][2] in tile order, or null
   int64_t grid_rs;
   int64_t f_rs;
   R edge;

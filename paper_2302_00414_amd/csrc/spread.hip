@@ -391,18 +391,21 @@ __global__ __launch_bounds__(256) void interp_kernel(InterpArgs<R> a) {
     int l[D];
     R psi[D][2 * MW + 1];
     bool any_edge = false;
+    // the plan's window factor table (pairs per footprint cell) holds the
+    // same values as the polynomials
+    const bool tab = D == 2 && a.psi != nullptr;
+    R pairs[4 * MW];
+    if (tab) load_factors<R, 4 * MW>(pairs, a.psi + (int64_t)i * (4 * MW));
 #pragma unroll
     for (int t = 0; t < D; ++t) {
       l[t] = (int)((L >> (kLocBits * t)) & kLocMask);
       const bool e = (L >> (kEdgeShift + t)) & 1u;
       any_edge |= e;
-      if constexpr (D == 2) {
-        if (a.psi) {
-          // the plan's window factor table holds the same values
-          psi[t][0] = e ? a.edge : (R)0;
-          load_factors<R, 2 * MW>(&psi[t][1], a.psi + (int64_t)i * (4 * MW) + t * (2 * MW));
-          continue;
-        }
+      if (tab) {
+        psi[t][0] = e ? a.edge : (R)0;
+#pragma unroll
+        for (int c = 0; c < 2 * MW; ++c) psi[t][1 + c] = pairs[2 * c + t];
+        continue;
       }
       kb_poly<R, MW>(a.frac[t * N + i], e, a.edge, a.coef, psi[t]);
     }

@@ -135,24 +135,24 @@ __device__ __forceinline__ void load_factors(R* dst, const R* q) {
 }
 
 // The same values from the table of window factors precomputed at plan time:
-// q holds the node's 2m factors of dimension 0, then the 2m of dimension 1.
-// Every lane of a group loads the row factors (one address per group), lane k
-// its column factor (q1; vx and vy are left to the caller).
+// q points to the node's 2m pairs (dimension-0 factor, dimension-1 factor) of
+// footprint cells 0..2m-1. Lane k loads pair k: p0 is the row factor it
+// broadcasts to its group where the factors are used, q1 its column factor
+// (rw, vx and vy are left to the caller, so nothing waits for the load here).
 template <typename R, int K2>
 __device__ __forceinline__ void prep_node_pre(NodePrep<R, K2>& h, const R* q, R cx, R cy,
                                               uint32_t L, int k) {
+  using V2 = typename std::conditional<std::is_same<R, float>::value, float2, double2>::type;
   h.cx = cx;
   h.cy = cy;
   h.l0 = (int)(L & kLocMask);
   h.e0 = (L >> kEdgeShift) & 1u;
   h.l1 = (int)((L >> kLocBits) & kLocMask);
   h.e1 = (L >> (kEdgeShift + 1)) & 1u;
-  load_factors<R, K2>(h.rw, q);
-  // the products with c_j are taken where they are used, so that nothing
-  // waits for these loads here
   const int kk = k < K2 ? k : 0;
-  h.q1 = q[K2 + kk];
-  h.p0 = q[kk];
+  const V2 pr = reinterpret_cast<const V2*>(q)[kk];
+  h.p0 = pr.x;
+  h.q1 = pr.y;
 }
 
 }  // namespace nfft

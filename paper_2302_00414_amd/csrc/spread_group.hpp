@@ -199,6 +199,13 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
         // step after its load was issued
         const R vx = PRE ? h.cx * h.q1 : h.vx;
         const R vy = PRE ? h.cy * h.q1 : h.vy;
+        // row factors: with the table lane i of the group loaded row i's
+        // factor, broadcast here (all 16 lanes of the group are active)
+        R rw[K2];
+        static_for<0, K2>([&](auto ic) {
+          constexpr int I = decltype(ic)::value;
+          rw[I] = PRE ? row_bcast<I>(h.p0) : h.rw[I];
+        });
         if constexpr (CS) {
           float* t = ptile + (h.l0 + 1) * P + col;
           float cur[K2];
@@ -209,7 +216,7 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
           fetch(hn, nn);
           if (k < K2) {
 #pragma unroll
-            for (int i = 0; i < K2; ++i) cur[i] += vx * h.rw[i];
+            for (int i = 0; i < K2; ++i) cur[i] += vx * rw[i];
 #pragma unroll
             for (int i = 0; i < K2; ++i) t[i * P] = cur[i];
           }
@@ -224,8 +231,8 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
           if (k < K2) {
 #pragma unroll
             for (int i = 0; i < K2; ++i) {
-              cur[i].x += vx * h.rw[i];
-              cur[i].y += vy * h.rw[i];
+              cur[i].x += vx * rw[i];
+              cur[i].y += vy * rw[i];
             }
 #pragma unroll
             for (int i = 0; i < K2; ++i) t[i * P] = cur[i];
@@ -255,9 +262,14 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
         const int col = h.l1 + 1 + k;
         const R vx = h.cx * h.q1;
         const R vy = h.cy * h.q1;
+        R rw[K2];
+        static_for<0, K2>([&](auto ic) {
+          constexpr int I = decltype(ic)::value;
+          rw[I] = row_bcast<I>(h.p0);
+        });
         if (k < K2) {
 #pragma unroll
-          for (int i = 0; i < K2; ++i) add1((h.l0 + 1 + i) * P + col, vx * h.rw[i], vy * h.rw[i]);
+          for (int i = 0; i < K2; ++i) add1((h.l0 + 1 + i) * P + col, vx * rw[i], vy * rw[i]);
         }
         edges(h, vx, vy, col);
       };

@@ -4,11 +4,13 @@
 // The nodes of a plan are fixed, so the 2m window factors per dimension that
 // the group kernel would otherwise evaluate on every call (two polynomials of
 // the per-cell fit per lane and node, plus the broadcasts of the row factors)
-// can be evaluated once. The table holds, in the plan's tile order, the 2m
-// factors of dimension 0 followed by the 2m of dimension 1 for every node:
-// 16 m bytes per node in float32, 32 m in float64. It is computed with the
-// same polynomials and the same arithmetic as the lanes of the group kernel,
-// so both spreading paths use identical factors.
+// can be evaluated once. The table holds, in the plan's tile order, for every
+// node and footprint cell c = 0..2m-1 the pair (factor of dimension 0,
+// factor of dimension 1): 16 m bytes per node in float32, 32 m in float64.
+// Lane c of a spreading group loads its pair (the row factor it broadcasts
+// to the group and its own column factor), one 8- or 16-byte load. The table
+// is computed with the same polynomials and the same arithmetic as the lanes
+// of the group kernel, so both spreading paths use identical factors.
 #include <type_traits>
 
 #include "spread_group.hpp"
@@ -24,9 +26,9 @@ __global__ __launch_bounds__(256) void psi_kernel(const R* frac, int64_t N, cons
   const int64_t i = j >> 1;   // node (tile order)
   const int t = (int)(j & 1);  // dimension
   const R y = (R)2 * frac[t * N + i] - (R)1;
-  R* out = psi + i * (2 * K2) + t * K2;
+  R* out = psi + i * (2 * K2) + t;
 #pragma unroll
-  for (int c = 0; c < K2; ++c) out[c] = horner<R>(coef + c * (DEG + 1), y);
+  for (int c = 0; c < K2; ++c) out[2 * c] = horner<R>(coef + c * (DEG + 1), y);
 }
 
 template <typename R, int MW>
