@@ -86,10 +86,54 @@ template <> struct GroupAcc<double> {
 // Per-node values a group needs for one node: the column factor times c_j
 // (vx, vy, lane k), the 2m row factors (rw, broadcast to every lane), the
 // node's tile-local cell and its on-grid-line flags.
+// acc[i] += (v of lane i of this 16-lane row) * x for i < K (K <= 16): the row
+// broadcast is the DPP operand modifier of the multiply-add itself, one
+// instruction per footprint row instead of a broadcast move and a
+// multiply-add. The leading s_nop covers the wait states a DPP read needs
+// after an EXEC write by a scalar instruction (five) or a VGPR write by a
+// vector instruction (two); the operands are plain registers, nothing is
+// loaded.
+#define NFFT_FMAC_BCAST(I, NOP)                                                              \
+  asm volatile(NOP "v_fmac_f32_dpp %0, %1, %2 row_newbcast:" #I " row_mask:0xf bank_mask:0xf" \
+               : "+v"(acc[I])                                                                \
+               : "v"(v), "v"(x))
+template <int K>
+__device__ __forceinline__ void fmac_row_bcast(float (&acc)[K], float v, float x) {
+  static_assert(K >= 1 && K <= 16, "one 16-lane row");
+  NFFT_FMAC_BCAST(0, "s_nop 4\n");
+  if constexpr (K > 1) NFFT_FMAC_BCAST(1, "");
+  if constexpr (K > 2) NFFT_FMAC_BCAST(2, "");
+  if constexpr (K > 3) NFFT_FMAC_BCAST(3, "");
+  if constexpr (K > 4) NFFT_FMAC_BCAST(4, "");
+  if constexpr (K > 5) NFFT_FMAC_BCAST(5, "");
+  if constexpr (K > 6) NFFT_FMAC_BCAST(6, "");
+  if constexpr (K > 7) NFFT_FMAC_BCAST(7, "");
+  if constexpr (K > 8) NFFT_FMAC_BCAST(8, "");
+  if constexpr (K > 9) NFFT_FMAC_BCAST(9, "");
+  if constexpr (K > 10) NFFT_FMAC_BCAST(10, "");
+  if constexpr (K > 11) NFFT_FMAC_BCAST(11, "");
+  if constexpr (K > 12) NFFT_FMAC_BCAST(12, "");
+  if constexpr (K > 13) NFFT_FMAC_BCAST(13, "");
+  if constexpr (K > 14) NFFT_FMAC_BCAST(14, "");
+  if constexpr (K > 15) NFFT_FMAC_BCAST(15, "");
+}
+#undef NFFT_FMAC_BCAST
+
+// Tile-local cell and on-grid-line flags of a d = 2 node.
+struct Cell2 {
+  int l0, l1;
+  bool e0, e1;
+};
+__device__ __forceinline__ Cell2 decode_cell2(uint32_t L) {
+  return {(int)(L & kLocMask), (int)((L >> kLocBits) & kLocMask), ((L >> kEdgeShift) & 1u) != 0,
+          ((L >> (kEdgeShift + 1)) & 1u) != 0};
+}
+
 template <typename R, int K2>
 struct NodePrep {
   R vx, vy, p0, cx, cy;
-  R q1;  // column factor of lane k, from the precomputed table
+  R q1;        // column factor of lane k, from the precomputed table
+  uint32_t L;  // cell word as loaded (table path: decoded where it is used)
   R rw[K2];
   int l0, l1;
   bool e0, e1;
@@ -138,17 +182,15 @@ __device__ __forceinline__ void load_factors(R* dst, const R* q) {
 // q points to the node's 2m pairs (dimension-0 factor, dimension-1 factor) of
 // footprint cells 0..2m-1. Lane k loads pair k: p0 is the row factor it
 // broadcasts to its group where the factors are used, q1 its column factor
-// (rw, vx and vy are left to the caller, so nothing waits for the load here).
+// (rw, vx, vy and the decoded cell word are left to the caller, so nothing
+// waits for the loads here).
 template <typename R, int K2>
 __device__ __forceinline__ void prep_node_pre(NodePrep<R, K2>& h, const R* q, R cx, R cy,
                                               uint32_t L, int k) {
   using V2 = typename std::conditional<std::is_same<R, float>::value, float2, double2>::type;
   h.cx = cx;
   h.cy = cy;
-  h.l0 = (int)(L & kLocMask);
-  h.e0 = (L >> kEdgeShift) & 1u;
-  h.l1 = (int)((L >> kLocBits) & kLocMask);
-  h.e1 = (L >> (kEdgeShift + 1)) & 1u;
+  h.L = L;
   const int kk = k < K2 ? k : 0;
   const V2 pr = reinterpret_cast<const V2*>(q)[kk];
   h.p0 = pr.x;

@@ -131,12 +131,25 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
     else
       prep_node<R, D, K2>(h, st_y0[n], st_y1[n], st_c0[n], CS ? (R)0 : st_cy[n], st_loc[n], cf);
   };
+  // The node's tile-local cell. With the factor table the cell word was
+  // loaded two nodes ahead and is decoded only here: the empty asm keeps the
+  // compiler from decoding it (and waiting for its load) earlier, e.g. where
+  // the loop turns around.
+  auto cell_of = [&](const NodePrep<R, K2>& h) -> Cell2 {
+    if constexpr (PRE) {
+      uint32_t L = h.L;
+      asm volatile("" : "+v"(L));
+      return decode_cell2(L);
+    } else {
+      return Cell2{h.l0, h.l1, h.e0, h.e1};
+    }
+  };
   // closed-edge cells of a d = 2 node on a grid line: row 0 and column 0
-  auto edges = [&](const NodePrep<R, K2>& h, R vx, R vy, int col) {
-    if (h.e0 | h.e1) {
-      if (h.e0 && k < K2) add1(h.l0 * P + col, vx * edge, vy * edge);
-      if (h.e1 && k < K2) add1((h.l0 + 1 + k) * P + h.l1, h.cx * h.p0 * edge, h.cy * h.p0 * edge);
-      if (h.e0 && h.e1 && k == 0) add1(h.l0 * P + h.l1, h.cx * edge * edge, h.cy * edge * edge);
+  auto edges = [&](const NodePrep<R, K2>& h, const Cell2& c, R vx, R vy, int col) {
+    if (c.e0 | c.e1) {
+      if (c.e0 && k < K2) add1(c.l0 * P + col, vx * edge, vy * edge);
+      if (c.e1 && k < K2) add1((c.l0 + 1 + k) * P + c.l1, h.cx * h.p0 * edge, h.cy * h.p0 * edge);
+      if (c.e0 && c.e1 && k == 0) add1(c.l0 * P + c.l1, h.cx * edge * edge, h.cy * edge * edge);
     }
   };
   issue(0);
@@ -194,7 +207,8 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
       // two headers in turn, so the next node's window is prepared into the
       // other one and nothing is copied between trips
       auto step = [&](const NodePrep<R, K2>& h, NodePrep<R, K2>& hn, int nn) {
-        const int col = h.l1 + 1 + k;
+        const Cell2 c = cell_of(h);
+        const int col = c.l1 + 1 + k;
         // with the factor table the column factor is multiplied in here, one
         // step after its load was issued
         const R vx = PRE ? h.cx * h.q1 : h.vx;
@@ -202,12 +216,14 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
         // row factors: with the table lane i of the group loaded row i's
         // factor, broadcast here (all 16 lanes of the group are active)
         R rw[K2];
-        static_for<0, K2>([&](auto ic) {
-          constexpr int I = decltype(ic)::value;
-          rw[I] = PRE ? row_bcast<I>(h.p0) : h.rw[I];
-        });
+        if constexpr (!(PRE && CS)) {
+          static_for<0, K2>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            rw[I] = PRE ? row_bcast<I>(h.p0) : h.rw[I];
+          });
+        }
         if constexpr (CS) {
-          float* t = ptile + (h.l0 + 1) * P + col;
+          float* t = ptile + (c.l0 + 1) * P + col;
           float cur[K2];
           if (k < K2) {
 #pragma unroll
@@ -215,13 +231,18 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
           }
           fetch(hn, nn);
           if (k < K2) {
+            if constexpr (PRE) {
+              // row factor i is lane i's p0, broadcast inside the multiply-add
+              fmac_row_bcast<K2>(cur, h.p0, vx);
+            } else {
 #pragma unroll
-            for (int i = 0; i < K2; ++i) cur[i] += vx * rw[i];
+              for (int i = 0; i < K2; ++i) cur[i] += vx * rw[i];
+            }
 #pragma unroll
             for (int i = 0; i < K2; ++i) t[i * P] = cur[i];
           }
         } else {
-          float2* t = acc.tile + (h.l0 + 1) * P + col;
+          float2* t = acc.tile + (c.l0 + 1) * P + col;
           float2 cur[K2];
           if (k < K2) {
 #pragma unroll
@@ -238,7 +259,7 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
             for (int i = 0; i < K2; ++i) t[i * P] = cur[i];
           }
         }
-        edges(h, vx, vy, col);
+        edges(h, c, vx, vy, col);
       };
       if constexpr (PRE) {
         run3(step);
@@ -259,7 +280,8 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
       // loaded before this node's atomics are issued
       auto step = [&](const NodePrep<R, K2>& h, NodePrep<R, K2>& hn, int nn) {
         fetch(hn, nn);
-        const int col = h.l1 + 1 + k;
+        const Cell2 c = cell_of(h);
+        const int col = c.l1 + 1 + k;
         const R vx = h.cx * h.q1;
         const R vy = h.cy * h.q1;
         R rw[K2];
@@ -269,9 +291,9 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
         });
         if (k < K2) {
 #pragma unroll
-          for (int i = 0; i < K2; ++i) add1((h.l0 + 1 + i) * P + col, vx * rw[i], vy * rw[i]);
+          for (int i = 0; i < K2; ++i) add1((c.l0 + 1 + i) * P + col, vx * rw[i], vy * rw[i]);
         }
-        edges(h, vx, vy, col);
+        edges(h, c, vx, vy, col);
       };
       run3(step);
     } else {
@@ -291,7 +313,7 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
 #pragma unroll
             for (int i = 0; i < K2; ++i) add1((h.l0 + 1 + i) * P + col, h.vx * h.rw[i], h.vy * h.rw[i]);
           }
-          edges(h, h.vx, h.vy, col);
+          edges(h, cell_of(h), h.vx, h.vy, col);
         }
         if (nn < nb) prep(h, nn);
       }
