@@ -114,9 +114,9 @@ def test_tunings_agree(tuning, prec):
     p.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("m", [1, 3, 4, 7, 8])
-def test_precomputed_window_factors(prec, m):
+@pytest.mark.parametrize("prec,planes", [("f64", 1), ("f32", 1), ("f32", 2)])
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 6, 7, 8])
+def test_precomputed_window_factors(prec, planes, m):
     """Spread mode 3 reads the window factors from a table built once per node
     set with the same polynomials and arithmetic as the lanes of mode 1: the
     same plan switched between the two modes gives the same adjoint (float32
@@ -130,7 +130,7 @@ def test_precomputed_window_factors(prec, m):
     w = (1.0 + 0.3 * wl.complex_normal(N, 91)) / N
     F = wl.complex_normal((3, N), 92)
     fh = wl.complex_normal((3, M * M), 93)
-    p = _plan(x, M, m, prec, max_rhs=3)
+    p = _plan(x, M, m, prec, max_rhs=3, tuning={"spread_planes": planes} if prec == "f32" else None)
     p.set_weights(w)
     bytes0 = p.info()["bytes"]
     a1 = _np(p.adjoint(torch.from_numpy(F)))
