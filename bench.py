@@ -305,7 +305,7 @@ def traffic_record(kernel):
 
 
 # sources of the d = 2 single-rhs spreading kernels
-SPREAD_SOURCES = ("spread.hip", "spread_common.hpp", "spread_group.hpp", "spread_pre.hip",
+SPREAD_SOURCES = ("spread.hip", "spread_common.hpp", "spread_group.hpp", "spread_pre.hip", "spread_late.hip",
                   "spread_rows.hip")
 
 
@@ -315,9 +315,9 @@ def spread_kernel_name(t):
     T, mode = t["tile_edge"], t["spread_mode"]
     if mode == 2 and T + 2 * MW <= 32:
         return f"spread_rows_kernel<float, {MW}, {T if T == 16 else 0}, 1>"
+    ws = {3: 1, 4: 2}.get(mode, 0)   # window source of the group kernel
     return (f"spread_group_kernel<float, 2, {MW}, {t['spread_threads']}, "
-            f"{T if T in (8, 16) else 0}, {'true' if t['spread_planes'] == 2 else 'false'}, "
-            f"{'true' if mode == 3 else 'false'}>")
+            f"{T if T in (8, 16) else 0}, {'true' if t['spread_planes'] == 2 else 'false'}, {ws}>")
 
 
 def spread_source_sha():

@@ -129,6 +129,12 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
  *                             per node; resolved to 1 for d != 2, and a
  *                             call with nrhs > 1 and NFFT_TUNE_RHS_PER_GROUP
  *                             > 1 spreads as mode 1 does.
+ *                             4 = as 3 without the table: each lane
+ *                             evaluates its two window polynomials when the
+ *                             node is spread, from offsets loaded from device
+ *                             memory two nodes ahead (no extra memory);
+ *                             resolved to 1 for d != 2, and as mode 3 for
+ *                             several right-hand sides per work-group.
  *                             Default 1; the row sweep wins with many
  *                             right-hand sides per call, and in float32
  *                             takes two of them per wave when

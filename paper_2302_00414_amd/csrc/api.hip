@@ -218,10 +218,10 @@ int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, in
   if (planes != 1 && planes != 2)
     return fail(p, NFFT_EINVAL, "spread planes %d: expected 1 or 2", planes);
   int& mode = out[NFFT_TUNE_SPREAD_MODE];
-  if (mode < 1 || mode > 3)
-    return fail(p, NFFT_EINVAL, "spread mode %d: expected 1, 2 or 3", mode);
+  if (mode < 1 || mode > 4)
+    return fail(p, NFFT_EINVAL, "spread mode %d: expected 1, 2, 3 or 4", mode);
   if (mode == 2 && !nfft::spread_rows_supported(d, T + 2 * m)) mode = 1;
-  if (mode == 3 && d != 2) mode = 1;  // the factor table is laid out for d = 2
+  if ((mode == 3 || mode == 4) && d != 2) mode = 1;  // laid out for d = 2
   const int fw = out[NFFT_TUNE_FFT_MIN_WG];
   if (fw < 1 || fw > 65536) return fail(p, NFFT_EINVAL, "fft min work-groups %d: expected 1..65536", fw);
   const int P = T + 2 * m;
@@ -1014,7 +1014,7 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
     planes = {1, 2};
   }
   if (d <= 2 && nrhs > 1) rpg = {1, 2, 4, 8};
-  if (d == 2) modes = {1, 2, 3};
+  if (d == 2) modes = {1, 2, 3, 4};
 
   nfft_plan_t best = nullptr;
   double best_t = -1.0;
@@ -1055,7 +1055,8 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
             // the LDS kernel's shape does not matter when another kernel spreads
             if ((nr > 1 || md == 2) && (nt != threads[0] || pl != planes[0])) continue;
             if (nr > 2 && md == 2) continue;  // the row sweep takes at most two rhs per wave
-            if (md == 3 && (!have_psi || nr > 1)) continue;  // mode 3 is single-rhs only
+            if (md == 3 && (!have_psi || nr > 1)) continue;  // modes 3, 4: single rhs only
+            if (md == 4 && nr > 1) continue;
             int res[NFFT_TUNE_COUNT];
             if (resolve_tuning(d, Ms, m, precision, in, NFFT_TUNE_COUNT, res, nullptr) != NFFT_OK)
               continue;

@@ -61,7 +61,8 @@ struct SpreadArgs {
   int nr;                    // right-hand sides per work-group (1, 2, 4 or 8; d <= 2)
   int planes;                // 2: float32 real and imaginary planes in separate groups
   int mode;                  // d = 2 single rhs: 1 LDS tiles, 2 register row sweep,
-                             // 3 LDS tiles with precomputed window factors
+                             // 3 LDS tiles with precomputed window factors,
+                             // 4 LDS tiles with the window evaluated late
   const R* psi;              // d = 2: window factors [N][2m][2] in tile order (mode 3)
 };
 template <typename R>
@@ -73,6 +74,9 @@ hipError_t launch_spread_rows(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
 // Group kernel reading the precomputed window factors (d = 2, a.psi set).
 template <typename R>
 hipError_t launch_spread_pre(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
+// Group kernel evaluating the window late from offsets in device memory (d = 2).
+template <typename R>
+hipError_t launch_spread_late(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
 // Window factors of every node (tile order), [N][2m][2], from the same
 // per-cell polynomials the spreading kernels evaluate (d = 2).
 template <typename R>

@@ -425,15 +425,15 @@ static hipError_t spread_dm(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
     // threads sharing one tile
     if constexpr (std::is_same<R, float>::value) {
       if (a.planes == 2) {
-        if (a.nt == 64) return spread_group_nt<R, D, MW, 64, true, false>(a, nrhs, s);
-        if (a.nt == 256) return spread_group_nt<R, D, MW, 256, true, false>(a, nrhs, s);
-        return spread_group_nt<R, D, MW, 128, true, false>(a, nrhs, s);
+        if (a.nt == 64) return spread_group_nt<R, D, MW, 64, true, 0>(a, nrhs, s);
+        if (a.nt == 256) return spread_group_nt<R, D, MW, 256, true, 0>(a, nrhs, s);
+        return spread_group_nt<R, D, MW, 128, true, 0>(a, nrhs, s);
       }
-      if (a.nt == 64) return spread_group_nt<R, D, MW, 64, false, false>(a, nrhs, s);
-      if (a.nt == 256) return spread_group_nt<R, D, MW, 256, false, false>(a, nrhs, s);
-      return spread_group_nt<R, D, MW, 128, false, false>(a, nrhs, s);
+      if (a.nt == 64) return spread_group_nt<R, D, MW, 64, false, 0>(a, nrhs, s);
+      if (a.nt == 256) return spread_group_nt<R, D, MW, 256, false, 0>(a, nrhs, s);
+      return spread_group_nt<R, D, MW, 128, false, 0>(a, nrhs, s);
     } else {
-      return spread_group_nt<R, D, MW, 256, false, false>(a, nrhs, s);
+      return spread_group_nt<R, D, MW, 256, false, 0>(a, nrhs, s);
     }
   } else {
     // d = 3: float32 two waves, one component plane each; float64 four
@@ -492,6 +492,7 @@ hipError_t launch_spread(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
   if (a.mode == 2 && spread_rows_supported(a.g.d, a.g.P)) return launch_spread_rows<R>(a, nrhs, s);
   if (a.nr > 1 && a.g.d <= 2) return launch_spread_multi<R>(a, nrhs, s);
   if (a.mode == 3 && a.psi && a.g.d == 2) return launch_spread_pre<R>(a, nrhs, s);
+  if (a.mode == 4 && a.g.d == 2) return launch_spread_late<R>(a, nrhs, s);
   switch (a.g.d) {
     case 1: NFFT_DISPATCH_M(spread_dm, R, 1, a, nrhs, s)
     case 2: NFFT_DISPATCH_M(spread_dm, R, 2, a, nrhs, s)

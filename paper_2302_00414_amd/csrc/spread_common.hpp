@@ -133,7 +133,8 @@ template <typename R, int K2>
 struct NodePrep {
   R vx, vy, p0, cx, cy;
   R q1;        // column factor of lane k, from the precomputed table
-  uint32_t L;  // cell word as loaded (table path: decoded where it is used)
+  R y0, y1;    // offsets (late evaluation: the window is evaluated where it is used)
+  uint32_t L;  // cell word as loaded (decoded where it is used)
   R rw[K2];
   int l0, l1;
   bool e0, e1;

@@ -24,14 +24,21 @@ namespace nfft {
 //            atomics.
 // A batch of nodes is first staged in LDS by the whole work-group (one node
 // per thread: offsets, c_j = w_j f_j and the packed cells).
-//   PRE:     the 2m window factors of each dimension come from the table
-//            precomputed at plan time (node order of the plan) instead of
-//            being evaluated by the lanes; the values are the same.
+//   WS (window source, d = 2): 0 = offsets, cell words and c_j staged in
+//            LDS, the window evaluated when a node is prepared; 1 = the 2m
+//            window factors per dimension from the table precomputed at plan
+//            time; 2 = evaluated in the step from offsets loaded from device
+//            memory. With 1 and 2 only c_j is staged, the cell word and the
+//            factors (or offsets) of a node are loaded from device memory two
+//            nodes ahead, and the row factors reach the group by DPP; all three
+//            give the same values.
 
-template <typename R, int D, int MW, int NT, int TT, bool CS, bool PRE>
+template <typename R, int D, int MW, int NT, int TT, bool CS, int WS>
 __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
   static_assert(D <= 2 && 2 * MW <= 16, "group spreading covers d <= 2, m <= 8");
-  static_assert(!PRE || D == 2, "precomputed window factors are laid out for d = 2");
+  static_assert(WS == 0 || D == 2, "the table and the late evaluation are laid out for d = 2");
+  constexpr bool PRE = WS != 0;   // node data from device memory, loaded ahead
+  constexpr bool TAB = WS == 1;   // window factors from the plan's table
   static_assert(!CS || std::is_same<R, float>::value, "component split is a float32 layout");
   constexpr int DEG = PolyDeg<R>::value;
   constexpr int NG = NT / 16;            // groups per work-group
@@ -90,7 +97,7 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
 
   // this lane's window polynomial (column k; lanes past 2m keep polynomial 0)
   R cf[DEG + 1];
-  if constexpr (!PRE) {
+  if constexpr (!TAB) {
     const int kk = k < K2 ? k : 0;
 #pragma unroll
     for (int p = 0; p <= DEG; ++p) cf[p] = a.coef[kk * (DEG + 1) + p];
@@ -126,9 +133,16 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
       // then on the vector-memory counter and does not also wait for this
       // group's LDS writes issued since (LDS operations complete in order)
       const int64_t i = start + b0 + n;
-      prep_node_pre<R, K2>(h, a.psi + i * (2 * K2), st_c0[n], CS ? (R)0 : st_cy[n], a.loc[i], k);
-    }
-    else
+      if constexpr (TAB) {
+        prep_node_pre<R, K2>(h, a.psi + i * (2 * K2), st_c0[n], CS ? (R)0 : st_cy[n], a.loc[i], k);
+      } else {
+        h.cx = st_c0[n];
+        h.cy = CS ? (R)0 : st_cy[n];
+        h.L = a.loc[i];
+        h.y0 = a.frac[i];      // offsets; the window is evaluated in the step
+        h.y1 = a.frac[N + i];
+      }
+    } else
       prep_node<R, D, K2>(h, st_y0[n], st_y1[n], st_c0[n], CS ? (R)0 : st_cy[n], st_loc[n], cf);
   };
   // The node's tile-local cell. With the factor table the cell word was
@@ -144,11 +158,22 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
       return Cell2{h.l0, h.l1, h.e0, h.e1};
     }
   };
+  // this lane's row factor (p0, broadcast to the group) and column factor
+  // (q1) of a node prepared with WS = 1 or 2
+  auto factors = [&](const NodePrep<R, K2>& h, R& p0, R& q1) {
+    if constexpr (TAB) {
+      p0 = h.p0;
+      q1 = h.q1;
+    } else {
+      p0 = horner<R>(cf, (R)2 * h.y0 - (R)1);
+      q1 = horner<R>(cf, (R)2 * h.y1 - (R)1);
+    }
+  };
   // closed-edge cells of a d = 2 node on a grid line: row 0 and column 0
-  auto edges = [&](const NodePrep<R, K2>& h, const Cell2& c, R vx, R vy, int col) {
+  auto edges = [&](const NodePrep<R, K2>& h, const Cell2& c, R vx, R vy, int col, R p0) {
     if (c.e0 | c.e1) {
       if (c.e0 && k < K2) add1(c.l0 * P + col, vx * edge, vy * edge);
-      if (c.e1 && k < K2) add1((c.l0 + 1 + k) * P + c.l1, h.cx * h.p0 * edge, h.cy * h.p0 * edge);
+      if (c.e1 && k < K2) add1((c.l0 + 1 + k) * P + c.l1, h.cx * p0 * edge, h.cy * p0 * edge);
       if (c.e0 && c.e1 && k == 0) add1(c.l0 * P + c.l1, h.cx * edge * edge, h.cy * edge * edge);
     }
   };
@@ -209,17 +234,19 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
       auto step = [&](const NodePrep<R, K2>& h, NodePrep<R, K2>& hn, int nn) {
         const Cell2 c = cell_of(h);
         const int col = c.l1 + 1 + k;
-        // with the factor table the column factor is multiplied in here, one
-        // step after its load was issued
-        const R vx = PRE ? h.cx * h.q1 : h.vx;
-        const R vy = PRE ? h.cy * h.q1 : h.vy;
-        // row factors: with the table lane i of the group loaded row i's
-        // factor, broadcast here (all 16 lanes of the group are active)
+        // with WS = 1, 2 the factors are formed here, two steps after their
+        // loads were issued, and the column factor multiplied in
+        R p0 = h.p0, q1 = h.q1;
+        if constexpr (PRE) factors(h, p0, q1);
+        const R vx = PRE ? h.cx * q1 : h.vx;
+        const R vy = PRE ? h.cy * q1 : h.vy;
+        // row factors: lane i of the group holds row i's factor, broadcast
+        // here (all 16 lanes of the group are active)
         R rw[K2];
         if constexpr (!(PRE && CS)) {
           static_for<0, K2>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
-            rw[I] = PRE ? row_bcast<I>(h.p0) : h.rw[I];
+            rw[I] = PRE ? row_bcast<I>(p0) : h.rw[I];
           });
         }
         if constexpr (CS) {
@@ -233,7 +260,7 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
           if (k < K2) {
             if constexpr (PRE) {
               // row factor i is lane i's p0, broadcast inside the multiply-add
-              fmac_row_bcast<K2>(cur, h.p0, vx);
+              fmac_row_bcast<K2>(cur, p0, vx);
             } else {
 #pragma unroll
               for (int i = 0; i < K2; ++i) cur[i] += vx * rw[i];
@@ -259,7 +286,7 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
             for (int i = 0; i < K2; ++i) t[i * P] = cur[i];
           }
         }
-        edges(h, c, vx, vy, col);
+        edges(h, c, vx, vy, col, p0);
       };
       if constexpr (PRE) {
         run3(step);
@@ -282,18 +309,20 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
         fetch(hn, nn);
         const Cell2 c = cell_of(h);
         const int col = c.l1 + 1 + k;
-        const R vx = h.cx * h.q1;
-        const R vy = h.cy * h.q1;
+        R p0, q1;
+        factors(h, p0, q1);
+        const R vx = h.cx * q1;
+        const R vy = h.cy * q1;
         R rw[K2];
         static_for<0, K2>([&](auto ic) {
           constexpr int I = decltype(ic)::value;
-          rw[I] = row_bcast<I>(h.p0);
+          rw[I] = row_bcast<I>(p0);
         });
         if (k < K2) {
 #pragma unroll
           for (int i = 0; i < K2; ++i) add1((c.l0 + 1 + i) * P + col, vx * rw[i], vy * rw[i]);
         }
-        edges(h, c, vx, vy, col);
+        edges(h, c, vx, vy, col, p0);
       };
       run3(step);
     } else {
@@ -313,7 +342,7 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
 #pragma unroll
             for (int i = 0; i < K2; ++i) add1((h.l0 + 1 + i) * P + col, h.vx * h.rw[i], h.vy * h.rw[i]);
           }
-          edges(h, cell_of(h), h.vx, h.vy, col);
+          edges(h, cell_of(h), h.vx, h.vy, col, h.p0);
         }
         if (nn < nb) prep(h, nn);
       }
@@ -369,25 +398,25 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
 }
 
 // d <= 2 single right-hand side: float32 private group tiles, nt threads
-template <typename R, int D, int MW, int NT, bool CS, bool PRE>
+template <typename R, int D, int MW, int NT, bool CS, int WS>
 static hipError_t spread_group_nt(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
   constexpr int NG = NT / 16;
   const size_t acc = CS ? (size_t)NG * a.g.Ptot * 4
                         : std::is_same<R, float>::value ? (size_t)NG * a.g.Ptot * 8
                                                         : (size_t)2 * a.g.Ptot * 8;
-  const size_t lds = acc + (size_t)NT * (PRE ? 2 * sizeof(R) : 4 * sizeof(R) + 4);
+  const size_t lds = acc + (size_t)NT * (WS != 0 ? 2 * sizeof(R) : 4 * sizeof(R) + 4);
   const dim3 grid(a.g.nsub, nrhs);
   if constexpr (D == 2) {
     if (a.g.T == 16) {
-      hipLaunchKernelGGL((spread_group_kernel<R, D, MW, NT, 16, CS, PRE>), grid, dim3(NT), lds, s, a);
+      hipLaunchKernelGGL((spread_group_kernel<R, D, MW, NT, 16, CS, WS>), grid, dim3(NT), lds, s, a);
       return hipGetLastError();
     }
     if (a.g.T == 8) {
-      hipLaunchKernelGGL((spread_group_kernel<R, D, MW, NT, 8, CS, PRE>), grid, dim3(NT), lds, s, a);
+      hipLaunchKernelGGL((spread_group_kernel<R, D, MW, NT, 8, CS, WS>), grid, dim3(NT), lds, s, a);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((spread_group_kernel<R, D, MW, NT, 0, CS, PRE>), grid, dim3(NT), lds, s, a);
+  hipLaunchKernelGGL((spread_group_kernel<R, D, MW, NT, 0, CS, WS>), grid, dim3(NT), lds, s, a);
   return hipGetLastError();
 }
 

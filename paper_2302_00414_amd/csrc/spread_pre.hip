@@ -61,15 +61,15 @@ template <typename R, int MW>
 static hipError_t spread_pre_m(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
   if constexpr (std::is_same<R, float>::value) {
     if (a.planes == 2) {
-      if (a.nt == 64) return spread_group_nt<R, 2, MW, 64, true, true>(a, nrhs, s);
-      if (a.nt == 256) return spread_group_nt<R, 2, MW, 256, true, true>(a, nrhs, s);
-      return spread_group_nt<R, 2, MW, 128, true, true>(a, nrhs, s);
+      if (a.nt == 64) return spread_group_nt<R, 2, MW, 64, true, 1>(a, nrhs, s);
+      if (a.nt == 256) return spread_group_nt<R, 2, MW, 256, true, 1>(a, nrhs, s);
+      return spread_group_nt<R, 2, MW, 128, true, 1>(a, nrhs, s);
     }
-    if (a.nt == 64) return spread_group_nt<R, 2, MW, 64, false, true>(a, nrhs, s);
-    if (a.nt == 256) return spread_group_nt<R, 2, MW, 256, false, true>(a, nrhs, s);
-    return spread_group_nt<R, 2, MW, 128, false, true>(a, nrhs, s);
+    if (a.nt == 64) return spread_group_nt<R, 2, MW, 64, false, 1>(a, nrhs, s);
+    if (a.nt == 256) return spread_group_nt<R, 2, MW, 256, false, 1>(a, nrhs, s);
+    return spread_group_nt<R, 2, MW, 128, false, 1>(a, nrhs, s);
   } else {
-    return spread_group_nt<R, 2, MW, 256, false, true>(a, nrhs, s);
+    return spread_group_nt<R, 2, MW, 256, false, 1>(a, nrhs, s);
   }
 }
 

@@ -85,7 +85,8 @@ def test_f64_3d_large_m_unsupported():
     (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 70000], _lib.NFFT_EINVAL),  # fft min work-groups
     (2, 6, _lib.NFFT_F32, [-1], _lib.NFFT_EINVAL),                # negative entry
     (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 3], _lib.NFFT_EINVAL),  # spread planes not 1/2
-    (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 4], _lib.NFFT_EINVAL),  # spread mode not 1/2/3
+    (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 5], _lib.NFFT_EINVAL),  # spread mode not 1..4
+    (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 4], _lib.NFFT_OK),   # window evaluated late
     (2, 6, _lib.NFFT_F64, [0, 0, 0, 0, 0, 0, 3], _lib.NFFT_OK),   # precomputed window factors
     (3, 4, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 3], _lib.NFFT_OK),   # mode 3 resolves to 1 for d = 3
     (2, 8, _lib.NFFT_F32, [32, 0, 256, 0, 0, 2], _lib.NFFT_OK),   # 16 float32 48^2 planes fit

@@ -81,6 +81,9 @@ TUNINGS = [
     {"spread_mode": 3, "spread_planes": 2, "spread_threads": 64},
     {"spread_mode": 3, "tile_edge": 8, "item_nodes": 32, "spread_threads": 256},
     {"spread_mode": 3, "tile_edge": 32, "item_nodes": 1000},
+    {"spread_mode": 4},
+    {"spread_mode": 4, "spread_planes": 2, "spread_threads": 256},
+    {"spread_mode": 4, "tile_edge": 8, "item_nodes": 32, "spread_threads": 64},
 ]
 
 
@@ -158,6 +161,34 @@ def test_precomputed_window_factors(prec, planes, m):
     from paper_2302_00414_amd.nfft import nfft_footprint
     assert nfft_footprint(2, M, 2.0, m, N, prec, 3) >= p.info()["bytes"]
     assert metrics.rel_err(_np(p.adjoint(torch.from_numpy(F))), a3) <= tol
+    p.close()
+
+
+@pytest.mark.parametrize("prec,planes", [("f64", 1), ("f32", 1), ("f32", 2)])
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 6, 8])
+def test_window_evaluated_late(prec, planes, m):
+    """Spread mode 4 evaluates the same window polynomials with the same
+    arithmetic as mode 1, in another place of the pipeline: the same plan in
+    the two modes gives the same adjoint (up to the last bit for the float32
+    kernels, which sum in a fixed order), for one and for several right-hand
+    sides, and needs no extra memory."""
+    M = 32
+    x = _nodes(2, M, 110 + m)
+    N = x.shape[0]
+    w = (1.0 + 0.3 * wl.complex_normal(N, 111)) / N
+    F = wl.complex_normal((3, N), 112)
+    p = _plan(x, M, m, prec, max_rhs=3, tuning={"spread_planes": planes} if prec == "f32" else None)
+    p.set_weights(w)
+    bytes0 = p.info()["bytes"]
+    a1 = _np(p.adjoint(torch.from_numpy(F)))
+    p.set_tuning("spread_mode", 4)
+    assert p.tuning()["spread_mode"] == 4 and p.info()["bytes"] == bytes0
+    a4 = _np(p.adjoint(torch.from_numpy(F)))
+    tol = {"f64": 1e-14, "f32": 1e-7}[prec]
+    ref = onfft.adjoint(x, w[None, :] * F, M, 2.0, m)
+    for r in range(3):
+        assert metrics.rel_err(a4[r], a1[r]) <= tol, r
+        assert metrics.rel_err(a4[r], ref[r]) <= TOL_O2[prec], r
     p.close()
 
 
