@@ -65,9 +65,9 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
   const size_t acc_bytes = CS     ? (size_t)NG * Ptot * sizeof(float)
                            : PRIV ? (size_t)NG * Ptot * sizeof(float2)
                                   : (size_t)2 * Ptot * sizeof(double);
-  // staged per node: c_j, and without the factor table also the offsets and
-  // the cell word (with it those come from device memory; the smaller
-  // staging area lets one more work-group share a compute unit)
+  // staged per node: c_j, and with WS = 0 also the offsets and the cell word
+  // (with WS = 1, 2 those come from device memory; the smaller staging area
+  // lets one more work-group share a compute unit)
   R* st_cx = reinterpret_cast<R*>(base + acc_bytes);
   R* st_cy = st_cx + NT;
   R* st_y0 = st_cy + NT;
@@ -145,8 +145,8 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
     } else
       prep_node<R, D, K2>(h, st_y0[n], st_y1[n], st_c0[n], CS ? (R)0 : st_cy[n], st_loc[n], cf);
   };
-  // The node's tile-local cell. With the factor table the cell word was
-  // loaded two nodes ahead and is decoded only here: the empty asm keeps the
+  // The node's tile-local cell. With WS = 1, 2 the cell word was loaded two
+  // nodes ahead and is decoded only here: the empty asm keeps the
   // compiler from decoding it (and waiting for its load) earlier, e.g. where
   // the loop turns around.
   auto cell_of = [&](const NodePrep<R, K2>& h) -> Cell2 {
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
     // reads of the current node are in flight. LDS operations of a wave
     // execute in order, so the next node's reads always see this node's
     // writes.
-    // The next node's header. With the factor table its loads are issued on
+    // The next node's header. With WS = 1, 2 its loads are issued on
     // every trip (past the batch end for the last node again, whose header
     // is then unused): a load issued on some paths only would make the
     // compiler wait for all loads in flight where the paths join.
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
       else if (nn < nb)
         prep(hn, nn);
     };
-    // With the factor table the loads are issued two nodes ahead: three
+    // With WS = 1, 2 the loads are issued two nodes ahead: three
     // headers in turn, so a load has two steps of this group's LDS work to
     // arrive in.
     auto run3 = [&](auto&& step) {
@@ -303,8 +303,8 @@ __global__ __launch_bounds__(NT) void spread_group_kernel(SpreadArgs<R> a) {
         }
       }
     } else if constexpr (PRE) {
-      // float64 with the factor table: the factors of the node two ahead are
-      // loaded before this node's atomics are issued
+      // float64 with WS = 1, 2: the data of the node two ahead is loaded
+      // before this node's atomics are issued
       auto step = [&](const NodePrep<R, K2>& h, NodePrep<R, K2>& hn, int nn) {
         fetch(hn, nn);
         const Cell2 c = cell_of(h);
