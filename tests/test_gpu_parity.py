@@ -22,11 +22,11 @@ TOL_O2 = {"f64": 1e-12, "f32": 1e-5}
 TOL_EXACT = {"f64": 1e-10, "f32": 1e-5}
 
 
-def _plan(x, M, sigma, m, prec, max_rhs=1):
+def _plan(x, M, sigma, m, prec, max_rhs=1, tuning=None):
     from paper_2302_00414_amd.nfft import Plan
-    print(f"[case] N={x.shape[0]} d={x.shape[1]} M={M} sigma={sigma} m={m} {prec} rhs={max_rhs}",
-          flush=True)
-    return Plan(x, M, sigma, m, precision=prec, max_rhs=max_rhs, device="cuda:0")
+    print(f"[case] N={x.shape[0]} d={x.shape[1]} M={M} sigma={sigma} m={m} {prec} rhs={max_rhs} "
+          f"tuning={tuning}", flush=True)
+    return Plan(x, M, sigma, m, precision=prec, max_rhs=max_rhs, device="cuda:0", tuning=tuning)
 
 
 def _np(t):
@@ -239,15 +239,17 @@ def _sample_k(M, d, n, seed):
     return sel, K[sel]
 
 
+# "auto": the autotuned plan, the launch configuration the benchmark times
+@pytest.mark.parametrize("tuning", [None, "auto"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_polar_512x512_M256(prec):
+def test_polar_512x512_M256(prec, tuning):
     """Polar grid R = T = 512 (N = 262144), M = 256, sigma = 2, m = 6, area
     weights: sampled outputs against the exact weighted sums."""
     R = T = 512
     x = wl.polar_nodes(R, T)
     w = wl.polar_area_weights(R, T)
     f = wl.complex_normal(x.shape[0], 3)
-    p = _plan(x, 256, 2.0, 6, prec)
+    p = _plan(x, 256, 2.0, 6, prec, tuning=tuning)
     p.set_weights(w)
     got = _np(p.adjoint(torch.from_numpy(f)))
     sel, K = _sample_k(256, 2, 300, 11)
@@ -256,14 +258,15 @@ def test_polar_512x512_M256(prec):
     p.close()
 
 
-def test_jittered_3d_M64():
+@pytest.mark.parametrize("tuning", [None, "auto"])
+def test_jittered_3d_M64(tuning):
     """Jittered 128 x 64 x 64 grid (N = 524288), d = 3, M = 64, m = 4, float32:
     sampled outputs against the exact sums."""
     x = wl.jittered_nodes((128, 64, 64), 4)
     N = x.shape[0]
     w = np.full(N, 1.0 / N, dtype=np.complex128)
     f = wl.complex_normal(N, 5)
-    p = _plan(x, 64, 2.0, 4, "f32")
+    p = _plan(x, 64, 2.0, 4, "f32", tuning=tuning)
     p.set_weights(w)
     got = _np(p.adjoint(torch.from_numpy(f)))
     sel, K = _sample_k(64, 3, 200, 12)
@@ -272,14 +275,15 @@ def test_jittered_3d_M64():
     p.close()
 
 
-def test_spiral_32_rhs():
+@pytest.mark.parametrize("tuning", [None, "auto"])
+def test_spiral_32_rhs(tuning):
     """Archimedean spiral N = 131072, M = 256, m = 6, 32 right-hand sides in one
     float32 call: every right-hand side's sampled outputs against the exact sums."""
     N, M, nrhs = 131072, 256, 32
     x = wl.spiral_nodes(N, M)
     w = wl.spiral_area_weights(N, M)
     F = wl.complex_normal((nrhs, N), 6)
-    p = _plan(x, M, 2.0, 6, "f32", max_rhs=nrhs)
+    p = _plan(x, M, 2.0, 6, "f32", max_rhs=nrhs, tuning=tuning)
     p.set_weights(w)
     got = _np(p.adjoint(torch.from_numpy(F)))
     sel, K = _sample_k(M, 2, 60, 13)
