@@ -6,6 +6,7 @@ compare sampled outputs computed one by one from the exact sums.
 Tolerances (relative l2 error): float64 path 1e-10, float32 path 1e-5; for
 float64 against O2 only rounding separates the two, so 1e-12 is used there.
 """
+import functools
 import math
 
 import numpy as np
@@ -108,6 +109,38 @@ def test_forward_matches_oracle(d, M, sigma, m, N, prec):
     got = _np(p.forward(torch.from_numpy(fh)))
     ref = onfft.forward(x, fh, M, sigma, m)
     assert metrics.rel_err(got, ref) <= TOL_O2[prec]
+    p.close()
+
+
+# the largest oversampled grid built, M_sigma = 4096 per dimension (d = 1, 2;
+# the oracle's cost grows with the footprint, hence m = 2 for d = 2)
+MAX_GRID = [
+    # d, M, m, N
+    (1, 2048, 8, 20000),
+    (2, 2048, 2, 3000),
+]
+
+
+@functools.lru_cache(maxsize=None)
+def _max_grid_case(d, M, m, N):
+    x = wl.uniform_nodes(N, d, 400 + d)
+    w = (1.0 + 0.3 * wl.complex_normal(N, 401)) / N
+    f = wl.complex_normal(N, 402)
+    fh = wl.complex_normal(M ** d, 403)
+    return x, w, f, fh, onfft.adjoint(x, w * f, M, 2.0, m), onfft.forward(x, fh, M, 2.0, m)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("d,M,m,N", MAX_GRID)
+def test_maximum_grid(d, M, m, N, prec):
+    x, w, f, fh, ref_a, ref_f = _max_grid_case(d, M, m, N)
+    p = _plan(x, M, 2.0, m, prec)
+    assert p.info()["Ms"] == 4096
+    p.set_weights(w)
+    got = _np(p.adjoint(torch.from_numpy(f)))
+    assert metrics.rel_err(got, ref_a) <= TOL_O2[prec]
+    got_f = _np(p.forward(torch.from_numpy(fh)))
+    assert metrics.rel_err(got_f, ref_f) <= TOL_O2[prec]
     p.close()
 
 
