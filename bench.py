@@ -344,7 +344,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the reconstruction of one request runs on one "
-              "device and this build has no multi-GPU path (run with --gpus 1).", file=sys.stderr)
+              "device and the library has no multi-GPU path (run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import torch

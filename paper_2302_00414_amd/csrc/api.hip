@@ -846,7 +846,7 @@ const char* nfft_strerror(int status) {
     case NFFT_ENOMEM: return "device memory allocation failed";
     case NFFT_EDEVICE: return "HIP device or kernel failure";
     case NFFT_ESTATE: return "call not allowed in the plan's current state";
-    case NFFT_EUNSUPPORTED: return "parameters valid but not supported by this build";
+    case NFFT_EUNSUPPORTED: return "parameters valid but not supported by this library";
     default: return "unknown status";
   }
 }
