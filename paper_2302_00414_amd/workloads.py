@@ -7,7 +7,7 @@ and the CPU oracle consume, so that the two sides see identical inputs.
 Node sets follow the grids of the paper's numerical section (Remark 5.1):
 uniform random points, the jittered Cartesian grid, the polar grid with signed
 radius (eq. (5.2)), plus an Archimedean spiral trajectory and plain
-equispaced grids. All nodes are returned as float64 arrays of shape (N, d),
+equispaced grids, and the band-limited test function of Example 5.5. All nodes are returned as float64 arrays of shape (N, d),
 row-major, in the torus coordinates [-1/2, 1/2)^d.
 """
 from __future__ import annotations
@@ -22,6 +22,8 @@ __all__ = [
     "polar_area_weights",
     "spiral_nodes",
     "equispaced_nodes",
+    "triangle_pulse_coefficients",
+    "triangle_pulse_samples",
     "complex_normal",
     "uniform_coefficients",
     "CONFIGS",
@@ -125,6 +127,27 @@ def equispaced_nodes(n: int, d: int) -> np.ndarray:
     ax = np.arange(-n // 2, n // 2) / n
     mesh = np.meshgrid(*([ax] * d), indexing="ij")
     return np.stack([a.reshape(-1) for a in mesh], axis=1).astype(np.float64)
+
+
+def triangle_pulse_coefficients(M: int, d: int, b: int) -> np.ndarray:
+    """Example 5.5: fhat(v) = prod_t g(v_t) with the triangular pulse
+    g(v) = (1 - |v / b|) on [-b, b] (zero outside), sampled at k in I_M
+    (C order, k_t = -M/2 .. M/2 - 1), complex128."""
+    k = np.arange(-M // 2, M // 2, dtype=np.float64)
+    g = np.clip(1.0 - np.abs(k) / b, 0.0, None)
+    out = g
+    for _ in range(d - 1):
+        out = np.multiply.outer(out, g)
+    return out.reshape(-1).astype(np.complex128)
+
+
+def triangle_pulse_samples(x: np.ndarray, b: int) -> np.ndarray:
+    """Example 5.5: the inverse Fourier transform of the pulse above,
+    f(x) = prod_t b sinc^2(b pi x_t) with sinc(t) = sin(t) / t, at the rows
+    of x (a function on R^d, band-limited to [-b, b]^d), complex128."""
+    x = np.asarray(x, dtype=np.float64)
+    # numpy's sinc is sin(pi y) / (pi y)
+    return np.prod(b * np.sinc(b * x) ** 2, axis=1).astype(np.complex128)
 
 
 def complex_normal(shape, seed: int) -> np.ndarray:
