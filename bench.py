@@ -216,6 +216,80 @@ def run_bopt(steps):
                 build_s=t_build, ms_per_reconstruction=ms, points_per_s=N / (ms / 1e3), **info)
 
 
+def run_refine(steps, iters=4):
+    """Weighted iterative refinement (nfft_refine) on the polar workload of
+    the headline (512 x 512 nodes, M = 256, m = 6, area weights, float32):
+    milliseconds per call of `iters` steps (each one forward and one weighted
+    adjoint plus two vector passes) and the relative residuals per step, for
+    samples of a random trigonometric polynomial of degree M (made with the
+    plan's forward transform)."""
+    import torch
+    from paper_2302_00414_amd import workloads as wl
+    from paper_2302_00414_amd.nfft import Plan
+
+    x = wl.polar_nodes(512, 512)
+    N = x.shape[0]
+    plan = Plan(x, M, SIGMA, 6, precision="f32")
+    plan.set_weights(wl.polar_area_weights(512, 512).astype(np.complex128))
+    fh = torch.from_numpy(wl.complex_normal(M * M, 14)).to("cuda", torch.complex64)
+    f = plan.forward(fh)
+    out = torch.empty(M * M, dtype=torch.complex64, device="cuda")
+    _, res = plan.refine(f, iters, out=out, residuals=True)
+    for _ in range(3):
+        plan.refine(f, iters, out=out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.refine(f, iters, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    plan.close()
+    return dict(workload=f"polar 512x512 (N=262144), d=2, M=256, m=6, area weights, float32, "
+                         f"{iters} refinement steps, samples of a random polynomial",
+                ms_per_call=ms, ms_per_step=ms / iters, relative_residuals=[float(r) for r in res])
+
+
+def run_bandlimited():
+    """Example 5.5: the triangular pulse b = 24 sampled on a jittered 144 x 144
+    grid, M = 64; largest pointwise error of the reconstructed fhat(k) for the
+    weights of Algorithm 3.6, the optimized sparse matrix (sigma = 2, m = 4),
+    the PCF weights (3.62) and an equispaced 144 x 144 grid (float64)."""
+    import torch
+    from paper_2302_00414_amd import workloads as wl
+    from paper_2302_00414_amd.nfft import Plan, compute_weights
+
+    Mb, b, n = 64, 24, 144
+    fh = wl.triangle_pulse_coefficients(Mb, 2, b)
+
+    def rec(x, w):
+        p = Plan(x, Mb, 2.0, 6, precision="f64")
+        p.set_weights(w)
+        h = p.adjoint(torch.from_numpy(wl.triangle_pulse_samples(x, b)).cuda()).cpu().numpy()
+        p.close()
+        return float(np.max(np.abs(h - fh)))
+
+    xe = wl.equispaced_nodes(n, 2)
+    out = {"equispaced": rec(xe, np.full(xe.shape[0], 1.0 / xe.shape[0], dtype=np.complex128))}
+    x = wl.jittered_nodes((n, n), 5, jitter=1.0)
+    t0 = time.perf_counter()
+    w, _ = compute_weights(x, Mb, 2.0, 8, 1e-13, 2000)
+    torch.cuda.synchronize()
+    out["alg3.6_weights_s"] = time.perf_counter() - t0
+    out["alg3.6"] = rec(x, w.cpu().numpy())
+    wp, _ = compute_weights(x, Mb, 2.0, 8, scheme="pcf")
+    out["pcf"] = rec(x, wp.cpu().numpy())
+    p = Plan(x, Mb, 2.0, 4, precision="f64")
+    p.build_bopt(x)
+    h = p.bopt_adjoint(torch.from_numpy(wl.triangle_pulse_samples(x, b)).cuda()).cpu().numpy()
+    p.close()
+    out["bopt"] = float(np.max(np.abs(h - fh)))
+    return dict(workload="Example 5.5: triangular pulse b=24, jittered 144x144, M=64, "
+                         "max |fhat_rec(k) - fhat(k)|", **out)
+
+
 def run_batched(steps):
     """Spiral trajectory, N = 131072, 32 right-hand sides, M = 256, m = 6: one
     fused float32 adjoint of all 32 against 32 float64 single calls."""
@@ -443,6 +517,8 @@ def main():
                            "f64": run_forward("f64", x, max(10, args.steps // 5))}
         line["weights_gpu"] = run_weights()
         line["bopt"] = run_bopt(max(10, args.steps // 5))
+        line["refine"] = run_refine(max(10, args.steps // 20))
+        line["bandlimited"] = run_bandlimited()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(x, w, f, r32["out"], r64["out"])
         line["cpu_baseline"] = cb["baseline"]

@@ -238,6 +238,34 @@ int nfft_adjoint(nfft_plan_t plan, const void *f, void *fhat, int nrhs, void *st
 int nfft_forward(nfft_plan_t plan, const void *fhat, void *f, int nrhs, void *stream);
 
 /*
+ * nfft_refine -- the reconstruction of nfft_adjoint improved iteratively with
+ * the same weights: fhat_0 = A^* W f (eq. (3.7)), then
+ *     fhat_{k+1} = fhat_k + A^* W (f - A fhat_k),   k = 0 .. iters-1,
+ * with A and A^* the plan's nfft_forward and weighted nfft_adjoint. The
+ * iterates are the partial sums of the Neumann series of (A^* W A)^{-1} in the
+ * proof of Theorem 3.15 applied to A^* W f: with A^* W A = I + E and
+ * ||E||_2 < 1 (e.g. |I_M| eps < 1, eps of (3.36)) they tend to the weighted
+ * least-squares solution (A^* W A)^{-1} A^* W f, and for samples of a
+ * trigonometric polynomial of degree M the error shrinks by ||E||_2 per
+ * step (k = 0 is the bound (3.37)). The paper leaves the iteration open;
+ * this is the plain one with the weights as approximate inverse.
+ *   f      device, nrhs*N complex (plan precision), caller's node order
+ *   fhat   device, nrhs*M^d complex (plan precision), output fhat_iters
+ *   nrhs   1 .. max_rhs
+ *   iters  0 .. 1000 correction steps (0: the same result as nfft_adjoint)
+ *   res    NULL, or host memory for iters+1 doubles: the relative residuals
+ *          ||f - A fhat_k||_2 / ||f||_2, k = 0..iters, over all right-hand
+ *          sides (float64 sums in a fixed order; one more forward transform,
+ *          and the call waits for `stream`)
+ * Each step costs one forward and one adjoint. The first call allocates
+ * max_rhs * (N + M^d) complex values of workspace for the plan (NFFT_ENOMEM
+ * if there is none). NFFT_ESTATE without weights; NFFT_EINVAL for a bad
+ * nrhs or iters, before anything is enqueued.
+ */
+int nfft_refine(nfft_plan_t plan, const void *f, void *fhat, int nrhs, int iters, double *res,
+                void *stream);
+
+/*
  * nfft_weights -- density-compensation weights of Algorithm 3.6 for a node
  * set, computed on the device in float64. The conditions (3.14),
  * A_2M^T w = e_0 on I_2M, are solved by conjugate gradients from zero: on

@@ -21,7 +21,8 @@ NFFT_TUNE_COUNT = 7
 EXPORTS = (
     "nfft_plan", "nfft_plan_tuned", "nfft_plan_autotune", "nfft_get_tuning", "nfft_set_tuning",
     "nfft_plan_clone",
-    "nfft_set_weights", "nfft_adjoint", "nfft_forward", "nfft_weights", "nfft_weights_ex",
+    "nfft_set_weights", "nfft_adjoint", "nfft_forward", "nfft_refine", "nfft_weights",
+    "nfft_weights_ex",
     "nfft_bopt_build",
     "nfft_bopt_adjoint", "nfft_bopt_inverse_adjoint", "nfft_bopt_get", "nfft_destroy",
     "nfft_footprint", "nfft_strerror", "nfft_last_error", "nfft_plan_info",
@@ -70,6 +71,8 @@ def load() -> ctypes.CDLL:
     lib.nfft_adjoint.restype = i32
     lib.nfft_forward.argtypes = [vp, vp, vp, i32, vp]
     lib.nfft_forward.restype = i32
+    lib.nfft_refine.argtypes = [vp, vp, vp, i32, i32, ctypes.POINTER(dbl), vp]
+    lib.nfft_refine.restype = i32
     lib.nfft_weights.argtypes = [i32, i32, dbl, i32, i64, vp, dbl, i32, vp, ctypes.POINTER(dbl), vp]
     lib.nfft_weights.restype = i32
     lib.nfft_weights_ex.argtypes = [i32, i32, dbl, i32, i64, vp, i32, dbl, i32, vp,

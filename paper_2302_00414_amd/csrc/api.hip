@@ -113,6 +113,11 @@ struct nfft_plan_s {
   void* grid = nullptr;
   void* tw = nullptr;
   void* fac = nullptr;
+  // weighted iterative refinement, allocated on first use: residuals
+  // [max_rhs][N], corrections [max_rhs][M^d], norm partials and results
+  void* ref_r = nullptr;
+  void* ref_h = nullptr;
+  double* ref_red = nullptr;
   std::vector<void*> allocs;
   // profiling
   bool profiling = false;
@@ -806,6 +811,49 @@ int run_forward(nfft_plan_t p, const void* fhat, void* f, int nrhs, hipStream_t 
   return NFFT_OK;
 }
 
+// Weighted iterative refinement: fhat_0 = A^* W f (Algorithm 3.7), then
+// fhat_{k+1} = fhat_k + A^* W (f - A fhat_k) for k < iters, so that fhat_k is
+// the partial sum up to n = k of the Neumann series sum_n (I - A^* W A)^n
+// applied to A^* W f (proof of Theorem 3.15); it tends to the weighted
+// least-squares solution when ||I - A^* W A||_2 < 1. With res, the squared
+// norms of f and of the residuals f - A fhat_k, k = 0..iters, are reduced on
+// the device and returned as relative residuals (the call then waits).
+constexpr int kMaxRefine = 1000;
+
+template <typename R>
+int run_refine(nfft_plan_t p, const void* f, void* fhat, int nrhs, int iters, double* res,
+               hipStream_t s) {
+  const int64_t nf = (int64_t)nrhs * p->N, nh = (int64_t)nrhs * ipow(p->M, p->d);
+  if (!p->ref_r) {
+    TRY(dalloc(p, &p->ref_r, (size_t)p->max_rhs * p->N * sizeof(cplx<R>), false));
+    TRY(dalloc(p, &p->ref_h, (size_t)p->max_rhs * ipow(p->M, p->d) * sizeof(cplx<R>), false));
+    TRY(dalloc(p, &p->ref_red, (nfft::kRefineBlocks + kMaxRefine + 2) * sizeof(double), false));
+  }
+  cplx<R>* r = (cplx<R>*)p->ref_r;
+  cplx<R>* c = (cplx<R>*)p->ref_h;
+  cplx<R>* h = (cplx<R>*)fhat;
+  const cplx<R>* fv = (const cplx<R>*)f;
+  double* part = p->ref_red;
+  double* norms = part + nfft::kRefineBlocks;  // ||f||^2, then ||r_k||^2
+  TRY(run_adjoint<R>(p, f, fhat, nrhs, s));    // fhat_0
+  if (res) HIP_TRY(p, nfft::launch_sumsq<R>(fv, nf, part, norms, s));
+  for (int k = 0; k <= iters; ++k) {
+    if (k == iters && !res) break;  // the last residual is only reported
+    TRY(run_forward<R>(p, fhat, r, nrhs, s));
+    HIP_TRY(p, nfft::launch_refine_residual<R>(fv, r, nf, part, res ? norms + 1 + k : nullptr, s));
+    if (k == iters) break;
+    TRY(run_adjoint<R>(p, r, c, nrhs, s));  // A^* W r_k
+    HIP_TRY(p, nfft::launch_refine_update<R>(h, c, nh, s));
+  }
+  if (res) {
+    std::vector<double> nv(iters + 2);
+    HIP_TRY(p, hipMemcpyAsync(nv.data(), norms, nv.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(p, hipStreamSynchronize(s));
+    for (int k = 0; k <= iters; ++k) res[k] = nv[0] > 0 ? std::sqrt(nv[1 + k] / nv[0]) : 0.0;
+  }
+  return NFFT_OK;
+}
+
 // Milliseconds per adjoint of nrhs right-hand sides: two warm-up calls, then
 // the better of two rounds of `reps` calls between HIP events.
 double time_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t s) {
@@ -963,6 +1011,8 @@ int nfft_plan_clone(nfft_plan_t src, int max_rhs, nfft_plan_t* out, void* stream
   p->last_error.clear();
   p->max_rhs = max_rhs;
   p->tilep = p->itemp = p->bufA = p->bufB = p->grid = nullptr;
+  p->ref_r = p->ref_h = nullptr;
+  p->ref_red = nullptr;
   hipStream_t s = (hipStream_t)stream;
   int st = (hipSetDevice(p->device) == hipSuccess) ? NFFT_OK : NFFT_EDEVICE;
   if (st == NFFT_OK)
@@ -1476,6 +1526,21 @@ int nfft_forward(nfft_plan_t p, const void* fhat, void* f, int nrhs, void* strea
   hipStream_t s = (hipStream_t)stream;
   return p->prec == NFFT_F64 ? run_forward<double>(p, fhat, f, nrhs, s)
                              : run_forward<float>(p, fhat, f, nrhs, s);
+}
+
+int nfft_refine(nfft_plan_t p, const void* f, void* fhat, int nrhs, int iters, double* res,
+                void* stream) {
+  if (!p) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
+  if (!f || !fhat) return fail(p, NFFT_EINVAL, "f or fhat is NULL");
+  if (nrhs < 1 || nrhs > p->max_rhs)
+    return fail(p, NFFT_EINVAL, "nrhs = %d outside 1..max_rhs = %d", nrhs, p->max_rhs);
+  if (iters < 0 || iters > kMaxRefine)
+    return fail(p, NFFT_EINVAL, "iters = %d outside 0..%d", iters, kMaxRefine);
+  if (!p->shared->has_weights) return fail(p, NFFT_ESTATE, "nfft_set_weights has not been called");
+  HIP_TRY(p, hipGetLastError());
+  hipStream_t s = (hipStream_t)stream;
+  return p->prec == NFFT_F64 ? run_refine<double>(p, f, fhat, nrhs, iters, res, s)
+                             : run_refine<float>(p, f, fhat, nrhs, iters, res, s);
 }
 
 int nfft_destroy(nfft_plan_t p) {

@@ -189,4 +189,18 @@ hipError_t launch_cg_update(cplx<double>* x, cplx<double>* r, const cplx<double>
 hipError_t launch_cg_direction(cplx<double>* p, const cplx<double>* r, int64_t n, double beta,
                                hipStream_t s);
 
+// ------------------------------------------------ weighted iterative refinement
+// partial sums of the norm reductions: at most kRefineBlocks doubles
+constexpr int kRefineBlocks = 512;
+// r = f - r over n values; with out, *out = ||r||_2^2 (float64, fixed order)
+template <typename R>
+hipError_t launch_refine_residual(const cplx<R>* f, cplx<R>* r, int64_t n, double* partial,
+                                  double* out, hipStream_t s);
+// *out = ||a||_2^2
+template <typename R>
+hipError_t launch_sumsq(const cplx<R>* a, int64_t n, double* partial, double* out, hipStream_t s);
+// h += c
+template <typename R>
+hipError_t launch_refine_update(cplx<R>* h, const cplx<R>* c, int64_t n, hipStream_t s);
+
 }  // namespace nfft

@@ -131,6 +131,17 @@ def nfft_forward(plan, fhat: torch.Tensor, f: torch.Tensor, nrhs: int, stream=No
                                    ctypes.c_void_p(f.data_ptr()), nrhs, _stream_ptr(stream)), plan)
 
 
+def nfft_refine(plan, f: torch.Tensor, fhat: torch.Tensor, nrhs: int, iters: int,
+                residuals: bool = False, stream=None) -> Optional[np.ndarray]:
+    """fhat_iters of the weighted iterative refinement (nfft_refine); with
+    residuals, the relative residuals ||f - A fhat_k|| / ||f||, k = 0..iters."""
+    res = (ctypes.c_double * (iters + 1))() if residuals and iters >= 0 else None
+    check(_lib.load().nfft_refine(plan, ctypes.c_void_p(f.data_ptr()),
+                                  ctypes.c_void_p(fhat.data_ptr()), nrhs, int(iters), res,
+                                  _stream_ptr(stream)), plan)
+    return np.array(res[:], dtype=np.float64) if res is not None else None
+
+
 def nfft_weights(d: int, M: int, sigma: float, m: int, nodes: torch.Tensor, tol: float,
                  maxit: int, w: torch.Tensor, stream=None) -> dict:
     """Algorithm 3.6 on the device (float64); w: complex128 device tensor of N."""
@@ -334,6 +345,22 @@ class Plan:
             out = torch.empty((nrhs, self.N), dtype=self.cdtype, device=self.device)
         nfft_forward(self._h, fhat, out, nrhs, stream)
         return out.reshape(self.N) if single else out
+
+    def refine(self, f, iters: int, out: Optional[torch.Tensor] = None, residuals: bool = False,
+               stream=None):
+        """The adjoint reconstruction improved by `iters` steps of
+        fhat <- fhat + A^* W (f - A fhat) (nfft_refine); f is (N,) or
+        (nrhs, N). Returns fhat, or (fhat, relative residuals k = 0..iters)
+        with residuals=True (the call then waits for the stream)."""
+        single = f.dim() == 1 if isinstance(f, torch.Tensor) else np.ndim(f) == 1
+        f = self._coerce(f, self.N)
+        nrhs = f.numel() // self.N
+        K = self.M ** self.d
+        if out is None:
+            out = torch.empty((nrhs, K), dtype=self.cdtype, device=self.device)
+        res = nfft_refine(self._h, f, out, nrhs, iters, residuals, stream)
+        out = out.reshape(K) if single else out
+        return (out, res) if residuals else out
 
     def _graph(self, fn, src: torch.Tensor, out: torch.Tensor):
         """Capture fn(src, out=out) (every kernel of one transform) into a HIP

@@ -143,6 +143,7 @@ def test_bad_counts_and_pointers():
     assert lib.nfft_plan(None, 2, 32, 2.0, 4, 4, x.ctypes.data, 0, 1, None) == _lib.NFFT_EINVAL
     assert lib.nfft_adjoint(None, None, None, 1, None) == _lib.NFFT_EINVAL
     assert lib.nfft_forward(None, None, None, 1, None) == _lib.NFFT_EINVAL
+    assert lib.nfft_refine(None, None, None, 1, 2, None, None) == _lib.NFFT_EINVAL
     assert lib.nfft_set_weights(None, None, None) == _lib.NFFT_EINVAL
     assert lib.nfft_destroy(None) == _lib.NFFT_OK
 
