@@ -317,14 +317,19 @@ int nfft_weights_ex(int d, int M, double sigma, int m, int64_t N, const double *
  * support reaches l periodically. Its values minimise
  * ||H_l b - |I_Ms|^{-1} D^{-1} f_l||_2 over real b (H_l of (4.11)), i.e.
  * solve Re(H_l^* H_l) b = Re(v_l) with (4.13) and (4.14); the values are kept
- * in the plan's precision. A node whose Cholesky pivot falls below 1e-13
- * |I_M| (a duplicate, or numerically dependent) gets the value zero.
+ * in the plan's precision. A column whose Cholesky meets a pivot below 1e-13
+ * |I_M| has singular normal equations (duplicate nodes, or more nodes than
+ * the polynomials of degree M tell apart within one window support); it is
+ * factorised again with 1e-12 |I_M| added to the diagonal, which reaches the
+ * least-squares objective. Columns of up to about 190 nodes keep their Gram
+ * triangle in LDS; larger ones, up to 4000 nodes, in a device-memory
+ * workspace (at most 1 GiB, freed before the call returns).
  *   nodes  the plan's nodes again, N*d float64 (host or device), same order
  *   info   host, 3 doubles, or NULL: largest column set, number of nonzeros,
- *          number of columns with a dropped node
- * NFFT_EUNSUPPORTED if some column holds more nodes than one work-group's
- * LDS can factor (about 190); NFFT_ESTATE if already built. Synchronises
- * `stream`.
+ *          number of columns with singular normal equations
+ * NFFT_EUNSUPPORTED if some column holds more than 4000 nodes (NFFT_ENOMEM
+ * if the workspace cannot be had); NFFT_ESTATE if already built.
+ * Synchronises `stream`.
  */
 int nfft_bopt_build(nfft_plan_t plan, const double *nodes, double *info, void *stream);
 

@@ -109,6 +109,17 @@ def _grid_index(c, Ms, d):
     return l
 
 
+def _solve_column(xw, js, c, M, sigma, m, rcond):
+    """Values of column c (nodes js): the real normal equations of (4.12),
+    Re(H^* H) b = Re(v), by a minimum-norm least-squares solve."""
+    Ms = window.oversampled_size(M, sigma)
+    l = _grid_index(c, Ms, xw.shape[1])
+    G = gram(xw[js], M)
+    v = rhs(xw[js], l, M, sigma, m)
+    b, *_ = np.linalg.lstsq(G.real, v.real, rcond=rcond)
+    return b
+
+
 def bopt(x, M, sigma, m, rcond=1e-13):
     """Algorithm 4.3. Returns B_opt as a scipy CSR matrix N x |I_Ms| (real)."""
     x = np.atleast_2d(np.asarray(x, dtype=np.float64))
@@ -121,14 +132,22 @@ def bopt(x, M, sigma, m, rcond=1e-13):
         s, e = indptr[c], indptr[c + 1]
         if s == e:
             continue
-        js = nodes[s:e]
-        l = _grid_index(c, Ms, d)
-        G = gram(xw[js], M)
-        v = rhs(xw[js], l, M, sigma, m)
-        b, *_ = np.linalg.lstsq(G.real, v.real, rcond=rcond)
-        vals[s:e] = b
+        vals[s:e] = _solve_column(xw, nodes[s:e], c, M, sigma, m, rcond)
     # stored by columns: transpose of CSC
     return sp.csc_matrix((vals, nodes, indptr), shape=(N, Ms ** d)).tocsr()
+
+
+def bopt_columns(x, M, sigma, m, cols, rcond=1e-13):
+    """The columns `cols` of Algorithm 4.3 alone: {c: (nodes, values)}, nodes
+    in increasing order (for checking single columns of large problems)."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    indptr, nodes = column_sets(x, M, sigma, m)
+    xw = _wrap(x)
+    out = {}
+    for c in cols:
+        js = nodes[indptr[c]:indptr[c + 1]]
+        out[int(c)] = (js, _solve_column(xw, js, c, M, sigma, m, rcond) if len(js) else np.zeros(0))
+    return out
 
 
 def bopt_dense(x, M, sigma, m):

@@ -159,6 +159,7 @@ int oversampled(int M, double sigma) {
 
 // Largest LDS a work-group may use on gfx950.
 constexpr size_t kMaxLds = 160 * 1024;
+constexpr int kMaxBoptColumn = 4000;  // nodes of one B_opt column (device-memory Gram triangle)
 
 size_t cbytes(int prec) { return prec == NFFT_F64 ? 16 : 8; }
 size_t rbytes(int prec) { return prec == NFFT_F64 ? 8 : 4; }
@@ -1348,15 +1349,23 @@ int nfft_bopt_build(nfft_plan_t p, const double* nodes, double* info, void* stre
     hp[c + 1] = hp[c] + hc[c];
     nmax = std::max(nmax, hc[c]);
   }
-  // the packed Gram matrix of the largest column must fit in LDS
-  if (nfft::bopt_solve_lds(nmax) > kMaxLds)
+  // columns whose packed Gram triangle fits in LDS are solved there; larger
+  // ones (up to the LDS of their other per-node arrays) with the triangle in
+  // a device-memory workspace
+  int cap_lds = 1, cap_big = 1;
+  while (nfft::bopt_solve_lds(cap_lds + 1, true) <= kMaxLds) ++cap_lds;
+  while (nfft::bopt_solve_lds(cap_big + 1, false) <= kMaxLds && cap_big < kMaxBoptColumn) ++cap_big;
+  if (nmax > cap_big)
     return fail(p, NFFT_EUNSUPPORTED,
-                "a grid column is reached by %d nodes; the column solve holds at most %d in LDS",
-                nmax, [] {
-                  int n = 1;
-                  while (nfft::bopt_solve_lds(n + 1) <= kMaxLds) ++n;
-                  return n;
-                }());
+                "a grid column is reached by %d nodes; the column solve takes at most %d", nmax,
+                cap_big);
+  std::vector<int64_t> big;  // columns solved with the triangle in device memory
+  int nbig = 0;
+  for (int64_t c = 0; c < ncols; ++c)
+    if (hc[c] > cap_lds) {
+      big.push_back(c);
+      nbig = std::max(nbig, hc[c]);
+    }
   const int64_t nnz = hp[ncols];
   const size_t rb = rbytes(p->prec);
   TRY(dalloc(p, &sd.bopt_ptr, (ncols + 1) * sizeof(int64_t)));
@@ -1376,14 +1385,34 @@ int nfft_bopt_build(nfft_plan_t p, const double* nodes, double* info, void* stre
   }
   HIP_TRY(p, hipMemcpyAsync(wh, hw.data(), M * sizeof(double), hipMemcpyHostToDevice, s));
   constexpr double kPivotRel = 1e-13;
-  if (p->prec == NFFT_F64)
-    HIP_TRY(p, nfft::launch_bopt_solve<double>((const double*)d_nodes, d, M, Ms, (const double*)wh,
-                                               sd.bopt_ptr, sd.bopt_node, (double*)sd.bopt_val,
-                                               ncols, std::max(1, nmax), kPivotRel, (int*)dropped, s));
-  else
-    HIP_TRY(p, nfft::launch_bopt_solve<float>((const double*)d_nodes, d, M, Ms, (const double*)wh,
-                                              sd.bopt_ptr, sd.bopt_node, (float*)sd.bopt_val,
-                                              ncols, std::max(1, nmax), kPivotRel, (int*)dropped, s));
+  // ridge on the Gram diagonal (which is |I_M|) for rank-deficient columns
+  const double ridge = 1e-12 * (double)ipow(M, d);
+  auto solve = [&](int64_t nc, int nm, const int64_t* cols, double* gA, int64_t stride) {
+    return p->prec == NFFT_F64
+               ? nfft::launch_bopt_solve<double>((const double*)d_nodes, d, M, Ms,
+                                                 (const double*)wh, sd.bopt_ptr, sd.bopt_node,
+                                                 (double*)sd.bopt_val, nc, nm, kPivotRel, ridge,
+                                                 (int*)dropped, cols, gA, stride, s)
+               : nfft::launch_bopt_solve<float>((const double*)d_nodes, d, M, Ms,
+                                                (const double*)wh, sd.bopt_ptr, sd.bopt_node,
+                                                (float*)sd.bopt_val, nc, nm, kPivotRel, ridge,
+                                                (int*)dropped, cols, gA, stride, s);
+  };
+  HIP_TRY(p, solve(ncols, std::max(1, std::min(nmax, cap_lds)), nullptr, nullptr, 0));
+  if (!big.empty()) {
+    // batches of work-groups whose triangles together take at most 1 GiB
+    const int64_t stride = (int64_t)nbig * (nbig + 1) / 2;
+    const int64_t batch = std::max<int64_t>(
+        1, std::min<int64_t>((int64_t)big.size(), (int64_t(1) << 30) / (stride * 8)));
+    void *d_cols, *ws;
+    TRY(talloc(&d_cols, big.size() * sizeof(int64_t)));
+    TRY(talloc(&ws, (size_t)batch * stride * sizeof(double)));
+    HIP_TRY(p, hipMemcpyAsync(d_cols, big.data(), big.size() * sizeof(int64_t),
+                              hipMemcpyHostToDevice, s));
+    for (int64_t b0 = 0; b0 < (int64_t)big.size(); b0 += batch)
+      HIP_TRY(p, solve(std::min<int64_t>(batch, (int64_t)big.size() - b0), nbig,
+                       (const int64_t*)d_cols + b0, (double*)ws, stride));
+  }
   // the same values by rows, for the inverse adjoint of Remark 4.6
   const int64_t F = ipow(2 * m + 1, d);
   TRY(dalloc(p, &sd.bopt_lo, N * d * sizeof(int32_t)));

@@ -10,9 +10,15 @@
 //   v_j = prod_t sum_{k=-M/2}^{M/2-1} w^(k) e^{2 pi i k (x_jt - l_t/M_s)}            (4.14),
 // D_{M/2-1}(s) = sin((M-1) pi s)/sin(pi s). One work-group per column builds
 // the packed lower triangle of the Gram matrix in LDS, factors it by Cholesky
-// (a pivot below a relative threshold marks a dependent node, which gets the
-// value zero: duplicate nodes share nothing, the residual is unchanged) and
-// solves by forward and back substitution.
+// and solves by forward and back substitution. A column with more nodes than
+// the polynomials of degree M tell apart inside one window support (or with
+// duplicate nodes) has singular normal equations: a pivot falls below a
+// relative threshold. Such a column is factorised again with a ridge of
+// 1e-12 times the Gram diagonal (|I_M|), and its solution then reaches the
+// least-squares objective (a Cholesky that only zeroes the small pivots loses
+// the fit there by orders of magnitude); other columns are solved exactly. Columns whose triangle does not
+// fit in LDS (dense node sets, sigma near 1) take the same steps with the
+// triangle in a device-memory workspace, one per work-group, in batches.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -90,25 +96,31 @@ __device__ __forceinline__ void window_series(const double* __restrict__ wh, int
 
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // i >= j
 
+// cols: the columns to solve (blockIdx.x indexes it), or null for all.
+// gA: null to keep the triangle in LDS (columns of more than nmax nodes are
+// left to the other launch), else this work-group's triangle lives at
+// gA + blockIdx.x * gA_stride in device memory.
 template <typename R>
 __global__ __launch_bounds__(256) void bopt_solve_kernel(
     const double* __restrict__ nodes, int d, int M, int Ms, const double* __restrict__ wh,
     const int64_t* __restrict__ col_ptr, int32_t* __restrict__ col_node, R* __restrict__ col_val,
-    int nmax, double piv_rel, int* __restrict__ dropped) {
+    int nmax, double piv_rel, double ridge, int* __restrict__ dropped,
+    const int64_t* __restrict__ cols, double* gA, int64_t gA_stride) {
   extern __shared__ double sm[];
-  const int64_t c = blockIdx.x;
+  const int64_t c = cols ? cols[blockIdx.x] : (int64_t)blockIdx.x;
   const int64_t start = col_ptr[c];
   const int n = (int)(col_ptr[c + 1] - start);
-  if (n == 0) return;
+  if (n == 0 || n > nmax) return;
   const int tid = threadIdx.x;
   const int NT = blockDim.x;
-  double* A = sm;                                     // packed lower triangle, n(n+1)/2
-  double* xs = A + (size_t)nmax * (nmax + 1) / 2;     // n x d coordinates
+  // packed lower triangle, n(n+1)/2
+  double* A = gA ? gA + (int64_t)blockIdx.x * gA_stride : sm;
+  double* xs = gA ? sm : A + (size_t)nmax * (nmax + 1) / 2;  // n x d coordinates
   double* v = xs + (size_t)nmax * 3;                  // right side, then solution
   int* ids = reinterpret_cast<int*>(v + nmax);        // sorted node ids
   int* idr = ids + nmax;                              // unsorted
-  __shared__ int ndrop;
-  if (tid == 0) ndrop = 0;
+  __shared__ int ndrop, ridged;
+  if (tid == 0) ridged = 0;
   for (int i = tid; i < n; i += NT) idr[i] = col_node[start + i];
   __syncthreads();
   // rank sort (ids are distinct): deterministic order by node id
@@ -141,52 +153,63 @@ __global__ __launch_bounds__(256) void bopt_solve_kernel(
     }
     v[i] = pr;
   }
-  // Gram matrix (4.13), real part, lower triangle
-  const int npairs = n * (n + 1) / 2;
-  for (int q = tid; q < npairs; q += NT) {
-    int i = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
-    while (tri(i, 0) > q) --i;
-    while (tri(i + 1, 0) <= q) ++i;
-    const int j = q - tri(i, 0);
-    double pr = 1.0, pi = 0.0;
-    for (int t = 0; t < d; ++t) {
-      double re, im;
-      dirichlet_term(M, xs[i * 3 + t] - xs[j * 3 + t], &re, &im);
-      const double nr = pr * re - pi * im;
-      pi = pr * im + pi * re;
-      pr = nr;
-    }
-    A[q] = pr;
-  }
-  __syncthreads();
-  // Cholesky, right-looking; a pivot below piv_rel * |I_M| (the diagonal of
-  // H^* H) drops the node: its column of L is zero and its value is zero
+  // Gram matrix (4.13), real part, lower triangle, and its Cholesky factor,
+  // right-looking; a pivot below piv_rel * |I_M| (the diagonal of H^* H)
+  // marks a dependent node. If the first pass finds one, the normal
+  // equations are singular and the factorisation is redone with the ridge
+  // on the diagonal; a pivot still below the threshold then drops its node
+  // (its column of L and its value are zero).
   double tol = piv_rel;
   for (int t = 0; t < d; ++t) tol *= (double)M;
-  for (int k = 0; k < n; ++k) {
-    const double akk = A[tri(k, k)];
-    const bool keep = akk > tol;
-    const double lkk = keep ? sqrt(akk) : 0.0;
-    __syncthreads();
-    if (tid == 0) {
-      A[tri(k, k)] = lkk;
-      if (!keep) ++ndrop;
-    }
-    for (int i = k + 1 + tid; i < n; i += NT) A[tri(i, k)] = keep ? A[tri(i, k)] / lkk : 0.0;
-    __syncthreads();
-    if (keep) {
-      const int rest = n - k - 1;
-      const int nup = rest * (rest + 1) / 2;
-      for (int q = tid; q < nup; q += NT) {
-        int i = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
-        while (tri(i, 0) > q) --i;
-        while (tri(i + 1, 0) <= q) ++i;
-        const int j = q - tri(i, 0);
-        const int ii = k + 1 + i, jj = k + 1 + j;
-        A[tri(ii, jj)] -= A[tri(ii, k)] * A[tri(jj, k)];
+  const int npairs = n * (n + 1) / 2;
+  for (int pass = 0; pass < 2; ++pass) {
+    const double rid = pass ? ridge : 0.0;
+    for (int q = tid; q < npairs; q += NT) {
+      int i = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+      while (tri(i, 0) > q) --i;
+      while (tri(i + 1, 0) <= q) ++i;
+      const int j = q - tri(i, 0);
+      double pr = 1.0, pi = 0.0;
+      for (int t = 0; t < d; ++t) {
+        double re, im;
+        dirichlet_term(M, xs[i * 3 + t] - xs[j * 3 + t], &re, &im);
+        const double nr = pr * re - pi * im;
+        pi = pr * im + pi * re;
+        pr = nr;
       }
+      A[q] = i == j ? pr + rid : pr;
     }
+    if (tid == 0) ndrop = 0;
     __syncthreads();
+    for (int k = 0; k < n; ++k) {
+      const double akk = A[tri(k, k)];
+      const bool keep = akk > tol;
+      const double lkk = keep ? sqrt(akk) : 0.0;
+      __syncthreads();
+      if (tid == 0) {
+        A[tri(k, k)] = lkk;
+        if (!keep) ++ndrop;
+      }
+      for (int i = k + 1 + tid; i < n; i += NT) A[tri(i, k)] = keep ? A[tri(i, k)] / lkk : 0.0;
+      __syncthreads();
+      if (keep) {
+        const int rest = n - k - 1;
+        const int nup = rest * (rest + 1) / 2;
+        for (int q = tid; q < nup; q += NT) {
+          int i = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+          while (tri(i, 0) > q) --i;
+          while (tri(i + 1, 0) <= q) ++i;
+          const int j = q - tri(i, 0);
+          const int ii = k + 1 + i, jj = k + 1 + j;
+          A[tri(ii, jj)] -= A[tri(ii, k)] * A[tri(jj, k)];
+        }
+      }
+      __syncthreads();
+    }
+    const bool singular = ndrop > 0;
+    __syncthreads();  // every thread has read ndrop before it is reset
+    if (!singular) break;
+    if (pass == 0 && tid == 0) ridged = 1;
   }
   // forward substitution L y = v
   for (int k = 0; k < n; ++k) {
@@ -211,7 +234,7 @@ __global__ __launch_bounds__(256) void bopt_solve_kernel(
     col_node[start + i] = ids[i];
     col_val[start + i] = (R)v[i];
   }
-  if (tid == 0 && ndrop) atomicAdd(dropped, 1);
+  if (tid == 0 && ridged) atomicAdd(dropped, 1);
 }
 
 // g_c = scale * sum over the column's nodes of b_cj f_j (one wave per
@@ -360,20 +383,23 @@ hipError_t launch_bopt_pattern(const double* nodes, int64_t N, int d, int Ms, in
   return hipGetLastError();
 }
 
-// dynamic LDS of the column solve for columns of up to nmax nodes (plus 64
-// bytes of headroom for the kernel's static LDS)
-size_t bopt_solve_lds(int nmax) {
-  return ((size_t)nmax * (nmax + 1) / 2 + (size_t)nmax * 4) * sizeof(double) +
-         (size_t)2 * nmax * sizeof(int) + 64;
+// dynamic LDS of the column solve for columns of up to nmax nodes, with the
+// Gram triangle in LDS or (in_lds false) in device memory (plus 64 bytes of
+// headroom for the kernel's static LDS)
+size_t bopt_solve_lds(int nmax, bool in_lds) {
+  const size_t tri_n = in_lds ? (size_t)nmax * (nmax + 1) / 2 : 0;
+  return (tri_n + (size_t)nmax * 4) * sizeof(double) + (size_t)2 * nmax * sizeof(int) + 64;
 }
 
 template <typename R>
 hipError_t launch_bopt_solve(const double* nodes, int d, int M, int Ms, const double* wh,
                              const int64_t* col_ptr, int32_t* col_node, R* col_val, int64_t ncols,
-                             int nmax, double piv_rel, int* dropped, hipStream_t s) {
+                             int nmax, double piv_rel, double ridge, int* dropped,
+                             const int64_t* cols, double* gA, int64_t gA_stride, hipStream_t s) {
   if (ncols == 0) return hipSuccess;
-  hipLaunchKernelGGL(bopt_solve_kernel<R>, dim3((unsigned)ncols), dim3(256), bopt_solve_lds(nmax),
-                     s, nodes, d, M, Ms, wh, col_ptr, col_node, col_val, nmax, piv_rel, dropped);
+  hipLaunchKernelGGL(bopt_solve_kernel<R>, dim3((unsigned)ncols), dim3(256),
+                     bopt_solve_lds(nmax, gA == nullptr), s, nodes, d, M, Ms, wh, col_ptr,
+                     col_node, col_val, nmax, piv_rel, ridge, dropped, cols, gA, gA_stride);
   return hipGetLastError();
 }
 
@@ -388,10 +414,12 @@ hipError_t launch_bopt_apply(const int64_t* col_ptr, const int32_t* col_node, co
 
 template hipError_t launch_bopt_solve<float>(const double*, int, int, int, const double*,
                                              const int64_t*, int32_t*, float*, int64_t, int,
-                                             double, int*, hipStream_t);
+                                             double, double, int*, const int64_t*, double*,
+                                             int64_t, hipStream_t);
 template hipError_t launch_bopt_solve<double>(const double*, int, int, int, const double*,
                                               const int64_t*, int32_t*, double*, int64_t, int,
-                                              double, int*, hipStream_t);
+                                              double, double, int*, const int64_t*, double*,
+                                              int64_t, hipStream_t);
 template hipError_t launch_bopt_apply<float>(const int64_t*, const int32_t*, const float*,
                                              const cplx<float>*, int64_t, cplx<float>*, int64_t,
                                              int64_t, int, double, hipStream_t);

@@ -189,7 +189,7 @@ def nfft_bopt_build(plan, nodes: torch.Tensor, stream=None) -> dict:
     info = (ctypes.c_double * 3)()
     check(_lib.load().nfft_bopt_build(plan, ctypes.c_void_p(nodes.data_ptr()), info,
                                       _stream_ptr(stream)), plan)
-    return {"max_column": int(info[0]), "nnz": int(info[1]), "columns_with_dropped_node": int(info[2])}
+    return {"max_column": int(info[0]), "nnz": int(info[1]), "singular_columns": int(info[2])}
 
 
 def nfft_bopt_adjoint(plan, f: torch.Tensor, fhat: torch.Tensor, nrhs: int, stream=None) -> None:

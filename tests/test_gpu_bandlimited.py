@@ -68,7 +68,7 @@ def errors():
     print("[case] optimized sparse matrix sigma=2 m=4", flush=True)
     p = Plan(x, M, 2.0, 4, precision="f64", device="cuda:0")
     info = p.build_bopt(x)
-    assert info["columns_with_dropped_node"] == 0
+    assert info["singular_columns"] == 0
     out["bopt"] = err(p.bopt_adjoint(torch.from_numpy(f).to("cuda:0")).cpu().numpy())
     p.close()
     print("[errors]", out, flush=True)

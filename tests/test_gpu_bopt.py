@@ -10,7 +10,7 @@ import pytest
 import scipy.sparse as sp
 import torch
 
-from oracle import bopt as ob, ndft, metrics
+from oracle import bopt as ob, ndft, metrics, window
 from paper_2302_00414_amd import workloads as wl
 
 pytestmark = [pytest.mark.gpu,
@@ -64,7 +64,10 @@ def test_reconstruction_matches_oracle(d, N, M, sigma, m, prec):
     p.close()
 
 
-def test_duplicate_nodes_are_dropped():
+def test_duplicate_nodes_share_their_value():
+    """Exact duplicates make a column's normal equations singular; the ridge
+    solve gives both copies the same value (as the oracle's minimum-norm
+    solution does), and the reconstruction matches the oracle's."""
     M, sigma, m = 16, 2.0, 2
     base = wl.uniform_nodes(120, 2, 50)
     x = np.concatenate([base, base[:10]])             # ten exact duplicates
@@ -72,7 +75,21 @@ def test_duplicate_nodes_are_dropped():
     f = ndft.forward(x, fh, M)                         # consistent samples
     p = _plan(x, M, sigma, m, "f64")
     info = p.build_bopt(x)
-    assert info["columns_with_dropped_node"] > 0
+    assert info["singular_columns"] > 0
+    G = _gpu_matrix(p, x.shape[0])
+    R = ob.bopt(x, M, sigma, m)
+    Gd = G.toarray()
+    # equal up to the rounding of a system whose ridge direction has
+    # eigenvalue 1e-12 |I_M|
+    assert np.max(np.abs(Gd[120:] - Gd[:10])) <= 1e-3 * np.max(np.abs(Gd))
+    xw = ob._wrap(x)
+    Gc, Rc = G.tocsc(), R.tocsc()
+    for c in np.nonzero(np.diff(Gc.indptr))[0]:
+        s0, e0 = Gc.indptr[c], Gc.indptr[c + 1]
+        js = Gc.indices[s0:e0]
+        q_gpu, scale = _column_objective(xw, js, c, Gc.data[s0:e0], M, sigma, m)
+        q_orc, _ = _column_objective(xw, js, c, Rc.data[Rc.indptr[c]:Rc.indptr[c + 1]], M, sigma, m)
+        assert q_gpu - q_orc <= 1e-9 * scale, c
     got = p.bopt_adjoint(torch.from_numpy(f)).cpu().numpy()
     ref = ob.reconstruct(x, f, ob.bopt(x, M, sigma, m), M, sigma, m)
     assert metrics.rel_err(got, ref) <= 1e-6
@@ -89,10 +106,18 @@ def test_states_and_limits():
     with pytest.raises(NfftError):
         p.build_bopt(x)                                            # built already
     p.close()
-    dense = wl.uniform_nodes(20000, 2, 61)                          # ~1600 nodes per column
+    # over 1000 nodes per column, more than |I_M| = 256: built with the Gram
+    # triangles in device memory
+    dense = wl.uniform_nodes(20000, 2, 61)
     q = _plan(dense, 16, 2.0, 4, "f64")
-    with pytest.raises(NfftError):
-        q.build_bopt(dense)
+    info = q.build_bopt(dense)
+    assert info["max_column"] > 1000
+    q.close()
+    denser = wl.uniform_nodes(80000, 2, 62)                         # ~5000 nodes per column
+    q = _plan(denser, 16, 2.0, 4, "f64")
+    with pytest.raises(NfftError) as e:
+        q.build_bopt(denser)
+    assert e.value.status == 5
     q.close()
 
 
@@ -162,4 +187,58 @@ def test_inverse_adjoint_on_random_nodes_solves_as_well():
     r_ref = metrics.rel_err(ndft.adjoint(x, ref, M), h)
     print(f"[bopt] residual of A^* f = h: gpu {r_gpu:.3e} oracle {r_ref:.3e}", flush=True)
     assert r_gpu <= 1.1 * r_ref + 1e-12
+    p.close()
+
+
+def _patch_nodes():
+    """A jittered 90 x 90 grid with its nodes in a 0.2 x 0.2 square replaced by
+    a finer jittered 30 x 30 patch: about 130 nodes per column of B outside the
+    patch and up to about 360 inside (sigma = 2, m = 4, M = 32)."""
+    base = wl.jittered_nodes((90, 90), 61, jitter=0.25)
+    inside = np.all(np.abs(base - 0.1) < 0.1, axis=1)
+    patch = 0.1 + 0.2 * wl.jittered_nodes((30, 30), 62, jitter=0.25)
+    return np.concatenate([base[~inside], patch])
+
+
+def _column_objective(xw, js, c, b, M, sigma, m):
+    """b^T Re(H^* H) b - 2 b^T Re(v): the column's objective ||H b - v||^2 up
+    to a constant, from the oracle's (4.13) and (4.14)."""
+    Ms = window.oversampled_size(M, sigma)
+    l = ob._grid_index(c, Ms, xw.shape[1])
+    G = ob.gram(xw[js], M).real
+    v = ob.rhs(xw[js], l, M, sigma, m).real
+    return float(b @ G @ b - 2 * b @ v), float(v @ v)
+
+
+def test_columns_beyond_lds_match_oracle():
+    """Columns whose packed Gram triangle does not fit in LDS (more than about
+    198 nodes) are solved with the triangle in device memory. Columns this
+    full hold far more nodes than the degree-M polynomials can tell apart
+    inside one window support, so their normal equations are rank deficient
+    and the values are not unique: the GPU's pivot-guarded Cholesky (dependent
+    nodes get 0) and the oracle's minimum-norm solve must reach the same
+    objective, and the pattern must agree. Columns of both kinds are sampled."""
+    M, sigma, m = 32, 2.0, 4
+    x = _patch_nodes()
+    N = x.shape[0]
+    xw = ob._wrap(x)
+    p = _plan(x, M, sigma, m, "f64")
+    info = p.build_bopt(x)
+    assert info["max_column"] > 300
+    G = _gpu_matrix(p, N).tocsc()
+    cnt = np.diff(G.indptr)
+    big = np.argsort(cnt)[::-1][:12]
+    small = np.nonzero((cnt > 0) & (cnt < 190))[0][::331][:12]
+    assert cnt[big].min() > 198 and len(small) == 12
+    for c, (js, vals) in ob.bopt_columns(x, M, sigma, m, np.concatenate([big, small])).items():
+        s, e = G.indptr[c], G.indptr[c + 1]
+        assert np.array_equal(G.indices[s:e], js), c
+        q_gpu, scale = _column_objective(xw, js, c, G.data[s:e], M, sigma, m)
+        q_orc, _ = _column_objective(xw, js, c, vals, M, sigma, m)
+        assert q_gpu - q_orc <= 1e-9 * scale, (c, cnt[c], q_gpu, q_orc, scale)
+    fh = wl.complex_normal(M * M, 63)
+    f = ndft.forward(x, fh, M)
+    got = p.bopt_adjoint(torch.from_numpy(f)).cpu().numpy()
+    print("[reconstruction]", metrics.rel_err(got, fh), flush=True)
+    assert metrics.rel_err(got, fh) <= 1e-2
     p.close()

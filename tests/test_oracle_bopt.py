@@ -170,3 +170,16 @@ def test_inverse_adjoint_solves_the_adjoint_system():
     c = np.vdot(r, h) / np.vdot(r, r)
     e_plain = metrics.rel_err(c * r, h)
     assert e_opt < 0.05 and e_opt < 0.2 * e_plain
+
+
+def test_single_columns_match_the_whole_matrix():
+    """bopt_columns (columns solved alone, for checking large problems) gives
+    the columns of bopt."""
+    x = wl.uniform_nodes(300, 2, 77)
+    M, sigma, m = 16, 2.0, 2
+    B = bopt.bopt(x, M, sigma, m).tocsc()
+    cols = [0, 5, 300, 511, 1023]
+    for c, (js, vals) in bopt.bopt_columns(x, M, sigma, m, cols).items():
+        s, e = B.indptr[c], B.indptr[c + 1]
+        assert np.array_equal(js, B.indices[s:e])
+        assert np.array_equal(vals, B.data[s:e])
