@@ -129,7 +129,7 @@ def run_gpu(prec, x, w, f, steps, warmup, tuning="auto"):
                 lat=np.array(lat), out=res, info=info, tuning=tuning)
 
 
-def run_forward(prec, x, steps):
+def run_forward(prec, x, steps, tuning="auto"):
     """Forward NFFT f = B F D fhat (Algorithm 2.1) on the same plan shape:
     milliseconds per call and per stage."""
     import torch
@@ -137,7 +137,7 @@ def run_forward(prec, x, steps):
     from paper_2302_00414_amd.nfft import Plan
 
     cdt = torch.complex64 if prec == "f32" else torch.complex128
-    plan = Plan(x, M, SIGMA, MW, precision=prec, tuning="auto")
+    plan = Plan(x, M, SIGMA, MW, precision=prec, tuning=tuning)
     fh = torch.from_numpy(wl.complex_normal(M ** D, 7)).to("cuda", cdt)
     out = torch.empty(x.shape[0], dtype=cdt, device="cuda")
     for _ in range(5):
@@ -290,7 +290,51 @@ def run_bandlimited():
                          "max |fhat_rec(k) - fhat(k)|", **out)
 
 
-def run_batched(steps):
+def run_jittered3d(steps, precs=("f32", "f64"), tuning="auto"):
+    """Jittered 128 x 64 x 64 grid (N = 524288), d = 3, M = 64, sigma = 2,
+    m = 4, weights 1/N: the weighted adjoint in float32 and float64 on
+    autotuned plans, milliseconds per call (plain events) and per stage
+    (stage events on a separate loop)."""
+    import torch
+    from paper_2302_00414_amd import workloads as wl
+    from paper_2302_00414_amd.nfft import Plan
+
+    M3, m3 = 64, 4
+    x = wl.jittered_nodes((128, 64, 64), 4)
+    N = x.shape[0]
+    w = np.full(N, 1.0 / N)
+    f = wl.complex_normal(N, 8)
+    res = {}
+    for prec in precs:
+        cdt = torch.complex64 if prec == "f32" else torch.complex128
+        plan = Plan(x, M3, SIGMA, m3, precision=prec, tuning=tuning)
+        plan.set_weights(w)
+        fd = torch.from_numpy(f).to("cuda", cdt)
+        out = torch.empty(M3 ** 3, dtype=cdt, device="cuda")
+        for _ in range(5):
+            plan.adjoint(fd, out=out)
+        plan.set_profiling(True)
+        for _ in range(max(5, steps // 4)):
+            plan.adjoint(fd, out=out)
+        torch.cuda.synchronize()
+        st = plan.stage_times(reset=True)
+        plan.set_profiling(False)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan.adjoint(fd, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[prec] = dict(ms_per_step=ms, points_per_s=N / (ms / 1e3), tuning=plan.tuning(),
+                         stage_us={k: round(v[0] / max(v[1], 1) * 1e3, 3)
+                                   for k, v in st.items() if v[1]})
+        plan.close()
+    return dict(workload="jittered 128x64x64 (N=524288), d=3, M=64, sigma=2, m=4, w=1/N", **res)
+
+
+def run_batched(steps, precs=("f32", "f64"), tuning="auto"):
     """Spiral trajectory, N = 131072, 32 right-hand sides, M = 256, m = 6: one
     fused float32 adjoint of all 32 against 32 float64 single calls."""
     import torch
@@ -303,8 +347,10 @@ def run_batched(steps):
     F = wl.complex_normal((R, N), 5)
     res = {}
     for prec, nrhs in (("f32", R), ("f64", 1)):
+        if prec not in precs:
+            continue
         cdt = torch.complex64 if prec == "f32" else torch.complex128
-        plan = Plan(x, M, SIGMA, MW, precision=prec, max_rhs=nrhs, tuning="auto")
+        plan = Plan(x, M, SIGMA, MW, precision=prec, max_rhs=nrhs, tuning=tuning)
         plan.set_weights(w)
         fd = torch.from_numpy(F).to("cuda", cdt)
         out = torch.empty((nrhs, M * M), dtype=cdt, device="cuda")
@@ -323,6 +369,8 @@ def run_batched(steps):
         ms = e0.elapsed_time(e1) / steps
         res[prec] = dict(ms_per_32_rhs=ms, points_per_s=N * R / (ms / 1e3), tuning=plan.tuning())
         plan.close()
+    if len(res) < 2:
+        return dict(workload="spiral N=131072, d=2, M=256, sigma=2, m=6, 32 rhs, area weights", **res)
     return dict(workload="spiral N=131072, d=2, M=256, sigma=2, m=6, 32 rhs, area weights",
                 f32_fused=res["f32"], f64_separate_calls=res["f64"],
                 speedup=res["f64"]["ms_per_32_rhs"] / res["f32"]["ms_per_32_rhs"])
@@ -412,6 +460,8 @@ def main():
                     help='profiling runs: "auto" (autotuner) or a JSON object of tuning keys')
     ap.add_argument("--precision", choices=["both", "f32", "f64"], default="both",
                     help="profiling runs: time one path only (the JSON line needs both)")
+    ap.add_argument("--only", choices=["jittered3d", "batched", "forward", "refine"], default=None,
+                    help="profiling runs: run one secondary workload alone and print its JSON")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="profiling runs: also launch one device-to-device copy of this size, "
                          "a known-size reference for the FETCH_SIZE / WRITE_SIZE counters")
@@ -432,6 +482,19 @@ def main():
     f = wl.complex_normal(x.shape[0], 3)
     N = x.shape[0]
     Ms = 2 * M
+
+    if args.only:
+        # one secondary workload, for profiling: --precision picks the path,
+        # --tuning a fixed tuning (so that no autotuner runs are traced)
+        k = max(10, args.steps // 5)
+        precs = ("f32", "f64") if args.precision == "both" else (args.precision,)
+        tun = "auto" if args.tuning == "auto" else json.loads(args.tuning)
+        sec = {"jittered3d": lambda: run_jittered3d(k, precs, tun),
+               "batched": lambda: run_batched(k, precs, tun),
+               "forward": lambda: {p: run_forward(p, x, k, tun) for p in precs},
+               "refine": lambda: run_refine(max(10, args.steps // 20))}[args.only]()
+        print(json.dumps({args.only: sec}), flush=True)
+        return
 
     if args.calibrate_copy_mib:
         n = args.calibrate_copy_mib * (1 << 20) // 4
@@ -517,6 +580,7 @@ def main():
                            "f64": run_forward("f64", x, max(10, args.steps // 5))}
         line["weights_gpu"] = run_weights()
         line["bopt"] = run_bopt(max(10, args.steps // 5))
+        line["jittered3d"] = run_jittered3d(max(10, args.steps // 10))
         line["refine"] = run_refine(max(10, args.steps // 20))
         line["bandlimited"] = run_bandlimited()
     if not args.no_cpu_baseline:
