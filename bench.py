@@ -409,6 +409,22 @@ def cpu_baseline(x, w, f, gpu_out32, gpu_out64, budget_s=12.0):
         if time.perf_counter() - t0 > budget_s or reps >= 20:
             break
     dt = (time.perf_counter() - t0) / reps
+    # the same oracle on one thread (BLAS and FFT pools limited to one)
+    dt1 = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t2 = time.perf_counter()
+            onfft.adjoint(x, c, M, SIGMA, MW)
+            dt1 = time.perf_counter() - t2
+    except Exception:
+        pass
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     K = ndft.index_set(M, D)
     rng = np.random.default_rng(17)
     sel = np.unique(np.concatenate([rng.choice(K.shape[0], 256, replace=False), [0, K.shape[0] - 1]]))
@@ -419,7 +435,9 @@ def cpu_baseline(x, w, f, gpu_out32, gpu_out64, budget_s=12.0):
         baseline=dict(value=x.shape[0] / dt, unit="points/s", cores=int(cores), kind="oracle",
                       sample=f"step-by-step FP64 NFFT oracle on the full polar 512x512 workload, "
                              f"{reps} run(s), {dt:.2f} s each; exact sums at {len(sel)} sampled "
-                             f"frequencies took {t_exact:.2f} s"),
+                             f"frequencies took {t_exact:.2f} s",
+                      cpu_model=model, nproc=os.cpu_count(),
+                      single_thread_points_per_s=(x.shape[0] / dt1) if dt1 else None),
         err32_vs_exact=metrics.rel_err(gpu_out32[sel], exact),
         err64_vs_exact=metrics.rel_err(gpu_out64[sel], exact),
         err32_vs_nfft_oracle=metrics.rel_err(gpu_out32, ref),
