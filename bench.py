@@ -566,6 +566,10 @@ def main():
                     hbm_view_gbs=round(alg / sp_avg_s / 1e9, 2),
                     hbm_view_frac=round(alg / sp_avg_s / 1e9 / HBM_PEAK_GBS, 5),
                     cell_updates_per_s=(2 * MW) ** D * N / sp_avg_s)
+    if roofline["traffic"]:
+        # the counters' HBM bytes per launch over the same launch time
+        roofline["traffic_gbs"] = round(roofline["traffic"] / sp_avg_s / 1e9, 1)
+        roofline["traffic_frac_of_hbm"] = round(roofline["traffic_gbs"] / HBM_PEAK_GBS, 4)
     stage_us = {k: round(v[0] / max(v[1], 1) * 1e3, 3) for k, v in r32["stages"].items() if v[1]}
     stage_us64 = {k: round(v[0] / max(v[1], 1) * 1e3, 3) for k, v in r64["stages"].items() if v[1]}
 
