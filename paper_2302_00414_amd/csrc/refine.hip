@@ -5,6 +5,8 @@
 // are the plan's forward (Algorithm 2.1) and weighted adjoint (Algorithm 2.4
 // with (3.7)). Norms are summed in float64 in a fixed order (block sums over a
 // fixed grid, then one block), so they do not depend on timing.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace nfft {
@@ -69,13 +71,13 @@ __global__ __launch_bounds__(kThreads) void sum_partials_kernel(const double* __
   if (threadIdx.x == 0) *out = sh[0];
 }
 
-// h += c
+// h += c (grid-stride)
 template <typename R>
 __global__ __launch_bounds__(kThreads) void update_kernel(cplx<R>* __restrict__ h,
                                                           const cplx<R>* __restrict__ c,
                                                           int64_t n) {
-  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  if (i < n) {
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
     const cplx<R> a = h[i], b = c[i];
     h[i] = mkc<R>(a.x + b.x, a.y + b.y);
   }
@@ -109,8 +111,8 @@ hipError_t launch_sumsq(const cplx<R>* a, int64_t n, double* partial, double* ou
 template <typename R>
 hipError_t launch_refine_update(cplx<R>* h, const cplx<R>* c, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(update_kernel<R>, dim3((unsigned)((n + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, s, h, c, n);
+  const int64_t nb = std::min<int64_t>((n + kThreads - 1) / kThreads, int64_t(1) << 20);
+  hipLaunchKernelGGL(update_kernel<R>, dim3((unsigned)nb), dim3(kThreads), 0, s, h, c, n);
   return hipGetLastError();
 }
 
