@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 # stage events are recorded on every PROFILE_EVERY-th step of a timed region
-PROFILE_EVERY = 8
+PROFILE_EVERY = 32
 R_POLAR = T_POLAR = 512
 M, SIGMA, MW, D = 256, 2.0, 6, 2
 
