@@ -825,11 +825,12 @@ template <typename R>
 int run_refine(nfft_plan_t p, const void* f, void* fhat, int nrhs, int iters, double* res,
                hipStream_t s) {
   const int64_t nf = (int64_t)nrhs * p->N, nh = (int64_t)nrhs * ipow(p->M, p->d);
-  if (!p->ref_r) {
-    TRY(dalloc(p, &p->ref_r, (size_t)p->max_rhs * p->N * sizeof(cplx<R>), false));
+  // each buffer on its first use (a failed allocation leaves the others)
+  if (!p->ref_r) TRY(dalloc(p, &p->ref_r, (size_t)p->max_rhs * p->N * sizeof(cplx<R>), false));
+  if (!p->ref_h)
     TRY(dalloc(p, &p->ref_h, (size_t)p->max_rhs * ipow(p->M, p->d) * sizeof(cplx<R>), false));
+  if (!p->ref_red)
     TRY(dalloc(p, &p->ref_red, (nfft::kRefineBlocks + kMaxRefine + 2) * sizeof(double), false));
-  }
   cplx<R>* r = (cplx<R>*)p->ref_r;
   cplx<R>* c = (cplx<R>*)p->ref_h;
   cplx<R>* h = (cplx<R>*)fhat;
