@@ -349,6 +349,65 @@ def run_jittered3d(steps, precs=("f32", "f64"), tuning="auto"):
     return dict(workload="jittered 128x64x64 (N=524288), d=3, M=64, sigma=2, m=4, w=1/N", **res)
 
 
+# Table 5.1 of the paper (linogram R = 2M, T = 2R, Shepp-Logan phantom,
+# hardware not stated): Alg. 3.7 precomputation [s], reconstruction [s], e_2
+PAPER_TABLE_5_1 = {64: (3.4324, 5.0420e-03, 2.5859e-14), 128: (9.4725, 2.9860e-02, 7.9006e-14),
+                   256: (38.365, 6.6443e-02, 2.6386e-13), 512: (140.20, 2.1674e-01, 1.0917e-12)}
+
+
+def run_table51(steps, Ms=(64, 128, 256, 512)):
+    """The setting of Table 5.1: linogram grids R = 2M, T = 2R (N = 8M^2),
+    weights of Algorithm 3.6 on the GPU (float64, NFFT window m = 8) timed
+    as the precomputation, the weighted adjoint of Algorithm 3.7 timed as the
+    reconstruction (float64 with m = 8, and float32 with m = 6), and e_2 of
+    (5.6) for random coefficients (the phantom is not available) whose
+    samples the float64 forward transform makes."""
+    import torch
+    from paper_2302_00414_amd import workloads as wl
+    from paper_2302_00414_amd.nfft import Plan, compute_weights
+
+    rows = {}
+    for Mt in Ms:
+        x = wl.linogram_nodes(2 * Mt, 4 * Mt)
+        N = x.shape[0]
+        fh = torch.from_numpy(wl.complex_normal(Mt * Mt, 160)).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        w, info = compute_weights(x, Mt, 2.0, 8)
+        torch.cuda.synchronize()
+        t_pre = time.perf_counter() - t0
+        row = dict(N=N, precompute_s=t_pre, cg_iterations=info["iterations"])
+        for prec, m in (("f64", 8), ("f32", 6)):
+            cdt = torch.complex64 if prec == "f32" else torch.complex128
+            p = Plan(x, Mt, 2.0, m, precision=prec)
+            p.set_weights(w)
+            if prec == "f64":
+                f = p.forward(fh)
+            fd = f.to(cdt)
+            out = torch.empty(Mt * Mt, dtype=cdt, device="cuda")
+            for _ in range(5):
+                p.adjoint(fd, out=out)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                p.adjoint(fd, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            e2 = float(torch.linalg.norm(out.to(torch.complex128) - fh) / torch.linalg.norm(fh))
+            row[prec] = dict(reconstruction_ms=ms, points_per_s=N / (ms / 1e3), e2=e2, m=m)
+            p.close()
+        if Mt in PAPER_TABLE_5_1:
+            pre, rec, e2p = PAPER_TABLE_5_1[Mt]
+            row["paper"] = dict(precompute_s=pre, reconstruction_s=rec, e2=e2p,
+                                note="Shepp-Logan phantom, hardware not stated")
+        rows[str(Mt)] = row
+    return dict(workload="linogram R=2M, T=2R (N=8M^2), d=2, sigma=2, Alg. 3.6 weights, "
+                         "random coefficients", **rows)
+
+
 def run_batched(steps, precs=("f32", "f64"), tuning="auto"):
     """Spiral trajectory, N = 131072, 32 right-hand sides, M = 256, m = 6: one
     fused float32 adjoint of all 32 against 32 float64 single calls."""
@@ -493,7 +552,8 @@ def main():
                     help='profiling runs: "auto" (autotuner) or a JSON object of tuning keys')
     ap.add_argument("--precision", choices=["both", "f32", "f64"], default="both",
                     help="profiling runs: time one path only (the JSON line needs both)")
-    ap.add_argument("--only", choices=["jittered3d", "batched", "forward", "refine"], default=None,
+    ap.add_argument("--only", choices=["jittered3d", "batched", "forward", "refine", "table51"],
+                    default=None,
                     help="profiling runs: run one secondary workload alone and print its JSON")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="profiling runs: also launch one device-to-device copy of this size, "
@@ -525,7 +585,8 @@ def main():
         sec = {"jittered3d": lambda: run_jittered3d(k, precs, tun),
                "batched": lambda: run_batched(k, precs, tun),
                "forward": lambda: {p: run_forward(p, x, k, tun) for p in precs},
-               "refine": lambda: run_refine(max(10, args.steps // 20))}[args.only]()
+               "refine": lambda: run_refine(max(10, args.steps // 20)),
+               "table51": lambda: run_table51(max(10, args.steps // 20))}[args.only]()
         print(json.dumps({args.only: sec}), flush=True)
         return
 
@@ -623,6 +684,7 @@ def main():
         line["weights_gpu"] = run_weights()
         line["bopt"] = run_bopt(max(10, args.steps // 5))
         line["jittered3d"] = run_jittered3d(max(10, args.steps // 10))
+        line["table51"] = run_table51(max(10, args.steps // 20))
         line["refine"] = run_refine(max(10, args.steps // 20))
         line["bandlimited"] = run_bandlimited()
     if not args.no_cpu_baseline:

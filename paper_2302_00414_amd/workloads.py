@@ -6,7 +6,7 @@ and the CPU oracle consume, so that the two sides see identical inputs.
 
 Node sets follow the grids of the paper's numerical section (Remark 5.1):
 uniform random points, the jittered Cartesian grid, the polar grid with signed
-radius (eq. (5.2)), plus an Archimedean spiral trajectory and plain
+radius (eq. (5.2)), the linogram grid (eq. (5.4)), plus an Archimedean spiral trajectory and plain
 equispaced grids, and the band-limited test function of Example 5.5. All nodes are returned as float64 arrays of shape (N, d),
 row-major, in the torus coordinates [-1/2, 1/2)^d.
 """
@@ -20,6 +20,7 @@ __all__ = [
     "jittered_nodes",
     "polar_nodes",
     "polar_area_weights",
+    "linogram_nodes",
     "spiral_nodes",
     "equispaced_nodes",
     "triangle_pulse_coefficients",
@@ -80,6 +81,20 @@ def polar_nodes(R: int, T: int) -> np.ndarray:
     x1 = np.outer(np.cos(th), r).reshape(-1)
     x2 = np.outer(np.sin(th), r).reshape(-1)
     return _wrap(np.stack([x1, x2], axis=1))
+
+
+def linogram_nodes(R: int, T: int) -> np.ndarray:
+    """Linogram (pseudo-polar) grid of eq. (5.4): points on concentric squares,
+    the set (j/R, (4t/T)(j/R)) and the set (-(4t/T)(j/R), j/R) for
+    j = -R/2 .. R/2-1 and t = -T/4 .. T/4-1; N = R*T nodes (the T/2 + T/2
+    points with j = 0 coincide at the origin). The Table 5.1 setting is
+    R = 2M, T = 2R."""
+    j = np.arange(-R // 2, R // 2, dtype=np.float64) / R
+    t = 4.0 * np.arange(-T // 4, T // 4, dtype=np.float64) / T
+    jj, tt = np.meshgrid(j, t, indexing="ij")
+    bh = np.stack([jj.reshape(-1), (tt * jj).reshape(-1)], axis=1)
+    bv = np.stack([-(tt * jj).reshape(-1), jj.reshape(-1)], axis=1)
+    return _wrap(np.concatenate([bh, bv]))
 
 
 def polar_area_weights(R: int, T: int) -> np.ndarray:

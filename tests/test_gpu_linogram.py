@@ -1,0 +1,35 @@
+"""Table 5.1's setting on the GPU: linogram grids R = 2M, T = 2R (eq. (5.4),
+N = 8M^2 > |I_2M|), weights of Algorithm 3.6 computed on the device, and the
+reconstruction of Algorithm 3.7 in float64. The table's e_2 column for
+Algorithm 3.7 (1.3e-15 at M = 8 to 7.9e-14 at M = 128, for the phantom's
+coefficients) fixes the order of magnitude; random coefficients stand in for
+the phantom, which is not available."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ndft, nfft as onfft, metrics
+from paper_2302_00414_amd import workloads as wl
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+@pytest.mark.parametrize("M", [8, 16, 32, 64, 128])
+def test_table_5_1_errors(M):
+    from paper_2302_00414_amd.nfft import Plan, compute_weights
+    x = wl.linogram_nodes(2 * M, 4 * M)
+    N = x.shape[0]
+    print(f"[case] linogram M={M} N={N}", flush=True)
+    fh = wl.complex_normal(M * M, 150 + M)
+    f = ndft.forward(x, fh, M) if M <= 32 else onfft.forward(x, fh, M, 2.0, 8)
+    w, info = compute_weights(x, M, 2.0, 8, 1e-13, 2000, device="cuda:0")
+    assert info["branch"] == "3.15"
+    # window m = 8 (its error is near rounding); at M = 8 that needs sigma = 4
+    p = Plan(x, M, 2.0 if M >= 16 else 4.0, 8, precision="f64", device="cuda:0")
+    p.set_weights(w)
+    h = p.adjoint(torch.from_numpy(f).to("cuda:0")).cpu().numpy()
+    p.close()
+    e2 = metrics.rel_err(h, fh)
+    print(f"[e2] M={M} {e2:.3e} iterations={info['iterations']} eps={info['epsilon']:.2e}", flush=True)
+    assert e2 <= 1e-11
