@@ -352,10 +352,11 @@ def run_jittered3d(steps, precs=("f32", "f64"), tuning="auto"):
 # Table 5.1 of the paper (linogram R = 2M, T = 2R, Shepp-Logan phantom,
 # hardware not stated): Alg. 3.7 precomputation [s], reconstruction [s], e_2
 PAPER_TABLE_5_1 = {64: (3.4324, 5.0420e-03, 2.5859e-14), 128: (9.4725, 2.9860e-02, 7.9006e-14),
-                   256: (38.365, 6.6443e-02, 2.6386e-13), 512: (140.20, 2.1674e-01, 1.0917e-12)}
+                   256: (38.365, 6.6443e-02, 2.6386e-13), 512: (140.20, 2.1674e-01, 1.0917e-12),
+                   1024: (721.53, 7.4896e-01, 4.2563e-12)}
 
 
-def run_table51(steps, Ms=(64, 128, 256, 512)):
+def run_table51(steps, Ms=(64, 128, 256, 512, 1024)):
     """The setting of Table 5.1: linogram grids R = 2M, T = 2R (N = 8M^2),
     weights of Algorithm 3.6 on the GPU (float64, NFFT window m = 8) timed
     as the precomputation, the weighted adjoint of Algorithm 3.7 timed as the
