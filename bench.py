@@ -405,8 +405,25 @@ def run_table51(steps, Ms=(64, 128, 256, 512, 1024)):
             row["paper"] = dict(precompute_s=pre, reconstruction_s=rec, e2=e2p,
                                 note="Shepp-Logan phantom, hardware not stated")
         rows[str(Mt)] = row
+    # Example 5.4's second setting, R = M, T = 2R (N = 2M^2 < |I_2M|): the
+    # weights are not exact there; Algorithm 4.4 and the refinement compared
+    Mr = 64
+    x = wl.linogram_nodes(Mr, 2 * Mr)
+    fh = torch.from_numpy(wl.complex_normal(Mr * Mr, 170)).cuda()
+    p = Plan(x, Mr, 2.0, 8, precision="f64")
+    f = p.forward(fh)
+    w, _ = compute_weights(x, Mr, 2.0, 8)
+    p.set_weights(w)
+    err = lambda h: float(torch.linalg.norm(h - fh) / torch.linalg.norm(fh))
+    r_m = dict(N=x.shape[0], alg3_7=err(p.adjoint(f)), alg3_7_refined_20=err(p.refine(f, 20)))
+    p.close()
+    q = Plan(x, Mr, 2.0, 4, precision="f64")
+    q.build_bopt(x)
+    r_m["alg4_4_sigma2_m4"] = err(q.bopt_adjoint(f))
+    q.close()
+    r_m["paper_M1024_phantom"] = dict(alg3_7=0.50585, alg4_4=2.2737e-3, voronoi=0.5304)
     return dict(workload="linogram R=2M, T=2R (N=8M^2), d=2, sigma=2, Alg. 3.6 weights, "
-                         "random coefficients", **rows)
+                         "random coefficients", **rows, R_equals_M_64=r_m)
 
 
 def run_batched(steps, precs=("f32", "f64"), tuning="auto"):
