@@ -441,6 +441,9 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--qps", type=float, nargs="+", default=[1000.0])
     ap.add_argument("--seconds", type=float, default=2.0)
+    ap.add_argument("--warmup-seconds", type=float, default=1.0,
+                    help="an untimed stream at the first rate first (first launches, "
+                         "workspaces)")
     ap.add_argument("--sets-per-M", type=int, default=2)
     ap.add_argument("--Ms", type=int, nargs="+", default=[64, 128, 256, 512])
     ap.add_argument("--slots", type=int, default=4)
@@ -469,9 +472,10 @@ def main():
              for s in sets}
     keys = [s["key"] for s in sets]
     out = []
-    for qps in args.qps:
+    for qps, seconds, timed in [(args.qps[0], args.warmup_seconds, False)] + \
+            [(q, args.seconds, True) for q in args.qps]:
         mark = len(srv.completed)
-        n = int(qps * args.seconds)
+        n = int(qps * seconds)
         gaps = rng.exponential(1.0 / qps, size=n)
         t0 = time.perf_counter()
         t_next = t0
@@ -489,6 +493,8 @@ def main():
             nrhs = int(rng.integers(1, 17))
             srv.submit(key, pools[key][:nrhs])
         srv.drain()
+        if not timed:
+            continue
         st = srv.stats(mark)
         st["qps"] = qps
         st["precision"] = args.precision
