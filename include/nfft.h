@@ -365,8 +365,9 @@ int nfft_destroy(nfft_plan_t plan);
  * nfft_footprint -- upper bound of the device bytes a plan with these
  * parameters and the default tile edge and work-item size allocates, the
  * window factor table of spread mode 3 included (the exact figure depends on
- * how the nodes fill the tiles; nfft_plan_info reports it). -1 on invalid
- * arguments.
+ * how the nodes fill the tiles; nfft_plan_info reports it). Not included:
+ * B_opt (nfft_bopt_build) and the workspace nfft_refine allocates on its
+ * first call. -1 on invalid arguments.
  */
 int64_t nfft_footprint(int d, int M, double sigma, int m, int64_t N, int precision, int max_rhs);
 
