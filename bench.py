@@ -234,9 +234,9 @@ def run_bopt(steps):
 def run_refine(steps, iters=4):
     """Weighted iterative refinement (nfft_refine) on the polar workload of
     the headline (512 x 512 nodes, M = 256, m = 6, area weights, float32):
-    milliseconds per call of `iters` steps (each one forward and one weighted
-    adjoint plus two vector passes) and the relative residuals per step, for
-    samples of a random trigonometric polynomial of degree M (made with the
+    milliseconds per call of `iters` steps (each one forward, which forms the
+    residual, and one weighted adjoint, which adds the correction; autotuned
+    plan) and the relative residuals per step, for samples of a random trigonometric polynomial of degree M (made with the
     plan's forward transform)."""
     import torch
     from paper_2302_00414_amd import workloads as wl
@@ -244,7 +244,7 @@ def run_refine(steps, iters=4):
 
     x = wl.polar_nodes(512, 512)
     N = x.shape[0]
-    plan = Plan(x, M, SIGMA, 6, precision="f32")
+    plan = Plan(x, M, SIGMA, 6, precision="f32", tuning="auto")
     plan.set_weights(wl.polar_area_weights(512, 512).astype(np.complex128))
     fh = torch.from_numpy(wl.complex_normal(M * M, 14)).to("cuda", torch.complex64)
     f = plan.forward(fh)

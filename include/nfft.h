@@ -257,9 +257,10 @@ int nfft_forward(nfft_plan_t plan, const void *fhat, void *f, int nrhs, void *st
  *          ||f - A fhat_k||_2 / ||f||_2, k = 0..iters, over all right-hand
  *          sides (float64 sums in a fixed order; one more forward transform,
  *          and the call waits for `stream`)
- * Each step costs one forward and one adjoint. The first call allocates
- * max_rhs * (N + M^d) complex values of workspace for the plan (NFFT_ENOMEM
- * if there is none). NFFT_ESTATE without weights; NFFT_EINVAL for a bad
+ * Each step costs one forward and one adjoint; the residual is formed where
+ * the forward writes its samples and the correction is added where the
+ * adjoint writes its coefficients. The first call allocates max_rhs * N
+ * complex values of workspace for the plan (NFFT_ENOMEM if there is none). NFFT_ESTATE without weights; NFFT_EINVAL for a bad
  * nrhs or iters, before anything is enqueued.
  */
 int nfft_refine(nfft_plan_t plan, const void *f, void *fhat, int nrhs, int iters, double *res,

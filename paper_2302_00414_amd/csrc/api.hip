@@ -116,7 +116,6 @@ struct nfft_plan_s {
   // weighted iterative refinement, allocated on first use: residuals
   // [max_rhs][N], corrections [max_rhs][M^d], norm partials and results
   void* ref_r = nullptr;
-  void* ref_h = nullptr;
   double* ref_red = nullptr;
   std::vector<void*> allocs;
   // profiling
@@ -630,8 +629,11 @@ void record(nfft_plan_t p, StageEvents& se, hipStream_t s) {
   se.ev[se.n++] = e;
 }
 
+// With accumulate, the last FFT pass adds its outputs to fhat instead of
+// writing them (fhat += A^* W f).
 template <typename R>
-int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t s) {
+int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t s,
+                bool accumulate = false) {
   const Geom& g = p->g;
   const int64_t Ms = p->Ms, M = p->M;
   StageEvents se{};
@@ -678,6 +680,7 @@ int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t 
   const auto fwd = nfft::kLoadMerge;
   if (p->d == 1) {
     auto a = fft_args<R>(p, 1, nullptr, 0, L, fhat, M);
+    a.accumulate = accumulate;
     HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, fwd, nfft::kStoreCropScaled, nrhs, s));
     record(p, se, s);
   } else if (p->d == 2) {
@@ -686,6 +689,7 @@ int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t 
     HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, fwd, nfft::kStoreCropScaled, nrhs, s));
     record(p, se, s);
     auto c = fft_args<R>(p, M, p->bufA, M * Ms, L, fhat, M * M);
+    c.accumulate = accumulate;
     HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, false, nfft::kLoadLine, nfft::kStoreCropScaled, nrhs, s));
   } else {
     // [s1][s2][s3] -> [k3][s1][s2] -> [k2][k3][s1] -> [k1][k2][k3]
@@ -695,6 +699,7 @@ int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t 
     auto c = fft_args<R>(p, M * Ms, p->bufA, M * Ms * Ms, L, p->bufB, M * M * Ms);
     HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, false, nfft::kLoadLine, nfft::kStoreCropScaled, nrhs, s));
     auto e = fft_args<R>(p, M * M, p->bufB, M * M * Ms, L, fhat, M * M * M);
+    e.accumulate = accumulate;
     HIP_TRY(p, nfft::launch_fft_pass<R>(e, L, false, nfft::kLoadLine, nfft::kStoreCropScaled, nrhs, s));
   }
   record(p, se, s);
@@ -780,8 +785,10 @@ int run_bopt_inverse_adjoint(nfft_plan_t p, const void* h, void* f, int nrhs, hi
   return NFFT_OK;
 }
 
+// With sub, the samples written are sub - A fhat (sub in the layout of f).
 template <typename R>
-int run_forward(nfft_plan_t p, const void* fhat, void* f, int nrhs, hipStream_t s) {
+int run_forward(nfft_plan_t p, const void* fhat, void* f, int nrhs, hipStream_t s,
+                const void* sub = nullptr) {
   const Geom& g = p->g;
   const int64_t Ms = p->Ms;
   StageEvents se{};
@@ -795,6 +802,7 @@ int run_forward(nfft_plan_t p, const void* fhat, void* f, int nrhs, hipStream_t 
   ia.perm = p->perm;
   ia.grid = (const cplx<R>*)p->grid;
   ia.f = (cplx<R>*)f;
+  ia.sub = (const cplx<R>*)sub;
   ia.item_start = p->item_start;
   ia.item_count = p->item_count;
   ia.item_bin = p->item_bin;
@@ -824,28 +832,24 @@ constexpr int kMaxRefine = 1000;
 template <typename R>
 int run_refine(nfft_plan_t p, const void* f, void* fhat, int nrhs, int iters, double* res,
                hipStream_t s) {
-  const int64_t nf = (int64_t)nrhs * p->N, nh = (int64_t)nrhs * ipow(p->M, p->d);
-  // each buffer on its first use (a failed allocation leaves the others)
+  const int64_t nf = (int64_t)nrhs * p->N;
+  // each buffer on its first use (a failed allocation leaves the other)
   if (!p->ref_r) TRY(dalloc(p, &p->ref_r, (size_t)p->max_rhs * p->N * sizeof(cplx<R>), false));
-  if (!p->ref_h)
-    TRY(dalloc(p, &p->ref_h, (size_t)p->max_rhs * ipow(p->M, p->d) * sizeof(cplx<R>), false));
   if (!p->ref_red)
     TRY(dalloc(p, &p->ref_red, (nfft::kRefineBlocks + kMaxRefine + 2) * sizeof(double), false));
   cplx<R>* r = (cplx<R>*)p->ref_r;
-  cplx<R>* c = (cplx<R>*)p->ref_h;
-  cplx<R>* h = (cplx<R>*)fhat;
-  const cplx<R>* fv = (const cplx<R>*)f;
   double* part = p->ref_red;
   double* norms = part + nfft::kRefineBlocks;  // ||f||^2, then ||r_k||^2
   TRY(run_adjoint<R>(p, f, fhat, nrhs, s));    // fhat_0
-  if (res) HIP_TRY(p, nfft::launch_sumsq<R>(fv, nf, part, norms, s));
+  if (res) HIP_TRY(p, nfft::launch_sumsq<R>((const cplx<R>*)f, nf, part, norms, s));
   for (int k = 0; k <= iters; ++k) {
     if (k == iters && !res) break;  // the last residual is only reported
-    TRY(run_forward<R>(p, fhat, r, nrhs, s));
-    HIP_TRY(p, nfft::launch_refine_residual<R>(fv, r, nf, part, res ? norms + 1 + k : nullptr, s));
+    // r_k = f - A fhat_k, formed where the window sums are written
+    TRY(run_forward<R>(p, fhat, r, nrhs, s, f));
+    if (res) HIP_TRY(p, nfft::launch_sumsq<R>(r, nf, part, norms + 1 + k, s));
     if (k == iters) break;
-    TRY(run_adjoint<R>(p, r, c, nrhs, s));  // A^* W r_k
-    HIP_TRY(p, nfft::launch_refine_update<R>(h, c, nh, s));
+    // fhat_{k+1} = fhat_k + A^* W r_k, added where the last FFT pass stores
+    TRY(run_adjoint<R>(p, r, fhat, nrhs, s, true));
   }
   if (res) {
     std::vector<double> nv(iters + 2);
@@ -1013,7 +1017,7 @@ int nfft_plan_clone(nfft_plan_t src, int max_rhs, nfft_plan_t* out, void* stream
   p->last_error.clear();
   p->max_rhs = max_rhs;
   p->tilep = p->itemp = p->bufA = p->bufB = p->grid = nullptr;
-  p->ref_r = p->ref_h = nullptr;
+  p->ref_r = nullptr;
   p->ref_red = nullptr;
   hipStream_t s = (hipStream_t)stream;
   int st = (hipSetDevice(p->device) == hipSuccess) ? NFFT_OK : NFFT_EDEVICE;

@@ -348,7 +348,12 @@ __device__ __forceinline__ void store_elem(const FftArgs<R>& a, int b, int64_t q
       kidx = e - L + M / 2;
     else
       return;
-    a.out[b * a.out_bs + (int64_t)kidx * a.nlines + q] = cscale<R>(v, a.fac[kidx]);
+    cplx<R>* o = a.out + b * a.out_bs + (int64_t)kidx * a.nlines + q;
+    const cplx<R> u = cscale<R>(v, a.fac[kidx]);
+    if (a.accumulate)
+      *o = mkc<R>(o->x + u.x, o->y + u.y);
+    else
+      *o = u;
   }
 }
 

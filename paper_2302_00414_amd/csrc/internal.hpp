@@ -110,6 +110,7 @@ struct InterpArgs {
   const int32_t* perm;
   const cplx<R>* grid;       // full oversampled grid, C order, rhs stride grid_rs
   cplx<R>* f;                // output samples, caller order, rhs stride f_rs
+  const cplx<R>* sub;        // if set: f = sub - (window sums), sub in caller order, stride f_rs
   const int32_t* item_start;
   const int32_t* item_count;
   const int32_t* item_bin;
@@ -144,6 +145,7 @@ struct FftArgs {
   int64_t tile_bs;
   const cplx<R>* tw;   // twiddles e^{-2 pi i q / L}, q < L
   const R* fac;        // deconvolution factors over I_M (compressed index)
+  int accumulate;      // kStoreCropScaled: add to the output instead of writing it
   int lpw;             // lines per work-group
   Geom g;
 };
@@ -197,15 +199,8 @@ hipError_t launch_cg_direction(cplx<double>* p, const cplx<double>* r, int64_t n
 // ------------------------------------------------ weighted iterative refinement
 // partial sums of the norm reductions: at most kRefineBlocks doubles
 constexpr int kRefineBlocks = 512;
-// r = f - r over n values; with out, *out = ||r||_2^2 (float64, fixed order)
-template <typename R>
-hipError_t launch_refine_residual(const cplx<R>* f, cplx<R>* r, int64_t n, double* partial,
-                                  double* out, hipStream_t s);
 // *out = ||a||_2^2
 template <typename R>
 hipError_t launch_sumsq(const cplx<R>* a, int64_t n, double* partial, double* out, hipStream_t s);
-// h += c
-template <typename R>
-hipError_t launch_refine_update(cplx<R>* h, const cplx<R>* c, int64_t n, hipStream_t s);
 
 }  // namespace nfft

@@ -1,12 +1,12 @@
-// Vector kernels of the weighted iterative refinement: the residual
-// r = f - A fhat with its squared 2-norm, and the update fhat += A^* W r.
-// The iterates are the partial sums of the Neumann series of (A^* W A)^{-1}
-// in the proof of Theorem 3.15 applied to A^* W f; the transforms themselves
-// are the plan's forward (Algorithm 2.1) and weighted adjoint (Algorithm 2.4
-// with (3.7)). Norms are summed in float64 in a fixed order (block sums over a
-// fixed grid, then one block), so they do not depend on timing.
-#include <algorithm>
-
+// Norm reductions of the weighted iterative refinement: the squared 2-norms
+// of f and of the residuals r = f - A fhat. The residual itself is formed
+// where the forward transform writes its window sums, and the update
+// fhat += A^* W r where the adjoint's last FFT pass stores. The iterates are
+// the partial sums of the Neumann series of (A^* W A)^{-1} in the proof of
+// Theorem 3.15 applied to A^* W f; the transforms themselves are the plan's
+// forward (Algorithm 2.1) and weighted adjoint (Algorithm 2.4 with (3.7)).
+// Norms are summed in float64 in a fixed order (block sums over a fixed
+// grid, then one block), so they do not depend on timing.
 #include "internal.hpp"
 
 namespace nfft {
@@ -22,26 +22,6 @@ __device__ __forceinline__ void block_sum(double* sh) {
     if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
-}
-
-// r = f - r; with partial, block sums of |r_i|^2 (grid-stride, fixed grid)
-template <typename R>
-__global__ __launch_bounds__(kThreads) void residual_kernel(const cplx<R>* __restrict__ f,
-                                                            cplx<R>* __restrict__ r, int64_t n,
-                                                            double* __restrict__ partial) {
-  __shared__ double sh[kThreads];
-  double acc = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kThreads) {
-    const cplx<R> a = f[i], b = r[i];
-    const cplx<R> d = mkc<R>(a.x - b.x, a.y - b.y);
-    r[i] = d;
-    acc += (double)d.x * (double)d.x + (double)d.y * (double)d.y;
-  }
-  if (!partial) return;
-  sh[threadIdx.x] = acc;
-  block_sum(sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
 // block sums of |a_i|^2
@@ -71,34 +51,12 @@ __global__ __launch_bounds__(kThreads) void sum_partials_kernel(const double* __
   if (threadIdx.x == 0) *out = sh[0];
 }
 
-// h += c (grid-stride)
-template <typename R>
-__global__ __launch_bounds__(kThreads) void update_kernel(cplx<R>* __restrict__ h,
-                                                          const cplx<R>* __restrict__ c,
-                                                          int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kThreads) {
-    const cplx<R> a = h[i], b = c[i];
-    h[i] = mkc<R>(a.x + b.x, a.y + b.y);
-  }
-}
-
 unsigned blocks_for(int64_t n) {
   const int64_t b = (n + kThreads - 1) / kThreads;
   return (unsigned)(b < kRefineBlocks ? (b > 0 ? b : 1) : kRefineBlocks);
 }
 
 }  // namespace
-
-template <typename R>
-hipError_t launch_refine_residual(const cplx<R>* f, cplx<R>* r, int64_t n, double* partial,
-                                  double* out, hipStream_t s) {
-  const unsigned nb = blocks_for(n);
-  hipLaunchKernelGGL(residual_kernel<R>, dim3(nb), dim3(kThreads), 0, s, f, r, n,
-                     out ? partial : nullptr);
-  if (out) hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kThreads), 0, s, partial, (int)nb, out);
-  return hipGetLastError();
-}
 
 template <typename R>
 hipError_t launch_sumsq(const cplx<R>* a, int64_t n, double* partial, double* out, hipStream_t s) {
@@ -108,22 +66,7 @@ hipError_t launch_sumsq(const cplx<R>* a, int64_t n, double* partial, double* ou
   return hipGetLastError();
 }
 
-template <typename R>
-hipError_t launch_refine_update(cplx<R>* h, const cplx<R>* c, int64_t n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const int64_t nb = std::min<int64_t>((n + kThreads - 1) / kThreads, int64_t(1) << 20);
-  hipLaunchKernelGGL(update_kernel<R>, dim3((unsigned)nb), dim3(kThreads), 0, s, h, c, n);
-  return hipGetLastError();
-}
-
-template hipError_t launch_refine_residual<float>(const cplx<float>*, cplx<float>*, int64_t, double*,
-                                                  double*, hipStream_t);
-template hipError_t launch_refine_residual<double>(const cplx<double>*, cplx<double>*, int64_t,
-                                                   double*, double*, hipStream_t);
 template hipError_t launch_sumsq<float>(const cplx<float>*, int64_t, double*, double*, hipStream_t);
 template hipError_t launch_sumsq<double>(const cplx<double>*, int64_t, double*, double*, hipStream_t);
-template hipError_t launch_refine_update<float>(cplx<float>*, const cplx<float>*, int64_t, hipStream_t);
-template hipError_t launch_refine_update<double>(cplx<double>*, const cplx<double>*, int64_t,
-                                                 hipStream_t);
 
 }  // namespace nfft

@@ -414,7 +414,12 @@ __global__ __launch_bounds__(256) void interp_kernel(InterpArgs<R> a) {
       v = sum_node<R, D, MW, true>(tile, P, l, psi);
     else
       v = sum_node<R, D, MW, false>(tile, P, l, psi);
-    f[a.perm[i]] = v;
+    const int j = a.perm[i];
+    if (a.sub) {
+      const cplx<R> u = a.sub[rhs * a.f_rs + j];
+      v = mkc<R>(u.x - v.x, u.y - v.y);
+    }
+    f[j] = v;
   }
 }
 
