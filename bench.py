@@ -231,12 +231,12 @@ def run_bopt(steps):
                 build_s=t_build, ms_per_reconstruction=ms, points_per_s=N / (ms / 1e3), **info)
 
 
-def run_refine(steps, iters=4):
+def run_refine(steps, iters=4, tuning="auto"):
     """Weighted iterative refinement (nfft_refine) on the polar workload of
     the headline (512 x 512 nodes, M = 256, m = 6, area weights, float32):
     milliseconds per call of `iters` steps (each one forward, which forms the
     residual, and one weighted adjoint, which adds the correction; autotuned
-    plan) and the relative residuals per step, for samples of a random trigonometric polynomial of degree M (made with the
+    plan unless a tuning is given) and the relative residuals per step, for samples of a random trigonometric polynomial of degree M (made with the
     plan's forward transform)."""
     import torch
     from paper_2302_00414_amd import workloads as wl
@@ -244,7 +244,7 @@ def run_refine(steps, iters=4):
 
     x = wl.polar_nodes(512, 512)
     N = x.shape[0]
-    plan = Plan(x, M, SIGMA, 6, precision="f32", tuning="auto")
+    plan = Plan(x, M, SIGMA, 6, precision="f32", tuning=tuning)
     plan.set_weights(wl.polar_area_weights(512, 512).astype(np.complex128))
     fh = torch.from_numpy(wl.complex_normal(M * M, 14)).to("cuda", torch.complex64)
     f = plan.forward(fh)
@@ -603,7 +603,7 @@ def main():
         sec = {"jittered3d": lambda: run_jittered3d(k, precs, tun),
                "batched": lambda: run_batched(k, precs, tun),
                "forward": lambda: {p: run_forward(p, x, k, tun) for p in precs},
-               "refine": lambda: run_refine(max(10, args.steps // 20)),
+               "refine": lambda: run_refine(max(10, args.steps // 20), tuning=tun),
                "table51": lambda: run_table51(max(10, args.steps // 20))}[args.only]()
         print(json.dumps({args.only: sec}), flush=True)
         return
