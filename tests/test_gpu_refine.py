@@ -3,7 +3,9 @@ O5 with the reference NFFT (O2) as A and A^*, and its convergence.
 
 * Parity: fhat_k and the relative residuals ||f - A fhat_k|| / ||f|| for
   k = 0..iters, d = 1, 2, 3, float64 and float32, one and three right-hand
-  sides, on jittered grids with weights 1/N, at sizes spanning several tiles.
+  sides, on jittered grids with weights 1/N, at sizes spanning several tiles;
+  and at the full polar 512 x 512, M = 256 size in the benchmark's
+  configuration (float32, autotuned, 4 steps).
 * iters = 0 is the plain weighted adjoint.
 * Convergence with the weights of Algorithm 3.6 where the direct method is
   not exact: for samples of a trigonometric polynomial the error falls with
@@ -100,3 +102,25 @@ def test_refine_argument_checks():
     out = p.refine(f, 2)
     assert out.shape == (2, 256) and float(out.abs().max()) == 0.0
     p.close()
+
+
+def test_refine_polar_512x512_M256_in_the_benchmark_configuration():
+    """The refinement as the benchmark times it: polar grid R = T = 512
+    (N = 262144, eq. (5.2)), M = 256, m = 6, area weights, float32, autotuned
+    launch configuration, 4 steps, against O5 on the reference NFFT (whole
+    iterate and every residual)."""
+    from paper_2302_00414_amd.nfft import Plan
+    x = wl.polar_nodes(512, 512)
+    N = x.shape[0]
+    w = wl.polar_area_weights(512, 512).astype(np.complex128)
+    f = wl.complex_normal(N, 31)
+    print(f"[case] refine polar 512x512 N={N} M=256 m=6 f32 tuning=auto iters=4", flush=True)
+    p = Plan(x, 256, 2.0, 6, precision="f32", device="cuda:0", tuning="auto")
+    p.set_weights(w)
+    got, res = p.refine(torch.from_numpy(f), 4, residuals=True)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    p.close()
+    want, wres = orf.refine(x, f, w, 256, 4, op="nfft", sigma=2.0, m=6)
+    assert metrics.rel_err(got, want) <= TOL["f32"]
+    assert np.allclose(res, wres, rtol=RES_TOL["f32"], atol=0)
