@@ -364,17 +364,24 @@ __global__ __launch_bounds__(256) void interp_kernel(InterpArgs<R> a) {
     }
   }
   const cplx<R>* grid = a.grid + rhs * a.grid_rs;
+  // rem / P as floor((rem + 1/2) / P) in float: for rem < 2^22 the rounding
+  // error (about rem / P * 2^-23) stays below the distance 1/(2P) of the
+  // exact quotient to an integer, and a tile in LDS has far fewer cells;
+  // the tile edge divides M_sigma, so tile cells lie in [-m, M_sigma + m)
+  // with m <= M_sigma and one wrap each way suffices
+  const float invP = 1.0f / (float)P;
   for (int i = threadIdx.x; i < Ptot; i += blockDim.x) {
     int rem = i;
     int64_t lin = 0;
     int p[3] = {0, 0, 0};
     for (int t = D - 1; t >= 0; --t) {
-      p[t] = rem % P;
-      rem /= P;
+      const int q = (int)(((float)rem + 0.5f) * invP);
+      p[t] = rem - q * P;
+      rem = q;
     }
     for (int t = 0; t < D; ++t) {
       int c = org[t] + p[t];
-      c = (c % Ms + Ms) % Ms;
+      c = c < 0 ? c + Ms : (c >= Ms ? c - Ms : c);
       lin = lin * Ms + c;
     }
     tile[i] = grid[lin];
