@@ -53,14 +53,21 @@ def spread(x, f, Ms, m, sigma):
     ell, val = _footprint(x, Ms, m, sigma)
     size = Ms ** d
     g = np.zeros((F.shape[0], size), dtype=np.complex128)
-    for off in itertools.product(range(2 * m + 1), repeat=d):
-        flat = np.zeros(N, dtype=np.int64)
-        wgt = np.ones(N)
-        for t in range(d):
-            flat = flat * Ms + np.mod(ell[:, t, off[t]], Ms)
-            wgt = wgt * val[:, t, off[t]]
+    offsets = list(itertools.product(range(2 * m + 1), repeat=d))
+    # the (2m+1)^d footprint offsets go to one bincount in blocks (one call
+    # per block and right-hand side instead of one per offset)
+    nblk = max(1, min(len(offsets), (1 << 24) // max(N, 1)))
+    for b0 in range(0, len(offsets), nblk):
+        blk = offsets[b0:b0 + nblk]
+        flat = np.zeros((len(blk), N), dtype=np.int64)
+        wgt = np.ones((len(blk), N))
+        for i, off in enumerate(blk):
+            for t in range(d):
+                flat[i] = flat[i] * Ms + np.mod(ell[:, t, off[t]], Ms)
+                wgt[i] = wgt[i] * val[:, t, off[t]]
+        flat = flat.reshape(-1)
         for r in range(F.shape[0]):
-            c = F[r] * wgt
+            c = (F[r][None, :] * wgt).reshape(-1)
             g[r] += np.bincount(flat, weights=c.real, minlength=size)
             g[r] += 1j * np.bincount(flat, weights=c.imag, minlength=size)
     return g.reshape((F.shape[0],) + (Ms,) * d)
