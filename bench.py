@@ -12,9 +12,12 @@ region). Prints one JSON line: points/s of the float32 path (value), per-step
 latency percentiles, the float64 path's figures, per-stage times with their
 HBM rates from algorithmic bytes, the roofline position of the spreading
 kernel (timed with HIP events on the library's stream inside the timed
-region, on every PROFILE_EVERY-th step), the batched form (spiral, 131072 nodes, 32 right-hand sides, one
-fused float32 call against 32 float64 calls) and the FP64 CPU oracle timed
-on a bounded sample.
+region, on every PROFILE_EVERY-th step), the accuracy condition of the
+metric (float32 against float64), and secondary workloads: the M = 32 float64
+request (latency), the batched form (spiral, 131072 nodes, 32 right-hand
+sides, one fused float32 call against 32 float64 calls), the forward
+transform, the served request stream (p50 / p99 latency and points/s at
+fractions of saturation), and the FP64 CPU oracle timed on bounded samples.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
 """
@@ -349,81 +352,94 @@ def run_jittered3d(steps, precs=("f32", "f64"), tuning="auto"):
     return dict(workload="jittered 128x64x64 (N=524288), d=3, M=64, sigma=2, m=4, w=1/N", **res)
 
 
-# Table 5.1 of the paper (linogram R = 2M, T = 2R, Shepp-Logan phantom,
-# hardware not stated): Alg. 3.7 precomputation [s], reconstruction [s], e_2
-PAPER_TABLE_5_1 = {64: (3.4324, 5.0420e-03, 2.5859e-14), 128: (9.4725, 2.9860e-02, 7.9006e-14),
-                   256: (38.365, 6.6443e-02, 2.6386e-13), 512: (140.20, 2.1674e-01, 1.0917e-12),
-                   1024: (721.53, 7.4896e-01, 4.2563e-12)}
+C1_M, C1_M_WIN, C1_N = 32, 4, 4096
 
 
-def run_table51(steps, Ms=(64, 128, 256, 512, 1024)):
-    """The setting of Table 5.1: linogram grids R = 2M, T = 2R (N = 8M^2),
-    weights of Algorithm 3.6 on the GPU (float64, NFFT window m = 8) timed
-    as the precomputation, the weighted adjoint of Algorithm 3.7 timed as the
-    reconstruction (float64 with m = 8, and float32 with m = 6), and e_2 of
-    (5.6) for random coefficients (the phantom is not available) whose
-    samples the float64 forward transform makes."""
-    import torch
+def c1_inputs():
+    """The M = 32 correctness workload: N = 4096 uniform nodes (seed 1),
+    random complex samples, and the Algorithm 3.6 weights of this node set
+    that the CPU oracle wrote to tests/golden/c1_weights.npz (|I_2M| = N,
+    minimum-norm solution of (3.15))."""
     from paper_2302_00414_amd import workloads as wl
-    from paper_2302_00414_amd.nfft import Plan, compute_weights
+    x = wl.uniform_nodes(C1_N, 2, 1)
+    w = np.load(os.path.join(ROOT, "tests", "golden", "c1_weights.npz"))["w_c1"]
+    f = wl.complex_normal(C1_N, 21)
+    return x, w, f
 
-    rows = {}
-    for Mt in Ms:
-        x = wl.linogram_nodes(2 * Mt, 4 * Mt)
-        N = x.shape[0]
-        fh = torch.from_numpy(wl.complex_normal(Mt * Mt, 160)).cuda()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        w, info = compute_weights(x, Mt, 2.0, 8)
-        torch.cuda.synchronize()
-        t_pre = time.perf_counter() - t0
-        row = dict(N=N, precompute_s=t_pre, cg_iterations=info["iterations"])
-        for prec, m in (("f64", 8), ("f32", 6)):
-            cdt = torch.complex64 if prec == "f32" else torch.complex128
-            p = Plan(x, Mt, 2.0, m, precision=prec)
-            p.set_weights(w)
-            if prec == "f64":
-                f = p.forward(fh)
-            fd = f.to(cdt)
-            out = torch.empty(Mt * Mt, dtype=cdt, device="cuda")
-            for _ in range(5):
-                p.adjoint(fd, out=out)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(steps):
-                p.adjoint(fd, out=out)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / steps
-            e2 = float(torch.linalg.norm(out.to(torch.complex128) - fh) / torch.linalg.norm(fh))
-            row[prec] = dict(reconstruction_ms=ms, points_per_s=N / (ms / 1e3), e2=e2, m=m)
-            p.close()
-        if Mt in PAPER_TABLE_5_1:
-            pre, rec, e2p = PAPER_TABLE_5_1[Mt]
-            row["paper"] = dict(precompute_s=pre, reconstruction_s=rec, e2=e2p,
-                                note="Shepp-Logan phantom, hardware not stated")
-        rows[str(Mt)] = row
-    # Example 5.4's second setting, R = M, T = 2R (N = 2M^2 < |I_2M|): the
-    # weights are not exact there; Algorithm 4.4 and the refinement compared
-    Mr = 64
-    x = wl.linogram_nodes(Mr, 2 * Mr)
-    fh = torch.from_numpy(wl.complex_normal(Mr * Mr, 170)).cuda()
-    p = Plan(x, Mr, 2.0, 8, precision="f64")
-    f = p.forward(fh)
-    w, _ = compute_weights(x, Mr, 2.0, 8)
-    p.set_weights(w)
-    err = lambda h: float(torch.linalg.norm(h - fh) / torch.linalg.norm(fh))
-    r_m = dict(N=x.shape[0], alg3_7=err(p.adjoint(f)), alg3_7_refined_20=err(p.refine(f, 20)))
-    p.close()
-    q = Plan(x, Mr, 2.0, 4, precision="f64")
-    q.build_bopt(x)
-    r_m["alg4_4_sigma2_m4"] = err(q.bopt_adjoint(f))
-    q.close()
-    r_m["paper_M1024_phantom"] = dict(alg3_7=0.50585, alg4_4=2.2737e-3, voronoi=0.5304)
-    return dict(workload="linogram R=2M, T=2R (N=8M^2), d=2, sigma=2, Alg. 3.6 weights, "
-                         "random coefficients", **rows, R_equals_M_64=r_m)
+
+def run_c1(steps):
+    """Latency of one float64 request on the M = 32 workload (d = 2, N = 4096,
+    sigma = 2, m = 4, default tuning): per-call p50 / p99 (synchronised,
+    HIP events around the call) and back-to-back throughput."""
+    import torch
+    from paper_2302_00414_amd.nfft import Plan
+
+    x, w, f = c1_inputs()
+    plan = Plan(x, C1_M, SIGMA, C1_M_WIN, precision="f64")
+    plan.set_weights(w)
+    fd = torch.from_numpy(f).to("cuda")
+    out = torch.empty(C1_M * C1_M, dtype=torch.complex128, device="cuda")
+    for _ in range(10):
+        plan.adjoint(fd, out=out)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(steps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        plan.adjoint(fd, out=out)
+        b.record()
+        b.synchronize()
+        lat.append(a.elapsed_time(b))
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.adjoint(fd, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    res = out.cpu().numpy()
+    plan.close()
+    lat = np.array(lat)
+    return dict(workload="d=2, M=32, N=4096 uniform (seed 1), sigma=2, m=4, float64, "
+                         "Algorithm 3.6 weights of the CPU oracle",
+                latency_ms=dict(p50=float(np.percentile(lat, 50)),
+                                p99=float(np.percentile(lat, 99))),
+                ms_per_call_back_to_back=ms, points_per_s=C1_N / (ms / 1e3)), res
+
+
+def run_served(seconds=2.0, fracs=(0.25, 0.5, 0.75, 0.9)):
+    """The served stream: d = 2 requests, M from {64, 128, 256, 512}, N = M^2
+    U(1, 4) uniform or polar nodes (8 resident node sets), 1-16 right-hand
+    sides of complex64 samples, Poisson arrivals; continuous batching over 4
+    streams, admission by device-memory footprint. Saturation throughput is
+    measured with a burst of requests first; the stream then runs at the
+    given fractions of it (as queries per second), and each rate reports
+    p50 / p99 latency and points/s."""
+    from paper_2302_00414_amd import serve
+
+    rng = np.random.default_rng(31)
+    srv, keys, pools, sets = serve.served_setup(precision="f32")
+    try:
+        serve.run_stream(srv, keys, pools, 1000.0, 1.0, rng)   # first launches, workspaces
+        sat = serve.saturation_points_per_s(srv, keys, pools, 400, rng)
+        mean_pts = float(np.mean([s["nodes"].shape[0] for s in sets])) * 8.5  # E[nrhs] = 8.5
+        rates = []
+        for fr in fracs:
+            qps = fr * sat / mean_pts
+            mark = serve.run_stream(srv, keys, pools, qps, seconds, rng)
+            st = srv.stats(mark)
+            rates.append(dict(fraction_of_saturation=fr, qps=round(qps, 1),
+                              p50_ms=st["p50_ms"], p99_ms=st["p99_ms"],
+                              points_per_s=st["points_per_s"], requests=st["requests"],
+                              batches=st["batches"], rejected=st["rejected"]))
+    finally:
+        srv.close()
+    return dict(workload="served stream: d=2, M in {64,128,256,512}, N=M^2*U(1,4) uniform or "
+                         "polar, 1-16 rhs complex64, Poisson arrivals, 4 slots, batches of up "
+                         "to 16 rhs, 8 resident node sets, m=6, float32",
+                saturation_points_per_s=sat, seconds_per_rate=seconds, rates=rates)
 
 
 def run_batched(steps, precs=("f32", "f64"), tuning="auto"):
@@ -468,16 +484,26 @@ def run_batched(steps, precs=("f32", "f64"), tuning="auto"):
                 speedup=res["f64"]["ms_per_32_rhs"] / res["f32"]["ms_per_32_rhs"])
 
 
-def cpu_baseline(x, w, f, gpu_out32, gpu_out64, budget_s=12.0):
-    """The FP64 oracle on the host: the step-by-step NFFT (O2) on the whole
-    workload, repeated up to the time budget; the exact sums (O1) at sampled
-    frequencies for the accuracy of the GPU results."""
+def cpu_baseline(x, w, f, gpu_out32, gpu_out64, c1=None, budget_s=10.0):
+    """The FP64 oracle on the host (its code as it stands), on bounded samples
+    of the benchmark workloads:
+      O2 -- the step-by-step NFFT (Algorithm 2.4) on the whole polar 512x512
+            workload, repeated up to the time budget; its steps (numpy
+            elementwise work, bincount, pocketfft) run on one thread, which a
+            second timing with every BLAS / OpenMP pool limited to one thread
+            confirms;
+      O1 -- the exact sums (2.6) at all M^2 outputs, once: phase tables on
+            one thread, contraction by BLAS matrix products on the BLAS pool.
+    Also the accuracy of the GPU results against both, and on the M = 32
+    workload (c1 = (x, w, f, gpu_out)) against O2 and O1."""
     from oracle import ndft, nfft as onfft, metrics
+    blas_threads = 1
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        from threadpoolctl import threadpool_info, threadpool_limits
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()
+                            if i.get("user_api") == "blas"] + [1])
     except Exception:
-        cores = os.cpu_count() or 1
+        threadpool_limits = None
     c = w * f
     reps, t0 = 0, time.perf_counter()
     while True:
@@ -486,40 +512,47 @@ def cpu_baseline(x, w, f, gpu_out32, gpu_out64, budget_s=12.0):
         if time.perf_counter() - t0 > budget_s or reps >= 20:
             break
     dt = (time.perf_counter() - t0) / reps
-    # the same oracle on one thread (BLAS and FFT pools limited to one)
     dt1 = None
-    try:
-        from threadpoolctl import threadpool_limits
+    if threadpool_limits is not None:
         with threadpool_limits(limits=1):
             t2 = time.perf_counter()
             onfft.adjoint(x, c, M, SIGMA, MW)
             dt1 = time.perf_counter() - t2
-    except Exception:
-        pass
+    t3 = time.perf_counter()
+    exact = ndft.adjoint(x, c, M)
+    t_o1 = time.perf_counter() - t3
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
             model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
     except OSError:
         pass
-    K = ndft.index_set(M, D)
-    rng = np.random.default_rng(17)
-    sel = np.unique(np.concatenate([rng.choice(K.shape[0], 256, replace=False), [0, K.shape[0] - 1]]))
-    t1 = time.perf_counter()
-    exact = ndft.adjoint_at(x, c, K[sel])
-    t_exact = time.perf_counter() - t1
-    return dict(
-        baseline=dict(value=x.shape[0] / dt, unit="points/s", cores=int(cores), kind="oracle",
-                      sample=f"step-by-step FP64 NFFT oracle on the full polar 512x512 workload, "
-                             f"{reps} run(s), {dt:.2f} s each; exact sums at {len(sel)} sampled "
-                             f"frequencies took {t_exact:.2f} s",
+    N = x.shape[0]
+    out = dict(
+        baseline=dict(value=N / dt, unit="points/s", cores=1, kind="oracle",
+                      sample=f"step-by-step FP64 NFFT oracle (O2) on the full polar 512x512 "
+                             f"workload, {reps} run(s) of {dt:.2f} s; one thread (with every "
+                             f"BLAS/OpenMP pool limited to one thread a run takes "
+                             f"{dt1 if dt1 is not None else float('nan'):.2f} s)",
                       cpu_model=model, nproc=os.cpu_count(),
-                      single_thread_points_per_s=(x.shape[0] / dt1) if dt1 else None),
-        err32_vs_exact=metrics.rel_err(gpu_out32[sel], exact),
-        err64_vs_exact=metrics.rel_err(gpu_out64[sel], exact),
+                      single_thread_points_per_s=(N / dt1) if dt1 else None,
+                      o1_all_outputs=dict(points_per_s=N / t_o1, seconds=t_o1,
+                                          outputs=M ** D, blas_threads=blas_threads,
+                                          note="exact sums (2.6) at every k in I_M: phase "
+                                               "tables on one thread, BLAS matrix products "
+                                               f"on {blas_threads} threads")),
+        err32_vs_exact=metrics.rel_err(gpu_out32, exact),
+        err64_vs_exact=metrics.rel_err(gpu_out64, exact),
         err32_vs_nfft_oracle=metrics.rel_err(gpu_out32, ref),
         err64_vs_nfft_oracle=metrics.rel_err(gpu_out64, ref),
     )
+    if c1 is not None:
+        x1, w1, f1, g1 = c1
+        r2 = onfft.adjoint(x1, w1 * f1, C1_M, SIGMA, C1_M_WIN)
+        r1 = ndft.adjoint(x1, w1 * f1, C1_M)
+        out["c1"] = dict(err_vs_nfft_oracle=metrics.rel_err(g1, r2),
+                         err_vs_exact=metrics.rel_err(g1, r1))
+    return out
 
 
 def traffic_record(kernel):
@@ -538,7 +571,7 @@ def traffic_record(kernel):
 
 # sources of the d = 2 single-rhs spreading kernels
 SPREAD_SOURCES = ("spread.hip", "spread_common.hpp", "spread_group.hpp", "spread_pre.hip", "spread_late.hip",
-                  "spread_rows.hip")
+                  "spread_rows.hip", "spread_reg.hip")
 
 
 def spread_kernel_name(t):
@@ -547,6 +580,9 @@ def spread_kernel_name(t):
     T, mode = t["tile_edge"], t["spread_mode"]
     if mode == 2 and T + 2 * MW <= 32:
         return f"spread_rows_kernel<float, {MW}, {T if T == 16 else 0}, 1>"
+    if mode in (5, 6) and T == 16:
+        nw = 4 if t["spread_threads"] == 256 else 2
+        return f"spread_reg_kernel<{MW}, {nw}, {1 if mode == 6 else 2}>"
     ws = {3: 1, 4: 2}.get(mode, 0)   # window source of the group kernel
     return (f"spread_group_kernel<float, 2, {MW}, {t['spread_threads']}, "
             f"{T if T in (8, 16) else 0}, {'true' if t['spread_planes'] == 2 else 'false'}, {ws}>")
@@ -565,12 +601,13 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true", help="skip the 32-rhs spiral figures")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the secondary workloads (C1, spiral batch, forward, served stream, ...)")
     ap.add_argument("--tuning", default="auto",
                     help='profiling runs: "auto" (autotuner) or a JSON object of tuning keys')
     ap.add_argument("--precision", choices=["both", "f32", "f64"], default="both",
                     help="profiling runs: time one path only (the JSON line needs both)")
-    ap.add_argument("--only", choices=["jittered3d", "batched", "forward", "refine", "table51"],
+    ap.add_argument("--only", choices=["jittered3d", "batched", "forward", "refine", "c1", "served"],
                     default=None,
                     help="profiling runs: run one secondary workload alone and print its JSON")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -604,7 +641,8 @@ def main():
                "batched": lambda: run_batched(k, precs, tun),
                "forward": lambda: {p: run_forward(p, x, k, tun) for p in precs},
                "refine": lambda: run_refine(max(10, args.steps // 20), tuning=tun),
-               "table51": lambda: run_table51(max(10, args.steps // 20))}[args.only]()
+               "c1": lambda: run_c1(max(50, args.steps))[0],
+               "served": lambda: run_served()}[args.only]()
         print(json.dumps({args.only: sec}), flush=True)
         return
 
@@ -695,23 +733,38 @@ def main():
         "paper_context": "Table 5.1, M=256 linogram N=524288: 6.6443e-02 s per reconstruction "
                          "(7.89e6 points/s), hardware not stated",
     }
+    # the metric's accuracy condition: the float32 result against the float64
+    # path (itself parity-tested against the oracle), on every run
+    err32 = float(np.linalg.norm(r32["out"] - r64["out"]) / np.linalg.norm(r64["out"]))
+    line["metric_condition"] = dict(rel_err_f32=err32, bound=1e-5, met=err32 <= 1e-5,
+                                    reference="float64 GPU result of the same step")
+    c1_out = None
     if not args.no_batched:
+        line["c1"], c1_out = run_c1(max(50, min(args.steps, 300)))
         line["batched"] = run_batched(max(10, min(args.steps // 10, 100)))
         line["forward"] = {"f32": run_forward("f32", x, max(10, args.steps // 5)),
                            "f64": run_forward("f64", x, max(10, args.steps // 5))}
         line["weights_gpu"] = run_weights()
         line["bopt"] = run_bopt(max(10, args.steps // 5))
         line["jittered3d"] = run_jittered3d(max(10, args.steps // 10))
-        line["table51"] = run_table51(max(10, args.steps // 20))
         line["refine"] = run_refine(max(10, args.steps // 20))
         line["bandlimited"] = run_bandlimited()
+        line["served"] = run_served()
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(x, w, f, r32["out"], r64["out"])
+        c1 = (*c1_inputs(), c1_out) if c1_out is not None else None
+        cb = cpu_baseline(x, w, f, r32["out"], r64["out"], c1)
         line["cpu_baseline"] = cb["baseline"]
-        line["rel_err"] = {"f32_vs_exact_sampled": cb["err32_vs_exact"],
-                           "f64_vs_exact_sampled": cb["err64_vs_exact"],
+        line["rel_err"] = {"f32_vs_exact": cb["err32_vs_exact"],
+                           "f64_vs_exact": cb["err64_vs_exact"],
                            "f32_vs_nfft_oracle": cb["err32_vs_nfft_oracle"],
                            "f64_vs_nfft_oracle": cb["err64_vs_nfft_oracle"]}
+        if "c1" in cb and "c1" in line:
+            line["c1"].update(cb["c1"])
+    if not line["metric_condition"]["met"]:
+        line["value"] = None
+        line["invalid"] = "float32 result outside the metric's rel err <= 1e-5"
+        print(json.dumps(line), flush=True)
+        sys.exit(1)
     print(json.dumps(line), flush=True)
 
 

@@ -135,6 +135,18 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
  *                             memory two nodes ahead (no extra memory);
  *                             resolved to 1 for d != 2, and as mode 3 for
  *                             several right-hand sides per work-group.
+ *                             5 = float32, d = 2, tile edge 16: every
+ *                             wave keeps the whole padded tile of its work
+ *                             item in registers (lane c of a 32-lane half
+ *                             owns padded column c) and takes two nodes at
+ *                             a time; no LDS accumulation, the waves' tiles
+ *                             are summed in a fixed order at the end; the
+ *                             window is evaluated per call as in mode 4.
+ *                             6 = as 5 with the window factors read from the
+ *                             table of mode 3 (same memory).
+ *                             Modes 5 and 6 resolve to 4 and 3 for float64
+ *                             plans and for other tile edges; they take one
+ *                             right-hand side per work-group.
  *                             Default 1; the row sweep wins with many
  *                             right-hand sides per call, and in float32
  *                             takes two of them per wave when

@@ -223,9 +223,13 @@ int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, in
   if (planes != 1 && planes != 2)
     return fail(p, NFFT_EINVAL, "spread planes %d: expected 1 or 2", planes);
   int& mode = out[NFFT_TUNE_SPREAD_MODE];
-  if (mode < 1 || mode > 4)
-    return fail(p, NFFT_EINVAL, "spread mode %d: expected 1, 2, 3 or 4", mode);
+  if (mode < 1 || mode > 6)
+    return fail(p, NFFT_EINVAL, "spread mode %d: expected 1 .. 6", mode);
   if (mode == 2 && !nfft::spread_rows_supported(d, T + 2 * m)) mode = 1;
+  // the register-tile kernel: float32, d = 2, tile edge 16; elsewhere the LDS
+  // kernel with the same window source
+  if ((mode == 5 || mode == 6) && !nfft::spread_reg_supported(d, T, precision == NFFT_F64))
+    mode = mode == 5 ? 4 : 3;
   if ((mode == 3 || mode == 4) && d != 2) mode = 1;  // laid out for d = 2
   const int fw = out[NFFT_TUNE_FFT_MIN_WG];
   if (fw < 1 || fw > 65536) return fail(p, NFFT_EINVAL, "fft min work-groups %d: expected 1..65536", fw);
@@ -371,7 +375,9 @@ int build_tables(nfft_plan_t p) {
     return fail(p, NFFT_EUNSUPPORTED, "window polynomial error %.3g exceeds %.1g", p->poly_err, tol);
   TRY(dalloc(p, &p->coef, coef.size() * sizeof(R)));
   HIP_TRY(p, hipMemcpy(p->coef, coef.data(), coef.size() * sizeof(R), hipMemcpyHostToDevice));
-  std::vector<R> fac(M);
+  // deconvolution factors of D (2.13), float64 for both precisions: the
+  // float32 path multiplies in float64 and rounds once
+  std::vector<double> fac(M);
   for (int kidx = 0; kidx < M; ++kidx) {
     const int k = kidx - M / 2;
     const long double a = 2.0L * 3.14159265358979323846264338327950288L * k / Ms;
@@ -380,7 +386,7 @@ int build_tables(nfft_plan_t p) {
     const long double arg = (long double)m * std::sqrt(std::max(b * b - a * a, 0.0L));
     const long double val = std::exp(b * m) /
                             (3.14159265358979323846264338327950288L * bessel_i0(arg));
-    fac[kidx] = (R)((k % 2 == 0) ? val : -val);
+    fac[kidx] = (double)((k % 2 == 0) ? val : -val);
   }
   std::vector<cplx<R>> tw(Ms);
   for (int q = 0; q < Ms; ++q) {
@@ -388,9 +394,9 @@ int build_tables(nfft_plan_t p) {
     tw[q].x = (R)std::cos(ang);
     tw[q].y = (R)(-std::sin(ang));
   }
-  TRY(dalloc(p, &p->fac, M * sizeof(R)));
+  TRY(dalloc(p, &p->fac, M * sizeof(double)));
   TRY(dalloc(p, &p->tw, Ms * sizeof(cplx<R>)));
-  HIP_TRY(p, hipMemcpy(p->fac, fac.data(), M * sizeof(R), hipMemcpyHostToDevice));
+  HIP_TRY(p, hipMemcpy(p->fac, fac.data(), M * sizeof(double), hipMemcpyHostToDevice));
   HIP_TRY(p, hipMemcpy(p->tw, tw.data(), Ms * sizeof(cplx<R>), hipMemcpyHostToDevice));
   return NFFT_OK;
 }
@@ -436,6 +442,9 @@ void drop_psi(nfft_plan_t p) {
   (void)hipFree(sd.psi);
   sd.psi = nullptr;
 }
+
+// Spread modes that read the window factor table.
+bool uses_psi(int mode) { return mode == 3 || mode == 6; }
 
 int ensure_psi_any(nfft_plan_t p, hipStream_t s) {
   return p->prec == NFFT_F64 ? ensure_psi<double>(p, s) : ensure_psi<float>(p, s);
@@ -581,7 +590,7 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
   TRY(dalloc(p, &p->w, N * sizeof(cplx<R>)));
   TRY(alloc_workspace<R>(p, s));
   TRY(build_tables<R>(p));
-  if (p->tune[NFFT_TUNE_SPREAD_MODE] == 3) TRY(ensure_psi<R>(p, s));
+  if (uses_psi(p->tune[NFFT_TUNE_SPREAD_MODE])) TRY(ensure_psi<R>(p, s));
   HIP_TRY(p, hipStreamSynchronize(s));
   return NFFT_OK;
 }
@@ -608,7 +617,7 @@ nfft::FftArgs<R> fft_args(nfft_plan_t p, int64_t nlines, const void* in, int64_t
   a.out = (cplx<R>*)out;
   a.out_bs = out_bs;
   a.tw = (const cplx<R>*)p->tw;
-  a.fac = (const R*)p->fac;
+  a.fac = (const double*)p->fac;
   a.g = p->g;
   a.tilep = (const cplx<R>*)p->tilep;
   a.tile_bs = (int64_t)p->g.nbins * p->g.Ptot;
@@ -629,24 +638,37 @@ void record(nfft_plan_t p, StageEvents& se, hipStream_t s) {
   se.ev[se.n++] = e;
 }
 
+// Intermediate buffers of one adjoint: tile partials, item partials of split
+// tiles, FFT buffers.
+struct Work {
+  void* tilep;
+  void* itemp;
+  void* bufA;
+  void* bufB;
+};
+
 // With accumulate, the last FFT pass adds its outputs to fhat instead of
-// writing them (fhat += A^* W f).
+// writing them (fhat += A^* W f). With wk, the intermediate buffers are wk's
+// instead of the plan's workspace (no stage events are recorded then).
 template <typename R>
 int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t s,
-                bool accumulate = false) {
+                bool accumulate = false, const Work* wk = nullptr) {
   const Geom& g = p->g;
   const int64_t Ms = p->Ms, M = p->M;
+  const Work own{p->tilep, p->itemp, p->bufA, p->bufB};
+  const Work& w = wk ? *wk : own;
+  const bool prof = p->profiling && !wk;
   StageEvents se{};
   se.kind = 0;
-  record(p, se, s);
+  if (prof) record(p, se, s);
   nfft::SpreadArgs<R> sa{};
   sa.loc = p->loc;
   sa.frac = (const R*)p->frac;
   sa.w = (const cplx<R>*)p->w;
   sa.perm = p->perm;
   sa.f = (const cplx<R>*)f;
-  sa.tilep = (cplx<R>*)p->tilep;
-  sa.itemp = (cplx<R>*)p->itemp;
+  sa.tilep = (cplx<R>*)w.tilep;
+  sa.itemp = (cplx<R>*)w.itemp;
   sa.item_start = p->item_start;
   sa.item_count = p->item_count;
   sa.item_bin = p->item_bin;
@@ -661,12 +683,12 @@ int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t 
   sa.nr = nrhs > 1 ? p->tune[NFFT_TUNE_RHS_PER_GROUP] : 1;
   sa.planes = p->tune[NFFT_TUNE_SPREAD_PLANES];
   sa.mode = p->tune[NFFT_TUNE_SPREAD_MODE];
-  sa.psi = sa.mode == 3 ? (const R*)p->shared->psi : nullptr;
+  sa.psi = uses_psi(sa.mode) ? (const R*)p->shared->psi : nullptr;
   HIP_TRY(p, nfft::launch_spread<R>(sa, nrhs, s));
-  record(p, se, s);
+  if (prof) record(p, se, s);
   nfft::ReduceArgs<R> ra{};
-  ra.tilep = (cplx<R>*)p->tilep;
-  ra.itemp = (const cplx<R>*)p->itemp;
+  ra.tilep = (cplx<R>*)w.tilep;
+  ra.itemp = (const cplx<R>*)w.itemp;
   ra.multi_bin = p->multi_bin;
   ra.multi_first = p->multi_first;
   ra.nmulti = p->nmulti;
@@ -674,36 +696,39 @@ int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t 
   ra.item_rs = sa.item_rs;
   ra.g = g;
   HIP_TRY(p, nfft::launch_tile_reduce<R>(ra, nrhs, s));
-  record(p, se, s);
+  if (prof) record(p, se, s);
 
   const int L = (int)Ms;
   const auto fwd = nfft::kLoadMerge;
   if (p->d == 1) {
     auto a = fft_args<R>(p, 1, nullptr, 0, L, fhat, M);
+    a.tilep = (const cplx<R>*)w.tilep;
     a.accumulate = accumulate;
     HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, fwd, nfft::kStoreCropScaled, nrhs, s));
-    record(p, se, s);
+    if (prof) record(p, se, s);
   } else if (p->d == 2) {
     // [s1][s2] -> [k2][s1] -> [k1][k2]
-    auto a = fft_args<R>(p, Ms, nullptr, 0, L, p->bufA, M * Ms);
+    auto a = fft_args<R>(p, Ms, nullptr, 0, L, w.bufA, M * Ms);
+    a.tilep = (const cplx<R>*)w.tilep;
     HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, fwd, nfft::kStoreCropScaled, nrhs, s));
-    record(p, se, s);
-    auto c = fft_args<R>(p, M, p->bufA, M * Ms, L, fhat, M * M);
+    if (prof) record(p, se, s);
+    auto c = fft_args<R>(p, M, w.bufA, M * Ms, L, fhat, M * M);
     c.accumulate = accumulate;
     HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, false, nfft::kLoadLine, nfft::kStoreCropScaled, nrhs, s));
   } else {
     // [s1][s2][s3] -> [k3][s1][s2] -> [k2][k3][s1] -> [k1][k2][k3]
-    auto a = fft_args<R>(p, Ms * Ms, nullptr, 0, L, p->bufA, M * Ms * Ms);
+    auto a = fft_args<R>(p, Ms * Ms, nullptr, 0, L, w.bufA, M * Ms * Ms);
+    a.tilep = (const cplx<R>*)w.tilep;
     HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, fwd, nfft::kStoreCropScaled, nrhs, s));
-    record(p, se, s);
-    auto c = fft_args<R>(p, M * Ms, p->bufA, M * Ms * Ms, L, p->bufB, M * M * Ms);
+    if (prof) record(p, se, s);
+    auto c = fft_args<R>(p, M * Ms, w.bufA, M * Ms * Ms, L, w.bufB, M * M * Ms);
     HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, false, nfft::kLoadLine, nfft::kStoreCropScaled, nrhs, s));
-    auto e = fft_args<R>(p, M * M, p->bufB, M * M * Ms, L, fhat, M * M * M);
+    auto e = fft_args<R>(p, M * M, w.bufB, M * M * Ms, L, fhat, M * M * M);
     e.accumulate = accumulate;
     HIP_TRY(p, nfft::launch_fft_pass<R>(e, L, false, nfft::kLoadLine, nfft::kStoreCropScaled, nrhs, s));
   }
-  record(p, se, s);
-  if (p->profiling && se.n > 0) p->pending.push_back(se);
+  if (prof) record(p, se, s);
+  if (prof && se.n > 0) p->pending.push_back(se);
   return NFFT_OK;
 }
 
@@ -932,7 +957,7 @@ int64_t nfft_footprint(int d, int M, double sigma, int m, int64_t N, int precisi
   if (d >= 2) bytes += R_ * ipow(Ms, d - 1) * M * cb;
   if (d == 3) bytes += R_ * Ms * M * M * cb;
   bytes += R_ * ipow(Ms, d) * cb;                         // forward grid
-  bytes += M * rb + Ms * cb;                              // tables
+  bytes += M * 8 + Ms * cb;                               // tables
   if (d == 2) bytes += N * 4 * m * rb;                    // window factors (spread mode 3)
   return bytes;
 }
@@ -1071,6 +1096,7 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
   }
   if (d <= 2 && nrhs > 1) rpg = {1, 2, 4, 8};
   if (d == 2) modes = {1, 2, 3, 4};
+  if (d == 2 && f32) modes = {1, 2, 3, 4, 5, 6};
 
   nfft_plan_t best = nullptr;
   double best_t = -1.0;
@@ -1110,8 +1136,12 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
             if (md) in[NFFT_TUNE_SPREAD_MODE] = md;
             // the LDS kernel's shape does not matter when another kernel spreads
             if ((nr > 1 || md == 2) && (nt != threads[0] || pl != planes[0])) continue;
+            // the register-tile kernel (modes 5, 6) takes one rhs per work-group and
+            // no LDS tile layout
+            if (md >= 5 && (nr > 1 || pl != planes[0])) continue;
             if (nr > 2 && md == 2) continue;  // the row sweep takes at most two rhs per wave
-            if (md == 3 && (!have_psi || nr > 1)) continue;  // modes 3, 4: single rhs only
+            if (uses_psi(md) && !have_psi) continue;
+            if (md == 3 && nr > 1) continue;  // modes 3, 4: single rhs only
             if (md == 4 && nr > 1) continue;
             int res[NFFT_TUNE_COUNT];
             if (resolve_tuning(d, Ms, m, precision, in, NFFT_TUNE_COUNT, res, nullptr) != NFFT_OK)
@@ -1153,7 +1183,7 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
     free_plan(best);
     return fail(nullptr, NFFT_EDEVICE, "device failure while timing candidates");
   }
-  if (best->tune[NFFT_TUNE_SPREAD_MODE] != 3) drop_psi(best);
+  if (!uses_psi(best->tune[NFFT_TUNE_SPREAD_MODE])) drop_psi(best);
   best->shared->has_weights = false;
   if (best_ms) *best_ms = best_t;
   *out = best;
@@ -1510,7 +1540,7 @@ int nfft_set_tuning(nfft_plan_t p, int knob, int value) {
   in[knob] = value;
   const int st = resolve_tuning(p->d, p->Ms, p->m, p->prec, in, NFFT_TUNE_COUNT, out, p);
   if (st != NFFT_OK) return st;
-  if (out[NFFT_TUNE_SPREAD_MODE] == 3 && !p->shared->psi) {
+  if (uses_psi(out[NFFT_TUNE_SPREAD_MODE]) && !p->shared->psi) {
     // the factor table is built once, on the null stream, before the switch
     TRY(ensure_psi_any(p, nullptr));
     HIP_TRY(p, hipStreamSynchronize(nullptr));

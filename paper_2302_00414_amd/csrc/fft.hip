@@ -315,7 +315,8 @@ __device__ __forceinline__ cplx<R> load_elem(const FftArgs<R>& a, int b, int64_t
     else
       return mkc<R>(0, 0);
     const cplx<R> v = a.in[b * a.in_bs + q * M + kidx];
-    return cscale<R>(v, a.fac[kidx]);
+    const double f = a.fac[kidx];
+    return mkc<R>((R)((double)v.x * f), (R)((double)v.y * f));
   } else {
     // merge: the line index enumerates the leading d-1 grid coordinates
     const cplx<R>* tp = a.tilep + b * a.tile_bs;
@@ -349,11 +350,16 @@ __device__ __forceinline__ void store_elem(const FftArgs<R>& a, int b, int64_t q
     else
       return;
     cplx<R>* o = a.out + b * a.out_bs + (int64_t)kidx * a.nlines + q;
-    const cplx<R> u = cscale<R>(v, a.fac[kidx]);
-    if (a.accumulate)
-      *o = mkc<R>(o->x + u.x, o->y + u.y);
-    else
-      *o = u;
+    // the factor is float64; the product is rounded once to the precision
+    // of the data
+    const double f = a.fac[kidx];
+    const double ux = (double)v.x * f, uy = (double)v.y * f;
+    if (a.accumulate) {
+      const cplx<R> c = *o;
+      *o = mkc<R>((R)((double)c.x + ux), (R)((double)c.y + uy));
+    } else {
+      *o = mkc<R>((R)ux, (R)uy);
+    }
   }
 }
 

@@ -1,0 +1,319 @@
+// Spreading for d = 2 in float32 with the padded tile of a work item held in
+// registers (Algorithm 2.4 step 1 with the weights of (3.7)).
+//
+// The LDS spreading kernels update a node's (2m)^2 footprint by
+// read-modify-write of LDS cells, and a lane group's next node has to wait
+// for those writes. Here every wave keeps a whole padded tile (P = 16 + 2m
+// rows and columns) in registers instead: lane c of a 32-lane half owns
+// padded column c and holds its P cells, real and imaginary part, in 2P
+// registers. A wave takes two nodes at a time, one per half. For a node with
+// tile-local cell (l0, l1) the rows l0+1 .. l0+2m are updated by
+//     acc[l0 + 1 + i] += a_i * (b_c * c_j),        i < 2m,
+// with a_i the row factor (dimension 0) broadcast to the lanes by the DPP
+// operand of the multiply-add, b_c the column factor of lane c (zero outside
+// the footprint) and c_j = w_j f_j. Register indices must be static, so the
+// update is dispatched on the (wave-uniform) row l0; the nodes of a tile are
+// sorted by row at plan time, so the two nodes of a wave step almost always
+// share their row (otherwise each half is applied under its own row with the
+// other half's value set to zero). Nothing is written to LDS inside the node
+// loop; at the end the waves' tiles are summed in LDS in a fixed order (the
+// result does not depend on timing) and the padded tile is written out like
+// the other kernels' (tile_reduce and the first FFT pass merge them).
+//   WS = 2: the window factors are evaluated per call from the node's offsets
+//           (lane p of the half's first 16-lane row evaluates polynomial p at
+//           the dimension-0 offset, lane p of its second row at the
+//           dimension-1 offset; the factors reach their lanes by ds_bpermute);
+//   WS = 1: they are read from the plan's table of window factors (same
+//           polynomials, same values).
+// Nodes exactly on a grid line get the closed-edge row l0 / column l1.
+#include "spread_common.hpp"
+
+namespace nfft {
+
+namespace {
+
+// acc[OFF + i] += (v of lane i of this lane's 16-lane row) * x, i < K: the
+// row broadcast is the DPP operand modifier of the multiply-add. The leading
+// s_nop covers the wait states of a DPP read after a VALU write of v (two)
+// or a scalar write of EXEC (five). All 64 lanes are active.
+#define NFFT_REG_FMAC(I, NOP)                                                                   \
+  if constexpr (K > I)                                                                          \
+  asm volatile(NOP "v_fmac_f32_dpp %0, %1, %2 row_newbcast:" #I " row_mask:0xf bank_mask:0xf" \
+               : "+v"(acc[OFF + I])                                                             \
+               : "v"(v), "v"(x))
+template <int OFF, int K, int P>
+__device__ __forceinline__ void fmac_rows(float (&acc)[P], float v, float x) {
+  static_assert(K >= 1 && K <= 16 && OFF + K <= P, "rows inside the padded tile");
+  NFFT_REG_FMAC(0, "s_nop 4\n");
+  NFFT_REG_FMAC(1, "");
+  NFFT_REG_FMAC(2, "");
+  NFFT_REG_FMAC(3, "");
+  NFFT_REG_FMAC(4, "");
+  NFFT_REG_FMAC(5, "");
+  NFFT_REG_FMAC(6, "");
+  NFFT_REG_FMAC(7, "");
+  NFFT_REG_FMAC(8, "");
+  NFFT_REG_FMAC(9, "");
+  NFFT_REG_FMAC(10, "");
+  NFFT_REG_FMAC(11, "");
+  NFFT_REG_FMAC(12, "");
+  NFFT_REG_FMAC(13, "");
+  NFFT_REG_FMAC(14, "");
+  NFFT_REG_FMAC(15, "");
+}
+#undef NFFT_REG_FMAC
+
+// The 2m footprint rows of a node whose tile-local row is r (0 <= r < 16).
+template <int K2, int P>
+__device__ __forceinline__ void rows_at(int r, float (&ar)[P], float (&ai)[P], float av, float vx,
+                                        float vy) {
+  switch (r) {
+#define NFFT_ROW_CASE(R)                   \
+  case R:                                  \
+    fmac_rows<R + 1, K2, P>(ar, av, vx);   \
+    fmac_rows<R + 1, K2, P>(ai, av, vy);   \
+    break;
+    NFFT_ROW_CASE(0) NFFT_ROW_CASE(1) NFFT_ROW_CASE(2) NFFT_ROW_CASE(3)
+    NFFT_ROW_CASE(4) NFFT_ROW_CASE(5) NFFT_ROW_CASE(6) NFFT_ROW_CASE(7)
+    NFFT_ROW_CASE(8) NFFT_ROW_CASE(9) NFFT_ROW_CASE(10) NFFT_ROW_CASE(11)
+    NFFT_ROW_CASE(12) NFFT_ROW_CASE(13) NFFT_ROW_CASE(14) NFFT_ROW_CASE(15)
+#undef NFFT_ROW_CASE
+    default: break;
+  }
+}
+
+// The closed-edge row r of a node on a grid line in dimension 0.
+template <int P>
+__device__ __forceinline__ void edge_row_at(int r, float (&ar)[P], float (&ai)[P], float x,
+                                            float y) {
+  switch (r) {
+#define NFFT_EDGE_CASE(R) \
+  case R:                 \
+    ar[R] += x;           \
+    ai[R] += y;           \
+    break;
+    NFFT_EDGE_CASE(0) NFFT_EDGE_CASE(1) NFFT_EDGE_CASE(2) NFFT_EDGE_CASE(3)
+    NFFT_EDGE_CASE(4) NFFT_EDGE_CASE(5) NFFT_EDGE_CASE(6) NFFT_EDGE_CASE(7)
+    NFFT_EDGE_CASE(8) NFFT_EDGE_CASE(9) NFFT_EDGE_CASE(10) NFFT_EDGE_CASE(11)
+    NFFT_EDGE_CASE(12) NFFT_EDGE_CASE(13) NFFT_EDGE_CASE(14) NFFT_EDGE_CASE(15)
+#undef NFFT_EDGE_CASE
+    default: break;
+  }
+}
+
+__device__ __forceinline__ float lane_pick(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+
+}  // namespace
+
+// Nodes staged per batch.
+constexpr int kRegBatch = 256;
+
+template <int MW, int WS>
+struct RegLds {
+  static constexpr int K2 = 2 * MW;
+  static constexpr int P = 16 + K2;
+  // staging: c_j (2 floats), cell word, and either the two offsets (WS = 2)
+  // or the node's 2m pairs of window factors (WS = 1)
+  static constexpr size_t per_node = 3 * 4 + (WS == 1 ? 2 * K2 * 4 : 2 * 4);
+  static constexpr size_t staging = kRegBatch * per_node;
+  static constexpr size_t combine = 2 * (size_t)P * P * sizeof(float2);
+  static constexpr size_t bytes = staging > combine ? staging : combine;
+};
+
+template <int MW, int NW, int WS>
+__global__ __launch_bounds__(64 * NW) void spread_reg_kernel(SpreadArgs<float> a) {
+  constexpr int K2 = 2 * MW;
+  constexpr int P = 16 + K2;
+  constexpr int NT = 64 * NW;
+  constexpr int NB = kRegBatch;
+  constexpr int DEG = PolyDeg<float>::value;
+  extern __shared__ float lds_f[];
+  float* st_cx = lds_f;
+  float* st_cy = st_cx + NB;
+  uint32_t* st_loc = reinterpret_cast<uint32_t*>(st_cy + NB);
+  float* st_w = reinterpret_cast<float*>(st_loc + NB);  // offsets [2][NB] or factors [NB][K2][2]
+
+  const int item = blockIdx.x;
+  const int rhs = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int half = lane >> 5;
+  const int col = lane & 31;     // padded column of this lane
+  const int p = lane & 15;       // position in the 16-lane row
+  const bool rowB = (lane & 16) != 0;
+  const int pc = p < K2 ? p : K2 - 1;
+
+  float cf[DEG + 1];
+  if constexpr (WS == 2) {
+#pragma unroll
+    for (int q = 0; q <= DEG; ++q) cf[q] = a.coef[pc * (DEG + 1) + q];
+  }
+
+  float ar[P], ai[P];
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    ar[r] = 0.0f;
+    ai[r] = 0.0f;
+  }
+
+  const int64_t N = a.g.N;
+  const int start = a.item_start[item];
+  const int cnt = a.item_count[item];
+  const float2* f = a.f + rhs * a.f_rs;
+  const float edge = a.edge;
+
+  for (int b0 = 0; b0 < cnt; b0 += NB) {
+    const int nb = (cnt - b0) < NB ? (cnt - b0) : NB;
+    __syncthreads();  // the previous batch is consumed
+    for (int t = tid; t < nb; t += NT) {
+      const int i = start + b0 + t;
+      const float2 wv = a.w[i];
+      const float2 fv = f[a.perm[i]];
+      st_cx[t] = wv.x * fv.x - wv.y * fv.y;
+      st_cy[t] = wv.x * fv.y + wv.y * fv.x;
+      st_loc[t] = a.loc[i];
+      if constexpr (WS == 2) {
+        st_w[t] = 2.0f * a.frac[i] - 1.0f;
+        st_w[NB + t] = 2.0f * a.frac[N + i] - 1.0f;
+      }
+    }
+    if constexpr (WS == 1) {
+      const float* src = a.psi + (int64_t)(start + b0) * (2 * K2);
+      for (int q = tid; q < nb * 2 * K2; q += NT) st_w[q] = src[q];
+    }
+    __syncthreads();
+
+    const int nsteps = (nb + 1) >> 1;
+    for (int s = wave; s < nsteps; s += NW) {
+      const int n = 2 * s + half;
+      const bool valid = n < nb;
+      const int nn = valid ? n : nb - 1;
+      const uint32_t L = st_loc[nn];
+      const float cx = valid ? st_cx[nn] : 0.0f;
+      const float cy = valid ? st_cy[nn] : 0.0f;
+      const int l0 = (int)(L & kLocMask);
+      const int l1 = (int)((L >> kLocBits) & kLocMask);
+      const bool e0 = valid && ((L >> kEdgeShift) & 1u);
+      const bool e1 = (L >> (kEdgeShift + 1)) & 1u;
+      const int k = col - l1 - 1;  // footprint column of this lane
+      float av, bk;
+      if constexpr (WS == 2) {
+        // first row of the half: factor p of dimension 0; second row: of dimension 1
+        const float y = rowB ? st_w[NB + nn] : st_w[nn];
+        const float hv = horner<float>(cf, y);
+        av = lane_pick(hv, (lane & 32) | p);
+        bk = lane_pick(hv, (lane & 32) | 16 | (k & 15));
+      } else {
+        const float* q = st_w + nn * (2 * K2);
+        av = q[2 * pc];
+        bk = q[2 * (k >= 0 && k < K2 ? k : 0) + 1];
+      }
+      const float bv = (k >= 0 && k < K2) ? bk : ((e1 && col == l1) ? edge : 0.0f);
+      const float vx = bv * cx;
+      const float vy = bv * cy;
+      // rows of the two nodes (wave-uniform); a missing second node takes the
+      // first's. Two rows: each half in a pass of its own, the other half's
+      // values zero.
+      const int r0 = __builtin_amdgcn_readfirstlane(l0);
+      const int r1n = __builtin_amdgcn_readlane(l0, 32);
+      const int r1 = (2 * s + 1 < nb) ? r1n : r0;
+      const int npass = r0 == r1 ? 1 : 2;
+      const bool any_edge = __builtin_amdgcn_ballot_w64(e0) != 0;
+      const float ex = e0 ? edge * vx : 0.0f, ey = e0 ? edge * vy : 0.0f;
+#pragma unroll 1
+      for (int ps = 0; ps < npass; ++ps) {
+        const int r = ps ? r1 : r0;
+        const bool act = npass == 1 || half == ps;
+        rows_at<K2, P>(r, ar, ai, av, act ? vx : 0.0f, act ? vy : 0.0f);
+        // closed-edge row of nodes on a grid line in dimension 0
+        if (any_edge) edge_row_at<P>(r, ar, ai, act ? ex : 0.0f, act ? ey : 0.0f);
+      }
+    }
+  }
+
+  // the waves' tiles summed in LDS in wave order, one tile per half, then the
+  // two halves added: a fixed order, so the result does not depend on timing
+  __syncthreads();
+  float2* tile0 = reinterpret_cast<float2*>(lds_f);
+  float2* tile1 = tile0 + P * P;
+  float2* mine = half ? tile1 : tile0;
+#pragma unroll 1
+  for (int w = 0; w < NW; ++w) {
+    if (wave == w && col < P) {
+      if (w == 0) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) mine[r * P + col] = make_float2(ar[r], ai[r]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+          float2 v = mine[r * P + col];
+          v.x += ar[r];
+          v.y += ai[r];
+          mine[r * P + col] = v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const int slot = a.item_slot[item];
+  float2* out = slot < 0 ? a.tilep + rhs * a.tile_rs + (int64_t)a.item_bin[item] * (P * P)
+                         : a.itemp + rhs * a.item_rs + (int64_t)slot * (P * P);
+  for (int i = tid; i < P * P; i += NT) {
+    const float2 u = tile0[i], v = tile1[i];
+    out[i] = make_float2(u.x + v.x, u.y + v.y);
+  }
+}
+
+bool spread_reg_supported(int d, int T, bool f64) { return d == 2 && T == 16 && !f64; }
+
+size_t spread_reg_lds_bytes(int m, int ws) {
+  switch (m) {
+#define NFFT_REG_LDS(MW) \
+  case MW:               \
+    return ws == 1 ? RegLds<MW, 1>::bytes : RegLds<MW, 2>::bytes;
+    NFFT_REG_LDS(1) NFFT_REG_LDS(2) NFFT_REG_LDS(3) NFFT_REG_LDS(4)
+    NFFT_REG_LDS(5) NFFT_REG_LDS(6) NFFT_REG_LDS(7) NFFT_REG_LDS(8)
+#undef NFFT_REG_LDS
+    default: return 0;
+  }
+}
+
+template <int MW, int WS>
+static hipError_t spread_reg_ws(const SpreadArgs<float>& a, int nrhs, hipStream_t s) {
+  const dim3 grid(a.g.nsub, nrhs);
+  const size_t lds = RegLds<MW, WS>::bytes;
+  // 64 or 128 threads: two waves; 256: four
+  if (a.nt == 256)
+    hipLaunchKernelGGL((spread_reg_kernel<MW, 4, WS>), grid, dim3(256), lds, s, a);
+  else
+    hipLaunchKernelGGL((spread_reg_kernel<MW, 2, WS>), grid, dim3(128), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int MW>
+static hipError_t spread_reg_m(const SpreadArgs<float>& a, int nrhs, hipStream_t s) {
+  if (a.psi) return spread_reg_ws<MW, 1>(a, nrhs, s);
+  return spread_reg_ws<MW, 2>(a, nrhs, s);
+}
+
+// a.psi set: the table variant; otherwise the window is evaluated per call.
+hipError_t launch_spread_reg(const SpreadArgs<float>& a, int nrhs, hipStream_t s) {
+  if (!spread_reg_supported(a.g.d, a.g.T, false)) return hipErrorInvalidValue;
+  if (a.g.nsub == 0) return hipSuccess;
+  switch (a.g.m) {
+    case 1: return spread_reg_m<1>(a, nrhs, s);
+    case 2: return spread_reg_m<2>(a, nrhs, s);
+    case 3: return spread_reg_m<3>(a, nrhs, s);
+    case 4: return spread_reg_m<4>(a, nrhs, s);
+    case 5: return spread_reg_m<5>(a, nrhs, s);
+    case 6: return spread_reg_m<6>(a, nrhs, s);
+    case 7: return spread_reg_m<7>(a, nrhs, s);
+    case 8: return spread_reg_m<8>(a, nrhs, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace nfft

