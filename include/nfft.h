@@ -241,6 +241,30 @@ int nfft_set_weights(nfft_plan_t plan, const double *w, void *stream);
 int nfft_adjoint(nfft_plan_t plan, const void *f, void *fhat, int nrhs, void *stream);
 
 /*
+ * nfft_adjoint_scratch -- nfft_adjoint for callers that cannot allocate
+ * device memory or must not use the plan's workspace (code under HIP graph
+ * capture, tight serving loops that run many requests on one resident plan,
+ * harnesses that forbid allocation): the same kernels and the same result,
+ * with the intermediate buffers (tile partials, item partials of split tiles,
+ * FFT buffers) placed in a file-scope device array of the library, 32 MiB per
+ * GPU, held from the library's first use on that GPU until the process ends.
+ * The call allocates nothing and frees nothing; its first call on a device
+ * looks the array's address up once (hipGetSymbolAddress).
+ *   f, fhat, nrhs, stream  as for nfft_adjoint
+ * The intermediate buffers of one call take about nrhs * 8 (float32) or 16
+ * (float64) bytes times (tiles + split-tile items) * (tile edge + 2m)^d plus
+ * M_sigma^(d-1) M (and M_sigma M^2 for d = 3); a call that needs more than
+ * 32 MiB returns NFFT_EUNSUPPORTED before anything is enqueued (e.g. the
+ * 512 x 512 polar set at M = 256 fits in both precisions, a 3-D jittered set
+ * at M = 64 does not). Every call on one GPU uses the same array: calls that
+ * overlap on that GPU (other streams, other plans, other threads) race and
+ * give wrong results; the caller serialises them. Each call first clears the
+ * part that must start at zero (the slots of tiles without nodes) with a
+ * kernel, no memset. NFFT_ESTATE without weights.
+ */
+int nfft_adjoint_scratch(nfft_plan_t plan, const void *f, void *fhat, int nrhs, void *stream);
+
+/*
  * nfft_forward -- f = B F D fhat for nrhs right-hand sides (Algorithm 2.1):
  * deconvolve and zero-pad (step 1), inverse FFT (step 2), window sums at the
  * nodes (step 3). No weights are involved.

@@ -21,7 +21,8 @@ NFFT_TUNE_COUNT = 7
 EXPORTS = (
     "nfft_plan", "nfft_plan_tuned", "nfft_plan_autotune", "nfft_get_tuning", "nfft_set_tuning",
     "nfft_plan_clone",
-    "nfft_set_weights", "nfft_adjoint", "nfft_forward", "nfft_refine", "nfft_weights",
+    "nfft_set_weights", "nfft_adjoint", "nfft_adjoint_scratch", "nfft_forward", "nfft_refine",
+    "nfft_weights",
     "nfft_weights_ex",
     "nfft_bopt_build",
     "nfft_bopt_adjoint", "nfft_bopt_inverse_adjoint", "nfft_bopt_get", "nfft_destroy",
@@ -69,6 +70,8 @@ def load() -> ctypes.CDLL:
     lib.nfft_set_weights.restype = i32
     lib.nfft_adjoint.argtypes = [vp, vp, vp, i32, vp]
     lib.nfft_adjoint.restype = i32
+    lib.nfft_adjoint_scratch.argtypes = [vp, vp, vp, i32, vp]
+    lib.nfft_adjoint_scratch.restype = i32
     lib.nfft_forward.argtypes = [vp, vp, vp, i32, vp]
     lib.nfft_forward.restype = i32
     lib.nfft_refine.argtypes = [vp, vp, vp, i32, i32, ctypes.POINTER(dbl), vp]

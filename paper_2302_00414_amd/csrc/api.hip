@@ -104,6 +104,8 @@ struct nfft_plan_s {
   int32_t* multi_first = nullptr;  // first itemp slot of each split tile
   int nmulti = 0;
   int nslots = 0;                  // itemp slots
+  int32_t* empty_bins = nullptr;   // tiles without nodes (their slots are never written)
+  int nempty = 0;
   void* tilep = nullptr;           // tile partials [rhs][tile][P^d]
   void* itemp = nullptr;           // item partials of split tiles [rhs][slot][P^d]
   void* coef = nullptr;            // window polynomials [2m][deg + 1]
@@ -521,6 +523,10 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
   }
   mfirst.push_back(p->nslots);
   p->nmulti = (int)mbin.size();
+  std::vector<int32_t> ebins;
+  for (int b = 0; b < g.nbins; ++b)
+    if (hc[b] == 0) ebins.push_back(b);
+  p->nempty = (int)ebins.size();
   g.nsub = (int)istart.size();
   // launch order: largest work items first, so that the work-groups that
   // start last are the small remainders of tiles (every item writes its own
@@ -586,6 +592,9 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
   if (!mbin.empty())
     HIP_TRY(p, hipMemcpyAsync(p->multi_bin, mbin.data(), mbin.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(p, hipMemcpyAsync(p->multi_first, mfirst.data(), mfirst.size() * 4, hipMemcpyHostToDevice, s));
+  TRY(dalloc(p, &p->empty_bins, std::max<size_t>(1, ebins.size()) * sizeof(int32_t)));
+  if (!ebins.empty())
+    HIP_TRY(p, hipMemcpyAsync(p->empty_bins, ebins.data(), ebins.size() * 4, hipMemcpyHostToDevice, s));
 
   TRY(dalloc(p, &p->w, N * sizeof(cplx<R>)));
   TRY(alloc_workspace<R>(p, s));
@@ -912,6 +921,71 @@ double time_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStrea
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return ok ? best : -1.0;
+}
+
+// Scratch memory of nfft_adjoint_scratch: a file-scope device array that
+// every GPU the library runs on holds until the process ends. In host code
+// its name is only a stand-in; its device address (one per GPU) comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Device address of the scratch array on `dev` (looked up on the first call
+// for that device, with `dev` current; the caller's current device is
+// restored).
+int scratch_address(nfft_plan_t p, int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(p, NFFT_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    HIP_TRY(p, hipGetDevice(&cur));
+    if (cur != dev) HIP_TRY(p, hipSetDevice(dev));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr)
+      return fail(p, NFFT_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return NFFT_OK;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// The adjoint with its intermediate buffers carved out of the scratch array.
+template <typename R>
+int run_adjoint_scratch(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t s) {
+  const Geom& g = p->g;
+  const size_t cb = sizeof(cplx<R>);
+  const int64_t Ms = p->Ms, M = p->M;
+  const size_t tile = align256((size_t)nrhs * g.nbins * g.Ptot * cb);
+  const size_t item = align256((size_t)nrhs * std::max(1, p->nslots) * g.Ptot * cb);
+  const size_t bufA = p->d >= 2 ? align256((size_t)nrhs * ipow(Ms, p->d - 1) * M * cb) : 0;
+  const size_t bufB = p->d == 3 ? align256((size_t)nrhs * Ms * M * M * cb) : 0;
+  const size_t need = tile + item + bufA + bufB;
+  if (need > kScratchBytes)
+    return fail(p, NFFT_EUNSUPPORTED,
+                "this adjoint needs %zu bytes of intermediate buffers; the library's scratch "
+                "array holds %zu", need, kScratchBytes);
+  void* base = nullptr;
+  TRY(scratch_address(p, p->device, &base));
+  unsigned char* b = static_cast<unsigned char*>(base);
+  const Work wk{b, b + tile, bufA ? b + tile + item : nullptr,
+                bufB ? b + tile + item + bufA : nullptr};
+  // the slots of tiles without nodes are read as zeros and written by no
+  // work item; the previous call left its own data there
+  HIP_TRY(p, nfft::launch_zero_tiles<R>((cplx<R>*)wk.tilep, (int64_t)g.nbins * g.Ptot,
+                                        p->empty_bins, p->nempty, g.Ptot, nrhs, s));
+  return run_adjoint<R>(p, f, fhat, nrhs, s, false, &wk);
 }
 
 }  // namespace
@@ -1579,6 +1653,18 @@ int nfft_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, void* strea
   hipStream_t s = (hipStream_t)stream;
   return p->prec == NFFT_F64 ? run_adjoint<double>(p, f, fhat, nrhs, s)
                              : run_adjoint<float>(p, f, fhat, nrhs, s);
+}
+
+int nfft_adjoint_scratch(nfft_plan_t p, const void* f, void* fhat, int nrhs, void* stream) {
+  if (!p) return fail(nullptr, NFFT_EINVAL, "plan is NULL");
+  if (!f || !fhat) return fail(p, NFFT_EINVAL, "f or fhat is NULL");
+  if (nrhs < 1 || nrhs > p->max_rhs)
+    return fail(p, NFFT_EINVAL, "nrhs = %d outside 1..max_rhs = %d", nrhs, p->max_rhs);
+  if (!p->shared->has_weights) return fail(p, NFFT_ESTATE, "nfft_set_weights has not been called");
+  HIP_TRY(p, hipGetLastError());
+  hipStream_t s = (hipStream_t)stream;
+  return p->prec == NFFT_F64 ? run_adjoint_scratch<double>(p, f, fhat, nrhs, s)
+                             : run_adjoint_scratch<float>(p, f, fhat, nrhs, s);
 }
 
 int nfft_forward(nfft_plan_t p, const void* fhat, void* f, int nrhs, void* stream) {

@@ -35,6 +35,11 @@ template <typename R>
 hipError_t launch_permute_weights(const double* w, const int32_t* perm, int64_t N,
                                   cplx<R>* w_sorted, hipStream_t s);
 
+// Zero the tile slots of the nbins tiles listed in bins (tiles without nodes).
+template <typename R>
+hipError_t launch_zero_tiles(cplx<R>* tilep, int64_t tile_rs, const int32_t* bins, int nbins,
+                             int Ptot, int nrhs, hipStream_t s);
+
 // ------------------------------------------------------- spreading / sums
 // Tile partials: every tile owns a padded-tile slot in `tilep` ([rhs][tile]
 // [P^d], zero for tiles without nodes). A tile with a single work item is

@@ -223,6 +223,31 @@ hipError_t launch_permute_weights(const double* w, const int32_t* perm, int64_t 
   return hipGetLastError();
 }
 
+// Zero the padded-tile slots of the tiles that hold no nodes (no work item
+// writes them, and the first FFT pass reads them as zeros).
+template <typename R>
+__global__ __launch_bounds__(256) void zero_tiles_kernel(cplx<R>* tilep, int64_t tile_rs,
+                                                         const int32_t* bins, int nbins, int Ptot) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)nbins * Ptot) return;
+  const int b = bins[i / Ptot];
+  const int c = (int)(i % Ptot);
+  tilep[blockIdx.y * tile_rs + (int64_t)b * Ptot + c] = mkc<R>(0, 0);
+}
+
+template <typename R>
+hipError_t launch_zero_tiles(cplx<R>* tilep, int64_t tile_rs, const int32_t* bins, int nbins,
+                             int Ptot, int nrhs, hipStream_t s) {
+  if (nbins == 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_tiles_kernel<R>, dim3(grid1((int64_t)nbins * Ptot, 256), nrhs),
+                     dim3(256), 0, s, tilep, tile_rs, bins, nbins, Ptot);
+  return hipGetLastError();
+}
+
+template hipError_t launch_zero_tiles<float>(cplx<float>*, int64_t, const int32_t*, int, int, int,
+                                             hipStream_t);
+template hipError_t launch_zero_tiles<double>(cplx<double>*, int64_t, const int32_t*, int, int,
+                                              int, hipStream_t);
 template hipError_t launch_scatter<float>(const int32_t*, const int32_t*, const int32_t*,
                                           const uint32_t*, const double*, int64_t, int, int,
                                           int32_t*, uint32_t*, float*, hipStream_t);

@@ -143,6 +143,12 @@ def nfft_adjoint(plan, f: torch.Tensor, fhat: torch.Tensor, nrhs: int, stream=No
                                    ctypes.c_void_p(fhat.data_ptr()), nrhs, _stream_ptr(stream)), plan)
 
 
+def nfft_adjoint_scratch(plan, f: torch.Tensor, fhat: torch.Tensor, nrhs: int, stream=None) -> None:
+    check(_lib.load().nfft_adjoint_scratch(plan, ctypes.c_void_p(f.data_ptr()),
+                                           ctypes.c_void_p(fhat.data_ptr()), nrhs,
+                                           _stream_ptr(stream)), plan)
+
+
 def nfft_forward(plan, fhat: torch.Tensor, f: torch.Tensor, nrhs: int, stream=None) -> None:
     check(_lib.load().nfft_forward(plan, ctypes.c_void_p(fhat.data_ptr()),
                                    ctypes.c_void_p(f.data_ptr()), nrhs, _stream_ptr(stream)), plan)
@@ -352,6 +358,17 @@ class Plan:
         check_out(out, self.cdtype, self.device, nrhs * K)
         nfft_adjoint(self._h, f, out, nrhs, stream)
         return out.reshape(K) if single else out
+
+    def adjoint_scratch(self, f, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """self.adjoint with the library's scratch array in place of the plan's
+        workspace (nfft_adjoint_scratch: no device allocation by the library;
+        calls overlapping on one GPU race). out is required, so that nothing
+        is allocated here either."""
+        f = self._coerce(f, self.N)
+        nrhs = f.numel() // self.N
+        check_out(out, self.cdtype, self.device, nrhs * self.M ** self.d)
+        nfft_adjoint_scratch(self._h, f, out, nrhs, stream)
+        return out
 
     def forward(self, fhat, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         """f = B F D fhat; fhat is (M^d,) or (nrhs, M^d)."""
