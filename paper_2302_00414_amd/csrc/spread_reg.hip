@@ -11,14 +11,16 @@
 //     acc[l0 + 1 + i] += a_i * (b_c * c_j),        i < 2m,
 // with a_i the row factor (dimension 0) broadcast to the lanes by the DPP
 // operand of the multiply-add, b_c the column factor of lane c (zero outside
-// the footprint) and c_j = w_j f_j. Register indices must be static, so the
-// update is dispatched on the (wave-uniform) row l0; the nodes of a tile are
-// sorted by row at plan time, so the two nodes of a wave step almost always
-// share their row (otherwise each half is applied under its own row with the
-// other half's value set to zero). Nothing is written to LDS inside the node
-// loop; at the end the waves' tiles are summed in LDS in a fixed order (the
-// result does not depend on timing) and the padded tile is written out like
-// the other kernels' (tile_reduce and the first FFT pass merge them).
+// the footprint) and c_j = w_j f_j. Register indices must be static: the
+// nodes of a tile are sorted by row at plan time, and the node loop runs
+// inside an unrolled loop over the 16 tile rows, so that for row r the
+// updated registers are the constants r+1 .. r+2m. The two nodes of a wave
+// step come from the same row (pairs of consecutive nodes of the row; the
+// pairs of all rows are dealt to the waves in turn). Nothing is written to
+// LDS inside the node loop; at the end the waves' tiles are summed in LDS in
+// a fixed order (the result does not depend on timing) and the padded tile
+// is written out like the other kernels' (tile_reduce and the first FFT pass
+// merge them).
 //   WS = 2: the window factors are evaluated per call from the node's offsets
 //           (lane p of the half's first 16-lane row evaluates polynomial p at
 //           the dimension-0 offset, lane p of its second row at the
@@ -63,44 +65,6 @@ __device__ __forceinline__ void fmac_rows(float (&acc)[P], float v, float x) {
 }
 #undef NFFT_REG_FMAC
 
-// The 2m footprint rows of a node whose tile-local row is r (0 <= r < 16).
-template <int K2, int P>
-__device__ __forceinline__ void rows_at(int r, float (&ar)[P], float (&ai)[P], float av, float vx,
-                                        float vy) {
-  switch (r) {
-#define NFFT_ROW_CASE(R)                   \
-  case R:                                  \
-    fmac_rows<R + 1, K2, P>(ar, av, vx);   \
-    fmac_rows<R + 1, K2, P>(ai, av, vy);   \
-    break;
-    NFFT_ROW_CASE(0) NFFT_ROW_CASE(1) NFFT_ROW_CASE(2) NFFT_ROW_CASE(3)
-    NFFT_ROW_CASE(4) NFFT_ROW_CASE(5) NFFT_ROW_CASE(6) NFFT_ROW_CASE(7)
-    NFFT_ROW_CASE(8) NFFT_ROW_CASE(9) NFFT_ROW_CASE(10) NFFT_ROW_CASE(11)
-    NFFT_ROW_CASE(12) NFFT_ROW_CASE(13) NFFT_ROW_CASE(14) NFFT_ROW_CASE(15)
-#undef NFFT_ROW_CASE
-    default: break;
-  }
-}
-
-// The closed-edge row r of a node on a grid line in dimension 0.
-template <int P>
-__device__ __forceinline__ void edge_row_at(int r, float (&ar)[P], float (&ai)[P], float x,
-                                            float y) {
-  switch (r) {
-#define NFFT_EDGE_CASE(R) \
-  case R:                 \
-    ar[R] += x;           \
-    ai[R] += y;           \
-    break;
-    NFFT_EDGE_CASE(0) NFFT_EDGE_CASE(1) NFFT_EDGE_CASE(2) NFFT_EDGE_CASE(3)
-    NFFT_EDGE_CASE(4) NFFT_EDGE_CASE(5) NFFT_EDGE_CASE(6) NFFT_EDGE_CASE(7)
-    NFFT_EDGE_CASE(8) NFFT_EDGE_CASE(9) NFFT_EDGE_CASE(10) NFFT_EDGE_CASE(11)
-    NFFT_EDGE_CASE(12) NFFT_EDGE_CASE(13) NFFT_EDGE_CASE(14) NFFT_EDGE_CASE(15)
-#undef NFFT_EDGE_CASE
-    default: break;
-  }
-}
-
 __device__ __forceinline__ float lane_pick(float v, int src) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
 }
@@ -115,9 +79,10 @@ struct RegLds {
   static constexpr int K2 = 2 * MW;
   static constexpr int P = 16 + K2;
   // staging: c_j (2 floats), cell word, and either the two offsets (WS = 2)
-  // or the node's 2m pairs of window factors (WS = 1)
+  // or the node's 2m pairs of window factors (WS = 1); the first node of
+  // every tile row in the batch (17 entries)
   static constexpr size_t per_node = 3 * 4 + (WS == 1 ? 2 * K2 * 4 : 2 * 4);
-  static constexpr size_t staging = kRegBatch * per_node;
+  static constexpr size_t staging = kRegBatch * per_node + 32 * 4;
   static constexpr size_t combine = 2 * (size_t)P * P * sizeof(float2);
   static constexpr size_t bytes = staging > combine ? staging : combine;
 };
@@ -134,11 +99,14 @@ __global__ __launch_bounds__(64 * NW) void spread_reg_kernel(SpreadArgs<float> a
   float* st_cy = st_cx + NB;
   uint32_t* st_loc = reinterpret_cast<uint32_t*>(st_cy + NB);
   float* st_w = reinterpret_cast<float*>(st_loc + NB);  // offsets [2][NB] or factors [NB][K2][2]
+  int* st_rs = reinterpret_cast<int*>(st_w + (WS == 1 ? NB * 2 * K2 : 2 * NB));  // row starts [17]
 
   const int item = blockIdx.x;
   const int rhs = blockIdx.y;
   const int tid = threadIdx.x;
-  const int wave = tid >> 6;
+  // wave-uniform (a scalar register), so that the node loop and the row
+  // dispatch below are scalar branches and EXEC stays full
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const int half = lane >> 5;
   const int col = lane & 31;     // padded column of this lane
@@ -185,53 +153,67 @@ __global__ __launch_bounds__(64 * NW) void spread_reg_kernel(SpreadArgs<float> a
       for (int q = tid; q < nb * 2 * K2; q += NT) st_w[q] = src[q];
     }
     __syncthreads();
-
-    const int nsteps = (nb + 1) >> 1;
-    for (int s = wave; s < nsteps; s += NW) {
-      const int n = 2 * s + half;
-      const bool valid = n < nb;
-      const int nn = valid ? n : nb - 1;
-      const uint32_t L = st_loc[nn];
-      const float cx = valid ? st_cx[nn] : 0.0f;
-      const float cy = valid ? st_cy[nn] : 0.0f;
-      const int l0 = (int)(L & kLocMask);
-      const int l1 = (int)((L >> kLocBits) & kLocMask);
-      const bool e0 = valid && ((L >> kEdgeShift) & 1u);
-      const bool e1 = (L >> (kEdgeShift + 1)) & 1u;
-      const int k = col - l1 - 1;  // footprint column of this lane
-      float av, bk;
-      if constexpr (WS == 2) {
-        // first row of the half: factor p of dimension 0; second row: of dimension 1
-        const float y = rowB ? st_w[NB + nn] : st_w[nn];
-        const float hv = horner<float>(cf, y);
-        av = lane_pick(hv, (lane & 32) | p);
-        bk = lane_pick(hv, (lane & 32) | 16 | (k & 15));
-      } else {
-        const float* q = st_w + nn * (2 * K2);
-        av = q[2 * pc];
-        bk = q[2 * (k >= 0 && k < K2 ? k : 0) + 1];
-      }
-      const float bv = (k >= 0 && k < K2) ? bk : ((e1 && col == l1) ? edge : 0.0f);
-      const float vx = bv * cx;
-      const float vy = bv * cy;
-      // rows of the two nodes (wave-uniform); a missing second node takes the
-      // first's. Two rows: each half in a pass of its own, the other half's
-      // values zero.
-      const int r0 = __builtin_amdgcn_readfirstlane(l0);
-      const int r1n = __builtin_amdgcn_readlane(l0, 32);
-      const int r1 = (2 * s + 1 < nb) ? r1n : r0;
-      const int npass = r0 == r1 ? 1 : 2;
-      const bool any_edge = __builtin_amdgcn_ballot_w64(e0) != 0;
-      const float ex = e0 ? edge * vx : 0.0f, ey = e0 ? edge * vy : 0.0f;
-#pragma unroll 1
-      for (int ps = 0; ps < npass; ++ps) {
-        const int r = ps ? r1 : r0;
-        const bool act = npass == 1 || half == ps;
-        rows_at<K2, P>(r, ar, ai, av, act ? vx : 0.0f, act ? vy : 0.0f);
-        // closed-edge row of nodes on a grid line in dimension 0
-        if (any_edge) edge_row_at<P>(r, ar, ai, act ? ex : 0.0f, act ? ey : 0.0f);
-      }
+    // first node of each tile row (the batch is sorted by row): node t opens
+    // the rows after its predecessor's up to its own; the last node closes
+    // the rest
+    for (int t = tid; t < nb; t += NT) {
+      const int rt = (int)(st_loc[t] & kLocMask);
+      const int rp = t > 0 ? (int)(st_loc[t - 1] & kLocMask) : -1;
+      for (int r = rp + 1; r <= rt; ++r) st_rs[r] = t;
+      if (t == nb - 1)
+        for (int r = rt + 1; r <= 16; ++r) st_rs[r] = nb;
     }
+    __syncthreads();
+
+    // pairs of consecutive nodes within each row; the pairs of all rows are
+    // numbered in row order and wave w takes pairs w, w + NW, ...
+    int pbase = 0;  // pairs of the rows before r
+    static_for<0, 16>([&](auto rc) {
+      constexpr int r = decltype(rc)::value;
+      const int n0 = __builtin_amdgcn_readfirstlane(st_rs[r]);
+      const int n1 = __builtin_amdgcn_readfirstlane(st_rs[r + 1]);
+      const int np = (n1 - n0 + 1) >> 1;
+      // first pair of this row that belongs to this wave
+      int q = wave - pbase % NW;
+      q = q < 0 ? q + NW : q;
+      for (; q < np; q += NW) {
+        const int n = n0 + 2 * q + half;
+        const bool valid = n < n1;
+        const int nn = valid ? n : n1 - 1;
+        // nn is a node of this batch: the reads need no guard
+        const uint32_t L = st_loc[nn];
+        const float sx = st_cx[nn], sy = st_cy[nn];
+        const float cx = valid ? sx : 0.0f;
+        const float cy = valid ? sy : 0.0f;
+        const int l1 = (int)((L >> kLocBits) & kLocMask);
+        const bool e0 = valid && ((L >> kEdgeShift) & 1u);
+        const bool e1 = (L >> (kEdgeShift + 1)) & 1u;
+        const int k = col - l1 - 1;  // footprint column of this lane
+        float av, bk;
+        if constexpr (WS == 2) {
+          // first row of the half: factor p of dimension 0; second row: of dimension 1
+          const float y = rowB ? st_w[NB + nn] : st_w[nn];
+          const float hv = horner<float>(cf, y);
+          av = lane_pick(hv, (lane & 32) | p);
+          bk = lane_pick(hv, (lane & 32) | 16 | (k & 15));
+        } else {
+          const float* qf = st_w + nn * (2 * K2);
+          av = qf[2 * pc];
+          bk = qf[2 * (k >= 0 && k < K2 ? k : 0) + 1];
+        }
+        const float bv = (k >= 0 && k < K2) ? bk : ((e1 && col == l1) ? edge : 0.0f);
+        const float vx = bv * cx;
+        const float vy = bv * cy;
+        fmac_rows<r + 1, K2, P>(ar, av, vx);
+        fmac_rows<r + 1, K2, P>(ai, av, vy);
+        // closed-edge row of nodes on a grid line in dimension 0
+        if (__builtin_amdgcn_ballot_w64(e0)) {
+          ar[r] += e0 ? edge * vx : 0.0f;
+          ai[r] += e0 ? edge * vy : 0.0f;
+        }
+      }
+      pbase += np;
+    });
   }
 
   // the waves' tiles summed in LDS in wave order, one tile per half, then the
