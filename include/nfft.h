@@ -102,7 +102,8 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
  *                             16..65536 (default 256). Fixed at plan time.
  *   NFFT_TUNE_SPREAD_THREADS  threads of a spreading work-group for d <= 2,
  *                             float32, one right-hand side per work-group:
- *                             64, 128 or 256 (default 128).
+ *                             64, 128 or 256 (default 128); 512 for spread
+ *                             mode 5 (resolved to 256 for the others).
  *   NFFT_TUNE_RHS_PER_GROUP   right-hand sides that one spreading work-group
  *                             takes when nrhs > 1 and d <= 2: 1, 2, 4 or 8
  *                             (default 1). Above 1 the node data and window
@@ -138,15 +139,13 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
  *                             5 = float32, d = 2, tile edge 16: every
  *                             wave keeps the whole padded tile of its work
  *                             item in registers (lane c of a 32-lane half
- *                             owns padded column c) and takes two nodes at
- *                             a time; no LDS accumulation, the waves' tiles
- *                             are summed in a fixed order at the end; the
- *                             window is evaluated per call as in mode 4.
- *                             6 = as 5 with the window factors read from the
- *                             table of mode 3 (same memory).
- *                             Modes 5 and 6 resolve to 4 and 3 for float64
- *                             plans and for other tile edges; they take one
- *                             right-hand side per work-group.
+ *                             owns padded column c) and takes two nodes of
+ *                             one tile row at a time; no LDS accumulation,
+ *                             the waves' tiles are summed in a fixed order
+ *                             at the end; the window is evaluated per call
+ *                             as in mode 4. Resolved to 4 for float64 plans
+ *                             and other tile edges; one right-hand side per
+ *                             work-group.
  *                             Default 1; the row sweep wins with many
  *                             right-hand sides per call, and in float32
  *                             takes two of them per wave when

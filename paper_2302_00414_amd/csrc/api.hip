@@ -214,9 +214,9 @@ int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, in
   if (T < m) return fail(p, NFFT_EUNSUPPORTED, "tile edge %d < m = %d", T, m);
   const int K = out[NFFT_TUNE_ITEM_NODES];
   if (K < 16 || K > 65536) return fail(p, NFFT_EINVAL, "item nodes %d: expected 16..65536", K);
-  const int nt = out[NFFT_TUNE_SPREAD_THREADS];
-  if (nt != 64 && nt != 128 && nt != 256)
-    return fail(p, NFFT_EINVAL, "spread threads %d: expected 64, 128 or 256", nt);
+  int& nt = out[NFFT_TUNE_SPREAD_THREADS];
+  if (nt != 64 && nt != 128 && nt != 256 && nt != 512)
+    return fail(p, NFFT_EINVAL, "spread threads %d: expected 64, 128, 256 or 512", nt);
   const int nr = out[NFFT_TUNE_RHS_PER_GROUP];
   if (nr != 1 && nr != 2 && nr != 4 && nr != 8)
     return fail(p, NFFT_EINVAL, "rhs per group %d: expected 1, 2, 4 or 8", nr);
@@ -225,20 +225,22 @@ int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, in
   if (planes != 1 && planes != 2)
     return fail(p, NFFT_EINVAL, "spread planes %d: expected 1 or 2", planes);
   int& mode = out[NFFT_TUNE_SPREAD_MODE];
-  if (mode < 1 || mode > 6)
-    return fail(p, NFFT_EINVAL, "spread mode %d: expected 1 .. 6", mode);
+  if (mode < 1 || mode > 5)
+    return fail(p, NFFT_EINVAL, "spread mode %d: expected 1 .. 5", mode);
   if (mode == 2 && !nfft::spread_rows_supported(d, T + 2 * m)) mode = 1;
   // the register-tile kernel: float32, d = 2, tile edge 16; elsewhere the LDS
-  // kernel with the same window source
-  if ((mode == 5 || mode == 6) && !nfft::spread_reg_supported(d, T, precision == NFFT_F64))
-    mode = mode == 5 ? 4 : 3;
+  // kernel with the same window evaluation
+  if (mode == 5 && !nfft::spread_reg_supported(d, T, precision == NFFT_F64)) mode = 4;
   if ((mode == 3 || mode == 4) && d != 2) mode = 1;  // laid out for d = 2
+  // 512 threads: the register-tile kernel only
+  if (nt == 512 && mode != 5) nt = 256;
   const int fw = out[NFFT_TUNE_FFT_MIN_WG];
   if (fw < 1 || fw > 65536) return fail(p, NFFT_EINVAL, "fft min work-groups %d: expected 1..65536", fw);
   const int P = T + 2 * m;
   const int Ptot = (int)ipow(P, d);
   const bool f64 = precision == NFFT_F64;
-  const size_t one = nfft::spread_lds_bytes(d, f64, m, T, Ptot, nt, 1, planes);
+  const size_t one = mode == 5 ? nfft::spread_reg_lds_bytes(m)
+                                : nfft::spread_lds_bytes(d, f64, m, T, Ptot, nt, 1, planes);
   const size_t multi = out[NFFT_TUNE_RHS_PER_GROUP] > 1
                            ? nfft::spread_lds_bytes(d, f64, m, T, Ptot, nt,
                                                     out[NFFT_TUNE_RHS_PER_GROUP], planes)
@@ -446,7 +448,7 @@ void drop_psi(nfft_plan_t p) {
 }
 
 // Spread modes that read the window factor table.
-bool uses_psi(int mode) { return mode == 3 || mode == 6; }
+bool uses_psi(int mode) { return mode == 3; }
 
 int ensure_psi_any(nfft_plan_t p, hipStream_t s) {
   return p->prec == NFFT_F64 ? ensure_psi<double>(p, s) : ensure_psi<float>(p, s);
@@ -630,7 +632,17 @@ nfft::FftArgs<R> fft_args(nfft_plan_t p, int64_t nlines, const void* in, int64_t
   a.g = p->g;
   a.tilep = (const cplx<R>*)p->tilep;
   a.tile_bs = (int64_t)p->g.nbins * p->g.Ptot;
-  a.lpw = lines_per_wg<R>(p->Ms, nlines, p->tune[NFFT_TUNE_FFT_MIN_WG]);
+  const int min_wg = p->tune[NFFT_TUNE_FFT_MIN_WG];
+  a.lpw = lines_per_wg<R>(p->Ms, nlines, min_wg);
+  // one line per work-group and still few of them: more threads per line
+  // (ignored by the first adjoint pass, whose merge loader takes radix 8)
+  a.r0 = 8;
+  if (a.lpw == 1 && 2 * nlines <= min_wg)
+    a.r0 = 2;
+  else if (a.lpw == 1 && nlines < 2 * (int64_t)min_wg)
+    a.r0 = 4;
+  // at most 512 threads per work-group (the passes' launch bound)
+  while (a.r0 < 8 && p->Ms / a.r0 > 512) a.r0 *= 2;
   return a;
 }
 
@@ -1160,17 +1172,18 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
     return fail(nullptr, NFFT_EDEVICE, "hipMemsetAsync failed");
 
   std::vector<int> tiles, items = {128, 256, 512};
+  if (d == 2 && f32) items.push_back(1024);
   if (d == 1) tiles = {64, 128, 256};
   else if (d == 2) tiles = {8, 16, 32};
   else tiles = {8, 16};
   std::vector<int> threads = {0}, planes = {0}, rpg = {0}, modes = {0};
   if (d <= 2 && f32) {
-    threads = {64, 128, 256};
+    threads = {64, 128, 256, 512};
     planes = {1, 2};
   }
   if (d <= 2 && nrhs > 1) rpg = {1, 2, 4, 8};
   if (d == 2) modes = {1, 2, 3, 4};
-  if (d == 2 && f32) modes = {1, 2, 3, 4, 5, 6};
+  if (d == 2 && f32) modes = {1, 2, 3, 4, 5};
 
   nfft_plan_t best = nullptr;
   double best_t = -1.0;
@@ -1210,9 +1223,10 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
             if (md) in[NFFT_TUNE_SPREAD_MODE] = md;
             // the LDS kernel's shape does not matter when another kernel spreads
             if ((nr > 1 || md == 2) && (nt != threads[0] || pl != planes[0])) continue;
-            // the register-tile kernel (modes 5, 6) takes one rhs per work-group and
+            // the register-tile kernel (mode 5) takes one rhs per work-group and
             // no LDS tile layout
-            if (md >= 5 && (nr > 1 || pl != planes[0])) continue;
+            if (md == 5 && (nr > 1 || pl != planes[0])) continue;
+            if (nt == 512 && md < 5) continue;
             if (nr > 2 && md == 2) continue;  // the row sweep takes at most two rhs per wave
             if (uses_psi(md) && !have_psi) continue;
             if (md == 3 && nr > 1) continue;  // modes 3, 4: single rhs only

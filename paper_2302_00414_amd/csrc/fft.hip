@@ -363,55 +363,87 @@ __device__ __forceinline__ void store_elem(const FftArgs<R>& a, int b, int64_t q
   }
 }
 
-template <typename R, int LOG2L, bool INV, int LD, int ST>
+// Lines of a pass are dealt to work-groups so that consecutive lines land on
+// one XCD: work-groups are dispatched to the 8 XCDs in turn, so work-group
+// i runs on XCD i mod 8, and line block (i mod 8) * (n / 8) + i / 8 gives
+// each XCD a contiguous range of lines. The lines one XCD reads and the
+// output elements it writes (the transformed axis becomes the slowest, so
+// consecutive lines are consecutive outputs) then share that XCD's L2
+// instead of being split into partial cache lines between XCDs.
+__device__ __forceinline__ int64_t xcd_block(unsigned bx, unsigned nblk) {
+  if (nblk < 16 || (nblk & 7) != 0) return bx;
+  return (int64_t)(bx & 7) * (nblk >> 3) + (bx >> 3);
+}
+
+// First stage: radix R0 on elements loaded straight into registers (Ns = 1,
+// no twiddles); thread j of a line takes elements j + r L/R0. R0 = 8 (L/8
+// threads per line) is the default; 4 and 2 give a line more threads where a
+// pass has few lines.
+template <typename R, int LOG2L, bool INV, int LD, int ST, int R0>
 __global__ __launch_bounds__(512) void fft_pass_kernel(FftArgs<R> a) {
   constexpr int L = 1 << LOG2L;
-  constexpr int TPL = L / 8;  // threads per line (one radix-8 butterfly each)
+  constexpr int TPL = L / R0;  // threads per line (one radix-R0 butterfly each)
   constexpr int LS = L + L / 8 + 1;  // LDS line stride: padded line plus one slot
+  static_assert(R0 == 8 || LD != kLoadMerge, "the merge loader takes eight elements a thread");
   extern __shared__ unsigned char smem_raw[];
   const int lpw = a.lpw;      // blockDim.x == lpw * TPL
   cplx<R>* buf0 = reinterpret_cast<cplx<R>*>(smem_raw);
   cplx<R>* buf1 = buf0 + lpw * LS;
   const int64_t nlines = a.nlines;
-  const int64_t q0 = (int64_t)blockIdx.x * lpw;
+  const int64_t q0 = xcd_block(blockIdx.x, gridDim.x) * lpw;
   const int b = blockIdx.y;
 
-  // first radix-8 pass (Ns = 1, no twiddles) on elements loaded straight
-  // into registers: thread j of a line takes elements j + r L/8
   {
     const int l = threadIdx.x / TPL;
     const int j = threadIdx.x - l * TPL;
     const int64_t q = q0 + l;
-    cplx<R> v[8];
+    cplx<R> v[R0];
     bool per_line = false;
     if constexpr (LD == kLoadMerge)
       per_line = a.g.d >= 2 && a.g.T >= 2 * a.g.m && (TPL & (a.g.T - 1)) == 0;
-    if (q < nlines && per_line) {
-      if (a.g.d == 2)
-        merge_line<R, 2, TPL>(a, b, q, j, v);
-      else
-        merge_line<R, 3, TPL>(a, b, q, j, v);
-    } else if (q < nlines) {
+    if constexpr (LD == kLoadMerge) {
+      if (q < nlines && per_line) {
+        if (a.g.d == 2)
+          merge_line<R, 2, TPL>(a, b, q, j, v);
+        else
+          merge_line<R, 3, TPL>(a, b, q, j, v);
+      } else if (q < nlines) {
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = load_elem<R, LD>(a, b, q, j + r * TPL, L);
+        for (int r = 0; r < R0; ++r) v[r] = load_elem<R, LD>(a, b, q, j + r * TPL, L);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R0; ++r) v[r] = mkc<R>(0, 0);
+      }
     } else {
+      if (q < nlines) {
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = mkc<R>(0, 0);
+        for (int r = 0; r < R0; ++r) v[r] = load_elem<R, LD>(a, b, q, j + r * TPL, L);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R0; ++r) v[r] = mkc<R>(0, 0);
+      }
     }
-    dft8<R, INV>(v);
+    if constexpr (R0 == 8) {
+      dft8<R, INV>(v);
+    } else if constexpr (R0 == 4) {
+      dft4<R, INV>(v[0], v[1], v[2], v[3]);
+    } else {
+      dft2<R, INV>(v);
+    }
     cplx<R>* o = buf0 + l * LS;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) o[lpad(j * 8 + r)] = v[r];
+    for (int r = 0; r < R0; ++r) o[lpad(j * R0 + r)] = v[r];
   }
   __syncthreads();
 
   cplx<R>* src = buf0;
   cplx<R>* dst = buf1;
-  int Ns = 8;
-  constexpr int n8 = LOG2L / 3;
-  constexpr int rem = LOG2L % 3;
+  int Ns = R0;
+  constexpr int LOG2R0 = R0 == 8 ? 3 : (R0 == 4 ? 2 : 1);
+  constexpr int n8 = (LOG2L - LOG2R0) / 3;
+  constexpr int rem = (LOG2L - LOG2R0) % 3;
 #pragma unroll 1
-  for (int p = 1; p < n8; ++p) {
+  for (int p = 0; p < n8; ++p) {
     stockham_pass<R, 8, INV>(src, dst, L, LS, lpw, Ns, a.tw);
     __syncthreads();
     cplx<R>* t = src;
@@ -438,15 +470,32 @@ __global__ __launch_bounds__(512) void fft_pass_kernel(FftArgs<R> a) {
   }
 }
 
-template <typename R, int LOG2L, bool INV, int LD, int ST>
-static hipError_t fft_launch(const FftArgs<R>& a, int nbatch, hipStream_t s) {
+template <typename R, int LOG2L, bool INV, int LD, int ST, int R0>
+static hipError_t fft_launch_r0(const FftArgs<R>& a, int nbatch, hipStream_t s) {
   constexpr int L = 1 << LOG2L;
   const unsigned nblk = (unsigned)((a.nlines + a.lpw - 1) / a.lpw);
   const size_t lds = 2 * (size_t)a.lpw * (L + L / 8 + 1) * sizeof(cplx<R>);
-  const int threads = a.lpw * (L / 8);
-  hipLaunchKernelGGL((fft_pass_kernel<R, LOG2L, INV, LD, ST>), dim3(nblk, nbatch), dim3(threads),
-                     lds, s, a);
+  const int threads = a.lpw * (L / R0);
+  if (threads > 512) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((fft_pass_kernel<R, LOG2L, INV, LD, ST, R0>), dim3(nblk, nbatch),
+                     dim3(threads), lds, s, a);
   return hipGetLastError();
+}
+
+// A pass whose lines already go one per work-group and still give few
+// work-groups gets two or four times the threads per line (a.r0: first stage
+// radix 4 or 2); the merge loader keeps radix 8.
+template <typename R, int LOG2L, bool INV, int LD, int ST>
+static hipError_t fft_launch(const FftArgs<R>& a, int nbatch, hipStream_t s) {
+  constexpr int L = 1 << LOG2L;
+  // L / R0 threads per line, at most 512 (the launch bound)
+  if constexpr (LD != kLoadMerge && L >= 64 && L <= 1024) {
+    if (a.lpw == 1 && a.r0 == 2) return fft_launch_r0<R, LOG2L, INV, LD, ST, 2>(a, nbatch, s);
+  }
+  if constexpr (LD != kLoadMerge && L >= 64 && L <= 2048) {
+    if (a.lpw == 1 && a.r0 == 4) return fft_launch_r0<R, LOG2L, INV, LD, ST, 4>(a, nbatch, s);
+  }
+  return fft_launch_r0<R, LOG2L, INV, LD, ST, 8>(a, nbatch, s);
 }
 
 template <typename R, int LOG2L>

@@ -68,9 +68,8 @@ struct SpreadArgs {
   int mode;                  // d = 2 single rhs: 1 LDS tiles, 2 register row sweep,
                              // 3 LDS tiles with precomputed window factors,
                              // 4 LDS tiles with the window evaluated late,
-                             // 5 / 6 padded tile in registers, window evaluated
-                             // per call / precomputed (float32)
-  const R* psi;              // d = 2: window factors [N][2m][2] in tile order (modes 3, 6)
+                             // 5 padded tile in registers (float32)
+  const R* psi;              // d = 2: window factors [N][2m][2] in tile order (mode 3)
 };
 template <typename R>
 hipError_t launch_spread(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
@@ -88,10 +87,10 @@ hipError_t launch_spread_late(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
 // per-cell polynomials the spreading kernels evaluate (d = 2).
 template <typename R>
 hipError_t launch_psi(const R* frac, int64_t N, int m, const R* coef, R* psi, hipStream_t s);
-// Register-tile spreading (float32, d = 2, tile edge 16): the window
-// evaluated per call, or read from a.psi when it is set.
+// Register-tile spreading (float32, d = 2, tile edge 16, nodes row-sorted
+// within tiles).
 bool spread_reg_supported(int d, int T, bool f64);
-size_t spread_reg_lds_bytes(int m, int ws);
+size_t spread_reg_lds_bytes(int m);
 hipError_t launch_spread_reg(const SpreadArgs<float>& a, int nrhs, hipStream_t s);
 // Several right-hand sides per work-group (d <= 2, nr > 1).
 template <typename R>
@@ -159,6 +158,7 @@ struct FftArgs {
   const double* fac;   // deconvolution factors over I_M (compressed index), float64
   int accumulate;      // kStoreCropScaled: add to the output instead of writing it
   int lpw;             // lines per work-group
+  int r0;              // radix of the first stage (8, 4 or 2: L/r0 threads per line)
   Geom g;
 };
 template <typename R>

@@ -504,7 +504,7 @@ hipError_t launch_spread(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
   if (a.mode == 2 && spread_rows_supported(a.g.d, a.g.P)) return launch_spread_rows<R>(a, nrhs, s);
   if (a.nr > 1 && a.g.d <= 2) return launch_spread_multi<R>(a, nrhs, s);
   if constexpr (std::is_same<R, float>::value) {
-    if ((a.mode == 5 || a.mode == 6) && spread_reg_supported(a.g.d, a.g.T, false))
+    if (a.mode == 5 && spread_reg_supported(a.g.d, a.g.T, false))
       return launch_spread_reg(a, nrhs, s);
   }
   if (a.mode == 3 && a.psi && a.g.d == 2) return launch_spread_pre<R>(a, nrhs, s);

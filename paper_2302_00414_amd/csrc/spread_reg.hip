@@ -21,12 +21,10 @@
 // a fixed order (the result does not depend on timing) and the padded tile
 // is written out like the other kernels' (tile_reduce and the first FFT pass
 // merge them).
-//   WS = 2: the window factors are evaluated per call from the node's offsets
-//           (lane p of the half's first 16-lane row evaluates polynomial p at
-//           the dimension-0 offset, lane p of its second row at the
-//           dimension-1 offset; the factors reach their lanes by ds_bpermute);
-//   WS = 1: they are read from the plan's table of window factors (same
-//           polynomials, same values).
+// The window factors are evaluated per call from the node's offsets (lane p
+// of the half's first 16-lane row evaluates polynomial p at the dimension-0
+// offset, lane p of its second row at the dimension-1 offset; the factors
+// reach their lanes by ds_bpermute).
 // Nodes exactly on a grid line get the closed-edge row l0 / column l1.
 #include "spread_common.hpp"
 
@@ -74,20 +72,19 @@ __device__ __forceinline__ float lane_pick(float v, int src) {
 // Nodes staged per batch.
 constexpr int kRegBatch = 256;
 
-template <int MW, int WS>
+template <int MW>
 struct RegLds {
   static constexpr int K2 = 2 * MW;
   static constexpr int P = 16 + K2;
-  // staging: c_j (2 floats), cell word, and either the two offsets (WS = 2)
-  // or the node's 2m pairs of window factors (WS = 1); the first node of
-  // every tile row in the batch (17 entries)
-  static constexpr size_t per_node = 3 * 4 + (WS == 1 ? 2 * K2 * 4 : 2 * 4);
+  // staging: c_j (2 floats), cell word and the two offsets per node; the
+  // first node of every tile row in the batch (17 entries)
+  static constexpr size_t per_node = 3 * 4 + 2 * 4;
   static constexpr size_t staging = kRegBatch * per_node + 32 * 4;
   static constexpr size_t combine = 2 * (size_t)P * P * sizeof(float2);
   static constexpr size_t bytes = staging > combine ? staging : combine;
 };
 
-template <int MW, int NW, int WS>
+template <int MW, int NW>
 __global__ __launch_bounds__(64 * NW) void spread_reg_kernel(SpreadArgs<float> a) {
   constexpr int K2 = 2 * MW;
   constexpr int P = 16 + K2;
@@ -98,8 +95,8 @@ __global__ __launch_bounds__(64 * NW) void spread_reg_kernel(SpreadArgs<float> a
   float* st_cx = lds_f;
   float* st_cy = st_cx + NB;
   uint32_t* st_loc = reinterpret_cast<uint32_t*>(st_cy + NB);
-  float* st_w = reinterpret_cast<float*>(st_loc + NB);  // offsets [2][NB] or factors [NB][K2][2]
-  int* st_rs = reinterpret_cast<int*>(st_w + (WS == 1 ? NB * 2 * K2 : 2 * NB));  // row starts [17]
+  float* st_w = reinterpret_cast<float*>(st_loc + NB);  // offsets [2][NB]
+  int* st_rs = reinterpret_cast<int*>(st_w + 2 * NB);    // row starts [17]
 
   const int item = blockIdx.x;
   const int rhs = blockIdx.y;
@@ -115,10 +112,8 @@ __global__ __launch_bounds__(64 * NW) void spread_reg_kernel(SpreadArgs<float> a
   const int pc = p < K2 ? p : K2 - 1;
 
   float cf[DEG + 1];
-  if constexpr (WS == 2) {
 #pragma unroll
-    for (int q = 0; q <= DEG; ++q) cf[q] = a.coef[pc * (DEG + 1) + q];
-  }
+  for (int q = 0; q <= DEG; ++q) cf[q] = a.coef[pc * (DEG + 1) + q];
 
   float ar[P], ai[P];
 #pragma unroll
@@ -143,14 +138,8 @@ __global__ __launch_bounds__(64 * NW) void spread_reg_kernel(SpreadArgs<float> a
       st_cx[t] = wv.x * fv.x - wv.y * fv.y;
       st_cy[t] = wv.x * fv.y + wv.y * fv.x;
       st_loc[t] = a.loc[i];
-      if constexpr (WS == 2) {
-        st_w[t] = 2.0f * a.frac[i] - 1.0f;
-        st_w[NB + t] = 2.0f * a.frac[N + i] - 1.0f;
-      }
-    }
-    if constexpr (WS == 1) {
-      const float* src = a.psi + (int64_t)(start + b0) * (2 * K2);
-      for (int q = tid; q < nb * 2 * K2; q += NT) st_w[q] = src[q];
+      st_w[t] = 2.0f * a.frac[i] - 1.0f;
+      st_w[NB + t] = 2.0f * a.frac[N + i] - 1.0f;
     }
     __syncthreads();
     // first node of each tile row (the batch is sorted by row): node t opens
@@ -189,18 +178,11 @@ __global__ __launch_bounds__(64 * NW) void spread_reg_kernel(SpreadArgs<float> a
         const bool e0 = valid && ((L >> kEdgeShift) & 1u);
         const bool e1 = (L >> (kEdgeShift + 1)) & 1u;
         const int k = col - l1 - 1;  // footprint column of this lane
-        float av, bk;
-        if constexpr (WS == 2) {
-          // first row of the half: factor p of dimension 0; second row: of dimension 1
-          const float y = rowB ? st_w[NB + nn] : st_w[nn];
-          const float hv = horner<float>(cf, y);
-          av = lane_pick(hv, (lane & 32) | p);
-          bk = lane_pick(hv, (lane & 32) | 16 | (k & 15));
-        } else {
-          const float* qf = st_w + nn * (2 * K2);
-          av = qf[2 * pc];
-          bk = qf[2 * (k >= 0 && k < K2 ? k : 0) + 1];
-        }
+        // first row of the half: factor p of dimension 0; second row: of dimension 1
+        const float y = rowB ? st_w[NB + nn] : st_w[nn];
+        const float hv = horner<float>(cf, y);
+        const float av = lane_pick(hv, (lane & 32) | p);
+        const float bk = lane_pick(hv, (lane & 32) | 16 | (k & 15));
         const float bv = (k >= 0 && k < K2) ? bk : ((e1 && col == l1) ? edge : 0.0f);
         const float vx = bv * cx;
         const float vy = bv * cy;
@@ -251,11 +233,11 @@ __global__ __launch_bounds__(64 * NW) void spread_reg_kernel(SpreadArgs<float> a
 
 bool spread_reg_supported(int d, int T, bool f64) { return d == 2 && T == 16 && !f64; }
 
-size_t spread_reg_lds_bytes(int m, int ws) {
+size_t spread_reg_lds_bytes(int m) {
   switch (m) {
 #define NFFT_REG_LDS(MW) \
   case MW:               \
-    return ws == 1 ? RegLds<MW, 1>::bytes : RegLds<MW, 2>::bytes;
+    return RegLds<MW>::bytes;
     NFFT_REG_LDS(1) NFFT_REG_LDS(2) NFFT_REG_LDS(3) NFFT_REG_LDS(4)
     NFFT_REG_LDS(5) NFFT_REG_LDS(6) NFFT_REG_LDS(7) NFFT_REG_LDS(8)
 #undef NFFT_REG_LDS
@@ -263,25 +245,20 @@ size_t spread_reg_lds_bytes(int m, int ws) {
   }
 }
 
-template <int MW, int WS>
-static hipError_t spread_reg_ws(const SpreadArgs<float>& a, int nrhs, hipStream_t s) {
+template <int MW>
+static hipError_t spread_reg_m(const SpreadArgs<float>& a, int nrhs, hipStream_t s) {
   const dim3 grid(a.g.nsub, nrhs);
-  const size_t lds = RegLds<MW, WS>::bytes;
-  // 64 or 128 threads: two waves; 256: four
-  if (a.nt == 256)
-    hipLaunchKernelGGL((spread_reg_kernel<MW, 4, WS>), grid, dim3(256), lds, s, a);
+  const size_t lds = RegLds<MW>::bytes;
+  // 64 or 128 threads: two waves; 256: four; 512: eight
+  if (a.nt == 512)
+    hipLaunchKernelGGL((spread_reg_kernel<MW, 8>), grid, dim3(512), lds, s, a);
+  else if (a.nt == 256)
+    hipLaunchKernelGGL((spread_reg_kernel<MW, 4>), grid, dim3(256), lds, s, a);
   else
-    hipLaunchKernelGGL((spread_reg_kernel<MW, 2, WS>), grid, dim3(128), lds, s, a);
+    hipLaunchKernelGGL((spread_reg_kernel<MW, 2>), grid, dim3(128), lds, s, a);
   return hipGetLastError();
 }
 
-template <int MW>
-static hipError_t spread_reg_m(const SpreadArgs<float>& a, int nrhs, hipStream_t s) {
-  if (a.psi) return spread_reg_ws<MW, 1>(a, nrhs, s);
-  return spread_reg_ws<MW, 2>(a, nrhs, s);
-}
-
-// a.psi set: the table variant; otherwise the window is evaluated per call.
 hipError_t launch_spread_reg(const SpreadArgs<float>& a, int nrhs, hipStream_t s) {
   if (!spread_reg_supported(a.g.d, a.g.T, false)) return hipErrorInvalidValue;
   if (a.g.nsub == 0) return hipSuccess;

@@ -85,9 +85,11 @@ def test_f64_3d_large_m_unsupported():
     (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 70000], _lib.NFFT_EINVAL),  # fft min work-groups
     (2, 6, _lib.NFFT_F32, [-1], _lib.NFFT_EINVAL),                # negative entry
     (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 3], _lib.NFFT_EINVAL),  # spread planes not 1/2
-    (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 7], _lib.NFFT_EINVAL),  # spread mode not 1..6
+    (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 6], _lib.NFFT_EINVAL),  # spread mode not 1..5
     (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 5], _lib.NFFT_OK),   # padded tile in registers
-    (2, 6, _lib.NFFT_F64, [0, 0, 0, 0, 0, 0, 6], _lib.NFFT_OK),   # float64: resolved to mode 3
+    (2, 6, _lib.NFFT_F32, [0, 0, 512, 0, 0, 0, 5], _lib.NFFT_OK),  # eight waves a work-group
+    (2, 6, _lib.NFFT_F32, [0, 0, 512], _lib.NFFT_OK),             # LDS kernel: resolved to 256
+    (2, 6, _lib.NFFT_F64, [0, 0, 0, 0, 0, 0, 5], _lib.NFFT_OK),   # float64: resolved to mode 4
     (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 4], _lib.NFFT_OK),   # window evaluated late
     (2, 6, _lib.NFFT_F64, [0, 0, 0, 0, 0, 0, 3], _lib.NFFT_OK),   # precomputed window factors
     (3, 4, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 3], _lib.NFFT_OK),   # mode 3 resolves to 1 for d = 3

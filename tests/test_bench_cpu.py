@@ -34,9 +34,9 @@ def test_kernel_names_follow_the_tuning():
     assert bench.spread_kernel_name(dict(t, spread_mode=1, tile_edge=32)) == \
         "spread_group_kernel<float, 2, 6, 256, 0, true, 0>"
     assert bench.spread_kernel_name(dict(t, spread_mode=2)) == "spread_rows_kernel<float, 6, 16, 1>"
-    assert bench.spread_kernel_name(dict(t, spread_mode=5)) == "spread_reg_kernel<6, 4, 2>"
-    assert bench.spread_kernel_name(dict(t, spread_mode=6, spread_threads=128)) == \
-        "spread_reg_kernel<6, 2, 1>"
+    assert bench.spread_kernel_name(dict(t, spread_mode=5)) == "spread_reg_kernel<6, 4>"
+    assert bench.spread_kernel_name(dict(t, spread_mode=5, spread_threads=512)) == \
+        "spread_reg_kernel<6, 8>"
 
 
 def test_traffic_record_is_tied_to_the_sources():

@@ -86,14 +86,15 @@ TUNINGS = [
     {"spread_mode": 4, "tile_edge": 8, "item_nodes": 32, "spread_threads": 64},
     {"spread_mode": 5},
     {"spread_mode": 5, "spread_threads": 256, "item_nodes": 1000},
-    {"spread_mode": 6, "item_nodes": 32},
-    {"spread_mode": 6, "spread_threads": 256},
+    {"spread_mode": 5, "item_nodes": 32},
+    {"spread_mode": 5, "item_nodes": 2048},
     {"spread_mode": 5, "tile_edge": 8},   # register tiles need tile edge 16: mode 4
+    {"spread_mode": 5, "spread_threads": 512, "item_nodes": 1024},
 ]
 
-# modes the register-tile kernel resolves to where it does not apply
-# (float64, or a tile edge other than 16)
-REG_FALLBACK = {5: 4, 6: 3}
+# the mode the register-tile kernel resolves to where it does not apply
+# (float64, a tile edge other than 16)
+REG_FALLBACK = {5: 4}
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -115,9 +116,13 @@ def test_tunings_agree(tuning, prec):
         if k == "spread_mode" and v == 2 and tuning.get("tile_edge") == 32:
             assert got_t[k] == 1
             continue
-        if k == "spread_mode" and v in REG_FALLBACK and (prec == "f64" or
-                                                          tuning.get("tile_edge", 16) != 16):
+        reg = tuning.get("spread_mode") in REG_FALLBACK and prec == "f32" and \
+            tuning.get("tile_edge", 16) == 16
+        if k == "spread_mode" and v in REG_FALLBACK and not reg:
             assert got_t[k] == REG_FALLBACK[v], got_t
+            continue
+        if k == "spread_threads" and v == 512 and not reg:
+            assert got_t[k] == 256, got_t   # 512 threads: register tiles only
             continue
         assert got_t[k] == v, (k, got_t)
     p.set_weights(w)
@@ -262,21 +267,22 @@ def test_row_sweep_multi_rhs(prec, m, rpg):
 
 
 @pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6, 7, 8])
-@pytest.mark.parametrize("mode", [5, 6])
-@pytest.mark.parametrize("nt", [128, 256])
-def test_register_tile_spreading(m, mode, nt):
-    """Spread modes 5 and 6 (float32, d = 2, tile edge 16) keep the padded
-    tile in registers: against the oracle (O2) and against the LDS kernel of
-    mode 1 on the same plan (another summation order), for three right-hand
-    sides, with grid-aligned nodes (closed edge), a crowded cluster whose
-    tiles split into several work items, and work items longer than one
-    staged batch of 256 nodes."""
+@pytest.mark.parametrize("items", [600, 1024])
+@pytest.mark.parametrize("nt", [128, 256, 512])
+def test_register_tile_spreading(m, items, nt):
+    """Spread mode 5 (float32, d = 2, tile edge 16) keeps the padded tile in
+    registers: against the oracle (O2) and against the LDS kernel of mode 1
+    on the same plan (another summation order), for three right-hand sides,
+    with grid-aligned nodes (closed edge), a crowded cluster whose tiles split
+    into several work items, and work items longer than one staged batch of
+    256 nodes."""
+    mode = 5
     M = 32
     x = _nodes(2, M, 300 + m)
     N = x.shape[0]
     w = (1.0 + 0.3 * wl.complex_normal(N, 301)) / N
     F = wl.complex_normal((3, N), 302)
-    p = _plan(x, M, m, "f32", max_rhs=3, tuning={"item_nodes": 600})
+    p = _plan(x, M, m, "f32", max_rhs=3, tuning={"item_nodes": items})
     p.set_weights(w)
     a1 = _np(p.adjoint(torch.from_numpy(F)))
     p.set_tuning("spread_mode", mode)
