@@ -358,12 +358,16 @@ int nfft_weights_ex(int d, int M, double sigma, int m, int64_t N, const double *
  * the polynomials of degree M tell apart within one window support); it is
  * factorised again with 1e-12 |I_M| added to the diagonal, which reaches the
  * least-squares objective. Columns of up to about 190 nodes keep their Gram
- * triangle in LDS; larger ones, up to 4000 nodes, in a device-memory
- * workspace (at most 1 GiB, freed before the call returns).
+ * triangle in LDS; larger ones, up to 16000 nodes, keep it and their
+ * per-node arrays in a device-memory workspace of 8 (n^2/2 + 5.5 n) bytes
+ * for n nodes, largest columns first, in batches of at most 4 GiB (or one
+ * column), freed before the call returns; their Cholesky goes by panels of
+ * 32 columns. A column of n nodes costs about n^3 / 3 float64 operations on
+ * one work-group.
  *   nodes  the plan's nodes again, N*d float64 (host or device), same order
  *   info   host, 3 doubles, or NULL: largest column set, number of nonzeros,
  *          number of columns with singular normal equations
- * NFFT_EUNSUPPORTED if some column holds more than 4000 nodes (NFFT_ENOMEM
+ * NFFT_EUNSUPPORTED if some column holds more than 16000 nodes (NFFT_ENOMEM
  * if the workspace cannot be had); NFFT_ESTATE if already built.
  * Synchronises `stream`.
  */
@@ -372,7 +376,9 @@ int nfft_bopt_build(nfft_plan_t plan, const double *nodes, double *info, void *s
 /*
  * nfft_bopt_adjoint -- h_opt = D^* F^* B_opt^* f for nrhs right-hand sides
  * (Algorithm 4.4 step 1); f and fhat as for nfft_adjoint. NFFT_ESTATE before
- * nfft_bopt_build.
+ * nfft_bopt_build. The sparse product runs a group of lanes per grid column,
+ * 4 to 64 lanes sized at build time to the mean column length (the
+ * environment variable NFFT_BOPT_LANES, read by nfft_bopt_build, fixes it).
  */
 int nfft_bopt_adjoint(nfft_plan_t plan, const void *f, void *fhat, int nrhs, void *stream);
 
@@ -430,18 +436,20 @@ int nfft_plan_info(nfft_plan_t plan, int64_t *out, int n);
 int nfft_permutation(nfft_plan_t plan, int32_t *perm_host);
 
 /*
- * Stage timing. With profiling on, nfft_adjoint and nfft_forward record HIP
- * events on their stream around each kernel stage; nfft_stage_times waits for
- * them and returns, per stage, the accumulated milliseconds and the number of
- * calls since the last reset:
+ * Stage timing. With profiling on, nfft_adjoint, nfft_forward and
+ * nfft_bopt_adjoint record HIP events on their stream around each kernel
+ * stage; nfft_stage_times waits for them and returns, per stage, the
+ * accumulated milliseconds and the number of calls since the last reset:
  *   out[2*s] = milliseconds, out[2*s+1] = calls, for s = 0..NFFT_STAGES-1
  * Stages: 0 spreading (adjoint step 1), 1 sum of tiles split into several
  * work items, 2 first FFT pass with the merge of tile partials into grid
  * cells, 3 remaining FFT passes with deconvolution and crop (adjoint steps 2
  * and 3), 4 forward deconvolution, zero padding and FFT passes (Algorithm 2.1
- * steps 1-2), 5 forward window sums (Algorithm 2.1 step 3).
+ * steps 1-2), 5 forward window sums (Algorithm 2.1 step 3), 6 the sparse
+ * product B_opt^* f of nfft_bopt_adjoint (Algorithm 4.4 step 1), 7 its FFT
+ * passes with deconvolution and crop.
  */
-#define NFFT_STAGES 6
+#define NFFT_STAGES 8
 int nfft_set_profiling(nfft_plan_t plan, int enable);
 int nfft_stage_times(nfft_plan_t plan, double *out, int n, int reset);
 

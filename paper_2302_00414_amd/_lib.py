@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libnfft_mi355x.so")
 
 NFFT_OK, NFFT_EINVAL, NFFT_ENOMEM, NFFT_EDEVICE, NFFT_ESTATE, NFFT_EUNSUPPORTED = range(6)
 NFFT_F64, NFFT_F32 = 0, 1
-NFFT_STAGES = 6
+NFFT_STAGES = 8
 (NFFT_TUNE_TILE_EDGE, NFFT_TUNE_ITEM_NODES, NFFT_TUNE_SPREAD_THREADS, NFFT_TUNE_RHS_PER_GROUP,
  NFFT_TUNE_FFT_MIN_WG, NFFT_TUNE_SPREAD_PLANES, NFFT_TUNE_SPREAD_MODE) = range(7)
 NFFT_TUNE_COUNT = 7

@@ -52,7 +52,7 @@ thread_local std::string g_noplan_error;
 struct StageEvents {
   hipEvent_t ev[5];
   int n;       // events used
-  int kind;    // 0 adjoint, 1 forward
+  int kind;    // 0 adjoint, 1 forward, 2 adjoint with B_opt
 };
 
 // Device data that clones of a plan share: the sorted nodes, the weights, the
@@ -69,6 +69,7 @@ struct SharedData {
   void* bopt_val = nullptr;       // values (plan precision), by column
   int64_t bopt_nnz = 0;
   int bopt_nmax = 0;
+  int bopt_lanes = 64;            // lanes per column of the sparse product
   int32_t* bopt_lo = nullptr;     // first support cell per node and dimension (caller order)
   void* bopt_rows = nullptr;      // values by rows: N x (2m+1)^d in footprint order
   // window factors of every node (d = 2, spread mode 3), [N][2m][2] in tile order
@@ -160,7 +161,9 @@ int oversampled(int M, double sigma) {
 
 // Largest LDS a work-group may use on gfx950.
 constexpr size_t kMaxLds = 160 * 1024;
-constexpr int kMaxBoptColumn = 4000;  // nodes of one B_opt column (device-memory Gram triangle)
+// nodes of one B_opt column: a Cholesky of O(n^3) on one work-group with the
+// triangle in device memory (at 16000 nodes, 1 GiB per column)
+constexpr int kMaxBoptColumn = 16000;
 
 size_t cbytes(int prec) { return prec == NFFT_F64 ? 16 : 8; }
 size_t rbytes(int prec) { return prec == NFFT_F64 ? 8 : 4; }
@@ -764,9 +767,13 @@ int run_bopt_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStre
   // the deconvolution table divides by the window scaled by pi e^{-b m} in
   // every dimension
   const double scale = std::pow(M_PI * std::exp(-p->b * p->m), p->d);
+  StageEvents se{};
+  se.kind = 2;
+  record(p, se, s);
   HIP_TRY(p, nfft::launch_bopt_apply<R>(sd.bopt_ptr, sd.bopt_node, (const R*)sd.bopt_val,
                                         (const cplx<R>*)f, p->N, (cplx<R>*)p->grid, ncols,
-                                        ncols, nrhs, scale, s));
+                                        ncols, nrhs, scale, sd.bopt_lanes, s));
+  record(p, se, s);
   const int L = (int)Ms;
   const auto ld = nfft::kLoadLine;
   const auto st = nfft::kStoreCropScaled;
@@ -786,6 +793,8 @@ int run_bopt_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStre
     auto e = fft_args<R>(p, M * M, p->bufB, M * M * Ms, L, fhat, M * M * M);
     HIP_TRY(p, nfft::launch_fft_pass<R>(e, L, false, ld, st, nrhs, s));
   }
+  record(p, se, s);
+  if (p->profiling && se.n > 0) p->pending.push_back(se);
   return NFFT_OK;
 }
 
@@ -1473,22 +1482,36 @@ int nfft_bopt_build(nfft_plan_t p, const double* nodes, double* info, void* stre
     nmax = std::max(nmax, hc[c]);
   }
   // columns whose packed Gram triangle fits in LDS are solved there; larger
-  // ones (up to the LDS of their other per-node arrays) with the triangle in
-  // a device-memory workspace
-  int cap_lds = 1, cap_big = 1;
-  while (nfft::bopt_solve_lds(cap_lds + 1, true) <= kMaxLds) ++cap_lds;
-  while (nfft::bopt_solve_lds(cap_big + 1, false) <= kMaxLds && cap_big < kMaxBoptColumn) ++cap_big;
-  if (nmax > cap_big)
+  // ones with the triangle and their per-node arrays in a device-memory
+  // workspace
+  int cap_lds = 1;
+  while (nfft::bopt_solve_lds(cap_lds + 1) <= kMaxLds) ++cap_lds;
+  if (nmax > kMaxBoptColumn)
     return fail(p, NFFT_EUNSUPPORTED,
                 "a grid column is reached by %d nodes; the column solve takes at most %d", nmax,
-                cap_big);
-  std::vector<int64_t> big;  // columns solved with the triangle in device memory
-  int nbig = 0;
+                kMaxBoptColumn);
+  // columns solved in device memory, largest first, in batches whose
+  // workspaces together take at most kBoptBatchBytes (one column at least);
+  // off[i]: the i-th column's workspace offset (doubles) within its batch
+  std::vector<int64_t> big;
   for (int64_t c = 0; c < ncols; ++c)
-    if (hc[c] > cap_lds) {
-      big.push_back(c);
-      nbig = std::max(nbig, hc[c]);
+    if (hc[c] > cap_lds) big.push_back(c);
+  std::stable_sort(big.begin(), big.end(),
+                   [&](int64_t a, int64_t b) { return hc[a] > hc[b]; });
+  constexpr int64_t kBoptBatchBytes = int64_t(4) << 30;
+  std::vector<int64_t> off(big.size()), batch_start;
+  int64_t ws_doubles = 0;
+  for (size_t i = 0, used = 0; i < big.size(); ++i) {
+    const int64_t need = nfft::bopt_workspace_doubles(hc[big[i]]);
+    if (i == 0 || (int64_t)(used + need) * 8 > kBoptBatchBytes) {
+      batch_start.push_back((int64_t)i);
+      used = 0;
     }
+    off[i] = (int64_t)used;
+    used += need;
+    ws_doubles = std::max<int64_t>(ws_doubles, (int64_t)used);
+  }
+  batch_start.push_back((int64_t)big.size());
   const int64_t nnz = hp[ncols];
   const size_t rb = rbytes(p->prec);
   TRY(dalloc(p, &sd.bopt_ptr, (ncols + 1) * sizeof(int64_t)));
@@ -1510,31 +1533,31 @@ int nfft_bopt_build(nfft_plan_t p, const double* nodes, double* info, void* stre
   constexpr double kPivotRel = 1e-13;
   // ridge on the Gram diagonal (which is |I_M|) for rank-deficient columns
   const double ridge = 1e-12 * (double)ipow(M, d);
-  auto solve = [&](int64_t nc, int nm, const int64_t* cols, double* gA, int64_t stride) {
+  auto solve = [&](int64_t nc, int nm, const int64_t* cols, double* ws, const int64_t* ws_off) {
     return p->prec == NFFT_F64
                ? nfft::launch_bopt_solve<double>((const double*)d_nodes, d, M, Ms,
                                                  (const double*)wh, sd.bopt_ptr, sd.bopt_node,
                                                  (double*)sd.bopt_val, nc, nm, kPivotRel, ridge,
-                                                 (int*)dropped, cols, gA, stride, s)
+                                                 (int*)dropped, cols, ws, ws_off, s)
                : nfft::launch_bopt_solve<float>((const double*)d_nodes, d, M, Ms,
                                                 (const double*)wh, sd.bopt_ptr, sd.bopt_node,
                                                 (float*)sd.bopt_val, nc, nm, kPivotRel, ridge,
-                                                (int*)dropped, cols, gA, stride, s);
+                                                (int*)dropped, cols, ws, ws_off, s);
   };
-  HIP_TRY(p, solve(ncols, std::max(1, std::min(nmax, cap_lds)), nullptr, nullptr, 0));
+  HIP_TRY(p, solve(ncols, std::max(1, std::min(nmax, cap_lds)), nullptr, nullptr, nullptr));
   if (!big.empty()) {
-    // batches of work-groups whose triangles together take at most 1 GiB
-    const int64_t stride = (int64_t)nbig * (nbig + 1) / 2;
-    const int64_t batch = std::max<int64_t>(
-        1, std::min<int64_t>((int64_t)big.size(), (int64_t(1) << 30) / (stride * 8)));
-    void *d_cols, *ws;
+    void *d_cols, *d_off, *ws;
     TRY(talloc(&d_cols, big.size() * sizeof(int64_t)));
-    TRY(talloc(&ws, (size_t)batch * stride * sizeof(double)));
+    TRY(talloc(&d_off, big.size() * sizeof(int64_t)));
+    TRY(talloc(&ws, (size_t)ws_doubles * sizeof(double)));
     HIP_TRY(p, hipMemcpyAsync(d_cols, big.data(), big.size() * sizeof(int64_t),
                               hipMemcpyHostToDevice, s));
-    for (int64_t b0 = 0; b0 < (int64_t)big.size(); b0 += batch)
-      HIP_TRY(p, solve(std::min<int64_t>(batch, (int64_t)big.size() - b0), nbig,
-                       (const int64_t*)d_cols + b0, (double*)ws, stride));
+    HIP_TRY(p, hipMemcpyAsync(d_off, off.data(), off.size() * sizeof(int64_t),
+                              hipMemcpyHostToDevice, s));
+    for (size_t b = 0; b + 1 < batch_start.size(); ++b)
+      HIP_TRY(p, solve(batch_start[b + 1] - batch_start[b], kMaxBoptColumn,
+                       (const int64_t*)d_cols + batch_start[b], (double*)ws,
+                       (const int64_t*)d_off + batch_start[b]));
   }
   // the same values by rows, for the inverse adjoint of Remark 4.6
   const int64_t F = ipow(2 * m + 1, d);
@@ -1554,6 +1577,12 @@ int nfft_bopt_build(nfft_plan_t p, const double* nodes, double* info, void* stre
   sd.has_bopt = true;
   sd.bopt_nnz = nnz;
   sd.bopt_nmax = nmax;
+  // lanes per column of nfft_bopt_adjoint's sparse product: NFFT_BOPT_LANES
+  // (4, 8, 16, 32 or 64) if set, else sized to the mean column length
+  const int lanes = env_int("NFFT_BOPT_LANES", 0);
+  sd.bopt_lanes = (lanes >= 4 && lanes <= 64 && (lanes & (lanes - 1)) == 0)
+                      ? lanes
+                      : nfft::bopt_apply_lanes((double)nnz / (double)ncols);
   if (info) {
     info[0] = nmax;
     info[1] = (double)nnz;
@@ -1749,11 +1778,13 @@ int nfft_stage_times(nfft_plan_t p, double* out, int n, int reset) {
         p->stage_calls[i] += 1;
       }
     } else {
-      // forward: start, after FFT passes, after window sums
+      // forward: start, after FFT passes, after window sums;
+      // B_opt adjoint: start, after the sparse product, after FFT passes
+      const int base = se.kind == 1 ? 4 : 6;
       for (int i = 0; i + 1 < se.n && i < 2; ++i) {
         HIP_TRY(p, hipEventElapsedTime(&ms, se.ev[i], se.ev[i + 1]));
-        p->stage_ms[4 + i] += ms;
-        p->stage_calls[4 + i] += 1;
+        p->stage_ms[base + i] += ms;
+        p->stage_calls[base + i] += 1;
       }
     }
     for (int i = 0; i < se.n; ++i) p->event_pool.push_back(se.ev[i]);

@@ -170,20 +170,27 @@ hipError_t launch_fft_pass(const FftArgs<R>& a, int L, bool inverse, LoadMode ld
 hipError_t launch_bopt_pattern(const double* nodes, int64_t N, int d, int Ms, int m, int op,
                                int* count, const int64_t* col_ptr, int* fill, int32_t* col_node,
                                hipStream_t s);
-// LDS of one column solve for up to nmax nodes, the Gram triangle in LDS or not
-size_t bopt_solve_lds(int nmax, bool in_lds);
-// Column solves. cols null: columns 0..ncols-1 with the Gram triangle in LDS,
-// columns of more than nmax nodes skipped; cols set: the ncols columns listed,
-// each work-group's triangle at gA + i * gA_stride (device memory).
+// LDS of one column solve for up to nmax nodes with the Gram triangle and the
+// per-node arrays in LDS
+size_t bopt_solve_lds(int nmax);
+// doubles of the device-memory workspace of a column of n nodes
+int64_t bopt_workspace_doubles(int n);
+// Column solves. ws null: columns 0..ncols-1 (or the ncols listed in cols)
+// with everything in LDS, columns of more than nmax nodes skipped; ws set:
+// the ncols columns listed in cols, the i-th with its workspace at
+// ws + ws_off[i] (device memory), factorised by panels.
 template <typename R>
 hipError_t launch_bopt_solve(const double* nodes, int d, int M, int Ms, const double* wh,
                              const int64_t* col_ptr, int32_t* col_node, R* col_val, int64_t ncols,
                              int nmax, double piv_rel, double ridge, int* dropped,
-                             const int64_t* cols, double* gA, int64_t gA_stride, hipStream_t s);
+                             const int64_t* cols, double* ws, const int64_t* ws_off,
+                             hipStream_t s);
 template <typename R>
 hipError_t launch_bopt_apply(const int64_t* col_ptr, const int32_t* col_node, const R* col_val,
                              const cplx<R>* f, int64_t f_rs, cplx<R>* grid, int64_t g_rs,
-                             int64_t ncols, int nrhs, double scale, hipStream_t s);
+                             int64_t ncols, int nrhs, double scale, int lanes, hipStream_t s);
+// lanes per column of the apply (4..64) for columns of mean length avg
+int bopt_apply_lanes(double avg);
 
 hipError_t launch_bopt_lo(const double* nodes, int64_t N, int d, int Ms, int m, int32_t* lo,
                           hipStream_t s);

@@ -277,7 +277,7 @@ def nfft_set_profiling(plan, enable: bool) -> None:
 
 
 STAGE_NAMES = ("spread", "split_tile_reduce", "fft_merge", "fft_rest_deconv", "fwd_fft_deconv",
-               "fwd_sums")
+               "fwd_sums", "bopt_apply", "bopt_fft")
 
 
 def nfft_stage_times(plan, reset: bool = False) -> dict:

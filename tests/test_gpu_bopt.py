@@ -113,11 +113,11 @@ def test_states_and_limits():
     info = q.build_bopt(dense)
     assert info["max_column"] > 1000
     q.close()
-    denser = wl.uniform_nodes(80000, 2, 62)                         # ~5000 nodes per column
+    denser = wl.uniform_nodes(260000, 2, 62)                        # ~20000 nodes per column
     q = _plan(denser, 16, 2.0, 4, "f64")
     with pytest.raises(NfftError) as e:
         q.build_bopt(denser)
-    assert e.value.status == 5
+    assert e.value.status == 5                                      # above 16000: refused
     q.close()
 
 
@@ -215,9 +215,10 @@ def test_columns_beyond_lds_match_oracle():
     198 nodes) are solved with the triangle in device memory. Columns this
     full hold far more nodes than the degree-M polynomials can tell apart
     inside one window support, so their normal equations are rank deficient
-    and the values are not unique: the GPU's pivot-guarded Cholesky (dependent
-    nodes get 0) and the oracle's minimum-norm solve must reach the same
-    objective, and the pattern must agree. Columns of both kinds are sampled."""
+    and the values are not unique: the GPU's Cholesky with a ridge on the
+    diagonal of the singular normal equations and the oracle's minimum-norm
+    solve must reach the same objective, and the pattern must agree. Columns
+    of both kinds are sampled."""
     M, sigma, m = 32, 2.0, 4
     x = _patch_nodes()
     N = x.shape[0]
@@ -241,4 +242,35 @@ def test_columns_beyond_lds_match_oracle():
     got = p.bopt_adjoint(torch.from_numpy(f)).cpu().numpy()
     print("[reconstruction]", metrics.rel_err(got, fh), flush=True)
     assert metrics.rel_err(got, fh) <= 1e-2
+    p.close()
+
+
+def test_linogram_sigma1_columns_beyond_4000_nodes():
+    """Table 5.1's setting for Algorithm 4.4 (sigma = 1, m = 4) on the
+    linogram grid (5.4) with R = 2M, T = 2R at M = 64: the columns near the
+    origin hold up to 4352 nodes and every column more than fit in LDS. The
+    build succeeds with all columns in device memory (factorised by panels);
+    the two largest columns and six spread over the sizes reach the oracle's
+    objective (the columns are rank deficient, so values are not unique)."""
+    M, sigma, m = 64, 1.0, 4
+    x = wl.linogram_nodes(2 * M, 4 * M)
+    N = x.shape[0]
+    xw = ob._wrap(x)
+    p = _plan(x, M, sigma, m, "f64")
+    info = p.build_bopt(x)
+    print("[bopt]", info, flush=True)
+    assert info["max_column"] > 4000
+    G = _gpu_matrix(p, N).tocsc()
+    cnt = np.diff(G.indptr)
+    order = np.argsort(cnt, kind="stable")
+    big = order[::-1][:2]
+    spread = order[:: len(order) // 6][:6]
+    assert cnt[big].min() > 4000 and cnt.min() > 198
+    for c, (js, vals) in ob.bopt_columns(x, M, sigma, m, np.concatenate([big, spread])).items():
+        s, e = G.indptr[c], G.indptr[c + 1]
+        assert np.array_equal(G.indices[s:e], js), c
+        q_gpu, scale = _column_objective(xw, js, c, G.data[s:e], M, sigma, m)
+        q_orc, _ = _column_objective(xw, js, c, vals, M, sigma, m)
+        print(f"[column {c}] {cnt[c]} nodes: objective gpu {q_gpu:.6e} oracle {q_orc:.6e}", flush=True)
+        assert q_gpu - q_orc <= 1e-9 * scale, (c, cnt[c], q_gpu, q_orc, scale)
     p.close()
