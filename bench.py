@@ -497,6 +497,16 @@ def run_batched(steps, precs=("f32", "f64"), tuning="auto"):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         res[prec] = dict(ms_per_32_rhs=ms, points_per_s=N * R / (ms / 1e3), tuning=plan.tuning())
+        if nrhs == R:
+            # stage split of the fused call from the library's own events
+            plan.set_profiling(True)
+            plan.stage_times(reset=True)
+            for _ in range(steps):
+                calls()
+            torch.cuda.synchronize()
+            plan.set_profiling(False)
+            st = plan.stage_times(reset=True)
+            res[prec]["stage_us"] = {k: round(1e3 * v[0] / v[1], 2) for k, v in st.items() if v[1]}
         plan.close()
     if len(res) < 2:
         return dict(workload="spiral N=131072, d=2, M=256, sigma=2, m=6, 32 rhs, area weights", **res)

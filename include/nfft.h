@@ -146,6 +146,19 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
  *                             as in mode 4. Resolved to 4 for float64 plans
  *                             and other tile edges; one right-hand side per
  *                             work-group.
+ *                             6 = float32, d = 2, tile edge 16, m <= 8, for
+ *                             many right-hand sides: a work-group owns one
+ *                             16 x 16 tile of the grid and 32 right-hand
+ *                             sides (lane r + 32 c: component c of
+ *                             right-hand side r), visits the nodes of that
+ *                             tile and of its eight neighbours whose window
+ *                             reaches it, and sums every grid cell in one
+ *                             float32 register in a fixed node order; the
+ *                             grid is written once, so there are no tile
+ *                             partials, split-tile sums or halo merges.
+ *                             Ignores the thread count, planes and
+ *                             right-hand sides per group. Resolved to 5 (and
+ *                             so on) where not supported.
  *                             Default 1; the row sweep wins with many
  *                             right-hand sides per call, and in float32
  *                             takes two of them per wave when

@@ -74,6 +74,16 @@ struct SharedData {
   void* bopt_rows = nullptr;      // values by rows: N x (2m+1)^d in footprint order
   // window factors of every node (d = 2, spread mode 3), [N][2m][2] in tile order
   void* psi = nullptr;
+  // first node of every tile (tile order), nbins + 1, on the host
+  std::vector<int32_t> hbin_start;
+  // spread mode 6: per-tile lists of the nodes that reach the tile, the work
+  // units over them and the tiles cut into several units (nfft::GatherArgs)
+  int32_t* gl_node = nullptr;
+  int32_t* gl_hdr = nullptr;
+  int32_t* g_units = nullptr;
+  int32_t* g_split = nullptr;
+  int g_nunits = 0, g_nsplit = 0, g_nslots = 0;
+  int64_t g_bytes = 0;
   ~SharedData() {
     for (void* q : allocs) (void)hipFree(q);
   }
@@ -106,6 +116,8 @@ struct nfft_plan_s {
   int nmulti = 0;
   int nslots = 0;                  // itemp slots
   int32_t* empty_bins = nullptr;   // tiles without nodes (their slots are never written)
+  void* gpart = nullptr;           // spread mode 6 partials [max_rhs][slot][256]
+  void* gft = nullptr;             // spread mode 6 node-major samples [groups of 32][N][32]
   int nempty = 0;
   void* tilep = nullptr;           // tile partials [rhs][tile][P^d]
   void* itemp = nullptr;           // item partials of split tiles [rhs][slot][P^d]
@@ -228,8 +240,11 @@ int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, in
   if (planes != 1 && planes != 2)
     return fail(p, NFFT_EINVAL, "spread planes %d: expected 1 or 2", planes);
   int& mode = out[NFFT_TUNE_SPREAD_MODE];
-  if (mode < 1 || mode > 5)
-    return fail(p, NFFT_EINVAL, "spread mode %d: expected 1 .. 5", mode);
+  if (mode < 1 || mode > 6)
+    return fail(p, NFFT_EINVAL, "spread mode %d: expected 1 .. 6", mode);
+  // the grid-tile gather: float32, d = 2, tile edge 16, m <= 8; elsewhere
+  // the register-tile kernel (and its own fallback)
+  if (mode == 6 && !nfft::spread_gather_supported(d, T, precision == NFFT_F64, m)) mode = 5;
   if (mode == 2 && !nfft::spread_rows_supported(d, T + 2 * m)) mode = 1;
   // the register-tile kernel: float32, d = 2, tile edge 16; elsewhere the LDS
   // kernel with the same window evaluation
@@ -242,8 +257,9 @@ int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, in
   const int P = T + 2 * m;
   const int Ptot = (int)ipow(P, d);
   const bool f64 = precision == NFFT_F64;
-  const size_t one = mode == 5 ? nfft::spread_reg_lds_bytes(m)
-                                : nfft::spread_lds_bytes(d, f64, m, T, Ptot, nt, 1, planes);
+  const size_t one = mode == 6   ? nfft::spread_gather_lds_bytes(m)
+                     : mode == 5 ? nfft::spread_reg_lds_bytes(m)
+                                 : nfft::spread_lds_bytes(d, f64, m, T, Ptot, nt, 1, planes);
   const size_t multi = out[NFFT_TUNE_RHS_PER_GROUP] > 1
                            ? nfft::spread_lds_bytes(d, f64, m, T, Ptot, nt,
                                                     out[NFFT_TUNE_RHS_PER_GROUP], planes)
@@ -410,6 +426,8 @@ int build_tables(nfft_plan_t p) {
 
 // Per-handle workspace for max_rhs right-hand sides: tile and item partials,
 // FFT buffers and the forward grid.
+int ensure_gather_part(nfft_plan_t p);
+
 template <typename R>
 int alloc_workspace(nfft_plan_t p, hipStream_t s) {
   const Geom& g = p->g;
@@ -424,6 +442,8 @@ int alloc_workspace(nfft_plan_t p, hipStream_t s) {
   if (d >= 2) TRY(dalloc(p, &p->bufA, (size_t)R_ * ipow(Ms, d - 1) * M * sizeof(cplx<R>), false));
   if (d == 3) TRY(dalloc(p, &p->bufB, (size_t)R_ * Ms * M * M * sizeof(cplx<R>), false));
   TRY(dalloc(p, &p->grid, (size_t)R_ * ipow(Ms, d) * sizeof(cplx<R>), false));
+  p->gpart = p->gft = nullptr;
+  TRY(ensure_gather_part(p));  // a clone of a plan with the gather tables
   return NFFT_OK;
 }
 
@@ -455,6 +475,167 @@ bool uses_psi(int mode) { return mode == 3; }
 
 int ensure_psi_any(nfft_plan_t p, hipStream_t s) {
   return p->prec == NFFT_F64 ? ensure_psi<double>(p, s) : ensure_psi<float>(p, s);
+}
+
+bool gather_supported(nfft_plan_t p) {
+  return nfft::spread_gather_supported(p->d, p->g.T, p->prec == NFFT_F64, p->m);
+}
+
+// Samples of spread mode 6 copied node-major: groups of 32 right-hand sides.
+size_t gather_ft_bytes(int64_t N, int nrhs) {
+  return (size_t)((nrhs + 31) / 32) * 32 * N * sizeof(float2);
+}
+
+// This handle's partial slots and node-major samples of spread mode 6
+// (max_rhs right-hand sides).
+int ensure_gather_part(nfft_plan_t p) {
+  const SharedData& sd = *p->shared;
+  if (!sd.g_units) return NFFT_OK;
+  if (!p->gft) TRY(dalloc(p, &p->gft, gather_ft_bytes(p->N, p->max_rhs), false));
+  if (sd.g_nslots == 0 || p->gpart) return NFFT_OK;
+  return dalloc(p, &p->gpart, (size_t)p->max_rhs * sd.g_nslots * 256 * sizeof(float2), false);
+}
+
+// Spread mode 6 tables, built once per node set from the sorted cell words:
+// for every tile the nodes of the 3 x 3 tiles around it whose closed window
+// support reaches it, with the footprint origin relative to the tile, sorted
+// by the footprint's column offset (source tiles in row order and nodes in
+// tile order within one offset); the units cut each tile's list into runs
+// of at most item_nodes entries.
+int ensure_gather(nfft_plan_t p, hipStream_t s) {
+  if (!gather_supported(p)) return NFFT_OK;
+  SharedData& sd = *p->shared;
+  if (!sd.g_units) {
+    const Geom& g = p->g;
+    const int64_t N = p->N;
+    const int nb = g.nb, m = p->m, ntiles = g.nbins;
+    std::vector<uint32_t> hloc(N);
+    HIP_TRY(p, hipMemcpyAsync(hloc.data(), p->loc, N * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(p, hipStreamSynchronize(s));
+    const std::vector<int32_t>& bs = sd.hbin_start;
+    std::vector<int64_t> start(ntiles + 1, 0);
+    std::vector<int32_t> node, hdr;
+    for (int pass = 0; pass < 2; ++pass) {
+      if (pass) {
+        node.resize(start[ntiles]);
+        hdr.resize(start[ntiles]);
+      }
+      for (int t = 0; t < ntiles; ++t) {
+        const int t0 = t / nb, t1 = t % nb;
+        int64_t pos = pass ? start[t] : 0;
+        for (int ds0 = -1; ds0 <= 1; ++ds0)
+          for (int ds1 = -1; ds1 <= 1; ++ds1) {
+            const int S = ((t0 + ds0 + nb) % nb) * nb + (t1 + ds1 + nb) % nb;
+            for (int32_t i = bs[S]; i < bs[S + 1]; ++i) {
+              const uint32_t L = hloc[i];
+              const int b0 = 16 * ds0 - m + (int)(L & nfft::kLocMask);
+              const int b1 = 16 * ds1 - m + (int)((L >> nfft::kLocBits) & nfft::kLocMask);
+              const int e0 = (int)((L >> nfft::kEdgeShift) & 1u);
+              const int e1 = (int)((L >> (nfft::kEdgeShift + 1)) & 1u);
+              if (b0 + (1 - e0) > 15 || b0 + 2 * m < 0 || b1 + (1 - e1) > 15 || b1 + 2 * m < 0)
+                continue;
+              if (pass) {
+                node[pos] = i;
+                hdr[pos] = (b0 + 64) | ((b1 + 64) << 8) | (e0 << 16) | (e1 << 17);
+              }
+              ++pos;
+            }
+          }
+        if (!pass) {
+          start[t + 1] = start[t] + pos;
+          continue;
+        }
+        // by the column offset of the footprint (bits 8-15), in source and
+        // node order within one offset: the kernel takes each offset in turn
+        std::vector<int64_t> ix(start[t + 1] - start[t]);
+        std::iota(ix.begin(), ix.end(), start[t]);
+        std::stable_sort(ix.begin(), ix.end(), [&](int64_t u, int64_t v) {
+          return ((hdr[u] >> 8) & 0xff) < ((hdr[v] >> 8) & 0xff);
+        });
+        std::vector<int32_t> tn(ix.size()), th(ix.size());
+        for (size_t q = 0; q < ix.size(); ++q) {
+          tn[q] = node[ix[q]];
+          th[q] = hdr[ix[q]];
+        }
+        std::copy(tn.begin(), tn.end(), node.begin() + start[t]);
+        std::copy(th.begin(), th.end(), hdr.begin() + start[t]);
+      }
+    }
+    if (start[ntiles] > INT32_MAX)
+      return fail(p, NFFT_EUNSUPPORTED, "spread mode 6: %lld list entries exceed int32",
+                  (long long)start[ntiles]);
+    const int C = p->tune[NFFT_TUNE_ITEM_NODES];
+    std::vector<int32_t> units, split;
+    int nslots = 0;
+    for (int t = 0; t < ntiles; ++t) {
+      const int64_t n = start[t + 1] - start[t];
+      const int64_t k = std::max<int64_t>(1, (n + C - 1) / C);
+      if (k > 1) split.insert(split.end(), {t, nslots, (int32_t)k, 0});
+      for (int64_t j = 0; j < k; ++j)
+        units.insert(units.end(), {t, (int32_t)(start[t] + j * n / k),
+                                   (int32_t)(start[t] + (j + 1) * n / k),
+                                   k > 1 ? nslots++ : -1});
+    }
+    // launch order: longest units first (the crowded tiles' units start
+    // before the many short ones that fill in behind them)
+    const int nu = (int)(units.size() / 4), n8 = (nu + 7) / 8;
+    std::vector<int> byLen(nu);
+    std::iota(byLen.begin(), byLen.end(), 0);
+    std::stable_sort(byLen.begin(), byLen.end(), [&](int x, int y) {
+      return units[4 * x + 2] - units[4 * x + 1] > units[4 * y + 2] - units[4 * y + 1];
+    });
+    std::vector<int32_t> order(4 * 8 * (size_t)n8, -1);
+    for (int u = 0; u < nu; ++u)
+      std::copy(units.begin() + 4 * byLen[u], units.begin() + 4 * byLen[u] + 4,
+                order.begin() + 4 * u);
+    const size_t ne = std::max<size_t>(1, node.size());
+    const int64_t bytes0 = sd.bytes;
+    TRY(dalloc(p, &sd.gl_node, ne * sizeof(int32_t)));
+    TRY(dalloc(p, &sd.gl_hdr, ne * sizeof(int32_t)));
+    TRY(dalloc(p, &sd.g_units, order.size() * sizeof(int32_t)));
+    TRY(dalloc(p, &sd.g_split, std::max<size_t>(4, split.size()) * sizeof(int32_t)));
+    if (!node.empty()) {
+      HIP_TRY(p, hipMemcpyAsync(sd.gl_node, node.data(), node.size() * 4, hipMemcpyHostToDevice, s));
+      HIP_TRY(p, hipMemcpyAsync(sd.gl_hdr, hdr.data(), hdr.size() * 4, hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(p, hipMemcpyAsync(sd.g_units, order.data(), order.size() * 4, hipMemcpyHostToDevice, s));
+    if (!split.empty())
+      HIP_TRY(p, hipMemcpyAsync(sd.g_split, split.data(), split.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(p, hipStreamSynchronize(s));  // the host vectors go out of scope
+    sd.g_nunits = 8 * n8;
+    sd.g_nsplit = (int)(split.size() / 4);
+    sd.g_nslots = nslots;
+    sd.g_bytes = sd.bytes - bytes0;
+  }
+  return ensure_gather_part(p);
+}
+
+// Free the mode 6 tables and this handle's partials (nothing may still read
+// them; the handle must be the only one referring to the tables).
+void drop_gather(nfft_plan_t p) {
+  SharedData& sd = *p->shared;
+  auto release = [](std::vector<void*>& v, void* q) {
+    auto it = std::find(v.begin(), v.end(), q);
+    if (it != v.end()) v.erase(it);
+    (void)hipFree(q);
+  };
+  if (p->gpart) {
+    release(p->allocs, p->gpart);
+    p->bytes -= (int64_t)((size_t)p->max_rhs * sd.g_nslots * 256 * sizeof(float2));
+    p->gpart = nullptr;
+  }
+  if (p->gft) {
+    release(p->allocs, p->gft);
+    p->bytes -= (int64_t)gather_ft_bytes(p->N, p->max_rhs);
+    p->gft = nullptr;
+  }
+  if (!sd.g_units) return;
+  for (void* q : {(void*)sd.gl_node, (void*)sd.gl_hdr, (void*)sd.g_units, (void*)sd.g_split})
+    release(sd.allocs, q);
+  sd.bytes -= sd.g_bytes;
+  sd.gl_node = sd.gl_hdr = sd.g_units = sd.g_split = nullptr;
+  sd.g_nunits = sd.g_nsplit = sd.g_nslots = 0;
+  sd.g_bytes = 0;
 }
 
 template <typename R>
@@ -553,6 +734,7 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
   }
   HIP_TRY(p, hipMemcpyAsync(bstart, hstart.data(), (g.nbins + 1) * sizeof(int32_t),
                             hipMemcpyHostToDevice, s));
+  p->shared->hbin_start = hstart;
 
   HIP_TRY(p, nfft::launch_rank((const int32_t*)bin, N, g.nbins, (int32_t*)rank,
                                (int32_t*)chunk_count, s));
@@ -605,6 +787,7 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
   TRY(alloc_workspace<R>(p, s));
   TRY(build_tables<R>(p));
   if (uses_psi(p->tune[NFFT_TUNE_SPREAD_MODE])) TRY(ensure_psi<R>(p, s));
+  if (p->tune[NFFT_TUNE_SPREAD_MODE] == 6) TRY(ensure_gather(p, s));
   HIP_TRY(p, hipStreamSynchronize(s));
   return NFFT_OK;
 }
@@ -663,12 +846,15 @@ void record(nfft_plan_t p, StageEvents& se, hipStream_t s) {
 }
 
 // Intermediate buffers of one adjoint: tile partials, item partials of split
-// tiles, FFT buffers.
+// tiles, FFT buffers, and the grid and unit partials of spread mode 6.
 struct Work {
   void* tilep;
   void* itemp;
   void* bufA;
   void* bufB;
+  void* grid;
+  void* gpart;
+  void* gft;
 };
 
 // With accumulate, the last FFT pass adds its outputs to fhat instead of
@@ -679,7 +865,7 @@ int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t 
                 bool accumulate = false, const Work* wk = nullptr) {
   const Geom& g = p->g;
   const int64_t Ms = p->Ms, M = p->M;
-  const Work own{p->tilep, p->itemp, p->bufA, p->bufB};
+  const Work own{p->tilep, p->itemp, p->bufA, p->bufB, p->grid, p->gpart, p->gft};
   const Work& w = wk ? *wk : own;
   const bool prof = p->profiling && !wk;
   StageEvents se{};
@@ -708,6 +894,44 @@ int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t 
   sa.planes = p->tune[NFFT_TUNE_SPREAD_PLANES];
   sa.mode = p->tune[NFFT_TUNE_SPREAD_MODE];
   sa.psi = uses_psi(sa.mode) ? (const R*)p->shared->psi : nullptr;
+  if constexpr (std::is_same<R, float>::value) {
+    if (sa.mode == 6) {
+      // the grid of every right-hand side from the per-tile lists; the
+      // partials of the tiles cut into several units are summed into it (the
+      // split-tile stage), and the first FFT pass reads plain lines
+      const SharedData& sd = *p->shared;
+      if (!sd.g_units || (sd.g_nslots > 0 && !w.gpart) || !w.gft)
+        return fail(p, NFFT_ESTATE, "spread mode 6 tables are missing");
+      nfft::GatherArgs ga{};
+      ga.units = sd.g_units;
+      ga.nunits = sd.g_nunits;
+      ga.gl_node = sd.gl_node;
+      ga.gl_hdr = sd.gl_hdr;
+      ga.split = sd.g_split;
+      ga.nsplit = sd.g_nsplit;
+      ga.grid = (float2*)w.grid;
+      ga.grid_rs = Ms * Ms;
+      ga.part = (float2*)w.gpart;
+      ga.part_rs = (int64_t)sd.g_nslots * 256;
+      ga.fT = (float2*)w.gft;
+      HIP_TRY(p, nfft::launch_spread_gather(sa, ga, nrhs, s));
+      if (prof) record(p, se, s);
+      HIP_TRY(p, nfft::launch_gather_reduce(ga, g.nb, (int)Ms, nrhs, s));
+      if (prof) record(p, se, s);
+      const int L = (int)Ms;
+      auto a = fft_args<R>(p, Ms, w.grid, Ms * Ms, L, w.bufA, M * Ms);
+      HIP_TRY(p, nfft::launch_fft_pass<R>(a, L, false, nfft::kLoadLine, nfft::kStoreCropScaled,
+                                          nrhs, s));
+      if (prof) record(p, se, s);
+      auto c = fft_args<R>(p, M, w.bufA, M * Ms, L, fhat, M * M);
+      c.accumulate = accumulate;
+      HIP_TRY(p, nfft::launch_fft_pass<R>(c, L, false, nfft::kLoadLine, nfft::kStoreCropScaled,
+                                          nrhs, s));
+      if (prof) record(p, se, s);
+      if (prof && se.n > 0) p->pending.push_back(se);
+      return NFFT_OK;
+    }
+  }
   HIP_TRY(p, nfft::launch_spread<R>(sa, nrhs, s));
   if (prof) record(p, se, s);
   nfft::ReduceArgs<R> ra{};
@@ -992,7 +1216,11 @@ int run_adjoint_scratch(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipS
   const size_t item = align256((size_t)nrhs * std::max(1, p->nslots) * g.Ptot * cb);
   const size_t bufA = p->d >= 2 ? align256((size_t)nrhs * ipow(Ms, p->d - 1) * M * cb) : 0;
   const size_t bufB = p->d == 3 ? align256((size_t)nrhs * Ms * M * M * cb) : 0;
-  const size_t need = tile + item + bufA + bufB;
+  const bool gather = p->tune[NFFT_TUNE_SPREAD_MODE] == 6;
+  const size_t gpart =
+      gather ? align256((size_t)nrhs * p->shared->g_nslots * 256 * sizeof(float2)) : 0;
+  const size_t gft = gather ? align256(gather_ft_bytes(p->N, nrhs)) : 0;
+  const size_t need = tile + item + bufA + bufB + gpart + gft;
   if (need > kScratchBytes)
     return fail(p, NFFT_EUNSUPPORTED,
                 "this adjoint needs %zu bytes of intermediate buffers; the library's scratch "
@@ -1000,8 +1228,12 @@ int run_adjoint_scratch(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipS
   void* base = nullptr;
   TRY(scratch_address(p, p->device, &base));
   unsigned char* b = static_cast<unsigned char*>(base);
+  // spread mode 6 writes its grid (nrhs * Ms^d cells, fewer than the tile
+  // partials') where the tile partials would be
   const Work wk{b, b + tile, bufA ? b + tile + item : nullptr,
-                bufB ? b + tile + item + bufA : nullptr};
+                bufB ? b + tile + item + bufA : nullptr, b,
+                gpart ? b + tile + item + bufA + bufB : nullptr,
+                gft ? b + tile + item + bufA + bufB + gpart : nullptr};
   // the slots of tiles without nodes are read as zeros and written by no
   // work item; the previous call left its own data there
   HIP_TRY(p, nfft::launch_zero_tiles<R>((cplx<R>*)wk.tilep, (int64_t)g.nbins * g.Ptot,
@@ -1193,6 +1425,8 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
   if (d <= 2 && nrhs > 1) rpg = {1, 2, 4, 8};
   if (d == 2) modes = {1, 2, 3, 4};
   if (d == 2 && f32) modes = {1, 2, 3, 4, 5};
+  // the grid-tile gather holds 32 right-hand sides in the lanes of a wave
+  if (d == 2 && f32 && nrhs >= 8) modes.push_back(6);
 
   nfft_plan_t best = nullptr;
   double best_t = -1.0;
@@ -1220,6 +1454,10 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
       bool mine = false;  // p is (or became) the best plan
       // the factor table of mode 3; without room for it mode 3 is skipped
       const bool have_psi = d == 2 && ensure_psi_any(p, s) == NFFT_OK;
+      // the node lists of mode 6, likewise
+      const bool have_gather = gather_supported(p) &&
+                               std::find(modes.begin(), modes.end(), 6) != modes.end() &&
+                               ensure_gather(p, s) == NFFT_OK && p->shared->g_units;
       for (int md : modes)
       for (int nt : threads)
         for (int pl : planes)
@@ -1235,9 +1473,12 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
             // the register-tile kernel (mode 5) takes one rhs per work-group and
             // no LDS tile layout
             if (md == 5 && (nr > 1 || pl != planes[0])) continue;
+            // the gather (mode 6) has one shape
+            if (md == 6 && (nr > 1 || pl != planes[0] || nt != threads[0])) continue;
             if (nt == 512 && md < 5) continue;
             if (nr > 2 && md == 2) continue;  // the row sweep takes at most two rhs per wave
             if (uses_psi(md) && !have_psi) continue;
+            if (md == 6 && !have_gather) continue;
             if (md == 3 && nr > 1) continue;  // modes 3, 4: single rhs only
             if (md == 4 && nr > 1) continue;
             int res[NFFT_TUNE_COUNT];
@@ -1281,6 +1522,7 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
     return fail(nullptr, NFFT_EDEVICE, "device failure while timing candidates");
   }
   if (!uses_psi(best->tune[NFFT_TUNE_SPREAD_MODE])) drop_psi(best);
+  if (best->tune[NFFT_TUNE_SPREAD_MODE] != 6) drop_gather(best);
   best->shared->has_weights = false;
   if (best_ms) *best_ms = best_t;
   *out = best;
@@ -1660,6 +1902,11 @@ int nfft_set_tuning(nfft_plan_t p, int knob, int value) {
   if (uses_psi(out[NFFT_TUNE_SPREAD_MODE]) && !p->shared->psi) {
     // the factor table is built once, on the null stream, before the switch
     TRY(ensure_psi_any(p, nullptr));
+    HIP_TRY(p, hipStreamSynchronize(nullptr));
+  }
+  if (out[NFFT_TUNE_SPREAD_MODE] == 6) {
+    // likewise the node lists of the gather and this handle's partials
+    TRY(ensure_gather(p, nullptr));
     HIP_TRY(p, hipStreamSynchronize(nullptr));
   }
   std::copy(out, out + NFFT_TUNE_COUNT, p->tune);

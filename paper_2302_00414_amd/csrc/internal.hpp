@@ -68,11 +68,38 @@ struct SpreadArgs {
   int mode;                  // d = 2 single rhs: 1 LDS tiles, 2 register row sweep,
                              // 3 LDS tiles with precomputed window factors,
                              // 4 LDS tiles with the window evaluated late,
-                             // 5 padded tile in registers (float32)
+                             // 5 padded tile in registers (float32),
+                             // 6 grid tiles gathered for 32 rhs per work-group
+                             //   (float32; see launch_spread_gather)
   const R* psi;              // d = 2: window factors [N][2m][2] in tile order (mode 3)
 };
 template <typename R>
 hipError_t launch_spread(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
+// Spreading by output tiles for 32 right-hand sides per work-group (d = 2,
+// float32, tile edge 16, m <= 8) into the grid [rhs][Ms^2]. Per tile the plan
+// lists the nodes whose window reaches it (gl_node: node in tile order,
+// gl_hdr: footprint origin relative to the tile + 64 in bits 0-7 (rows) and
+// 8-15 (columns), closed-edge flags in bits 16, 17); a unit (tile, first
+// entry, end, slot) spreads a run of one tile's list into the grid (slot -1)
+// or into a partial slot [rhs][slot][256] that the reduction sums.
+struct GatherArgs {
+  const int32_t* units;   // [nunits][4]: tile (-1: padding), begin, end, slot
+  int nunits;
+  const int32_t* gl_node;
+  const int32_t* gl_hdr;
+  const int32_t* split;   // [nsplit][4]: tile, first slot, slots, 0
+  int nsplit;
+  float2* grid;
+  int64_t grid_rs;
+  float2* part;
+  int64_t part_rs;
+  float2* fT;             // node-major samples [ceil(nrhs/32)][N][32] (written first)
+};
+bool spread_gather_supported(int d, int T, bool f64, int m);
+size_t spread_gather_lds_bytes(int m);
+hipError_t launch_spread_gather(const SpreadArgs<float>& a, const GatherArgs& ga, int nrhs,
+                                hipStream_t s);
+hipError_t launch_gather_reduce(const GatherArgs& ga, int nb, int Ms, int nrhs, hipStream_t s);
 // Register row sweep (d = 2, padded tile edge <= 32, nodes row-sorted in tiles).
 bool spread_rows_supported(int d, int P);
 template <typename R>

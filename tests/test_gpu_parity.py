@@ -330,7 +330,7 @@ def _c4_inputs():
     return x, w, F, onfft.adjoint(x, w[None, :] * F, M, 2.0, 6)
 
 
-@pytest.mark.parametrize("tuning", [None, "auto"])
+@pytest.mark.parametrize("tuning", [None, "auto", {"spread_mode": 6}])
 def test_spiral_32_rhs(tuning):
     """Archimedean spiral N = 131072, M = 256, m = 6, 32 right-hand sides in one
     float32 call: every right-hand side's full output vector against O2, and

@@ -90,11 +90,14 @@ TUNINGS = [
     {"spread_mode": 5, "item_nodes": 2048},
     {"spread_mode": 5, "tile_edge": 8},   # register tiles need tile edge 16: mode 4
     {"spread_mode": 5, "spread_threads": 512, "item_nodes": 1024},
+    {"spread_mode": 6},
+    {"spread_mode": 6, "item_nodes": 32},
+    {"spread_mode": 6, "tile_edge": 8},   # the gather needs tile edge 16: mode 4
 ]
 
-# the mode the register-tile kernel resolves to where it does not apply
-# (float64, a tile edge other than 16)
-REG_FALLBACK = {5: 4}
+# the mode the register-tile kernel and the grid-tile gather resolve to where
+# they do not apply (float64, a tile edge other than 16)
+REG_FALLBACK = {5: 4, 6: 4}
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -296,4 +299,37 @@ def test_register_tile_spreading(m, items, nt):
     # fixed summation order: a second call gives the same bits
     again = _np(p.adjoint(torch.from_numpy(F)))
     assert np.array_equal(again, got)
+    p.close()
+
+
+@pytest.mark.parametrize("m", [1, 2, 4, 6, 8])
+@pytest.mark.parametrize("M,nrhs", [(32, 32), (32, 5), (64, 40), (16, 33)])
+def test_grid_tile_gather(M, nrhs, m):
+    """Spread mode 6 sums each grid cell of a 16 x 16 tile in one register
+    for 32 right-hand sides at a time, visiting the nodes of the tile and of
+    its eight neighbours (periodically: at M = 16 the grid has two tiles per
+    dimension, so the neighbours on both sides are the same tile). Every
+    right-hand side against the oracle (O2); against the register-tile
+    kernel (mode 5) of the same plan up to rounding order; two calls give the
+    same bits (one lane sums a cell in a fixed order). Right-hand-side counts
+    below, at and above one group of 32; nodes uniform, on grid lines (closed
+    edge) and crowded into one tile."""
+    x = _nodes(2, M, 130 + m)
+    N = x.shape[0]
+    w = (1.0 + 0.3 * wl.complex_normal(N, 131)) / N
+    F = wl.complex_normal((nrhs, N), 132 + nrhs)
+    p = _plan(x, M, m, "f32", max_rhs=nrhs, tuning={"spread_mode": 6})
+    assert p.tuning()["spread_mode"] == 6
+    p.set_weights(w)
+    Ft = torch.from_numpy(F)
+    got = _np(p.adjoint(Ft))
+    again = _np(p.adjoint(Ft))
+    assert np.array_equal(got.view(np.uint32), again.view(np.uint32))
+    ref = onfft.adjoint(x, w[None, :] * F, M, 2.0, m)
+    e = metrics.rel_err_rows(got, ref)
+    print(f"[gather] M={M} m={m} nrhs={nrhs}: max rel err vs O2 {e.max():.3e}", flush=True)
+    assert e.max() <= TOL_O2["f32"]
+    p.set_tuning("spread_mode", 5)
+    reg = _np(p.adjoint(Ft))
+    assert metrics.rel_err(got, reg) <= TOL_ORDER["f32"]
     p.close()
