@@ -2,31 +2,31 @@
 // float32; Algorithm 2.4 step 1 with the weights of (3.7), Remark 3.1 (ii)).
 //
 // Right-hand sides that share a node set share every node's cell and window
-// factors; only c_j^(r) = w_j f_j^(r) differs. Here a work-group owns one
-// 16 x 16 tile of the oversampled grid and 32 right-hand sides, and lane
-// r + 32 c of each wave holds component c (real, imaginary) of right-hand
-// side r: every lane does useful work on every node, and the node's window
-// factors are the same for all lanes (LDS broadcasts). Wave w keeps the tile
-// rows 4w .. 4w+3, all 16 columns, in 64 registers. The nodes whose window
-// support reaches a tile (its own and those of the eight neighbouring tiles
-// that come within m cells; the window spans 2m + 1 <= 17 cells, so no
-// farther tile can) are listed per tile at plan time, with the footprint
-// origin relative to the tile. A work unit is a run of at most item_nodes
-// entries of one tile's list: the work-group stages their window factors and
-// samples in LDS and adds
-//     acc[row][col] += (c_j * a_q) * b_k
-// for the footprint row q and column k that fall on the wave's cells.
-// Register indices must be static: each tile's list is sorted at plan time by
-// the column offset of the footprint inside the tile, and the node loop runs
-// inside an unrolled loop over the 16 + 2m possible offsets, so that for
-// offset C the updated registers are constants and only the cells a node
-// reaches are updated. The samples are first copied node-major (32 samples of
-// a node in 256 contiguous bytes), so that the staging reads whole lines. A tile with one unit writes its grid
+// factors; only c_j^(r) = w_j f_j^(r) differs. For a tile of grid cells and
+// 32 right-hand sides the spreading is the contraction
+//     g[m][cell] = sum_j C[m][j] W_j[cell],   m = (component, rhs) < 64,
+// C[m][j] the real or imaginary part of c_j^(r), W_j[cell] = a_q b_k the
+// window factor of node j at that cell (zero outside its footprint): a
+// product of a 64 x n and an n x cells matrix, with about 24 flops per byte
+// of input. A work-group owns one 16 x 16 tile of the oversampled grid,
+// split into sixteen 4 x 4 sub-tiles; wave w owns the four sub-tiles of tile
+// rows 4w .. 4w+3 and keeps their 64 x 16 sums as four 16 x 16 blocks each
+// (v_mfma_f32_16x16x4f32 accumulators, 64 registers). The nodes whose window
+// support reaches the tile (its own and those of the eight neighbouring tiles
+// that come within m cells; 2m + 1 <= 17, so no farther tile can) are listed
+// per tile at plan time with the footprint origin relative to the tile. A
+// work unit is a run of at most item_nodes entries of one tile's list; the
+// work-group stages 64 entries at a time in LDS (window factors, and the
+// samples of the 32 right-hand sides, read from a node-major copy so that a
+// node's 32 samples are 256 contiguous bytes), a ballot gives each sub-tile
+// the set of staged entries that reach it, and each wave feeds those entries
+// four at a time (K = 4) to the matrix cores: lane (k, cell) forms
+// W_k[cell], lane (k, m) loads C[m][k]. A tile with one unit writes its grid
 // cells directly; a tile whose list was cut into several units (the crowded
 // tiles) writes one 16 x 16 partial per unit, and a second kernel sums the
-// partials in unit order with compensation (Neumaier) into the grid. Each
-// partial is one float32 sum per cell in a fixed node order, so the result
-// does not depend on timing; no halo is written or merged.
+// partials in unit order with compensation (Neumaier) into the grid. Every
+// sum runs in a fixed order, so the result does not depend on timing; no halo
+// is written or merged.
 #include "spread_common.hpp"
 
 namespace nfft {
@@ -41,34 +41,16 @@ struct GatherLds {
   static constexpr int K = 2 * MW + 1;             // footprint cells per dimension
   static constexpr int XS = (K + 3) / 4 * 4;       // column factors stored per node
   static constexpr int YS = (K + 8 + 3) / 4 * 4;   // row factors: 4 zeros, K values, 4 zeros
-  static constexpr int NC = 16 + 2 * MW;           // column offsets
   // per entry: header, caller index, two offsets, weight, factors, samples
   static constexpr size_t staging =
       kGatherNb * (2 * sizeof(int) + 4 * sizeof(float) + (XS + YS) * sizeof(float) +
-                   2 * kGatherRhs * sizeof(float)) +
-      (NC + 1) * sizeof(int);
+                   2 * kGatherRhs * sizeof(float));
   // one wave's tile for the output transpose: [rhs][65 cells][2] floats
   static constexpr size_t transpose = (size_t)kGatherRhs * 65 * 2 * sizeof(float);
   static constexpr size_t bytes = staging > transpose ? staging : transpose;
 };
 
-// acc[i][col] += t_i * b_k for the footprint columns k whose tile column
-// col = C - 2m + k lies in 0..15 (C: the case of the column dispatch), rows
-// i of the wave that the node reaches.
-template <int C, int MW>
-__device__ __forceinline__ void gather_cols(float (&acc)[4][16], const float (&t)[4],
-                                            const bool (&act)[4], const float (&bx)[2 * MW + 1]) {
-  static_for<0, 4>([&](auto ic) {
-    constexpr int i = decltype(ic)::value;
-    if (act[i]) {
-      static_for<0, 2 * MW + 1>([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        constexpr int col = C - 2 * MW + k;
-        if constexpr (col >= 0 && col < 16) acc[i][col] = fmaf(t[i], bx[k], acc[i][col]);
-      });
-    }
-  });
-}
+typedef float gather_v4f __attribute__((ext_vector_type(4)));
 
 }  // namespace
 
@@ -90,9 +72,9 @@ __global__ __launch_bounds__(256) void spread_gather_kernel(
   float* s_ay = reinterpret_cast<float*>(s_w + NB);  // row factors [NB][YS], entry q at 4 + q
   float* s_bx = s_ay + NB * YS;                         // column factors [NB][XS]
   float* s_c = s_bx + NB * XS;                          // samples [NB][re 32 | im 32]
-  int* s_cs = reinterpret_cast<int*>(s_c + NB * 2 * kGatherRhs);  // first entry per offset
-  constexpr int NC = GatherLds<MW>::NC;
   __shared__ float s_cf[2 * MW * (DEG + 1)];
+  __shared__ uint64_t s_mask[16];  // staged entries that reach each 4 x 4 sub-tile
+  static_assert(NB == 64, "one wave ballots the staged entries");
 
   const int* u = units + 4 * (int64_t)blockIdx.x;
   const int tile = u[0], e_begin = u[1], e_end = u[2], slot = u[3];
@@ -106,66 +88,73 @@ __global__ __launch_bounds__(256) void spread_gather_kernel(
   const int64_t N = a.g.N;
   for (int i = tid; i < 2 * MW * (DEG + 1); i += 256) s_cf[i] = a.coef[i];
 
-  float acc[4][16];
+  // acc[sc][mb]: sub-tile (w, sc), rows mb*16 .. mb*16+15 of the 64 x 16 sums
+  gather_v4f acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[i][j] = 0.0f;
+    for (int j = 0; j < 4; ++j) acc[i][j] = gather_v4f{0.0f, 0.0f, 0.0f, 0.0f};
 
+  // node data of a round's entries, loaded by wave 0 (one entry per lane)
+  // one round ahead, so that its latency hides behind the round before
+  int p_hd = 0, p_pm = 0;
+  float p_y0 = 0.0f, p_y1 = 0.0f;
+  float2 p_w = make_float2(0.0f, 0.0f);
+  auto fetch = [&](int cb) {
+    if (tid < NB && cb + tid < e_end) {
+      p_hd = gl_hdr[cb + tid];
+      const int i = gl_node[cb + tid];
+      p_y0 = 2.0f * a.frac[i] - 1.0f;
+      p_y1 = 2.0f * a.frac[N + i] - 1.0f;
+      p_w = a.w[i];
+      p_pm = a.perm[i];
+    }
+  };
+  fetch(e_begin);
   for (int c0 = e_begin; c0 < e_end; c0 += NB) {
     const int nk = (e_end - c0) < NB ? (e_end - c0) : NB;
     __syncthreads();  // the previous round is consumed
-    // per entry its node's data (every load of a thread issued together)
-    if (tid < nk) {
-      const int hd = gl_hdr[c0 + tid];
-      const int hp = tid > 0 ? gl_hdr[c0 + tid - 1] : 0;
-      const int i = gl_node[c0 + tid];
-      const float fr0 = a.frac[i], fr1 = a.frac[N + i];
-      const float2 wv = a.w[i];
-      const int pm = a.perm[i];
-      s_hdr[tid] = hd;
-      s_perm[tid] = pm;
-      s_y[tid] = 2.0f * fr0 - 1.0f;
-      s_y[NB + tid] = 2.0f * fr1 - 1.0f;
-      s_w[tid] = wv;
-      // first entry of every column offset (the list is sorted by offset):
-      // entry t opens the offsets after its predecessor's up to its own, the
-      // last entry closes the rest
-      const int ct = ((hd >> 8) & 0xff) - 64 + 2 * MW;
-      const int cp = tid > 0 ? ((hp >> 8) & 0xff) - 64 + 2 * MW : -1;
-      for (int c = cp + 1; c <= ct; ++c) s_cs[c] = tid;
-      if (tid == nk - 1)
-        for (int c = ct + 1; c <= NC; ++c) s_cs[c] = nk;
+    // the prefetched entries into LDS, and per sub-tile the staged entries
+    // whose footprint reaches it (wave 0)
+    if (tid < NB) {
+      uint32_t reach = 0;
+      if (tid < nk) {
+        const int hd = p_hd;
+        const int b0 = (hd & 0xff) - 64, b1 = ((hd >> 8) & 0xff) - 64;
+        const int r0 = max(0, b0 + (((hd >> 16) & 1) ? 0 : 1)), r1 = min(15, b0 + 2 * MW);
+        const int k0 = max(0, b1 + (((hd >> 17) & 1) ? 0 : 1)), k1 = min(15, b1 + 2 * MW);
+        for (int sr = r0 >> 2; sr <= r1 >> 2; ++sr)
+          for (int sc = k0 >> 2; sc <= k1 >> 2; ++sc) reach |= 1u << (4 * sr + sc);
+        s_hdr[tid] = hd;
+        s_perm[tid] = p_pm;
+        s_y[tid] = p_y0;
+        s_y[NB + tid] = p_y1;
+        s_w[tid] = p_w;
+      }
+#pragma unroll
+      for (int st = 0; st < 16; ++st) {
+        const uint64_t bal = __builtin_amdgcn_ballot_w64((reach >> st) & 1u);
+        if (tid == 0) s_mask[st] = bal;
+      }
+      fetch(c0 + NB);  // the next round's entries, in flight from here
     }
     __syncthreads();
     // samples c_j = w_j f_j of the work-group's right-hand sides, from the
     // node-major copy (a node's 32 samples are 256 contiguous bytes): item
-    // e = tid + 256 j is right-hand side e mod 32 of entry e / 32
-    {
-      constexpr int SPT = NB * kGatherRhs / 256;
-      const float2* fg = fT + (int64_t)blockIdx.y * N * kGatherRhs;
-      float2 fv[SPT];
+    // e = tid + 256 j is right-hand side e mod 32 of entry e / 32; the window
+    // factors are evaluated while the loads are in flight
+    constexpr int SPT = NB * kGatherRhs / 256;
+    const float2* fg = fT + (int64_t)blockIdx.y * N * kGatherRhs;
+    float2 fv[SPT];
 #pragma unroll
-      for (int j = 0; j < SPT; ++j) {
-        const int e = tid + 256 * j;
-        const int k = e / kGatherRhs, r = e % kGatherRhs;
-        fv[j] = make_float2(0.0f, 0.0f);
-        if (k < nk) fv[j] = fg[(int64_t)s_perm[k] * kGatherRhs + r];
-      }
-#pragma unroll
-      for (int j = 0; j < SPT; ++j) {
-        const int e = tid + 256 * j;
-        const int k = e / kGatherRhs, r = e % kGatherRhs;
-        if (k < nk) {
-          const float2 wv = s_w[k];
-          s_c[k * 2 * kGatherRhs + r] = wv.x * fv[j].x - wv.y * fv[j].y;
-          s_c[k * 2 * kGatherRhs + kGatherRhs + r] = wv.x * fv[j].y + wv.y * fv[j].x;
-        }
-      }
+    for (int j = 0; j < SPT; ++j) {
+      const int e = tid + 256 * j;
+      const int k = e / kGatherRhs, r = e % kGatherRhs;
+      fv[j] = make_float2(0.0f, 0.0f);
+      if (k < nk) fv[j] = fg[(int64_t)s_perm[k] * kGatherRhs + r];
     }
-    // window factors: entry 0 the closed-edge cell, 1 + i polynomial i; the
-    // row factors with four zeros on either side, so that the four rows of a
-    // wave are read unconditionally
+    // window factors: entry 0 the closed-edge cell, 1 + i polynomial i (the
+    // row factors stored from index 4)
     for (int e = tid; e < nk * 2 * K; e += 256) {
       const int k = e / (2 * K);
       const int rem = e - k * (2 * K);
@@ -178,57 +167,77 @@ __global__ __launch_bounds__(256) void spread_gather_kernel(
       else
         s_ay[k * YS + 4 + q] = v;
     }
-    for (int e = tid; e < nk * 8; e += 256) {
-      const int k = e >> 3, z = e & 7;
-      s_ay[k * YS + (z < 4 ? z : K + z)] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+      const int e = tid + 256 * j;
+      const int k = e / kGatherRhs, r = e % kGatherRhs;
+      if (k < nk) {
+        const float2 wv = s_w[k];
+        s_c[k * 2 * kGatherRhs + r] = wv.x * fv[j].x - wv.y * fv[j].y;
+        s_c[k * 2 * kGatherRhs + kGatherRhs + r] = wv.x * fv[j].y + wv.y * fv[j].x;
+      }
     }
     __syncthreads();
-    int cs[NC + 1];
+    // the wave's four sub-tiles: entries reaching a sub-tile, four at a time
+    const int kk = lane >> 4, j = lane & 15;
+    const int row = 4 * wave + (j >> 2);  // tile cell of lane (kk, j) in B
 #pragma unroll
-    for (int c = 0; c <= NC; ++c) cs[c] = s_cs[c];
-    static_for<0, NC>([&](auto cc) {
-      constexpr int C = decltype(cc)::value;
-      const int k0 = __builtin_amdgcn_readfirstlane(cs[C]);
-      const int k1 = __builtin_amdgcn_readfirstlane(cs[C + 1]);
-      int hd_next = k0 < k1 ? s_hdr[k0] : 0;
-      for (int k = k0; k < k1; ++k) {
-        const int hd = __builtin_amdgcn_readfirstlane(hd_next);
-        if (k + 1 < k1) hd_next = s_hdr[k + 1];  // the next header, read ahead
-        const int b0 = (hd & 0xff) - 64;
-        const int qlo = ((hd >> 16) & 1) ? 0 : 1;
-        const int q0 = 4 * wave - b0;  // footprint row of the wave's first row
-        if (q0 + 3 < qlo || q0 > 2 * MW) continue;
-        const float cv = s_c[k * 2 * kGatherRhs + lane];
-        float bx[K];
+    for (int sc = 0; sc < 4; ++sc) {
+      const int col = 4 * sc + (j & 3);
+      uint64_t msk = ((uint64_t)__builtin_amdgcn_readfirstlane((int)(s_mask[4 * wave + sc] >> 32))
+                      << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((int)s_mask[4 * wave + sc]);
+      while (msk) {
+        int kq[4];
 #pragma unroll
-        for (int q = 0; q < K; ++q) bx[q] = s_bx[k * XS + q];
-        // rows q0 .. q0+3 of the padded row factors (zeros outside the footprint)
-        const float* ay = s_ay + k * YS + 4 + q0;
-        float t[4];
-        bool act[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int q = q0 + i;
-          act[i] = q >= qlo && q <= 2 * MW;
-          t[i] = cv * ay[i];
+        for (int q = 0; q < 4; ++q) {
+          kq[q] = msk ? __builtin_ctzll(msk) : -1;
+          msk &= msk - 1;
         }
-        gather_cols<C, MW>(acc, t, act, bx);
+        const int kx = kk == 0 ? kq[0] : kk == 1 ? kq[1] : kk == 2 ? kq[2] : kq[3];
+        // every load unconditional (indices clamped into the staged data), so
+        // that they are issued together; a missing entry (kx < 0, the last
+        // group) and cells outside the footprint get W = 0, which also
+        // cancels the A values loaded for them (staged, finite)
+        const int kc = kx >= 0 ? kx : 0;
+        const int hd = s_hdr[kc];
+        const int qy = row - ((hd & 0xff) - 64), qx = col - (((hd >> 8) & 0xff) - 64);
+        const bool in = kx >= 0 && qy >= 0 && qy <= 2 * MW && qx >= 0 && qx <= 2 * MW;
+        const float fa = s_ay[kc * YS + 4 + min(max(qy, 0), 2 * MW)];
+        const float fb = s_bx[kc * XS + min(max(qx, 0), 2 * MW)];
+        const float bw = in ? fa * fb : 0.0f;
+        const float* cc = s_c + kc * 2 * kGatherRhs + j;
+        float av[4];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) av[mb] = cc[16 * mb];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+          acc[sc][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb], bw, acc[sc][mb], 0, 0, 0);
       }
-    });
+    }
   }
 
   // output: each wave in turn transposes its rows through LDS so that a
   // store writes 16 consecutive cells of one right-hand side: to the grid,
   // or to the unit's partial slot (cells in tile order)
+  // (accumulator element v of lane l in block mb: row m = 16 mb + 4 (l >> 4)
+  // + v of the 64 (m < 32: real part of right-hand side m, else imaginary
+  // part of m - 32), cell l & 15 of the sub-tile)
   float* tr = lds_f;
-  const int r = lane & 31, comp = lane >> 5;
   for (int w = 0; w < 4; ++w) {
     __syncthreads();
     if (wave == w) {
+      // element (sc, mb, v) goes to float ((m mod 32) * 65 + cell) * 2 + m / 32:
+      // a lane-dependent base plus a constant
+      const int cj = lane & 15;
+      float* base = tr + (4 * (lane >> 4) * 65 + (cj >> 2) * 16 + (cj & 3)) * 2;
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int sc = 0; sc < 4; ++sc)
 #pragma unroll
-        for (int j = 0; j < 16; ++j) tr[(r * 65 + i * 16 + j) * 2 + comp] = acc[i][j];
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            base[((16 * (mb & 1) + v) * 65 + 4 * sc) * 2 + (mb >> 1)] = acc[sc][mb][v];
     }
     __syncthreads();
     if (wave == w) {
@@ -242,9 +251,12 @@ __global__ __launch_bounds__(256) void spread_gather_kernel(
         dst = part + (int64_t)slot * 256 + 64 * w + lane;
         rs = part_rs;
       }
-      for (int rr = 0; rr < kGatherRhs && rhs0 + rr < nrhs; ++rr) {
+      dst += (int64_t)rhs0 * rs;
+      const int nr = min(kGatherRhs, nrhs - rhs0);
+#pragma unroll 2
+      for (int rr = 0; rr < nr; ++rr, dst += rs) {
         const float* src = tr + (rr * 65 + lane) * 2;
-        dst[(int64_t)(rhs0 + rr) * rs] = make_float2(src[0], src[1]);
+        *dst = make_float2(src[0], src[1]);
       }
     }
   }
