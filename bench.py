@@ -507,6 +507,18 @@ def run_batched(steps, precs=("f32", "f64"), tuning="auto"):
             plan.set_profiling(False)
             st = plan.stage_times(reset=True)
             res[prec]["stage_us"] = {k: round(1e3 * v[0] / v[1], 2) for k, v in st.items() if v[1]}
+            # the spreading of all 32 right-hand sides (spreading stage plus
+            # the sums of split tiles) against the float32 peak: a contraction
+            # of (2m)^2 window cells per node and right-hand side
+            us = res[prec]["stage_us"].get("spread", 0) + res[prec]["stage_us"].get(
+                "split_tile_reduce", 0)
+            fl = spread_flops(N, MW, D) * R
+            if us > 0:
+                res[prec]["spread_roofline"] = dict(
+                    bound="mfma" if plan.tuning()["spread_mode"] == 6 else "alu",
+                    achieved=round(fl / (us * 1e-6) / 1e12, 3), peak=FP32_PEAK_TFLOPS,
+                    unit="TFLOP/s", frac=round(fl / (us * 1e-6) / 1e12 / FP32_PEAK_TFLOPS, 4),
+                    algorithmic_flops=fl, us=round(us, 2))
         plan.close()
     if len(res) < 2:
         return dict(workload="spiral N=131072, d=2, M=256, sigma=2, m=6, 32 rhs, area weights", **res)
@@ -663,6 +675,14 @@ def main():
     N = x.shape[0]
     Ms = 2 * M
 
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"calibration copy: {n * 4} bytes read, {n * 4} bytes written", file=sys.stderr)
     if args.only:
         # one secondary workload, for profiling: --precision picks the path,
         # --tuning a fixed tuning (so that no autotuner runs are traced)
@@ -679,14 +699,6 @@ def main():
         print(json.dumps({args.only: sec}), flush=True)
         return
 
-    if args.calibrate_copy_mib:
-        n = args.calibrate_copy_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(f"calibration copy: {n * 4} bytes read, {n * 4} bytes written", file=sys.stderr)
     tuning = args.tuning if args.tuning == "auto" else json.loads(args.tuning)
     if args.precision != "both":
         r = run_gpu(args.precision, x, w, f, args.steps, args.warmup, tuning)
