@@ -9,14 +9,14 @@
 // window factor of node j at that cell (zero outside its footprint): a
 // product of a 64 x n and an n x cells matrix, with about 24 flops per byte
 // of input. A work-group owns one 16 x 16 tile of the oversampled grid,
-// split into sixteen 4 x 4 sub-tiles; wave w owns the four sub-tiles of tile
-// rows 4w .. 4w+3 and keeps their 64 x 16 sums as four 16 x 16 blocks each
-// (v_mfma_f32_16x16x4f32 accumulators, 64 registers). The nodes whose window
+// split into sixteen 4 x 4 sub-tiles; each of its eight waves owns two
+// sub-tiles and keeps their 64 x 16 sums as four 16 x 16 blocks each
+// (v_mfma_f32_16x16x4f32 accumulators, 32 registers). The nodes whose window
 // support reaches the tile (its own and those of the eight neighbouring tiles
 // that come within m cells; 2m + 1 <= 17, so no farther tile can) are listed
 // per tile at plan time with the footprint origin relative to the tile. A
 // work unit is a run of at most item_nodes entries of one tile's list; the
-// work-group stages 64 entries at a time in LDS (window factors, and the
+// work-group stages 128 entries at a time in LDS (window factors, and the
 // samples of the 32 right-hand sides, read from a node-major copy so that a
 // node's 32 samples are 256 contiguous bytes), a ballot gives each sub-tile
 // the set of staged entries that reach it, and each wave feeds those entries
@@ -34,7 +34,8 @@ namespace nfft {
 namespace {
 
 constexpr int kGatherRhs = 32;  // right-hand sides per work-group
-constexpr int kGatherNb = 64;   // list entries staged per round
+constexpr int kGatherNb = 128;  // list entries staged per round
+constexpr int kGatherNt = 512;  // threads per work-group (8 waves)
 
 template <int MW>
 struct GatherLds {
@@ -55,7 +56,7 @@ typedef float gather_v4f __attribute__((ext_vector_type(4)));
 }  // namespace
 
 template <int MW>
-__global__ __launch_bounds__(256) void spread_gather_kernel(
+__global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
     SpreadArgs<float> a, const int32_t* __restrict__ units, const int32_t* __restrict__ gl_node,
     const int32_t* __restrict__ gl_hdr, const float2* __restrict__ fT, float2* __restrict__ grid,
     int64_t grid_rs, float2* __restrict__ part, int64_t part_rs, int nrhs) {
@@ -71,10 +72,15 @@ __global__ __launch_bounds__(256) void spread_gather_kernel(
   constexpr int YS = GatherLds<MW>::YS;
   float* s_ay = reinterpret_cast<float*>(s_w + NB);  // row factors [NB][YS], entry q at 4 + q
   float* s_bx = s_ay + NB * YS;                         // column factors [NB][XS]
-  float* s_c = s_bx + NB * XS;                          // samples [NB][re 32 | im 32]
+  // samples: component row m = 32 c + r (c: real 0, imaginary 1; r: rhs) of
+  // entry k at s_c[k][m mod 16][m / 16], so that a lane's four A values (one
+  // per 16-row block) are one 16-byte read
+  float* s_c = s_bx + NB * XS;
   __shared__ float s_cf[2 * MW * (DEG + 1)];
-  __shared__ uint64_t s_mask[16];  // staged entries that reach each 4 x 4 sub-tile
-  static_assert(NB == 64, "one wave ballots the staged entries");
+  // staged entries that reach each 4 x 4 sub-tile: [sub-tile][half of the round]
+  __shared__ uint64_t s_mask[16 * 2];
+  static_assert(NB == 128 && kGatherNt == 512, "two waves ballot the staged entries");
+  constexpr int NT = kGatherNt;
 
   const int* u = units + 4 * (int64_t)blockIdx.x;
   const int tile = u[0], e_begin = u[1], e_end = u[2], slot = u[3];
@@ -86,16 +92,16 @@ __global__ __launch_bounds__(256) void spread_gather_kernel(
   const int t0 = tile / nb, t1 = tile - (tile / nb) * nb;
   const int rhs0 = blockIdx.y * kGatherRhs;
   const int64_t N = a.g.N;
-  for (int i = tid; i < 2 * MW * (DEG + 1); i += 256) s_cf[i] = a.coef[i];
+  for (int i = tid; i < 2 * MW * (DEG + 1); i += NT) s_cf[i] = a.coef[i];
 
-  // acc[sc][mb]: sub-tile (w, sc), rows mb*16 .. mb*16+15 of the 64 x 16 sums
-  gather_v4f acc[4][4];
+  // acc[q][mb]: sub-tile 2 wave + q, rows mb*16 .. mb*16+15 of the 64 x 16 sums
+  gather_v4f acc[2][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = gather_v4f{0.0f, 0.0f, 0.0f, 0.0f};
 
-  // node data of a round's entries, loaded by wave 0 (one entry per lane)
+  // node data of a round's entries, loaded by waves 0 and 1 (one entry per lane)
   // one round ahead, so that its latency hides behind the round before
   int p_hd = 0, p_pm = 0;
   float p_y0 = 0.0f, p_y1 = 0.0f;
@@ -115,7 +121,7 @@ __global__ __launch_bounds__(256) void spread_gather_kernel(
     const int nk = (e_end - c0) < NB ? (e_end - c0) : NB;
     __syncthreads();  // the previous round is consumed
     // the prefetched entries into LDS, and per sub-tile the staged entries
-    // whose footprint reaches it (wave 0)
+    // whose footprint reaches it (waves 0 and 1, 64 entries each)
     if (tid < NB) {
       uint32_t reach = 0;
       if (tid < nk) {
@@ -134,28 +140,28 @@ __global__ __launch_bounds__(256) void spread_gather_kernel(
 #pragma unroll
       for (int st = 0; st < 16; ++st) {
         const uint64_t bal = __builtin_amdgcn_ballot_w64((reach >> st) & 1u);
-        if (tid == 0) s_mask[st] = bal;
+        if ((tid & 63) == 0) s_mask[2 * st + (tid >> 6)] = bal;
       }
       fetch(c0 + NB);  // the next round's entries, in flight from here
     }
     __syncthreads();
     // samples c_j = w_j f_j of the work-group's right-hand sides, from the
     // node-major copy (a node's 32 samples are 256 contiguous bytes): item
-    // e = tid + 256 j is right-hand side e mod 32 of entry e / 32; the window
+    // e = tid + NT j is right-hand side e mod 32 of entry e / 32; the window
     // factors are evaluated while the loads are in flight
-    constexpr int SPT = NB * kGatherRhs / 256;
+    constexpr int SPT = NB * kGatherRhs / NT;
     const float2* fg = fT + (int64_t)blockIdx.y * N * kGatherRhs;
     float2 fv[SPT];
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
-      const int e = tid + 256 * j;
+      const int e = tid + NT * j;
       const int k = e / kGatherRhs, r = e % kGatherRhs;
       fv[j] = make_float2(0.0f, 0.0f);
       if (k < nk) fv[j] = fg[(int64_t)s_perm[k] * kGatherRhs + r];
     }
     // window factors: entry 0 the closed-edge cell, 1 + i polynomial i (the
     // row factors stored from index 4)
-    for (int e = tid; e < nk * 2 * K; e += 256) {
+    for (int e = tid; e < nk * 2 * K; e += NT) {
       const int k = e / (2 * K);
       const int rem = e - k * (2 * K);
       const int dim = rem >= K ? 1 : 0;
@@ -169,29 +175,34 @@ __global__ __launch_bounds__(256) void spread_gather_kernel(
     }
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
-      const int e = tid + 256 * j;
+      const int e = tid + NT * j;
       const int k = e / kGatherRhs, r = e % kGatherRhs;
       if (k < nk) {
         const float2 wv = s_w[k];
-        s_c[k * 2 * kGatherRhs + r] = wv.x * fv[j].x - wv.y * fv[j].y;
-        s_c[k * 2 * kGatherRhs + kGatherRhs + r] = wv.x * fv[j].y + wv.y * fv[j].x;
+        // m = r (real part): block r / 16; m = 32 + r (imaginary): block 2 + r / 16
+        float* ck = s_c + k * 2 * kGatherRhs + (r & 15) * 4 + (r >> 4);
+        ck[0] = wv.x * fv[j].x - wv.y * fv[j].y;
+        ck[2] = wv.x * fv[j].y + wv.y * fv[j].x;
       }
     }
     __syncthreads();
-    // the wave's four sub-tiles: entries reaching a sub-tile, four at a time
+    // the wave's two sub-tiles: entries reaching a sub-tile, four at a time
     const int kk = lane >> 4, j = lane & 15;
-    const int row = 4 * wave + (j >> 2);  // tile cell of lane (kk, j) in B
 #pragma unroll
-    for (int sc = 0; sc < 4; ++sc) {
-      const int col = 4 * sc + (j & 3);
-      uint64_t msk = ((uint64_t)__builtin_amdgcn_readfirstlane((int)(s_mask[4 * wave + sc] >> 32))
+    for (int q = 0; q < 2; ++q) {
+      const int st = 2 * wave + q;
+      const int row = 4 * (st >> 2) + (j >> 2);  // tile cell of lane (kk, j) in B
+      const int col = 4 * (st & 3) + (j & 3);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+      uint64_t msk = ((uint64_t)__builtin_amdgcn_readfirstlane((int)(s_mask[2 * st + h] >> 32))
                       << 32) |
-                     (uint32_t)__builtin_amdgcn_readfirstlane((int)s_mask[4 * wave + sc]);
+                     (uint32_t)__builtin_amdgcn_readfirstlane((int)s_mask[2 * st + h]);
       while (msk) {
         int kq[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          kq[q] = msk ? __builtin_ctzll(msk) : -1;
+        for (int t = 0; t < 4; ++t) {
+          kq[t] = msk ? 64 * h + __builtin_ctzll(msk) : -1;
           msk &= msk - 1;
         }
         const int kx = kk == 0 ? kq[0] : kk == 1 ? kq[1] : kk == 2 ? kq[2] : kq[3];
@@ -206,55 +217,59 @@ __global__ __launch_bounds__(256) void spread_gather_kernel(
         const float fa = s_ay[kc * YS + 4 + min(max(qy, 0), 2 * MW)];
         const float fb = s_bx[kc * XS + min(max(qx, 0), 2 * MW)];
         const float bw = in ? fa * fb : 0.0f;
-        const float* cc = s_c + kc * 2 * kGatherRhs + j;
-        float av[4];
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb) av[mb] = cc[16 * mb];
+        const float4 a4 = *reinterpret_cast<const float4*>(s_c + kc * 2 * kGatherRhs + j * 4);
+        const float av[4] = {a4.x, a4.y, a4.z, a4.w};
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb)
-          acc[sc][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb], bw, acc[sc][mb], 0, 0, 0);
+          acc[q][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb], bw, acc[q][mb], 0, 0, 0);
+      }
       }
     }
   }
 
-  // output: each wave in turn transposes its rows through LDS so that a
-  // store writes 16 consecutive cells of one right-hand side: to the grid,
-  // or to the unit's partial slot (cells in tile order)
-  // (accumulator element v of lane l in block mb: row m = 16 mb + 4 (l >> 4)
-  // + v of the 64 (m < 32: real part of right-hand side m, else imaginary
-  // part of m - 32), cell l & 15 of the sub-tile)
+  // output: the two waves of each band of four tile rows in turn transpose
+  // their sub-tiles through LDS, so that a store writes 16 consecutive cells
+  // of one right-hand side: to the grid, or to the unit's partial slot (cells
+  // in tile order). (Accumulator element v of lane l in block mb: row m =
+  // 16 mb + 4 (l >> 4) + v of the 64 (m < 32: real part of right-hand side m,
+  // else imaginary part of m - 32), cell l & 15 of the sub-tile.)
   float* tr = lds_f;
-  for (int w = 0; w < 4; ++w) {
+  const int band = wave >> 1;
+  for (int b = 0; b < 4; ++b) {
     __syncthreads();
-    if (wave == w) {
-      // element (sc, mb, v) goes to float ((m mod 32) * 65 + cell) * 2 + m / 32:
+    if (band == b) {
+      // element (q, mb, v) goes to float ((m mod 32) * 65 + cell) * 2 + m / 32:
       // a lane-dependent base plus a constant
       const int cj = lane & 15;
       float* base = tr + (4 * (lane >> 4) * 65 + (cj >> 2) * 16 + (cj & 3)) * 2;
 #pragma unroll
-      for (int sc = 0; sc < 4; ++sc)
+      for (int q = 0; q < 2; ++q) {
+        const int sc = (2 * wave + q) & 3;
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            base[((16 * (mb & 1) + v) * 65 + 4 * sc) * 2 + (mb >> 1)] = acc[sc][mb][v];
+            base[((16 * (mb & 1) + v) * 65 + 4 * sc) * 2 + (mb >> 1)] = acc[q][mb][v];
+      }
     }
     __syncthreads();
-    if (wave == w) {
+    if (band == b) {
       const int i = lane >> 4, j = lane & 15;
       float2* dst;
       int64_t rs;
       if (slot < 0) {
-        dst = grid + (int64_t)(16 * t0 + 4 * w + i) * a.g.Ms + 16 * t1 + j;
+        dst = grid + (int64_t)(16 * t0 + 4 * b + i) * a.g.Ms + 16 * t1 + j;
         rs = grid_rs;
       } else {
-        dst = part + (int64_t)slot * 256 + 64 * w + lane;
+        dst = part + (int64_t)slot * 256 + 64 * b + lane;
         rs = part_rs;
       }
-      dst += (int64_t)rhs0 * rs;
-      const int nr = min(kGatherRhs, nrhs - rhs0);
+      // the band's two waves store right-hand sides 0..15 and 16..31
+      const int r0 = 16 * (wave & 1);
+      const int r1 = min(r0 + 16, nrhs - rhs0);
+      dst += (int64_t)(rhs0 + r0) * rs;
 #pragma unroll 2
-      for (int rr = 0; rr < nr; ++rr, dst += rs) {
+      for (int rr = r0; rr < r1; ++rr, dst += rs) {
         const float* src = tr + (rr * 65 + lane) * 2;
         *dst = make_float2(src[0], src[1]);
       }
@@ -332,7 +347,7 @@ template <int MW>
 static hipError_t spread_gather_m(const SpreadArgs<float>& a, const GatherArgs& ga, int nrhs,
                                   hipStream_t s) {
   const dim3 blocks(ga.nunits, (nrhs + kGatherRhs - 1) / kGatherRhs);
-  hipLaunchKernelGGL((spread_gather_kernel<MW>), blocks, dim3(256), GatherLds<MW>::bytes, s, a,
+  hipLaunchKernelGGL((spread_gather_kernel<MW>), blocks, dim3(kGatherNt), GatherLds<MW>::bytes, s, a,
                      ga.units, ga.gl_node, ga.gl_hdr, ga.fT, ga.grid, ga.grid_rs, ga.part,
                      ga.part_rs, nrhs);
   return hipGetLastError();
