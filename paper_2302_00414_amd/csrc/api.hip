@@ -792,17 +792,6 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
   return NFFT_OK;
 }
 
-// Lines per work-group of an FFT pass: bounded by 64 KiB of LDS for the two
-// buffers and by 256 threads (L/8 butterflies per line), and lowered while
-// that leaves fewer than 256 work-groups.
-template <typename R>
-int lines_per_wg(int L, int64_t nlines, int min_wg) {
-  const int lds_cap = std::max(1, 65536 / (2 * (L + L / 8 + 1) * (int)sizeof(cplx<R>)));
-  int lpw = std::max(1, std::min(lds_cap, 2048 / L));  // L/8 threads per line
-  while (lpw > 1 && nlines / lpw < min_wg) lpw /= 2;
-  return lpw;
-}
-
 template <typename R>
 nfft::FftArgs<R> fft_args(nfft_plan_t p, int64_t nlines, const void* in, int64_t in_bs, int Lin,
                           void* out, int64_t out_bs) {
@@ -818,17 +807,7 @@ nfft::FftArgs<R> fft_args(nfft_plan_t p, int64_t nlines, const void* in, int64_t
   a.g = p->g;
   a.tilep = (const cplx<R>*)p->tilep;
   a.tile_bs = (int64_t)p->g.nbins * p->g.Ptot;
-  const int min_wg = p->tune[NFFT_TUNE_FFT_MIN_WG];
-  a.lpw = lines_per_wg<R>(p->Ms, nlines, min_wg);
-  // one line per work-group and still few of them: more threads per line
-  // (ignored by the first adjoint pass, whose merge loader takes radix 8)
-  a.r0 = 8;
-  if (a.lpw == 1 && 2 * nlines <= min_wg)
-    a.r0 = 2;
-  else if (a.lpw == 1 && nlines < 2 * (int64_t)min_wg)
-    a.r0 = 4;
-  // at most 512 threads per work-group (the passes' launch bound)
-  while (a.r0 < 8 && p->Ms / a.r0 > 512) a.r0 *= 2;
+  a.min_wg = p->tune[NFFT_TUNE_FFT_MIN_WG];
   return a;
 }
 

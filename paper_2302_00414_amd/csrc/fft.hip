@@ -510,9 +510,39 @@ static hipError_t fft_modes(const FftArgs<R>& a, bool inverse, LoadMode ld, Stor
   return hipErrorInvalidValue;
 }
 
+// Work-group shape of a pass over nlines lines of nbatch batches. Lines per
+// work-group are bounded by 64 KiB of LDS for the two buffers and by 256
+// threads (L/8 butterflies per line; 512 measured slower) and lowered while
+// that leaves fewer than min_wg work-groups. A pass whose lines go one per work-group
+// and still give few work-groups gets two or four times the threads per line
+// (first stage radix 4 or 2; the merge loader keeps 8). The radix is decided
+// from one batch's lines, so a batched call computes exactly what separate
+// calls compute; only the lines per work-group count all batches.
 template <typename R>
-hipError_t launch_fft_pass(const FftArgs<R>& a, int L, bool inverse, LoadMode ld, StoreMode st,
+static int fft_lines_per_wg(int L, int64_t lines, int min_wg) {
+  const int lds_cap = max(1, 65536 / (2 * (L + L / 8 + 1) * (int)sizeof(cplx<R>)));
+  int lpw = max(1, min(lds_cap, 2048 / L));
+  while (lpw > 1 && lines / lpw < min_wg) lpw /= 2;
+  return lpw;
+}
+
+template <typename R>
+static void fft_shape(FftArgs<R>& a, int L, int nbatch) {
+  const int lpw1 = fft_lines_per_wg<R>(L, a.nlines, a.min_wg);
+  a.r0 = 8;
+  if (lpw1 == 1 && 2 * a.nlines <= a.min_wg)
+    a.r0 = 2;
+  else if (lpw1 == 1 && a.nlines < 2 * (int64_t)a.min_wg)
+    a.r0 = 4;
+  while (a.r0 < 8 && L / a.r0 > 512) a.r0 *= 2;  // at most 512 threads per work-group
+  a.lpw = a.r0 < 8 ? 1 : fft_lines_per_wg<R>(L, a.nlines * (int64_t)nbatch, a.min_wg);
+}
+
+template <typename R>
+hipError_t launch_fft_pass(const FftArgs<R>& args, int L, bool inverse, LoadMode ld, StoreMode st,
                            int nbatch, hipStream_t s) {
+  FftArgs<R> a = args;
+  fft_shape(a, L, nbatch);
   switch (L) {
     case 8: return fft_modes<R, 3>(a, inverse, ld, st, nbatch, s);
     case 16: return fft_modes<R, 4>(a, inverse, ld, st, nbatch, s);

@@ -184,8 +184,10 @@ struct FftArgs {
   const cplx<R>* tw;   // twiddles e^{-2 pi i q / L}, q < L
   const double* fac;   // deconvolution factors over I_M (compressed index), float64
   int accumulate;      // kStoreCropScaled: add to the output instead of writing it
-  int lpw;             // lines per work-group
-  int r0;              // radix of the first stage (8, 4 or 2: L/r0 threads per line)
+  int min_wg;          // the launch keeps at least this many work-groups where it can
+  int lpw;             // lines per work-group (set by launch_fft_pass)
+  int r0;              // radix of the first stage (8, 4 or 2: L/r0 threads per line;
+                       // set by launch_fft_pass)
   Geom g;
 };
 template <typename R>

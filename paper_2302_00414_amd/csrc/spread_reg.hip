@@ -69,8 +69,8 @@ __device__ __forceinline__ float lane_pick(float v, int src) {
 
 }  // namespace
 
-// Nodes staged per batch.
-constexpr int kRegBatch = 256;
+// Nodes staged per batch (a work item of up to 512 nodes in one batch).
+constexpr int kRegBatch = 512;
 
 template <int MW>
 struct RegLds {
@@ -131,6 +131,7 @@ __global__ __launch_bounds__(64 * NW) void spread_reg_kernel(SpreadArgs<float> a
   for (int b0 = 0; b0 < cnt; b0 += NB) {
     const int nb = (cnt - b0) < NB ? (cnt - b0) : NB;
     __syncthreads();  // the previous batch is consumed
+#pragma unroll 2
     for (int t = tid; t < nb; t += NT) {
       const int i = start + b0 + t;
       const float2 wv = a.w[i];
