@@ -66,6 +66,24 @@ def test_scratch_adjoint_matches_workspace_adjoint(prec, tuning):
             assert err <= TOL[prec], r
 
 
+def test_scratch_adjoint_with_gather_spreading():
+    """Spread mode 6 through the scratch array (its grid where the tile
+    partials would be, its unit partials and node-major samples after the
+    FFT buffers): a crowded node set whose densest tile is cut into several
+    units, then a smaller one, each against nfft_adjoint on the same plan
+    (float32, same bits)."""
+    rng = np.random.default_rng(405)
+    x1 = np.concatenate([wl.uniform_nodes(6000, 2, 406),
+                         0.01 * rng.standard_normal((3000, 2))])
+    a1, b1 = _case(x1, 64, 6, "f32", 5, 407, {"spread_mode": 6, "item_nodes": 256})
+    x2 = -0.5 + 0.5 * (wl.uniform_nodes(3000, 2, 408) + 0.5)
+    a2, b2 = _case(x2, 32, 4, "f32", 2, 409, {"spread_mode": 6})
+    for a, b in ((a1, b1), (a2, b2)):
+        assert np.all(np.isfinite(b))
+        for r in range(a.shape[0]):
+            assert metrics.rel_err(b[r], a[r]) <= TOL["f32"], r
+
+
 def test_scratch_refuses_oversized_plan():
     """d = 3, M = 64 (4096 tiles of 16^3 padded cells): the tile partials
     alone exceed the scratch array; the call fails before launching and
