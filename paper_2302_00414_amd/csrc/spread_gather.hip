@@ -46,8 +46,8 @@ struct GatherLds {
   static constexpr size_t staging =
       kGatherNb * (2 * sizeof(int) + 4 * sizeof(float) + (XS + YS) * sizeof(float) +
                    2 * kGatherRhs * sizeof(float));
-  // one wave's tile for the output transpose: [rhs][65 cells][2] floats
-  static constexpr size_t transpose = (size_t)kGatherRhs * 65 * 2 * sizeof(float);
+  // the output transpose, per band of four tile rows: [rhs][65 cells][2] floats
+  static constexpr size_t transpose = (size_t)4 * kGatherRhs * 65 * 2 * sizeof(float);
   static constexpr size_t bytes = staging > transpose ? staging : transpose;
 };
 
@@ -227,17 +227,19 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
     }
   }
 
-  // output: the two waves of each band of four tile rows in turn transpose
-  // their sub-tiles through LDS, so that a store writes 16 consecutive cells
-  // of one right-hand side: to the grid, or to the unit's partial slot (cells
-  // in tile order). (Accumulator element v of lane l in block mb: row m =
-  // 16 mb + 4 (l >> 4) + v of the 64 (m < 32: real part of right-hand side m,
-  // else imaginary part of m - 32), cell l & 15 of the sub-tile.)
-  float* tr = lds_f;
+  // output: the two waves of each band of four tile rows transpose their
+  // sub-tiles through the band's LDS area, so that a store writes 16
+  // consecutive cells of one right-hand side: to the grid, or to the unit's
+  // partial slot (cells in tile order). (Accumulator element v of lane l in
+  // block mb: row m = 16 mb + 4 (l >> 4) + v of the 64 (m < 32: real part of
+  // right-hand side m, else imaginary part of m - 32), cell l & 15 of the
+  // sub-tile.)
   const int band = wave >> 1;
-  for (int b = 0; b < 4; ++b) {
+  float* tr = lds_f + band * (kGatherRhs * 65 * 2);
+  {
+    const int b = band;
     __syncthreads();
-    if (band == b) {
+    {
       // element (q, mb, v) goes to float ((m mod 32) * 65 + cell) * 2 + m / 32:
       // a lane-dependent base plus a constant
       const int cj = lane & 15;
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
       }
     }
     __syncthreads();
-    if (band == b) {
+    {
       const int i = lane >> 4, j = lane & 15;
       float2* dst;
       int64_t rs;
