@@ -18,8 +18,8 @@
 // work unit is a run of at most item_nodes entries of one tile's list; the
 // work-group stages 128 entries at a time in LDS (window factors, and the
 // samples of the 32 right-hand sides, read from a node-major copy so that a
-// node's 32 samples are 256 contiguous bytes), a ballot gives each sub-tile
-// the set of staged entries that reach it, and each wave feeds those entries
+// node's 32 samples are 256 contiguous bytes), a ballot lists for each
+// sub-tile the staged entries that reach it, and each wave feeds those entries
 // four at a time (K = 4) to the matrix cores: lane (k, cell) forms
 // W_k[cell], lane (k, m) loads C[m][k]. A tile with one unit writes its grid
 // cells directly; a tile whose list was cut into several units (the crowded
@@ -77,8 +77,10 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
   // per 16-row block) are one 16-byte read
   float* s_c = s_bx + NB * XS;
   __shared__ float s_cf[2 * MW * (DEG + 1)];
-  // staged entries that reach each 4 x 4 sub-tile: [sub-tile][half of the round]
-  __shared__ uint64_t s_mask[16 * 2];
+  // staged entries that reach each 4 x 4 sub-tile, per half of the round (in
+  // entry order), and their counts
+  __shared__ short s_list[16][2][64];
+  __shared__ int s_lcnt[16][2];
   static_assert(NB == 128 && kGatherNt == 512, "two waves ballot the staged entries");
   constexpr int NT = kGatherNt;
 
@@ -137,10 +139,15 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
         s_y[NB + tid] = p_y1;
         s_w[tid] = p_w;
       }
+      const int h = tid >> 6;
 #pragma unroll
       for (int st = 0; st < 16; ++st) {
-        const uint64_t bal = __builtin_amdgcn_ballot_w64((reach >> st) & 1u);
-        if ((tid & 63) == 0) s_mask[2 * st + (tid >> 6)] = bal;
+        const bool in = (reach >> st) & 1u;
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(in);
+        const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+        if (in) s_list[st][h][pos] = (short)tid;
+        if ((tid & 63) == 0) s_lcnt[st][h] = __popcll(bal);
       }
       fetch(c0 + NB);  // the next round's entries, in flight from here
     }
@@ -195,17 +202,10 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
       const int col = 4 * (st & 3) + (j & 3);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-      uint64_t msk = ((uint64_t)__builtin_amdgcn_readfirstlane((int)(s_mask[2 * st + h] >> 32))
-                      << 32) |
-                     (uint32_t)__builtin_amdgcn_readfirstlane((int)s_mask[2 * st + h]);
-      while (msk) {
-        int kq[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          kq[t] = msk ? 64 * h + __builtin_ctzll(msk) : -1;
-          msk &= msk - 1;
-        }
-        const int kx = kk == 0 ? kq[0] : kk == 1 ? kq[1] : kk == 2 ? kq[2] : kq[3];
+      const int cnt = __builtin_amdgcn_readfirstlane(s_lcnt[st][h]);
+      for (int g = 0; g < cnt; g += 4) {
+        // lane (kk, j) takes entry g + kk of the sub-tile's list (none past its end)
+        const int kx = g + kk < cnt ? (int)s_list[st][h][g + kk] : -1;
         // every load unconditional (indices clamped into the staged data), so
         // that they are issued together; a missing entry (kx < 0, the last
         // group) and cells outside the footprint get W = 0, which also
