@@ -515,7 +515,7 @@ def run_batched(steps, precs=("f32", "f64"), tuning="auto"):
             fl = spread_flops(N, MW, D) * R
             if us > 0:
                 res[prec]["spread_roofline"] = dict(
-                    bound="mfma" if plan.tuning()["spread_mode"] == 6 else "alu",
+                    bound="mfma" if plan.tuning()["spread_mode"] in (6, 7) else "alu",
                     achieved=round(fl / (us * 1e-6) / 1e12, 3), peak=FP32_PEAK_TFLOPS,
                     unit="TFLOP/s", frac=round(fl / (us * 1e-6) / 1e12 / FP32_PEAK_TFLOPS, 4),
                     algorithmic_flops=fl, us=round(us, 2))
@@ -614,7 +614,7 @@ def traffic_record(kernel):
 
 # sources of the d = 2 single-rhs spreading kernels
 SPREAD_SOURCES = ("spread.hip", "spread_common.hpp", "spread_group.hpp", "spread_pre.hip", "spread_late.hip",
-                  "spread_rows.hip", "spread_reg.hip")
+                  "spread_rows.hip", "spread_reg.hip", "spread_mma.hip")
 
 
 def spread_kernel_name(t):
@@ -623,9 +623,9 @@ def spread_kernel_name(t):
     T, mode = t["tile_edge"], t["spread_mode"]
     if mode == 2 and T + 2 * MW <= 32:
         return f"spread_rows_kernel<float, {MW}, {T if T == 16 else 0}, 1>"
-    if mode == 5 and T == 16:
+    if mode in (5, 7) and T == 16:
         nw = {256: 4, 512: 8}.get(t["spread_threads"], 2)
-        return f"spread_reg_kernel<{MW}, {nw}>"
+        return f"spread_{'mma' if mode == 7 else 'reg'}_kernel<{MW}, {nw}>"
     ws = {3: 1, 4: 2}.get(mode, 0)   # window source of the group kernel
     return (f"spread_group_kernel<float, 2, {MW}, {t['spread_threads']}, "
             f"{T if T in (8, 16) else 0}, {'true' if t['spread_planes'] == 2 else 'false'}, {ws}>")
@@ -718,7 +718,10 @@ def main():
     achieved = flops / sp_avg_s / 1e12
     t = r32["tuning"]
     kname = spread_kernel_name(t)
-    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_PEAK_TFLOPS,
+    # modes 6 and 7 form the sums on the matrix cores (float32 MFMA peak,
+    # the same figure as the vector peak); the others on the vector ALUs
+    roofline = dict(bound="mfma" if t["spread_mode"] in (6, 7) else "alu",
+                    achieved=round(achieved, 3), peak=FP32_PEAK_TFLOPS,
                     unit="TFLOP/s", frac=round(achieved / FP32_PEAK_TFLOPS, 5),
                     traffic=traffic_record(kname),
                     kernel=kname,

@@ -103,7 +103,7 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
  *   NFFT_TUNE_SPREAD_THREADS  threads of a spreading work-group for d <= 2,
  *                             float32, one right-hand side per work-group:
  *                             64, 128 or 256 (default 128); 512 for spread
- *                             mode 5 (resolved to 256 for the others).
+ *                             modes 5 and 7 (resolved to 256 for the others).
  *   NFFT_TUNE_RHS_PER_GROUP   right-hand sides that one spreading work-group
  *                             takes when nrhs > 1 and d <= 2: 1, 2, 4 or 8
  *                             (default 1). Above 1 the node data and window
@@ -149,16 +149,29 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
  *                             6 = float32, d = 2, tile edge 16, m <= 8, for
  *                             many right-hand sides: a work-group owns one
  *                             16 x 16 tile of the grid and 32 right-hand
- *                             sides (lane r + 32 c: component c of
- *                             right-hand side r), visits the nodes of that
- *                             tile and of its eight neighbours whose window
- *                             reaches it, and sums every grid cell in one
- *                             float32 register in a fixed node order; the
- *                             grid is written once, so there are no tile
- *                             partials, split-tile sums or halo merges.
- *                             Ignores the thread count, planes and
- *                             right-hand sides per group. Resolved to 5 (and
- *                             so on) where not supported.
+ *                             sides, visits the nodes of that tile and of
+ *                             its eight neighbours whose window reaches it
+ *                             (plan-time lists, cut into units of at most
+ *                             NFFT_TUNE_ITEM_NODES entries), and forms the
+ *                             sums on the matrix cores, every grid cell in
+ *                             one float32 accumulator in a fixed node order;
+ *                             tiles of one unit write the grid directly, the
+ *                             units of a longer list write partials summed
+ *                             in unit order; no halo merges. Ignores the
+ *                             thread count, planes and right-hand sides per
+ *                             group. Resolved to 5 (and so on) where not
+ *                             supported.
+ *                             7 = float32, d = 2, tile edge 16, 2m + 1 <= 16:
+ *                             the padded tile of a work item on the matrix
+ *                             cores; the nodes of one tile row reach 16
+ *                             padded rows, so four nodes at a time form a
+ *                             16 x 32 block of products (rows held as
+ *                             slots that shift with the tile row); the
+ *                             waves' tiles are summed in a fixed order at
+ *                             the end, and the output is the same padded
+ *                             tile as modes 1 .. 5 write. One right-hand
+ *                             side per work-group. Resolved to 5 (and so
+ *                             on) where not supported.
  *                             Default 1; the row sweep wins with many
  *                             right-hand sides per call, and in float32
  *                             takes two of them per wave when

@@ -39,9 +39,19 @@ DEVICE_FLAGS = [
 ]
 
 
+# Per-file additions. The matrix-core register tile clears single
+# accumulator elements between operations; with the accumulators in
+# ordinary VGPRs that is one move per element instead of a round trip of
+# the whole accumulator through AGPRs.
+FILE_FLAGS = {
+    "spread_mma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *DEVICE_FLAGS, f"-I{INCLUDE}", "-c", src, "-o", obj]
+    extra = FILE_FLAGS.get(os.path.basename(src), [])
+    cmd = [hipcc(), *DEVICE_FLAGS, *extra, f"-I{INCLUDE}", "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -240,8 +240,11 @@ int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, in
   if (planes != 1 && planes != 2)
     return fail(p, NFFT_EINVAL, "spread planes %d: expected 1 or 2", planes);
   int& mode = out[NFFT_TUNE_SPREAD_MODE];
-  if (mode < 1 || mode > 6)
-    return fail(p, NFFT_EINVAL, "spread mode %d: expected 1 .. 6", mode);
+  if (mode < 1 || mode > 7)
+    return fail(p, NFFT_EINVAL, "spread mode %d: expected 1 .. 7", mode);
+  // the matrix-core register tile: float32, d = 2, tile edge 16, 2m + 1 <= 16;
+  // elsewhere the vector register tile (and its own fallback)
+  if (mode == 7 && !nfft::spread_mma_supported(d, T, precision == NFFT_F64, m)) mode = 5;
   // the grid-tile gather: float32, d = 2, tile edge 16, m <= 8; elsewhere
   // the register-tile kernel (and its own fallback)
   if (mode == 6 && !nfft::spread_gather_supported(d, T, precision == NFFT_F64, m)) mode = 5;
@@ -250,14 +253,15 @@ int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, in
   // kernel with the same window evaluation
   if (mode == 5 && !nfft::spread_reg_supported(d, T, precision == NFFT_F64)) mode = 4;
   if ((mode == 3 || mode == 4) && d != 2) mode = 1;  // laid out for d = 2
-  // 512 threads: the register-tile kernel only
-  if (nt == 512 && mode != 5) nt = 256;
+  // 512 threads: the register-tile kernels only
+  if (nt == 512 && mode != 5 && mode != 7) nt = 256;
   const int fw = out[NFFT_TUNE_FFT_MIN_WG];
   if (fw < 1 || fw > 65536) return fail(p, NFFT_EINVAL, "fft min work-groups %d: expected 1..65536", fw);
   const int P = T + 2 * m;
   const int Ptot = (int)ipow(P, d);
   const bool f64 = precision == NFFT_F64;
   const size_t one = mode == 6   ? nfft::spread_gather_lds_bytes(m)
+                     : mode == 7 ? nfft::spread_mma_lds_bytes(m, nt)
                      : mode == 5 ? nfft::spread_reg_lds_bytes(m)
                                  : nfft::spread_lds_bytes(d, f64, m, T, Ptot, nt, 1, planes);
   const size_t multi = out[NFFT_TUNE_RHS_PER_GROUP] > 1
@@ -1403,7 +1407,7 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
   }
   if (d <= 2 && nrhs > 1) rpg = {1, 2, 4, 8};
   if (d == 2) modes = {1, 2, 3, 4};
-  if (d == 2 && f32) modes = {1, 2, 3, 4, 5};
+  if (d == 2 && f32) modes = {1, 2, 3, 4, 5, 7};
   // the grid-tile gather holds 32 right-hand sides in the lanes of a wave
   if (d == 2 && f32 && nrhs >= 8) modes.push_back(6);
 
@@ -1449,9 +1453,9 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
             if (md) in[NFFT_TUNE_SPREAD_MODE] = md;
             // the LDS kernel's shape does not matter when another kernel spreads
             if ((nr > 1 || md == 2) && (nt != threads[0] || pl != planes[0])) continue;
-            // the register-tile kernel (mode 5) takes one rhs per work-group and
-            // no LDS tile layout
-            if (md == 5 && (nr > 1 || pl != planes[0])) continue;
+            // the register-tile kernels (modes 5, 7) take one rhs per work-group
+            // and no LDS tile layout
+            if ((md == 5 || md == 7) && (nr > 1 || pl != planes[0])) continue;
             // the gather (mode 6) has one shape
             if (md == 6 && (nr > 1 || pl != planes[0] || nt != threads[0])) continue;
             if (nt == 512 && md < 5) continue;

@@ -70,7 +70,8 @@ struct SpreadArgs {
                              // 4 LDS tiles with the window evaluated late,
                              // 5 padded tile in registers (float32),
                              // 6 grid tiles gathered for 32 rhs per work-group
-                             //   (float32; see launch_spread_gather)
+                             //   (float32; see launch_spread_gather),
+                             // 7 padded tile on the matrix cores (float32)
   const R* psi;              // d = 2: window factors [N][2m][2] in tile order (mode 3)
 };
 template <typename R>
@@ -119,6 +120,11 @@ hipError_t launch_psi(const R* frac, int64_t N, int m, const R* coef, R* psi, hi
 bool spread_reg_supported(int d, int T, bool f64);
 size_t spread_reg_lds_bytes(int m);
 hipError_t launch_spread_reg(const SpreadArgs<float>& a, int nrhs, hipStream_t s);
+// Padded tile on the matrix cores, one tile row of nodes at a time (float32,
+// d = 2, tile edge 16, 2m + 1 <= 16, nodes row-sorted within tiles).
+bool spread_mma_supported(int d, int T, bool f64, int m);
+size_t spread_mma_lds_bytes(int m, int nt);
+hipError_t launch_spread_mma(const SpreadArgs<float>& a, int nrhs, hipStream_t s);
 // Several right-hand sides per work-group (d <= 2, nr > 1).
 template <typename R>
 hipError_t launch_spread_multi(const SpreadArgs<R>& a, int nrhs, hipStream_t s);

@@ -248,26 +248,22 @@ __global__ __launch_bounds__(256) void tile_reduce_kernel(ReduceArgs<R> a) {
   if (cell >= Ptot) return;
   const int s0 = a.multi_first[tix], s1 = a.multi_first[tix + 1];
   const cplx<R>* itemp = a.itemp + blockIdx.y * a.item_rs;
-  // four interleaved compensated sums keep four loads in flight; they are
-  // combined in a fixed order, so the result does not depend on timing
+  // slot k goes to compensated sum (k - s0) mod 4; the four are combined in
+  // a fixed order, so the result does not depend on timing. The loads of up
+  // to 16 slots are issued before the first add (one memory latency for a
+  // tile of at most 16 items).
   KSum<R> sx[4], sy[4];
-  int sidx = s0;
-  for (; sidx + 4 <= s1; sidx += 4) {
-    cplx<R> v[4];
+  for (int base = s0; base < s1; base += 16) {
+    cplx<R> v[16];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = itemp[(int64_t)(sidx + u) * Ptot + cell];
+    for (int u = 0; u < 16; ++u)
+      v[u] = base + u < s1 ? itemp[(int64_t)(base + u) * Ptot + cell] : mkc<R>(0, 0);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      sx[u].add(v[u].x);
-      sy[u].add(v[u].y);
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < 3; ++u) {
-    if (sidx + u < s1) {
-      const cplx<R> v = itemp[(int64_t)(sidx + u) * Ptot + cell];
-      sx[u].add(v.x);
-      sy[u].add(v.y);
+    for (int u = 0; u < 16; ++u) {
+      if (base + u < s1) {
+        sx[u & 3].add(v[u].x);
+        sy[u & 3].add(v[u].y);
+      }
     }
   }
   KSum<R> tx, ty;
@@ -506,6 +502,8 @@ hipError_t launch_spread(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
   if constexpr (std::is_same<R, float>::value) {
     if (a.mode == 5 && spread_reg_supported(a.g.d, a.g.T, false))
       return launch_spread_reg(a, nrhs, s);
+    if (a.mode == 7 && spread_mma_supported(a.g.d, a.g.T, false, a.g.m))
+      return launch_spread_mma(a, nrhs, s);
   }
   if (a.mode == 3 && a.psi && a.g.d == 2) return launch_spread_pre<R>(a, nrhs, s);
   if (a.mode == 4 && a.g.d == 2) return launch_spread_late<R>(a, nrhs, s);

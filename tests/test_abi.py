@@ -85,7 +85,10 @@ def test_f64_3d_large_m_unsupported():
     (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 70000], _lib.NFFT_EINVAL),  # fft min work-groups
     (2, 6, _lib.NFFT_F32, [-1], _lib.NFFT_EINVAL),                # negative entry
     (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 3], _lib.NFFT_EINVAL),  # spread planes not 1/2
-    (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 7], _lib.NFFT_EINVAL),  # spread mode not 1..6
+    (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 8], _lib.NFFT_EINVAL),  # spread mode not 1..7
+    (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 7], _lib.NFFT_OK),   # padded tile on the matrix cores
+    (2, 8, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 7], _lib.NFFT_OK),   # 2m + 1 > 16: resolved to mode 5
+    (2, 6, _lib.NFFT_F32, [0, 0, 512, 0, 0, 0, 7], _lib.NFFT_OK),  # eight waves a work-group
     (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 6], _lib.NFFT_OK),   # grid-tile gather
     (2, 6, _lib.NFFT_F64, [0, 0, 0, 0, 0, 0, 6], _lib.NFFT_OK),   # float64: resolved to mode 4
     (2, 6, _lib.NFFT_F32, [8, 0, 0, 0, 0, 0, 6], _lib.NFFT_OK),   # tile edge 8: resolved to mode 4

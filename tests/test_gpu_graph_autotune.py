@@ -26,7 +26,7 @@ def _plan(x, M, m, prec, **kw):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("nrhs,tuning", [(1, None), (4, {"rhs_per_group": 2}), (3, {"rhs_per_group": 1}),
-                                         (1, {"spread_mode": 5}),
+                                         (1, {"spread_mode": 5}), (2, {"spread_mode": 7}),
                                          (9, {"spread_mode": 6, "item_nodes": 128})])
 def test_graph_replays_match_eager(prec, nrhs, tuning):
     M, m = 64, 5

@@ -273,7 +273,7 @@ def _sample_k(M, d, n, seed):
 
 
 # "auto": the autotuned plan, the launch configuration the benchmark times
-@pytest.mark.parametrize("tuning", [None, "auto"])
+@pytest.mark.parametrize("tuning", [None, "auto", {"spread_mode": 5}, {"spread_mode": 7}])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_polar_512x512_M256(prec, tuning):
     """Polar grid R = T = 512 (N = 262144), M = 256, sigma = 2, m = 6, area

@@ -93,11 +93,18 @@ TUNINGS = [
     {"spread_mode": 6},
     {"spread_mode": 6, "item_nodes": 32},
     {"spread_mode": 6, "tile_edge": 8},   # the gather needs tile edge 16: mode 4
+    {"spread_mode": 7},
+    {"spread_mode": 7, "spread_threads": 256, "item_nodes": 1000},
+    {"spread_mode": 7, "item_nodes": 32},
+    {"spread_mode": 7, "item_nodes": 2048},
+    {"spread_mode": 7, "tile_edge": 8},   # register tiles need tile edge 16: mode 4
+    {"spread_mode": 7, "spread_threads": 512, "item_nodes": 1024},
+    {"spread_mode": 7, "spread_threads": 64},
 ]
 
-# the mode the register-tile kernel and the grid-tile gather resolve to where
+# the mode the register-tile kernels and the grid-tile gather resolve to where
 # they do not apply (float64, a tile edge other than 16)
-REG_FALLBACK = {5: 4, 6: 4}
+REG_FALLBACK = {5: 4, 6: 4, 7: 4}
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -269,17 +276,19 @@ def test_row_sweep_multi_rhs(prec, m, rpg):
     p.close()
 
 
+@pytest.mark.parametrize("mode", [5, 7])
 @pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("items", [600, 1024])
 @pytest.mark.parametrize("nt", [128, 256, 512])
-def test_register_tile_spreading(m, items, nt):
-    """Spread mode 5 (float32, d = 2, tile edge 16) keeps the padded tile in
-    registers: against the oracle (O2) and against the LDS kernel of mode 1
-    on the same plan (another summation order), for three right-hand sides,
-    with grid-aligned nodes (closed edge), a crowded cluster whose tiles split
+def test_register_tile_spreading(mode, m, items, nt):
+    """Spread modes 5 and 7 (float32, d = 2, tile edge 16) keep the padded
+    tile of a work item in registers, on the vector ALUs (5) or as slots of
+    matrix-core accumulators (7; 2m + 1 <= 16, so m = 8 resolves to 5):
+    against the oracle (O2) and against the LDS kernel of mode 1 on the same
+    plan (another summation order), for three right-hand sides, with
+    grid-aligned nodes (closed edge), a crowded cluster whose tiles split
     into several work items, and work items longer than one staged batch of
-    256 nodes."""
-    mode = 5
+    512 nodes."""
     M = 32
     x = _nodes(2, M, 300 + m)
     N = x.shape[0]
@@ -290,7 +299,7 @@ def test_register_tile_spreading(m, items, nt):
     a1 = _np(p.adjoint(torch.from_numpy(F)))
     p.set_tuning("spread_mode", mode)
     p.set_tuning("spread_threads", nt)
-    assert p.tuning()["spread_mode"] == mode
+    assert p.tuning()["spread_mode"] == (5 if mode == 7 and m == 8 else mode)
     got = _np(p.adjoint(torch.from_numpy(F)))
     ref = onfft.adjoint(x, w[None, :] * F, M, 2.0, m)
     for r in range(3):
