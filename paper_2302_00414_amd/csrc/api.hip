@@ -242,9 +242,12 @@ int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, in
   int& mode = out[NFFT_TUNE_SPREAD_MODE];
   if (mode < 1 || mode > 7)
     return fail(p, NFFT_EINVAL, "spread mode %d: expected 1 .. 7", mode);
-  // the matrix-core register tile: float32, d = 2, tile edge 16, 2m + 1 <= 16;
-  // elsewhere the vector register tile (and its own fallback)
-  if (mode == 7 && !nfft::spread_mma_supported(d, T, precision == NFFT_F64, m)) mode = 5;
+  // the matrix-core register tile: float32, d = 2, tile edge 16, 2m + 1 <= 16,
+  // or d = 3, tile edge 8, 2m <= 8; elsewhere the vector register tile (and
+  // its own fallback)
+  if (mode == 7 && !nfft::spread_mma_supported(d, T, precision == NFFT_F64, m) &&
+      !nfft::spread3_mma_supported(d, T, precision == NFFT_F64, m))
+    mode = 5;
   // the grid-tile gather: float32, d = 2, tile edge 16, m <= 8; elsewhere
   // the register-tile kernel (and its own fallback)
   if (mode == 6 && !nfft::spread_gather_supported(d, T, precision == NFFT_F64, m)) mode = 5;
@@ -261,6 +264,7 @@ int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, in
   const int Ptot = (int)ipow(P, d);
   const bool f64 = precision == NFFT_F64;
   const size_t one = mode == 6   ? nfft::spread_gather_lds_bytes(m)
+                     : mode == 7 && d == 3 ? nfft::spread3_mma_lds_bytes()
                      : mode == 7 ? nfft::spread_mma_lds_bytes(m, nt)
                      : mode == 5 ? nfft::spread_reg_lds_bytes(m)
                                  : nfft::spread_lds_bytes(d, f64, m, T, Ptot, nt, 1, planes);
@@ -751,9 +755,9 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
                                      (const int32_t*)offsets, (const uint32_t*)loc_u,
                                      (const double*)frac_u, N, d, g.nbins, p->perm, p->loc,
                                      (R*)p->frac, s));
-  if (d == 2) {
-    // within each tile, nodes ordered by tile row (the register row-sweep
-    // spreading consumes them row by row)
+  if (d >= 2) {
+    // within each tile, nodes ordered by their dimension-0 cell (the register
+    // row sweeps and the matrix-core tiles consume them row by row)
     void *perm2, *loc2, *frac2;
     TRY(talloc(&perm2, N * sizeof(int32_t)));
     TRY(talloc(&loc2, N * sizeof(uint32_t)));
@@ -1408,6 +1412,7 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
   if (d <= 2 && nrhs > 1) rpg = {1, 2, 4, 8};
   if (d == 2) modes = {1, 2, 3, 4};
   if (d == 2 && f32) modes = {1, 2, 3, 4, 5, 7};
+  if (d == 3 && f32) modes = {1, 7};
   // the grid-tile gather holds 32 right-hand sides in the lanes of a wave
   if (d == 2 && f32 && nrhs >= 8) modes.push_back(6);
 

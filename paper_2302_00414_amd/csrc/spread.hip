@@ -504,6 +504,8 @@ hipError_t launch_spread(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
       return launch_spread_reg(a, nrhs, s);
     if (a.mode == 7 && spread_mma_supported(a.g.d, a.g.T, false, a.g.m))
       return launch_spread_mma(a, nrhs, s);
+    if (a.mode == 7 && spread3_mma_supported(a.g.d, a.g.T, false, a.g.m))
+      return launch_spread3_mma(a, nrhs, s);
   }
   if (a.mode == 3 && a.psi && a.g.d == 2) return launch_spread_pre<R>(a, nrhs, s);
   if (a.mode == 4 && a.g.d == 2) return launch_spread_late<R>(a, nrhs, s);

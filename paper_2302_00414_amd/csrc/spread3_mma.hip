@@ -1,0 +1,196 @@
+// Spreading for d = 3 in float32 on the matrix cores (Algorithm 2.4 step 1
+// with the weights of (3.7)), tile edge 8 and 2m <= 8, so that the padded
+// tile of a work item (P = 8 + 2m <= 16 cells per dimension) fits in the
+// accumulators of one wave: plane i0 of the padded tile is one 16 x 16 block
+// (rows i1, columns i2) of v_mfma_f32_16x16x4f32 accumulators, real and
+// imaginary part, 2P blocks in all.
+//
+// A node at tile-local cell (l0, l1, l2) reaches the padded cells
+// (l0 + 1 + p0, l1 + 1 + p1, l2 + 1 + p2), p_t < 2m, with the window factors
+// a(p0) b(p1) e(p2), and on a grid plane of dimension t also the closed-edge
+// cell l_t of that dimension. For one plane i0 = l0 + 1 + p0 the update is
+//     G[i0][i1][i2] += sum_n (a_n(p0) b_n[i1] c_n) e_n[i2],
+// a product whose inner dimension runs over the nodes: four nodes of the
+// same tile row l0 = r at a time, lane (k, i) supplies A_k[i] = a_k(p0)
+// b_k[i] c_k and B_k[i] = e_k[i], two operations (real, imaginary part) per
+// plane. The planes a tile row reaches are compile-time constants (the
+// nodes of a tile are sorted by l0 at plan time and the node loop runs
+// inside an unrolled loop over the 8 tile rows and the 2m planes); a_k(p0)
+// reaches the lanes of node k by a DPP row broadcast, b_k and e_k by
+// ds_bpermute from the lanes that evaluated the window polynomials.
+// The padded tile is written out like the other kernels' (the split-tile
+// sums and the first FFT pass merge the tiles).
+#include "spread_common.hpp"
+
+namespace nfft {
+
+namespace {
+
+typedef float mma3_v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float lane_read3(float v, int byte_addr) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(byte_addr, __float_as_int(v)));
+}
+
+// sign-extended 8-bit field
+__device__ __forceinline__ int sext8(int v) { return (v << 24) >> 24; }
+
+}  // namespace
+
+// Nodes staged per batch; one wave per work item.
+constexpr int k3MmaBatch = 256;
+constexpr int k3MmaT = 8;
+
+template <int MW>
+__global__ __launch_bounds__(64) void spread3_mma_kernel(SpreadArgs<float> a) {
+  constexpr int K2 = 2 * MW;
+  constexpr int T = k3MmaT;
+  constexpr int P = T + K2;
+  constexpr int NB = k3MmaBatch;
+  constexpr int DEG = PolyDeg<float>::value;
+  static_assert(P <= 16, "a plane of the padded tile is one 16 x 16 block");
+  // node b: y0, y1, y2, Re c; Im c, edge factor of dimension 1 and of
+  // dimension 2 (0 off a grid plane), and a word: -(l1 + 1) in bits 0-7,
+  // -(l2 + 1) in bits 8-15, the edge flag of dimension 0 in bit 16, l0 from
+  // bit 20. Entry NB is a node with c = 0 for the missing members of a
+  // row's last group.
+  __shared__ float4 st_a[NB + 1];
+  __shared__ float4 st_b[NB + 1];
+  __shared__ int st_rs[T + 1];
+
+  const int item = blockIdx.x;
+  const int rhs = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int kq = lane >> 4;    // node of the group of four; accumulator row quarter
+  const int j = lane & 15;     // row i1 (A), column i2 (B), polynomial (Horner)
+  const int lrow = lane & 48;  // first lane of this lane's 16-lane row
+  const int pc = j < K2 ? j : K2 - 1;
+
+  float cf[DEG + 1];
+#pragma unroll
+  for (int q = 0; q <= DEG; ++q) cf[q] = a.coef[pc * (DEG + 1) + q];
+
+  mma3_v4f acc[P][2];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    acc[i][0] = mma3_v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    acc[i][1] = acc[i][0];
+  }
+
+  const int64_t N = a.g.N;
+  const int start = a.item_start[item];
+  const int cnt = a.item_count[item];
+  const float2* f = a.f + rhs * a.f_rs;
+  const float edge = a.edge;
+
+  if (lane == 0) {
+    st_a[NB] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    st_b[NB] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(0));
+  }
+  for (int b0 = 0; b0 < cnt; b0 += NB) {
+    const int nb = (cnt - b0) < NB ? (cnt - b0) : NB;
+    __syncthreads();  // the previous batch is consumed
+    for (int t = lane; t < nb; t += 64) {
+      const int i = start + b0 + t;
+      const float2 wv = a.w[i];
+      const float2 fv = f[a.perm[i]];
+      const uint32_t L = a.loc[i];
+      const int l0 = (int)(L & kLocMask);
+      const int l1 = (int)((L >> kLocBits) & kLocMask);
+      const int l2 = (int)((L >> (2 * kLocBits)) & kLocMask);
+      st_a[t] = make_float4(2.0f * a.frac[i] - 1.0f, 2.0f * a.frac[N + i] - 1.0f,
+                            2.0f * a.frac[2 * N + i] - 1.0f, wv.x * fv.x - wv.y * fv.y);
+      st_b[t] = make_float4(wv.x * fv.y + wv.y * fv.x,
+                            ((L >> (kEdgeShift + 1)) & 1u) ? edge : 0.0f,
+                            ((L >> (kEdgeShift + 2)) & 1u) ? edge : 0.0f,
+                            __int_as_float(((-(l1 + 1)) & 0xff) | (((-(l2 + 1)) & 0xff) << 8) |
+                                           (int)(((L >> kEdgeShift) & 1u) << 16) | (l0 << 20)));
+    }
+    __syncthreads();
+    // first node of each tile row (the batch is sorted by l0)
+    for (int t = lane; t < nb; t += 64) {
+      const int rt = __float_as_int(st_b[t].w) >> 20;
+      const int rp = t > 0 ? __float_as_int(st_b[t - 1].w) >> 20 : -1;
+      for (int r = rp + 1; r <= rt; ++r) st_rs[r] = t;
+      if (t == nb - 1)
+        for (int r = rt + 1; r <= T; ++r) st_rs[r] = nb;
+    }
+    __syncthreads();
+
+    static_for<0, T>([&](auto rc) {
+      constexpr int r = decltype(rc)::value;
+      const int n0 = __builtin_amdgcn_readfirstlane(st_rs[r]);
+      const int n1 = __builtin_amdgcn_readfirstlane(st_rs[r + 1]);
+      for (int g = n0; g < n1; g += 4) {
+        const int n = g + kq;
+        const bool valid = n < n1;
+        const int nn = valid ? n : NB;
+        const float4 na = st_a[nn];
+        const float4 nbv = st_b[nn];
+        const int bits = __float_as_int(nbv.w);
+        const int q1 = j + sext8(bits & 0xff);         // window cell of row i1 = j
+        const int q2 = j + sext8((bits >> 8) & 0xff);  // window cell of column i2 = j
+        const float h0 = horner<float>(cf, na.x);
+        const float h1 = horner<float>(cf, na.y);
+        const float h2 = horner<float>(cf, na.z);
+        const float v1 = lane_read3(h1, (lrow | (q1 & 15)) << 2);
+        const float v2 = lane_read3(h2, (lrow | (q2 & 15)) << 2);
+        const float b1 = (unsigned)q1 < (unsigned)K2 ? v1 : (q1 == -1 ? nbv.y : 0.0f);
+        const float e2 = (unsigned)q2 < (unsigned)K2 ? v2 : (q2 == -1 ? nbv.z : 0.0f);
+        const float ur = b1 * na.w;
+        const float ui = b1 * nbv.x;
+        static_for<0, K2>([&](auto pc_) {
+          constexpr int p = decltype(pc_)::value;
+          const float a0 = row_bcast<p>(h0);  // polynomial p at node kq's y0
+          acc[r + 1 + p][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0 * ur, e2, acc[r + 1 + p][0], 0, 0, 0);
+          acc[r + 1 + p][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0 * ui, e2, acc[r + 1 + p][1], 0, 0, 0);
+        });
+        // closed-edge plane r of nodes on a grid plane of dimension 0
+        const bool e0 = valid && ((bits >> 16) & 1);
+        if (__builtin_amdgcn_ballot_w64(e0)) {
+          const float ee = e0 ? edge : 0.0f;
+          acc[r][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ee * ur, e2, acc[r][0], 0, 0, 0);
+          acc[r][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ee * ui, e2, acc[r][1], 0, 0, 0);
+        }
+      }
+    });
+  }
+
+  // accumulator element v of lane l: row i1 = 4 (l >> 4) + v, column i2 = l & 15
+  const int slot = a.item_slot[item];
+  constexpr int Ptot = P * P * P;
+  float2* out = slot < 0 ? a.tilep + rhs * a.tile_rs + (int64_t)a.item_bin[item] * Ptot
+                         : a.itemp + rhs * a.item_rs + (int64_t)slot * Ptot;
+#pragma unroll
+  for (int i0 = 0; i0 < P; ++i0)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i1 = 4 * kq + v;
+      if (i1 < P && j < P) out[(i0 * P + i1) * P + j] = make_float2(acc[i0][0][v], acc[i0][1][v]);
+    }
+}
+
+bool spread3_mma_supported(int d, int T, bool f64, int m) {
+  return d == 3 && T == k3MmaT && !f64 && m >= 1 && k3MmaT + 2 * m <= 16;
+}
+
+// the kernel's staging arrays (static LDS)
+size_t spread3_mma_lds_bytes() {
+  return (size_t)2 * (k3MmaBatch + 1) * sizeof(float4) + (k3MmaT + 1) * sizeof(int);
+}
+
+hipError_t launch_spread3_mma(const SpreadArgs<float>& a, int nrhs, hipStream_t s) {
+  if (!spread3_mma_supported(a.g.d, a.g.T, false, a.g.m)) return hipErrorInvalidValue;
+  if (a.g.nsub == 0) return hipSuccess;
+  const dim3 grid(a.g.nsub, nrhs);
+  switch (a.g.m) {
+    case 1: hipLaunchKernelGGL((spread3_mma_kernel<1>), grid, dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((spread3_mma_kernel<2>), grid, dim3(64), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((spread3_mma_kernel<3>), grid, dim3(64), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((spread3_mma_kernel<4>), grid, dim3(64), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace nfft

@@ -301,7 +301,7 @@ def _c3_inputs():
     return x, w, f, onfft.adjoint(x, w * f, 64, 2.0, 4)
 
 
-@pytest.mark.parametrize("tuning", [None, "auto"])
+@pytest.mark.parametrize("tuning", [None, "auto", {"spread_mode": 7}])
 def test_jittered_3d_M64(tuning):
     """Jittered 128 x 64 x 64 grid (N = 524288), d = 3, M = 64, m = 4, float32:
     the full output vector against the step-by-step oracle (O2), and sampled
