@@ -11,13 +11,15 @@
 // cell l_t of that dimension. For one plane i0 = l0 + 1 + p0 the update is
 //     G[i0][i1][i2] += sum_n (a_n(p0) b_n[i1] c_n) e_n[i2],
 // a product whose inner dimension runs over the nodes: four nodes of the
-// same tile row l0 = r at a time, lane (k, i) supplies A_k[i] = a_k(p0)
-// b_k[i] c_k and B_k[i] = e_k[i], two operations (real, imaginary part) per
+// same tile row l0 = r at a time, lane (k, i) supplies A_k[i] = b_k[i] c_k
+// (real or imaginary part) and B_k[i] = a_k(p0) e_k[i], two operations per
 // plane. The planes a tile row reaches are compile-time constants (the
 // nodes of a tile are sorted by l0 at plan time and the node loop runs
-// inside an unrolled loop over the 8 tile rows and the 2m planes); a_k(p0)
-// reaches the lanes of node k by a DPP row broadcast, b_k and e_k by
-// ds_bpermute from the lanes that evaluated the window polynomials.
+// inside an unrolled loop over the 8 tile rows and the 2m planes). Lane
+// (k, p) of a node's 16-lane row evaluates window polynomial p at the
+// node's dimension-0 and dimension-1 offsets, lane (k, 8 + p) at its
+// dimension-2 offset; a_k(p0) reaches the lanes of node k by a DPP row
+// broadcast, b_k and e_k by ds_bpermute.
 // The padded tile is written out like the other kernels' (the split-tile
 // sums and the first FFT pass merge the tiles).
 #include "spread_common.hpp"
@@ -64,7 +66,8 @@ __global__ __launch_bounds__(64) void spread3_mma_kernel(SpreadArgs<float> a) {
   const int kq = lane >> 4;    // node of the group of four; accumulator row quarter
   const int j = lane & 15;     // row i1 (A), column i2 (B), polynomial (Horner)
   const int lrow = lane & 48;  // first lane of this lane's 16-lane row
-  const int pc = j < K2 ? j : K2 - 1;
+  const int pc = (j & 7) < K2 ? (j & 7) : K2 - 1;
+  const bool lo8 = j < 8;
 
   float cf[DEG + 1];
 #pragma unroll
@@ -130,27 +133,27 @@ __global__ __launch_bounds__(64) void spread3_mma_kernel(SpreadArgs<float> a) {
         const int bits = __float_as_int(nbv.w);
         const int q1 = j + sext8(bits & 0xff);         // window cell of row i1 = j
         const int q2 = j + sext8((bits >> 8) & 0xff);  // window cell of column i2 = j
-        const float h0 = horner<float>(cf, na.x);
-        const float h1 = horner<float>(cf, na.y);
-        const float h2 = horner<float>(cf, na.z);
-        const float v1 = lane_read3(h1, (lrow | (q1 & 15)) << 2);
-        const float v2 = lane_read3(h2, (lrow | (q2 & 15)) << 2);
+        // lanes p < 8: polynomial p at y0 (hA) and y1 (hB); lanes 8 + p: at y2 (hA)
+        const float hA = horner<float>(cf, lo8 ? na.x : na.z);
+        const float hB = horner<float>(cf, na.y);
+        const float v1 = lane_read3(hB, (lrow | (q1 & 7)) << 2);
+        const float v2 = lane_read3(hA, (lrow | 8 | (q2 & 7)) << 2);
         const float b1 = (unsigned)q1 < (unsigned)K2 ? v1 : (q1 == -1 ? nbv.y : 0.0f);
         const float e2 = (unsigned)q2 < (unsigned)K2 ? v2 : (q2 == -1 ? nbv.z : 0.0f);
         const float ur = b1 * na.w;
         const float ui = b1 * nbv.x;
         static_for<0, K2>([&](auto pc_) {
           constexpr int p = decltype(pc_)::value;
-          const float a0 = row_bcast<p>(h0);  // polynomial p at node kq's y0
-          acc[r + 1 + p][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0 * ur, e2, acc[r + 1 + p][0], 0, 0, 0);
-          acc[r + 1 + p][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0 * ui, e2, acc[r + 1 + p][1], 0, 0, 0);
+          const float bp = row_bcast<p>(hA) * e2;  // a_kq(p) e_kq[i2]
+          acc[r + 1 + p][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ur, bp, acc[r + 1 + p][0], 0, 0, 0);
+          acc[r + 1 + p][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ui, bp, acc[r + 1 + p][1], 0, 0, 0);
         });
         // closed-edge plane r of nodes on a grid plane of dimension 0
         const bool e0 = valid && ((bits >> 16) & 1);
         if (__builtin_amdgcn_ballot_w64(e0)) {
-          const float ee = e0 ? edge : 0.0f;
-          acc[r][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ee * ur, e2, acc[r][0], 0, 0, 0);
-          acc[r][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ee * ui, e2, acc[r][1], 0, 0, 0);
+          const float be = e0 ? edge * e2 : 0.0f;
+          acc[r][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ur, be, acc[r][0], 0, 0, 0);
+          acc[r][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ui, be, acc[r][1], 0, 0, 0);
         }
       }
     });
