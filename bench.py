@@ -369,6 +369,17 @@ def run_jittered3d(steps, precs=("f32", "f64"), tuning="auto"):
         res[prec] = dict(ms_per_step=ms, points_per_s=N / (ms / 1e3), tuning=plan.tuning(),
                          stage_us={k: round(v[0] / max(v[1], 1) * 1e3, 3)
                                    for k, v in st.items() if v[1]})
+        us = res[prec]["stage_us"].get("spread", 0)
+        if prec == "f32" and us > 0:
+            # the spreading stage against the float32 peak: (2m)^3 window
+            # cells per node, a complex sample times a real factor
+            fl = spread_flops(N, m3, 3)
+            mfma = plan.tuning()["spread_mode"] == 7
+            res[prec]["spread_roofline"] = dict(
+                bound="mfma" if mfma else "alu", achieved=round(fl / (us * 1e-6) / 1e12, 3),
+                peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                frac=round(fl / (us * 1e-6) / 1e12 / FP32_PEAK_TFLOPS, 4), algorithmic_flops=fl,
+                us=round(us, 2))
         plan.close()
     return dict(workload="jittered 128x64x64 (N=524288), d=3, M=64, sigma=2, m=4, w=1/N", **res)
 

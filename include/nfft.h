@@ -169,9 +169,13 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
  *                             slots that shift with the tile row); the
  *                             waves' tiles are summed in a fixed order at
  *                             the end, and the output is the same padded
- *                             tile as modes 1 .. 5 write. One right-hand
- *                             side per work-group. Resolved to 5 (and so
- *                             on) where not supported.
+ *                             tile as modes 1 .. 5 write. Also float32,
+ *                             d = 3, tile edge 8, 2m <= 8: one wave holds
+ *                             the padded 3-D tile (one 16 x 16 block per
+ *                             plane) and takes four nodes of one tile row
+ *                             at a time. One right-hand side per
+ *                             work-group. Resolved to 5 (and so on; mode 1
+ *                             for d = 3) where not supported.
  *                             Default 1; the row sweep wins with many
  *                             right-hand sides per call, and in float32
  *                             takes two of them per wave when
