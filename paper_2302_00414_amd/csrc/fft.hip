@@ -2,8 +2,9 @@
 // Stockham autosort with radix-8/4/2 butterflies.
 //
 // One launch transforms every line of one dimension of a d-dimensional
-// array. A work-group holds `lpw` whole lines of length L in LDS (two
-// ping-pong buffers). Lines are read contiguously and the transformed axis
+// array. A work-group holds `lpw` whole lines of length L in LDS (one
+// buffer, each stage read into registers and written back in place) and a
+// copy of the pass's twiddle table. Lines are read contiguously and the transformed axis
 // is written as the new slowest axis, so after d passes the array is back in
 // C order and every pass reads contiguous lines. Each pass is fused with its
 // neighbours' elementwise work:
@@ -76,39 +77,53 @@ __device__ __forceinline__ void dft8(cplx<R>* a) {
 // power-of-two strides of the Stockham passes across the LDS banks.
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 3); }
 
-// One Stockham pass of radix RAD over `lpw` lines of length L.
-template <typename R, int RAD, bool INV>
-__device__ __forceinline__ void stockham_pass(const cplx<R>* src, cplx<R>* dst, int L, int LS,
-                                              int lpw, int Ns, const cplx<R>* __restrict__ tw) {
+// One Stockham pass of radix RAD over `lpw` lines of length L, in place:
+// every thread reads the butterflies it owns (NIT of them, RAD elements
+// each) into registers, the work-group waits, then every thread writes its
+// results.
+template <typename R, int RAD, int NIT, bool INV>
+__device__ __forceinline__ void stockham_inplace(cplx<R>* buf, int L, int LS, int lpw, int Ns,
+                                                 const cplx<R>* __restrict__ tw) {
   const int nbf = L / RAD;
-  for (int q = threadIdx.x; q < lpw * nbf; q += blockDim.x) {
-    const int line = q / nbf;
-    const int j = q - line * nbf;
-    const cplx<R>* s = src + line * LS;
-    cplx<R>* o = dst + line * LS;
-    cplx<R> a[RAD];
+  const int total = lpw * nbf;
+  cplx<R> a[NIT][RAD];
 #pragma unroll
-    for (int r = 0; r < RAD; ++r) a[r] = s[lpad(j + r * nbf)];
-    const int jm = j & (Ns - 1);
-    if (Ns > 1) {
-      const int step = jm * (L / (Ns * RAD));
+  for (int it = 0; it < NIT; ++it) {
+    const int q = threadIdx.x + it * blockDim.x;
+    if (q < total) {
+      const int line = q / nbf;
+      const int j = q - line * nbf;
+      const cplx<R>* s = buf + line * LS;
 #pragma unroll
-      for (int r = 1; r < RAD; ++r) {
-        cplx<R> w = tw[step * r];
-        if (INV) w.y = -w.y;
-        a[r] = cmul<R>(a[r], w);
+      for (int r = 0; r < RAD; ++r) a[it][r] = s[lpad(j + r * nbf)];
+      const int jm = j & (Ns - 1);
+      if (Ns > 1) {
+        const int step = jm * (L / (Ns * RAD));
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) {
+          cplx<R> w = tw[step * r];
+          if (INV) w.y = -w.y;
+          a[it][r] = cmul<R>(a[it][r], w);
+        }
       }
+      if constexpr (RAD == 8) dft8<R, INV>(a[it]);
+      else if constexpr (RAD == 4) dft4<R, INV>(a[it][0], a[it][1], a[it][2], a[it][3]);
+      else dft2<R, INV>(a[it]);
     }
-    if constexpr (RAD == 8) {
-      dft8<R, INV>(a);
-    } else if constexpr (RAD == 4) {
-      dft4<R, INV>(a[0], a[1], a[2], a[3]);
-    } else {
-      dft2<R, INV>(a);
-    }
-    const int idx = (j - jm) * RAD + jm;
+  }
+  __syncthreads();
 #pragma unroll
-    for (int r = 0; r < RAD; ++r) o[lpad(idx + r * Ns)] = a[r];
+  for (int it = 0; it < NIT; ++it) {
+    const int q = threadIdx.x + it * blockDim.x;
+    if (q < total) {
+      const int line = q / nbf;
+      const int j = q - line * nbf;
+      const int jm = j & (Ns - 1);
+      cplx<R>* o = buf + line * LS;
+      const int idx = (j - jm) * RAD + jm;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) o[lpad(idx + r * Ns)] = a[it][r];
+    }
   }
 }
 
@@ -370,6 +385,10 @@ __device__ __forceinline__ void store_elem(const FftArgs<R>& a, int b, int64_t q
 // output elements it writes (the transformed axis becomes the slowest, so
 // consecutive lines are consecutive outputs) then share that XCD's L2
 // instead of being split into partial cache lines between XCDs.
+// work-groups of a pass from which on a first stage of radix 4 or 2 also
+// reads its twiddles from an LDS copy
+constexpr int64_t kFftTwiddleLdsGroups = 2048;
+
 __device__ __forceinline__ int64_t xcd_block(unsigned bx, unsigned nblk) {
   if (nblk < 16 || (nblk & 7) != 0) return bx;
   return (int64_t)(bx & 7) * (nblk >> 3) + (bx >> 3);
@@ -379,7 +398,7 @@ __device__ __forceinline__ int64_t xcd_block(unsigned bx, unsigned nblk) {
 // no twiddles); thread j of a line takes elements j + r L/R0. R0 = 8 (L/8
 // threads per line) is the default; 4 and 2 give a line more threads where a
 // pass has few lines.
-template <typename R, int LOG2L, bool INV, int LD, int ST, int R0>
+template <typename R, int LOG2L, bool INV, int LD, int ST, int R0, bool TWL>
 __global__ __launch_bounds__(512) void fft_pass_kernel(FftArgs<R> a) {
   constexpr int L = 1 << LOG2L;
   constexpr int TPL = L / R0;  // threads per line (one radix-R0 butterfly each)
@@ -388,7 +407,14 @@ __global__ __launch_bounds__(512) void fft_pass_kernel(FftArgs<R> a) {
   extern __shared__ unsigned char smem_raw[];
   const int lpw = a.lpw;      // blockDim.x == lpw * TPL
   cplx<R>* buf0 = reinterpret_cast<cplx<R>*>(smem_raw);
-  cplx<R>* buf1 = buf0 + lpw * LS;
+  // TWL: the twiddle table is copied to LDS behind the lines, where every
+  // butterfly of the later stages reads it (passes with many work-groups);
+  // else it is read from device memory (a pass of few work-groups with one
+  // line each would wait on the copy)
+  cplx<R>* twl = buf0 + lpw * LS;
+  if constexpr (TWL)
+    for (int i = threadIdx.x; i < L; i += blockDim.x) twl[i] = a.tw[i];
+  const cplx<R>* twp = TWL ? twl : a.tw;
   const int64_t nlines = a.nlines;
   const int64_t q0 = xcd_block(blockIdx.x, gridDim.x) * lpw;
   const int b = blockIdx.y;
@@ -437,28 +463,22 @@ __global__ __launch_bounds__(512) void fft_pass_kernel(FftArgs<R> a) {
   __syncthreads();
 
   cplx<R>* src = buf0;
-  cplx<R>* dst = buf1;
   int Ns = R0;
   constexpr int LOG2R0 = R0 == 8 ? 3 : (R0 == 4 ? 2 : 1);
   constexpr int n8 = (LOG2L - LOG2R0) / 3;
   constexpr int rem = (LOG2L - LOG2R0) % 3;
 #pragma unroll 1
   for (int p = 0; p < n8; ++p) {
-    stockham_pass<R, 8, INV>(src, dst, L, LS, lpw, Ns, a.tw);
+    stockham_inplace<R, 8, 1, INV>(src, L, LS, lpw, Ns, twp);
     __syncthreads();
-    cplx<R>* t = src;
-    src = dst;
-    dst = t;
     Ns *= 8;
   }
   if constexpr (rem == 2) {
-    stockham_pass<R, 4, INV>(src, dst, L, LS, lpw, Ns, a.tw);
+    stockham_inplace<R, 4, (R0 / 4 > 1 ? R0 / 4 : 1), INV>(src, L, LS, lpw, Ns, twp);
     __syncthreads();
-    src = dst;
   } else if constexpr (rem == 1) {
-    stockham_pass<R, 2, INV>(src, dst, L, LS, lpw, Ns, a.tw);
+    stockham_inplace<R, 2, R0 / 2, INV>(src, L, LS, lpw, Ns, twp);
     __syncthreads();
-    src = dst;
   }
 
   // store: consecutive threads walk across lines (the output axis is rotated)
@@ -474,11 +494,22 @@ template <typename R, int LOG2L, bool INV, int LD, int ST, int R0>
 static hipError_t fft_launch_r0(const FftArgs<R>& a, int nbatch, hipStream_t s) {
   constexpr int L = 1 << LOG2L;
   const unsigned nblk = (unsigned)((a.nlines + a.lpw - 1) / a.lpw);
-  const size_t lds = 2 * (size_t)a.lpw * (L + L / 8 + 1) * sizeof(cplx<R>);
   const int threads = a.lpw * (L / R0);
   if (threads > 512) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((fft_pass_kernel<R, LOG2L, INV, LD, ST, R0>), dim3(nblk, nbatch),
-                     dim3(threads), lds, s, a);
+  // the twiddle table in LDS for radix-8 first stages (several lines per
+  // work-group) and for passes of many work-groups
+  const size_t lines_lds = (size_t)a.lpw * (L + L / 8 + 1) * sizeof(cplx<R>);
+  if constexpr (R0 == 8) {
+    hipLaunchKernelGGL((fft_pass_kernel<R, LOG2L, INV, LD, ST, R0, true>), dim3(nblk, nbatch),
+                       dim3(threads), lines_lds + L * sizeof(cplx<R>), s, a);
+  } else {
+    if ((int64_t)nblk * nbatch >= kFftTwiddleLdsGroups)
+      hipLaunchKernelGGL((fft_pass_kernel<R, LOG2L, INV, LD, ST, R0, true>), dim3(nblk, nbatch),
+                         dim3(threads), lines_lds + L * sizeof(cplx<R>), s, a);
+    else
+      hipLaunchKernelGGL((fft_pass_kernel<R, LOG2L, INV, LD, ST, R0, false>), dim3(nblk, nbatch),
+                         dim3(threads), lines_lds, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -511,7 +542,7 @@ static hipError_t fft_modes(const FftArgs<R>& a, bool inverse, LoadMode ld, Stor
 }
 
 // Work-group shape of a pass over nlines lines of nbatch batches. Lines per
-// work-group are bounded by 64 KiB of LDS for the two buffers and by 256
+// work-group are bounded by 32 KiB of LDS for the line buffer and by 256
 // threads (L/8 butterflies per line; 512 measured slower) and lowered while
 // that leaves fewer than min_wg work-groups. A pass whose lines go one per work-group
 // and still give few work-groups gets two or four times the threads per line
@@ -520,7 +551,7 @@ static hipError_t fft_modes(const FftArgs<R>& a, bool inverse, LoadMode ld, Stor
 // calls compute; only the lines per work-group count all batches.
 template <typename R>
 static int fft_lines_per_wg(int L, int64_t lines, int min_wg) {
-  const int lds_cap = max(1, 65536 / (2 * (L + L / 8 + 1) * (int)sizeof(cplx<R>)));
+  const int lds_cap = max(1, 32768 / ((L + L / 8 + 1) * (int)sizeof(cplx<R>)));
   int lpw = max(1, min(lds_cap, 2048 / L));
   while (lpw > 1 && lines / lpw < min_wg) lpw /= 2;
   return lpw;
