@@ -93,6 +93,8 @@ __global__ __launch_bounds__(64) void spread3_mma_kernel(SpreadArgs<float> a) {
   for (int b0 = 0; b0 < cnt; b0 += NB) {
     const int nb = (cnt - b0) < NB ? (cnt - b0) : NB;
     __syncthreads();  // the previous batch is consumed
+    // two nodes a lane per step, so that their loads are in flight together
+#pragma unroll 2
     for (int t = lane; t < nb; t += 64) {
       const int i = start + b0 + t;
       const float2 wv = a.w[i];
