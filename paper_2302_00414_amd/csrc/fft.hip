@@ -2,9 +2,10 @@
 // Stockham autosort with radix-8/4/2 butterflies.
 //
 // One launch transforms every line of one dimension of a d-dimensional
-// array. A work-group holds `lpw` whole lines of length L in LDS (one
-// buffer, each stage read into registers and written back in place) and a
-// copy of the pass's twiddle table. Lines are read contiguously and the transformed axis
+// array. A work-group holds `lpw` whole lines of length L in LDS: in two
+// ping-pong buffers (passes of few work-groups), or in one buffer with each
+// stage read into registers and written back in place, beside a copy of the
+// pass's twiddle table (passes of many work-groups). Lines are read contiguously and the transformed axis
 // is written as the new slowest axis, so after d passes the array is back in
 // C order and every pass reads contiguous lines. Each pass is fused with its
 // neighbours' elementwise work:
@@ -77,10 +78,48 @@ __device__ __forceinline__ void dft8(cplx<R>* a) {
 // power-of-two strides of the Stockham passes across the LDS banks.
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 3); }
 
-// One Stockham pass of radix RAD over `lpw` lines of length L, in place:
-// every thread reads the butterflies it owns (NIT of them, RAD elements
-// each) into registers, the work-group waits, then every thread writes its
-// results.
+// One Stockham pass of radix RAD over `lpw` lines of length L, from buffer
+// src to buffer dst (the latency layout: two buffers, no barrier inside).
+template <typename R, int RAD, bool INV>
+__device__ __forceinline__ void stockham_pass(const cplx<R>* src, cplx<R>* dst, int L, int LS,
+                                              int lpw, int Ns, const cplx<R>* __restrict__ tw) {
+  const int nbf = L / RAD;
+  for (int q = threadIdx.x; q < lpw * nbf; q += blockDim.x) {
+    const int line = q / nbf;
+    const int j = q - line * nbf;
+    const cplx<R>* s = src + line * LS;
+    cplx<R>* o = dst + line * LS;
+    cplx<R> a[RAD];
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) a[r] = s[lpad(j + r * nbf)];
+    const int jm = j & (Ns - 1);
+    if (Ns > 1) {
+      const int step = jm * (L / (Ns * RAD));
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) {
+        cplx<R> w = tw[step * r];
+        if (INV) w.y = -w.y;
+        a[r] = cmul<R>(a[r], w);
+      }
+    }
+    if constexpr (RAD == 8) {
+      dft8<R, INV>(a);
+    } else if constexpr (RAD == 4) {
+      dft4<R, INV>(a[0], a[1], a[2], a[3]);
+    } else {
+      dft2<R, INV>(a);
+    }
+    const int idx = (j - jm) * RAD + jm;
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) o[lpad(idx + r * Ns)] = a[r];
+  }
+}
+
+
+// The same pass in place (the throughput layout): every thread reads the
+// butterflies it owns (NIT of them, RAD elements each) into registers, the
+// work-group waits, then every thread writes its results; one buffer, so
+// that the twiddle table fits beside the lines.
 template <typename R, int RAD, int NIT, bool INV>
 __device__ __forceinline__ void stockham_inplace(cplx<R>* buf, int L, int LS, int lpw, int Ns,
                                                  const cplx<R>* __restrict__ tw) {
@@ -385,8 +424,9 @@ __device__ __forceinline__ void store_elem(const FftArgs<R>& a, int b, int64_t q
 // output elements it writes (the transformed axis becomes the slowest, so
 // consecutive lines are consecutive outputs) then share that XCD's L2
 // instead of being split into partial cache lines between XCDs.
-// work-groups of a pass from which on a first stage of radix 4 or 2 also
-// reads its twiddles from an LDS copy
+// work-groups of a pass from which on its stages read the twiddles from an
+// LDS copy of the table (a pass of fewer work-groups is latency bound and
+// would wait on the copy; measured on 512-point passes)
 constexpr int64_t kFftTwiddleLdsGroups = 2048;
 
 __device__ __forceinline__ int64_t xcd_block(unsigned bx, unsigned nblk) {
@@ -407,14 +447,15 @@ __global__ __launch_bounds__(512) void fft_pass_kernel(FftArgs<R> a) {
   extern __shared__ unsigned char smem_raw[];
   const int lpw = a.lpw;      // blockDim.x == lpw * TPL
   cplx<R>* buf0 = reinterpret_cast<cplx<R>*>(smem_raw);
-  // TWL: the twiddle table is copied to LDS behind the lines, where every
-  // butterfly of the later stages reads it (passes with many work-groups);
-  // else it is read from device memory (a pass of few work-groups with one
-  // line each would wait on the copy)
-  cplx<R>* twl = buf0 + lpw * LS;
+  // TWL (passes with many work-groups, throughput bound): one line buffer
+  // with the stages in place and the twiddle table copied to LDS behind it,
+  // where every butterfly of the later stages reads it. Otherwise (latency
+  // bound): two line buffers, no barrier inside a stage, twiddles read from
+  // device memory.
+  cplx<R>* buf1 = buf0 + lpw * LS;
+  cplx<R>* twl = buf1;
   if constexpr (TWL)
     for (int i = threadIdx.x; i < L; i += blockDim.x) twl[i] = a.tw[i];
-  const cplx<R>* twp = TWL ? twl : a.tw;
   const int64_t nlines = a.nlines;
   const int64_t q0 = xcd_block(blockIdx.x, gridDim.x) * lpw;
   const int b = blockIdx.y;
@@ -467,18 +508,40 @@ __global__ __launch_bounds__(512) void fft_pass_kernel(FftArgs<R> a) {
   constexpr int LOG2R0 = R0 == 8 ? 3 : (R0 == 4 ? 2 : 1);
   constexpr int n8 = (LOG2L - LOG2R0) / 3;
   constexpr int rem = (LOG2L - LOG2R0) % 3;
+  if constexpr (TWL) {
 #pragma unroll 1
-  for (int p = 0; p < n8; ++p) {
-    stockham_inplace<R, 8, 1, INV>(src, L, LS, lpw, Ns, twp);
-    __syncthreads();
-    Ns *= 8;
-  }
-  if constexpr (rem == 2) {
-    stockham_inplace<R, 4, (R0 / 4 > 1 ? R0 / 4 : 1), INV>(src, L, LS, lpw, Ns, twp);
-    __syncthreads();
-  } else if constexpr (rem == 1) {
-    stockham_inplace<R, 2, R0 / 2, INV>(src, L, LS, lpw, Ns, twp);
-    __syncthreads();
+    for (int p = 0; p < n8; ++p) {
+      stockham_inplace<R, 8, 1, INV>(src, L, LS, lpw, Ns, twl);
+      __syncthreads();
+      Ns *= 8;
+    }
+    if constexpr (rem == 2) {
+      stockham_inplace<R, 4, (R0 / 4 > 1 ? R0 / 4 : 1), INV>(src, L, LS, lpw, Ns, twl);
+      __syncthreads();
+    } else if constexpr (rem == 1) {
+      stockham_inplace<R, 2, R0 / 2, INV>(src, L, LS, lpw, Ns, twl);
+      __syncthreads();
+    }
+  } else {
+    cplx<R>* dst = buf1;
+#pragma unroll 1
+    for (int p = 0; p < n8; ++p) {
+      stockham_pass<R, 8, INV>(src, dst, L, LS, lpw, Ns, a.tw);
+      __syncthreads();
+      cplx<R>* t = src;
+      src = dst;
+      dst = t;
+      Ns *= 8;
+    }
+    if constexpr (rem == 2) {
+      stockham_pass<R, 4, INV>(src, dst, L, LS, lpw, Ns, a.tw);
+      __syncthreads();
+      src = dst;
+    } else if constexpr (rem == 1) {
+      stockham_pass<R, 2, INV>(src, dst, L, LS, lpw, Ns, a.tw);
+      __syncthreads();
+      src = dst;
+    }
   }
 
   // store: consecutive threads walk across lines (the output axis is rotated)
@@ -496,20 +559,15 @@ static hipError_t fft_launch_r0(const FftArgs<R>& a, int nbatch, hipStream_t s) 
   const unsigned nblk = (unsigned)((a.nlines + a.lpw - 1) / a.lpw);
   const int threads = a.lpw * (L / R0);
   if (threads > 512) return hipErrorInvalidConfiguration;
-  // the twiddle table in LDS for radix-8 first stages (several lines per
-  // work-group) and for passes of many work-groups
+  // throughput layout (one line buffer and the twiddle table) for passes of
+  // many work-groups, latency layout (two line buffers) for the others
   const size_t lines_lds = (size_t)a.lpw * (L + L / 8 + 1) * sizeof(cplx<R>);
-  if constexpr (R0 == 8) {
+  if ((int64_t)nblk * nbatch >= kFftTwiddleLdsGroups)
     hipLaunchKernelGGL((fft_pass_kernel<R, LOG2L, INV, LD, ST, R0, true>), dim3(nblk, nbatch),
                        dim3(threads), lines_lds + L * sizeof(cplx<R>), s, a);
-  } else {
-    if ((int64_t)nblk * nbatch >= kFftTwiddleLdsGroups)
-      hipLaunchKernelGGL((fft_pass_kernel<R, LOG2L, INV, LD, ST, R0, true>), dim3(nblk, nbatch),
-                         dim3(threads), lines_lds + L * sizeof(cplx<R>), s, a);
-    else
-      hipLaunchKernelGGL((fft_pass_kernel<R, LOG2L, INV, LD, ST, R0, false>), dim3(nblk, nbatch),
-                         dim3(threads), lines_lds, s, a);
-  }
+  else
+    hipLaunchKernelGGL((fft_pass_kernel<R, LOG2L, INV, LD, ST, R0, false>), dim3(nblk, nbatch),
+                       dim3(threads), 2 * lines_lds, s, a);
   return hipGetLastError();
 }
 
@@ -542,7 +600,7 @@ static hipError_t fft_modes(const FftArgs<R>& a, bool inverse, LoadMode ld, Stor
 }
 
 // Work-group shape of a pass over nlines lines of nbatch batches. Lines per
-// work-group are bounded by 32 KiB of LDS for the line buffer and by 256
+// work-group are bounded by 32 KiB of LDS per line buffer and by 256
 // threads (L/8 butterflies per line; 512 measured slower) and lowered while
 // that leaves fewer than min_wg work-groups. A pass whose lines go one per work-group
 // and still give few work-groups gets two or four times the threads per line
