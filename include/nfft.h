@@ -104,6 +104,7 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
  *                             float32, one right-hand side per work-group:
  *                             64, 128 or 256 (default 128); 512 for spread
  *                             modes 5 and 7 (resolved to 256 for the others).
+ *                             Float64 plans use it in spread mode 7 only.
  *   NFFT_TUNE_RHS_PER_GROUP   right-hand sides that one spreading work-group
  *                             takes when nrhs > 1 and d <= 2: 1, 2, 4 or 8
  *                             (default 1). Above 1 the node data and window
@@ -161,9 +162,10 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
  *                             thread count, planes and right-hand sides per
  *                             group. Resolved to 5 (and so on) where not
  *                             supported.
- *                             7 = float32, d = 2, tile edge 16, 2m + 1 <= 16:
- *                             the padded tile of a work item on the matrix
- *                             cores; the nodes of one tile row reach 16
+ *                             7 = d = 2, tile edge 16, 2m + 1 <= 16, float32
+ *                             or float64 (sums in float64 accumulators, in a
+ *                             fixed order): the padded tile of a work item
+ *                             on the matrix cores; the nodes of one tile row reach 16
  *                             padded rows, so four nodes at a time form a
  *                             16 x 32 block of products (rows held as
  *                             slots that shift with the tile row); the

@@ -242,9 +242,9 @@ int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, in
   int& mode = out[NFFT_TUNE_SPREAD_MODE];
   if (mode < 1 || mode > 7)
     return fail(p, NFFT_EINVAL, "spread mode %d: expected 1 .. 7", mode);
-  // the matrix-core register tile: float32, d = 2, tile edge 16, 2m + 1 <= 16,
-  // or d = 3, tile edge 8, 2m <= 8; elsewhere the vector register tile (and
-  // its own fallback)
+  // the matrix-core register tile: d = 2, tile edge 16, 2m + 1 <= 16 (float32
+  // or float64), or float32, d = 3, tile edge 8, 2m <= 8; elsewhere the
+  // vector register tile (and its own fallback)
   if (mode == 7 && !nfft::spread_mma_supported(d, T, precision == NFFT_F64, m) &&
       !nfft::spread3_mma_supported(d, T, precision == NFFT_F64, m))
     mode = 5;
@@ -265,7 +265,7 @@ int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, in
   const bool f64 = precision == NFFT_F64;
   const size_t one = mode == 6   ? nfft::spread_gather_lds_bytes(m)
                      : mode == 7 && d == 3 ? nfft::spread3_mma_lds_bytes()
-                     : mode == 7 ? nfft::spread_mma_lds_bytes(m, nt)
+                     : mode == 7 ? nfft::spread_mma_lds_bytes(m, nt, precision == NFFT_F64)
                      : mode == 5 ? nfft::spread_reg_lds_bytes(m)
                                  : nfft::spread_lds_bytes(d, f64, m, T, Ptot, nt, 1, planes);
   const size_t multi = out[NFFT_TUNE_RHS_PER_GROUP] > 1
@@ -1410,7 +1410,9 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
     planes = {1, 2};
   }
   if (d <= 2 && nrhs > 1) rpg = {1, 2, 4, 8};
-  if (d == 2) modes = {1, 2, 3, 4};
+  // float64: the work-group size matters to the matrix-core register tile only
+  if (d == 2 && !f32) threads = {128, 256};
+  if (d == 2) modes = {1, 2, 3, 4, 7};
   if (d == 2 && f32) modes = {1, 2, 3, 4, 5, 7};
   if (d == 3 && f32) modes = {1, 7};
   // the grid-tile gather holds 32 right-hand sides in the lanes of a wave
@@ -1463,6 +1465,8 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
             if ((md == 5 || md == 7) && (nr > 1 || pl != planes[0])) continue;
             // the gather (mode 6) has one shape
             if (md == 6 && (nr > 1 || pl != planes[0] || nt != threads[0])) continue;
+            // float64: only mode 7 takes the thread count
+            if (!f32 && md != 7 && nt != threads[0]) continue;
             if (nt == 512 && md < 5) continue;
             if (nr > 2 && md == 2) continue;  // the row sweep takes at most two rhs per wave
             if (uses_psi(md) && !have_psi) continue;

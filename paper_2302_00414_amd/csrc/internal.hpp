@@ -71,8 +71,8 @@ struct SpreadArgs {
                              // 5 padded tile in registers (float32),
                              // 6 grid tiles gathered for 32 rhs per work-group
                              //   (float32; see launch_spread_gather),
-                             // 7 padded tile on the matrix cores (float32,
-                             //   d = 2 and d = 3)
+                             // 7 padded tile on the matrix cores (d = 2
+                             //   float32 and float64, d = 3 float32)
   const R* psi;              // d = 2: window factors [N][2m][2] in tile order (mode 3)
 };
 template <typename R>
@@ -121,11 +121,13 @@ hipError_t launch_psi(const R* frac, int64_t N, int m, const R* coef, R* psi, hi
 bool spread_reg_supported(int d, int T, bool f64);
 size_t spread_reg_lds_bytes(int m);
 hipError_t launch_spread_reg(const SpreadArgs<float>& a, int nrhs, hipStream_t s);
-// Padded tile on the matrix cores, one tile row of nodes at a time (float32,
-// d = 2, tile edge 16, 2m + 1 <= 16, nodes row-sorted within tiles).
+// Padded tile on the matrix cores, one tile row of nodes at a time (float32
+// or float64, d = 2, tile edge 16, 2m + 1 <= 16, nodes row-sorted within
+// tiles).
 bool spread_mma_supported(int d, int T, bool f64, int m);
-size_t spread_mma_lds_bytes(int m, int nt);
-hipError_t launch_spread_mma(const SpreadArgs<float>& a, int nrhs, hipStream_t s);
+size_t spread_mma_lds_bytes(int m, int nt, bool f64);
+template <typename R>
+hipError_t launch_spread_mma(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
 // The d = 3 form of mode 7: one wave holds the padded tile (tile edge 8,
 // 2m <= 8, nodes sorted by their dimension-0 cell within tiles) in
 // matrix-core accumulators, float32.

@@ -1,6 +1,6 @@
-// Spreading for d = 2 in float32 on the matrix cores, the nodes of a work
-// item taken one tile row at a time (Algorithm 2.4 step 1 with the weights
-// of (3.7)).
+// Spreading for d = 2 on the matrix cores (float32 and float64), the nodes
+// of a work item taken one tile row at a time (Algorithm 2.4 step 1 with the
+// weights of (3.7)).
 //
 // A node in tile row r (tile-local cell (r, l1)) reaches the padded rows
 // r .. r + 2m of the item's padded tile (P = 16 + 2m rows and columns): row
@@ -9,7 +9,7 @@
 // therefore update a block of 16 rows x 32 padded columns,
 //     G[i][c] += sum_n A_n[i] B_n[c] c_n,
 // a product whose inner dimension runs over the nodes. v_mfma_f32_16x16x4f32
-// takes four nodes at a time: lane (k, i) supplies A_k[i] (row factor times
+// (v_mfma_f64_16x16x4f64 in float64) takes four nodes at a time: lane (k, i) supplies A_k[i] (row factor times
 // the real or the imaginary part of c_k = w_k f_k) and B_k[i] (column
 // factor), and four operations per four nodes cover the two column blocks
 // (padded columns 0..15 and 16..31) times the real and imaginary parts.
@@ -31,48 +31,79 @@ namespace nfft {
 
 namespace {
 
-typedef float mma_v4f __attribute__((ext_vector_type(4)));
+// Per precision: the accumulator block of v_mfma_*_16x16x4 (four elements a
+// lane, column l & 15 of the 16 x 16 block; row 4 (l >> 4) + v for element v
+// of lane l in float32, row 4 v + (l >> 4) in float64), the operation, and a
+// lane read.
+template <typename R> struct MmaT;
+template <> struct MmaT<float> {
+  static constexpr bool kRowsByQuarter = true;  // row 4 (l >> 4) + v
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mfma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ float read(float v, int byte_addr) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(byte_addr, __float_as_int(v)));
+  }
+};
+template <> struct MmaT<double> {
+  static constexpr bool kRowsByQuarter = false;  // row 4 v + (l >> 4)
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mfma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ double read(double v, int byte_addr) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(byte_addr, (int)(u & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_ds_bpermute(byte_addr, (int)(u >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  }
+};
 
-__device__ __forceinline__ float lane_read(float v, int byte_addr) {
-  return __int_as_float(__builtin_amdgcn_ds_bpermute(byte_addr, __float_as_int(v)));
-}
+// y0, y1, Re c, Im c of a staged node
+template <typename R> struct alignas(4 * sizeof(R)) MmaNode {
+  R y0, y1, cx, cy;
+};
 
 }  // namespace
 
 // Nodes staged per batch (a work item of up to 512 nodes in one batch).
 constexpr int kMmaBatch = 512;
 
-template <int MW, int NW>
+template <typename R, int MW, int NW>
 struct MmaLds {
   static constexpr int P = 16 + 2 * MW;
   // staging, NB + 1 entries (the last one a node with c = 0 for the missing
-  // members of a row's last group): offsets and c_j as one float4; the
-  // closed-edge factors of the row and the column; the column shift and the
-  // tile row in one word; the first node of every tile row in the batch (17
-  // entries, 32 reserved); rounded up to 16 bytes. Four work-groups of four
+  // members of a row's last group): offsets and c_j; the closed-edge factors
+  // of the row and the column; the column shift and the tile row in one
+  // word; the first node of every tile row in the batch (17 entries, 32
+  // reserved); rounded up to 16 bytes. In float32 four work-groups of four
   // waves fit in a compute unit's LDS for m <= 6.
-  static constexpr size_t staging = ((size_t)(kMmaBatch + 1) * 28 + 32 * 4 + 15) / 16 * 16;
+  static constexpr size_t staging =
+      ((size_t)(kMmaBatch + 1) * (6 * sizeof(R) + 4) + 32 * 4 + 15) / 16 * 16;
   // one padded tile per wave
-  static constexpr size_t tiles = (size_t)NW * P * P * sizeof(float2);
+  static constexpr size_t tiles = (size_t)NW * P * P * sizeof(cplx<R>);
   static constexpr size_t bytes = staging + tiles;
 };
 
-template <int MW, int NW>
-__global__ __launch_bounds__(64 * NW) void spread_mma_kernel(SpreadArgs<float> a) {
+template <typename R, int MW, int NW>
+__global__ __launch_bounds__(64 * NW) void spread_mma_kernel(SpreadArgs<R> a) {
   constexpr int K2 = 2 * MW;
   constexpr int P = 16 + K2;
   constexpr int NT = 64 * NW;
   constexpr int NB = kMmaBatch;
-  constexpr int DEG = PolyDeg<float>::value;
+  constexpr int DEG = PolyDeg<R>::value;
+  typedef typename MmaT<R>::v4 v4;
+  constexpr bool QR = MmaT<R>::kRowsByQuarter;
   static_assert(K2 + 1 <= 16, "the rows of one tile row's nodes fit in 16 slots");
   static_assert((P * P) % 2 == 0 && P % 2 == 0, "tiles are summed two cells at a time");
-  extern __shared__ float lds_f[];
-  float4* st_n = reinterpret_cast<float4*>(lds_f);  // y0, y1, Re c, Im c
-  float2* st_e = reinterpret_cast<float2*>(st_n + (NB + 1));  // edge factors (0 off a grid line)
-  int* st_q = reinterpret_cast<int*>(st_e + (NB + 1));        // -(l1 + 1) in bits 0-15, tile row above
-  int* st_rs = st_q + (NB + 1);                                // row starts [17]
-  float2* tiles = reinterpret_cast<float2*>(
-      reinterpret_cast<char*>(lds_f) + MmaLds<MW, NW>::staging);  // [NW][P][P]
+  extern __shared__ double lds_d[];
+  MmaNode<R>* st_n = reinterpret_cast<MmaNode<R>*>(lds_d);
+  cplx<R>* st_e = reinterpret_cast<cplx<R>*>(st_n + (NB + 1));  // edge factors (0 off a grid line)
+  int* st_q = reinterpret_cast<int*>(st_e + (NB + 1));          // -(l1 + 1) in bits 0-15, tile row above
+  int* st_rs = st_q + (NB + 1);                                  // row starts [17]
+  cplx<R>* tiles = reinterpret_cast<cplx<R>*>(
+      reinterpret_cast<char*>(lds_d) + MmaLds<R, MW, NW>::staging);  // [NW][P][P]
 
   const int item = blockIdx.x;
   const int rhs = blockIdx.y;
@@ -86,24 +117,24 @@ __global__ __launch_bounds__(64 * NW) void spread_mma_kernel(SpreadArgs<float> a
   const int pc = j < K2 ? j : K2 - 1;
   const bool hi_in = 16 + j < P;  // padded column 16 + j exists
 
-  float cf[DEG + 1];
+  R cf[DEG + 1];
 #pragma unroll
   for (int q = 0; q <= DEG; ++q) cf[q] = a.coef[pc * (DEG + 1) + q];
 
-  mma_v4f acc0r = {0.0f, 0.0f, 0.0f, 0.0f}, acc0i = acc0r, acc1r = acc0r, acc1i = acc0r;
-  float2* mine = tiles + wave * (P * P);
+  v4 acc0r = {(R)0, (R)0, (R)0, (R)0}, acc0i = acc0r, acc1r = acc0r, acc1i = acc0r;
+  cplx<R>* mine = tiles + wave * (P * P);
 
   const int64_t N = a.g.N;
   const int start = a.item_start[item];
   const int cnt = a.item_count[item];
-  const float2* f = a.f + rhs * a.f_rs;
-  const float edge = a.edge;
+  const cplx<R>* f = a.f + rhs * a.f_rs;
+  const R edge = a.edge;
 
   if (tid == 0) {
     // the node with c = 0: its products are zero whatever its (finite)
     // window factors
-    st_n[NB] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    st_e[NB] = make_float2(0.0f, 0.0f);
+    st_n[NB] = MmaNode<R>{(R)0, (R)0, (R)0, (R)0};
+    st_e[NB] = mkc<R>(0, 0);
     st_q[NB] = 0xffff;
   }
   for (int b0 = 0; b0 < cnt; b0 += NB) {
@@ -113,13 +144,13 @@ __global__ __launch_bounds__(64 * NW) void spread_mma_kernel(SpreadArgs<float> a
 #pragma unroll 2
     for (int t = tid; t < nb; t += NT) {
       const int i = start + b0 + t;
-      const float2 wv = a.w[i];
-      const float2 fv = f[a.perm[i]];
+      const cplx<R> wv = a.w[i];
+      const cplx<R> fv = f[a.perm[i]];
       const uint32_t L = a.loc[i];
-      st_n[t] = make_float4(2.0f * a.frac[i] - 1.0f, 2.0f * a.frac[N + i] - 1.0f,
-                            wv.x * fv.x - wv.y * fv.y, wv.x * fv.y + wv.y * fv.x);
-      st_e[t] = make_float2(((L >> kEdgeShift) & 1u) ? edge : 0.0f,
-                            ((L >> (kEdgeShift + 1)) & 1u) ? edge : 0.0f);
+      st_n[t] = MmaNode<R>{(R)2 * a.frac[i] - (R)1, (R)2 * a.frac[N + i] - (R)1,
+                           wv.x * fv.x - wv.y * fv.y, wv.x * fv.y + wv.y * fv.x};
+      st_e[t] = mkc<R>(((L >> kEdgeShift) & 1u) ? edge : (R)0,
+                       ((L >> (kEdgeShift + 1)) & 1u) ? edge : (R)0);
       st_q[t] = ((-(int)((L >> kLocBits) & kLocMask) - 1) & 0xffff) | (int)((L & kLocMask) << 16);
     }
     __syncthreads();
@@ -154,41 +185,41 @@ __global__ __launch_bounds__(64 * NW) void spread_mma_kernel(SpreadArgs<float> a
       for (; q < ng; q += NW) {
         const int n = n0 + 4 * q + kq;
         const int nn = n < n1 ? n : NB;  // past the row: the node with c = 0
-        const float4 nd = st_n[nn];
-        const float2 ne = st_e[nn];
+        const MmaNode<R> nd = st_n[nn];
+        const cplx<R> ne = st_e[nn];
         const int qoff = (st_q[nn] << 16) >> 16;
-        const float h0 = horner<float>(cf, nd.x);
-        const float h1 = horner<float>(cf, nd.y);
+        const R h0 = horner<R>(cf, nd.y0);
+        const R h1 = horner<R>(cf, nd.y1);
         // row factor of slot j, column factors of padded columns j and 16 + j
-        const float ra = lane_read(h0, addrA);
+        const R ra = MmaT<R>::read(h0, addrA);
         const int qB = j + qoff;
-        const float cb = lane_read(h1, (lrow | (qB & 15)) << 2);
-        const float A = inA ? ra : (edA ? ne.x : 0.0f);
-        const float B0 = (unsigned)qB < (unsigned)K2 ? cb : (qB == -1 ? ne.y : 0.0f);
-        const float B1 = qB < K2 - 16 ? cb : 0.0f;
-        const float ar = A * nd.z;
-        const float ai = A * nd.w;
-        acc0r = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, B0, acc0r, 0, 0, 0);
-        acc1r = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, B1, acc1r, 0, 0, 0);
-        acc0i = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, B0, acc0i, 0, 0, 0);
-        acc1i = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, B1, acc1i, 0, 0, 0);
+        const R cb = MmaT<R>::read(h1, (lrow | (qB & 15)) << 2);
+        const R A = inA ? ra : (edA ? ne.x : (R)0);
+        const R B0 = (unsigned)qB < (unsigned)K2 ? cb : (qB == -1 ? ne.y : (R)0);
+        const R B1 = qB < K2 - 16 ? cb : (R)0;
+        const R ar = A * nd.cx;
+        const R ai = A * nd.cy;
+        acc0r = MmaT<R>::mfma(ar, B0, acc0r);
+        acc1r = MmaT<R>::mfma(ar, B1, acc1r);
+        acc0i = MmaT<R>::mfma(ai, B0, acc0i);
+        acc1i = MmaT<R>::mfma(ai, B1, acc1i);
       }
       gbase += ng;
-      // padded row r is complete for this wave: slot r, element r % 4 of the
-      // lanes of row quarter r / 4 (accumulator element v of lane l is slot
-      // 4 (l >> 4) + v, column l & 15 of its block)
-      constexpr int v = r & 3;
-      const bool done = kq == (r >> 2);
-      float2 lo = make_float2(acc0r[v], acc0i[v]);
-      float2 hi = make_float2(acc1r[v], acc1i[v]);
+      // padded row r is complete for this wave: slot r (accumulator element
+      // v of lane l is slot 4 (l >> 4) + v in float32, 4 v + (l >> 4) in
+      // float64; column l & 15 of its block)
+      constexpr int v = QR ? (r & 3) : (r >> 2);
+      const bool done = kq == (QR ? (r >> 2) : (r & 3));
+      cplx<R> lo = mkc<R>(acc0r[v], acc0i[v]);
+      cplx<R> hi = mkc<R>(acc1r[v], acc1i[v]);
       if (done) {
-        float2* rowp = mine + r * P;
+        cplx<R>* rowp = mine + r * P;
         if (!first) {
-          const float2 u = rowp[j];
+          const cplx<R> u = rowp[j];
           lo.x += u.x;
           lo.y += u.y;
           if (hi_in) {
-            const float2 w = rowp[16 + j];
+            const cplx<R> w = rowp[16 + j];
             hi.x += w.x;
             hi.y += w.y;
           }
@@ -198,25 +229,25 @@ __global__ __launch_bounds__(64 * NW) void spread_mma_kernel(SpreadArgs<float> a
       }
       // only element v of the finished quarter is cleared (a select, so that
       // the other accumulator elements stay where they are)
-      acc0r[v] = done ? 0.0f : acc0r[v];
-      acc0i[v] = done ? 0.0f : acc0i[v];
-      acc1r[v] = done ? 0.0f : acc1r[v];
-      acc1i[v] = done ? 0.0f : acc1i[v];
+      acc0r[v] = done ? (R)0 : acc0r[v];
+      acc0i[v] = done ? (R)0 : acc0i[v];
+      acc1r[v] = done ? (R)0 : acc1r[v];
+      acc1i[v] = done ? (R)0 : acc1i[v];
     });
     // padded rows 16 .. P-1: slot s holds padded row 16 + s
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int row = 16 + 4 * kq + v;
+      const int row = 16 + (QR ? 4 * kq + v : 4 * v + kq);
       if (row < P) {
-        float2* rowp = mine + row * P;
-        float2 lo = make_float2(acc0r[v], acc0i[v]);
-        float2 hi = make_float2(acc1r[v], acc1i[v]);
+        cplx<R>* rowp = mine + row * P;
+        cplx<R> lo = mkc<R>(acc0r[v], acc0i[v]);
+        cplx<R> hi = mkc<R>(acc1r[v], acc1i[v]);
         if (!first) {
-          const float2 u = rowp[j];
+          const cplx<R> u = rowp[j];
           lo.x += u.x;
           lo.y += u.y;
           if (hi_in) {
-            const float2 w = rowp[16 + j];
+            const cplx<R> w = rowp[16 + j];
             hi.x += w.x;
             hi.y += w.y;
           }
@@ -225,86 +256,114 @@ __global__ __launch_bounds__(64 * NW) void spread_mma_kernel(SpreadArgs<float> a
         if (hi_in) rowp[16 + j] = hi;
       }
     }
-    acc0r = mma_v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    acc0r = v4{(R)0, (R)0, (R)0, (R)0};
     acc0i = acc0r;
     acc1r = acc0r;
     acc1i = acc0r;
   }
 
-  // the waves' tiles summed in wave order, two cells at a time: a fixed
-  // order, so the result does not depend on timing
+  // the waves' tiles summed in wave order: a fixed order, so the result does
+  // not depend on timing (float32: two cells at a time)
   __syncthreads();
   const int slot = a.item_slot[item];
-  float2* out = slot < 0 ? a.tilep + rhs * a.tile_rs + (int64_t)a.item_bin[item] * (P * P)
-                         : a.itemp + rhs * a.item_rs + (int64_t)slot * (P * P);
-  const float4* t4 = reinterpret_cast<const float4*>(tiles);
-  float4* o4 = reinterpret_cast<float4*>(out);
-  for (int i = tid; i < P * P / 2; i += NT) {
-    float4 s = t4[i];
+  cplx<R>* out = slot < 0 ? a.tilep + rhs * a.tile_rs + (int64_t)a.item_bin[item] * (P * P)
+                          : a.itemp + rhs * a.item_rs + (int64_t)slot * (P * P);
+  if constexpr (std::is_same<R, float>::value) {
+    const float4* t4 = reinterpret_cast<const float4*>(tiles);
+    float4* o4 = reinterpret_cast<float4*>(out);
+    for (int i = tid; i < P * P / 2; i += NT) {
+      float4 s = t4[i];
 #pragma unroll
-    for (int w = 1; w < NW; ++w) {
-      const float4 u = t4[w * (P * P / 2) + i];
-      s.x += u.x;
-      s.y += u.y;
-      s.z += u.z;
-      s.w += u.w;
+      for (int w = 1; w < NW; ++w) {
+        const float4 u = t4[w * (P * P / 2) + i];
+        s.x += u.x;
+        s.y += u.y;
+        s.z += u.z;
+        s.w += u.w;
+      }
+      o4[i] = s;
     }
-    o4[i] = s;
+  } else {
+    for (int i = tid; i < P * P; i += NT) {
+      cplx<R> s = tiles[i];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) {
+        const cplx<R> u = tiles[w * (P * P) + i];
+        s.x += u.x;
+        s.y += u.y;
+      }
+      out[i] = s;
+    }
   }
 }
 
 bool spread_mma_supported(int d, int T, bool f64, int m) {
-  return d == 2 && T == 16 && !f64 && m >= 1 && 2 * m + 1 <= 16;
+  (void)f64;  // float32 and float64
+  return d == 2 && T == 16 && m >= 1 && 2 * m + 1 <= 16;
 }
 
 // 64 or 128 threads: two waves; 256: four; 512: eight
 static int mma_waves(int nt) { return nt >= 512 ? 8 : nt >= 256 ? 4 : 2; }
 
-template <int MW>
+template <typename R, int MW>
 static size_t mma_lds_m(int nw) {
-  return nw == 8 ? MmaLds<MW, 8>::bytes : nw == 4 ? MmaLds<MW, 4>::bytes : MmaLds<MW, 2>::bytes;
+  return nw == 8 ? MmaLds<R, MW, 8>::bytes
+                 : nw == 4 ? MmaLds<R, MW, 4>::bytes : MmaLds<R, MW, 2>::bytes;
 }
 
-size_t spread_mma_lds_bytes(int m, int nt) {
-  const int nw = mma_waves(nt);
+template <typename R>
+static size_t mma_lds(int m, int nw) {
   switch (m) {
-    case 1: return mma_lds_m<1>(nw);
-    case 2: return mma_lds_m<2>(nw);
-    case 3: return mma_lds_m<3>(nw);
-    case 4: return mma_lds_m<4>(nw);
-    case 5: return mma_lds_m<5>(nw);
-    case 6: return mma_lds_m<6>(nw);
-    case 7: return mma_lds_m<7>(nw);
+    case 1: return mma_lds_m<R, 1>(nw);
+    case 2: return mma_lds_m<R, 2>(nw);
+    case 3: return mma_lds_m<R, 3>(nw);
+    case 4: return mma_lds_m<R, 4>(nw);
+    case 5: return mma_lds_m<R, 5>(nw);
+    case 6: return mma_lds_m<R, 6>(nw);
+    case 7: return mma_lds_m<R, 7>(nw);
     default: return 0;
   }
 }
 
-template <int MW>
-static hipError_t spread_mma_m(const SpreadArgs<float>& a, int nrhs, hipStream_t s) {
+size_t spread_mma_lds_bytes(int m, int nt, bool f64) {
+  const int nw = mma_waves(nt);
+  return f64 ? mma_lds<double>(m, nw) : mma_lds<float>(m, nw);
+}
+
+template <typename R, int MW>
+static hipError_t spread_mma_m(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
   const dim3 grid(a.g.nsub, nrhs);
   const int nw = mma_waves(a.nt);
   if (nw == 8)
-    hipLaunchKernelGGL((spread_mma_kernel<MW, 8>), grid, dim3(512), (MmaLds<MW, 8>::bytes), s, a);
+    hipLaunchKernelGGL((spread_mma_kernel<R, MW, 8>), grid, dim3(512), (MmaLds<R, MW, 8>::bytes),
+                       s, a);
   else if (nw == 4)
-    hipLaunchKernelGGL((spread_mma_kernel<MW, 4>), grid, dim3(256), (MmaLds<MW, 4>::bytes), s, a);
+    hipLaunchKernelGGL((spread_mma_kernel<R, MW, 4>), grid, dim3(256), (MmaLds<R, MW, 4>::bytes),
+                       s, a);
   else
-    hipLaunchKernelGGL((spread_mma_kernel<MW, 2>), grid, dim3(128), (MmaLds<MW, 2>::bytes), s, a);
+    hipLaunchKernelGGL((spread_mma_kernel<R, MW, 2>), grid, dim3(128), (MmaLds<R, MW, 2>::bytes),
+                       s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_spread_mma(const SpreadArgs<float>& a, int nrhs, hipStream_t s) {
-  if (!spread_mma_supported(a.g.d, a.g.T, false, a.g.m)) return hipErrorInvalidValue;
+template <typename R>
+hipError_t launch_spread_mma(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
+  if (!spread_mma_supported(a.g.d, a.g.T, !std::is_same<R, float>::value, a.g.m))
+    return hipErrorInvalidValue;
   if (a.g.nsub == 0) return hipSuccess;
   switch (a.g.m) {
-    case 1: return spread_mma_m<1>(a, nrhs, s);
-    case 2: return spread_mma_m<2>(a, nrhs, s);
-    case 3: return spread_mma_m<3>(a, nrhs, s);
-    case 4: return spread_mma_m<4>(a, nrhs, s);
-    case 5: return spread_mma_m<5>(a, nrhs, s);
-    case 6: return spread_mma_m<6>(a, nrhs, s);
-    case 7: return spread_mma_m<7>(a, nrhs, s);
+    case 1: return spread_mma_m<R, 1>(a, nrhs, s);
+    case 2: return spread_mma_m<R, 2>(a, nrhs, s);
+    case 3: return spread_mma_m<R, 3>(a, nrhs, s);
+    case 4: return spread_mma_m<R, 4>(a, nrhs, s);
+    case 5: return spread_mma_m<R, 5>(a, nrhs, s);
+    case 6: return spread_mma_m<R, 6>(a, nrhs, s);
+    case 7: return spread_mma_m<R, 7>(a, nrhs, s);
     default: return hipErrorInvalidValue;
   }
 }
+
+template hipError_t launch_spread_mma<float>(const SpreadArgs<float>&, int, hipStream_t);
+template hipError_t launch_spread_mma<double>(const SpreadArgs<double>&, int, hipStream_t);
 
 }  // namespace nfft

@@ -103,7 +103,7 @@ TUNINGS = [
 ]
 
 # the mode the register-tile kernels and the grid-tile gather resolve to where
-# they do not apply (float64, a tile edge other than 16)
+# they do not apply (float64 for modes 5 and 6, a tile edge other than 16)
 REG_FALLBACK = {5: 4, 6: 4, 7: 4}
 
 
@@ -126,8 +126,9 @@ def test_tunings_agree(tuning, prec):
         if k == "spread_mode" and v == 2 and tuning.get("tile_edge") == 32:
             assert got_t[k] == 1
             continue
-        reg = tuning.get("spread_mode") in REG_FALLBACK and prec == "f32" and \
-            tuning.get("tile_edge", 16) == 16
+        # mode 7 at tile edge 16 in both precisions; modes 5 and 6 in float32
+        reg = tuning.get("spread_mode") in REG_FALLBACK and tuning.get("tile_edge", 16) == 16 and \
+            (prec == "f32" or tuning.get("spread_mode") == 7)
         if k == "spread_mode" and v in REG_FALLBACK and not reg:
             assert got_t[k] == REG_FALLBACK[v], got_t
             continue
@@ -308,6 +309,39 @@ def test_register_tile_spreading(mode, m, items, nt):
     # fixed summation order: a second call gives the same bits
     again = _np(p.adjoint(torch.from_numpy(F)))
     assert np.array_equal(again, got)
+    p.close()
+
+
+@pytest.mark.parametrize("m", [1, 3, 6, 7])
+@pytest.mark.parametrize("items", [600, 1024])
+@pytest.mark.parametrize("nt", [128, 256])
+def test_matrix_core_tile_float64(m, items, nt):
+    """Spread mode 7 in float64 (v_mfma_f64_16x16x4f64, the accumulators and
+    the sum of the waves' tiles in float64): against the oracle (O2) to the
+    float64 parity tolerance, against the LDS kernel of mode 1 on the same
+    plan (float64 LDS atomics, another order) to rounding, and two calls give
+    the same bits (a fixed summation order, unlike the LDS atomics); three
+    right-hand sides, grid-aligned nodes, crowded tiles, items of two
+    batches."""
+    M = 32
+    x = _nodes(2, M, 500 + m)
+    N = x.shape[0]
+    w = (1.0 + 0.3 * wl.complex_normal(N, 501)) / N
+    F = wl.complex_normal((3, N), 502)
+    p = _plan(x, M, m, "f64", max_rhs=3, tuning={"item_nodes": items})
+    p.set_weights(w)
+    Ft = torch.from_numpy(F)
+    a1 = _np(p.adjoint(Ft))
+    p.set_tuning("spread_mode", 7)
+    p.set_tuning("spread_threads", nt)
+    assert p.tuning()["spread_mode"] == 7
+    got = _np(p.adjoint(Ft))
+    again = _np(p.adjoint(Ft))
+    assert np.array_equal(got.view(np.uint64), again.view(np.uint64))
+    ref = onfft.adjoint(x, w[None, :] * F, M, 2.0, m)
+    for r in range(3):
+        assert metrics.rel_err(got[r], ref[r]) <= TOL_O2["f64"], r
+        assert metrics.rel_err(got[r], a1[r]) <= TOL_ORDER["f64"], r
     p.close()
 
 
