@@ -636,7 +636,9 @@ def spread_kernel_name(t):
         return f"spread_rows_kernel<float, {MW}, {T if T == 16 else 0}, 1>"
     if mode in (5, 7) and T == 16:
         nw = {256: 4, 512: 8}.get(t["spread_threads"], 2)
-        return f"spread_{'mma' if mode == 7 else 'reg'}_kernel<{MW}, {nw}>"
+        if mode == 7:
+            return f"spread_mma_kernel<float, {MW}, {nw}>"
+        return f"spread_reg_kernel<{MW}, {nw}>"
     ws = {3: 1, 4: 2}.get(mode, 0)   # window source of the group kernel
     return (f"spread_group_kernel<float, 2, {MW}, {t['spread_threads']}, "
             f"{T if T in (8, 16) else 0}, {'true' if t['spread_planes'] == 2 else 'false'}, {ws}>")

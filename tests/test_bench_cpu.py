@@ -35,7 +35,7 @@ def test_kernel_names_follow_the_tuning():
         "spread_group_kernel<float, 2, 6, 256, 0, true, 0>"
     assert bench.spread_kernel_name(dict(t, spread_mode=2)) == "spread_rows_kernel<float, 6, 16, 1>"
     assert bench.spread_kernel_name(dict(t, spread_mode=5)) == "spread_reg_kernel<6, 4>"
-    assert bench.spread_kernel_name(dict(t, spread_mode=7)) == "spread_mma_kernel<6, 4>"
+    assert bench.spread_kernel_name(dict(t, spread_mode=7)) == "spread_mma_kernel<float, 6, 4>"
     assert bench.spread_kernel_name(dict(t, spread_mode=5, spread_threads=512)) == \
         "spread_reg_kernel<6, 8>"
 
