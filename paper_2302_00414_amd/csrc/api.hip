@@ -242,9 +242,9 @@ int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, in
   int& mode = out[NFFT_TUNE_SPREAD_MODE];
   if (mode < 1 || mode > 7)
     return fail(p, NFFT_EINVAL, "spread mode %d: expected 1 .. 7", mode);
-  // the matrix-core register tile: d = 2, tile edge 16, 2m + 1 <= 16 (float32
-  // or float64), or float32, d = 3, tile edge 8, 2m <= 8; elsewhere the
-  // vector register tile (and its own fallback)
+  // the matrix-core register tile: d = 2, tile edge 16, 2m + 1 <= 16, or
+  // d = 3, tile edge 8, 2m <= 8 (float32 or float64); elsewhere the vector
+  // register tile (and its own fallback)
   if (mode == 7 && !nfft::spread_mma_supported(d, T, precision == NFFT_F64, m) &&
       !nfft::spread3_mma_supported(d, T, precision == NFFT_F64, m))
     mode = 5;
@@ -264,7 +264,7 @@ int resolve_tuning(int d, int Ms, int m, int precision, const int* in, int n, in
   const int Ptot = (int)ipow(P, d);
   const bool f64 = precision == NFFT_F64;
   const size_t one = mode == 6   ? nfft::spread_gather_lds_bytes(m)
-                     : mode == 7 && d == 3 ? nfft::spread3_mma_lds_bytes()
+                     : mode == 7 && d == 3 ? nfft::spread3_mma_lds_bytes(f64)
                      : mode == 7 ? nfft::spread_mma_lds_bytes(m, nt, precision == NFFT_F64)
                      : mode == 5 ? nfft::spread_reg_lds_bytes(m)
                                  : nfft::spread_lds_bytes(d, f64, m, T, Ptot, nt, 1, planes);
@@ -1414,7 +1414,7 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
   if (d == 2 && !f32) threads = {128, 256};
   if (d == 2) modes = {1, 2, 3, 4, 7};
   if (d == 2 && f32) modes = {1, 2, 3, 4, 5, 7};
-  if (d == 3 && f32) modes = {1, 7};
+  if (d == 3) modes = {1, 7};
   // the grid-tile gather holds 32 right-hand sides in the lanes of a wave
   if (d == 2 && f32 && nrhs >= 8) modes.push_back(6);
 

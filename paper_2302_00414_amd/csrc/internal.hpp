@@ -71,8 +71,8 @@ struct SpreadArgs {
                              // 5 padded tile in registers (float32),
                              // 6 grid tiles gathered for 32 rhs per work-group
                              //   (float32; see launch_spread_gather),
-                             // 7 padded tile on the matrix cores (d = 2
-                             //   float32 and float64, d = 3 float32)
+                             // 7 padded tile on the matrix cores (d = 2, 3;
+                             //   float32 and float64)
   const R* psi;              // d = 2: window factors [N][2m][2] in tile order (mode 3)
 };
 template <typename R>
@@ -130,10 +130,11 @@ template <typename R>
 hipError_t launch_spread_mma(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
 // The d = 3 form of mode 7: one wave holds the padded tile (tile edge 8,
 // 2m <= 8, nodes sorted by their dimension-0 cell within tiles) in
-// matrix-core accumulators, float32.
+// matrix-core accumulators, float32 or float64.
 bool spread3_mma_supported(int d, int T, bool f64, int m);
-size_t spread3_mma_lds_bytes();
-hipError_t launch_spread3_mma(const SpreadArgs<float>& a, int nrhs, hipStream_t s);
+size_t spread3_mma_lds_bytes(bool f64);
+template <typename R>
+hipError_t launch_spread3_mma(const SpreadArgs<R>& a, int nrhs, hipStream_t s);
 // Several right-hand sides per work-group (d <= 2, nr > 1).
 template <typename R>
 hipError_t launch_spread_multi(const SpreadArgs<R>& a, int nrhs, hipStream_t s);

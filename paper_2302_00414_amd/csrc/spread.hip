@@ -501,11 +501,11 @@ hipError_t launch_spread(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
   if (a.nr > 1 && a.g.d <= 2) return launch_spread_multi<R>(a, nrhs, s);
   if (a.mode == 7 && spread_mma_supported(a.g.d, a.g.T, !std::is_same<R, float>::value, a.g.m))
     return launch_spread_mma<R>(a, nrhs, s);
+  if (a.mode == 7 && spread3_mma_supported(a.g.d, a.g.T, !std::is_same<R, float>::value, a.g.m))
+    return launch_spread3_mma<R>(a, nrhs, s);
   if constexpr (std::is_same<R, float>::value) {
     if (a.mode == 5 && spread_reg_supported(a.g.d, a.g.T, false))
       return launch_spread_reg(a, nrhs, s);
-    if (a.mode == 7 && spread3_mma_supported(a.g.d, a.g.T, false, a.g.m))
-      return launch_spread3_mma(a, nrhs, s);
   }
   if (a.mode == 3 && a.psi && a.g.d == 2) return launch_spread_pre<R>(a, nrhs, s);
   if (a.mode == 4 && a.g.d == 2) return launch_spread_late<R>(a, nrhs, s);

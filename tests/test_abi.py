@@ -91,7 +91,7 @@ def test_f64_3d_large_m_unsupported():
     (2, 6, _lib.NFFT_F32, [0, 0, 512, 0, 0, 0, 7], _lib.NFFT_OK),  # eight waves a work-group
     (2, 6, _lib.NFFT_F64, [0, 0, 0, 0, 0, 0, 7], _lib.NFFT_OK),   # float64 on the matrix cores
     (3, 4, _lib.NFFT_F32, [8, 0, 0, 0, 0, 0, 7], _lib.NFFT_OK),   # d = 3 on the matrix cores
-    (3, 4, _lib.NFFT_F64, [8, 0, 0, 0, 0, 0, 7], _lib.NFFT_OK),   # float64: resolved to mode 1
+    (3, 4, _lib.NFFT_F64, [8, 0, 0, 0, 0, 0, 7], _lib.NFFT_OK),   # d = 3 float64 on the matrix cores
     (2, 6, _lib.NFFT_F32, [0, 0, 0, 0, 0, 0, 6], _lib.NFFT_OK),   # grid-tile gather
     (2, 6, _lib.NFFT_F64, [0, 0, 0, 0, 0, 0, 6], _lib.NFFT_OK),   # float64: resolved to mode 4
     (2, 6, _lib.NFFT_F32, [8, 0, 0, 0, 0, 0, 6], _lib.NFFT_OK),   # tile edge 8: resolved to mode 4
