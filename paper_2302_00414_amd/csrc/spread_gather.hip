@@ -40,12 +40,14 @@ constexpr int kGatherNt = 512;  // threads per work-group (8 waves)
 template <int MW>
 struct GatherLds {
   static constexpr int K = 2 * MW + 1;             // footprint cells per dimension
-  static constexpr int XS = (K + 3) / 4 * 4;       // column factors stored per node
-  static constexpr int YS = (K + 8 + 3) / 4 * 4;   // row factors: 4 zeros, K values, 4 zeros
-  // per entry: header, caller index, two offsets, weight, factors, samples
+  // factors stored per node and dimension: 4 zeros, K values, 4 or more zeros
+  static constexpr int YS = (K + 8 + 3) / 4 * 4;
+  static constexpr int XS = YS;
+  // per entry: header, caller index, two offsets, weight; factors and
+  // samples also for entry kGatherNb, all zeros (the padding of the lists)
   static constexpr size_t staging =
-      kGatherNb * (2 * sizeof(int) + 4 * sizeof(float) + (XS + YS) * sizeof(float) +
-                   2 * kGatherRhs * sizeof(float));
+      kGatherNb * (2 * sizeof(int) + 4 * sizeof(float)) +
+      (kGatherNb + 1) * ((XS + YS) * sizeof(float) + 2 * kGatherRhs * sizeof(float));
   // the output transpose, per band of four tile rows: [rhs][65 cells][2] floats
   static constexpr size_t transpose = (size_t)4 * kGatherRhs * 65 * 2 * sizeof(float);
   static constexpr size_t bytes = staging > transpose ? staging : transpose;
@@ -70,18 +72,21 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
   float* s_y = reinterpret_cast<float*>(s_perm + NB);  // offsets 2 frac - 1, [2][NB]
   float2* s_w = reinterpret_cast<float2*>(s_y + 2 * NB);  // weights
   constexpr int YS = GatherLds<MW>::YS;
-  float* s_ay = reinterpret_cast<float*>(s_w + NB);  // row factors [NB][YS], entry q at 4 + q
-  float* s_bx = s_ay + NB * YS;                         // column factors [NB][XS]
+  float* s_ay = reinterpret_cast<float*>(s_w + NB);  // row factors [NB + 1][YS], cell q at 4 + q
+  float* s_bx = s_ay + (NB + 1) * YS;                   // column factors [NB + 1][XS], likewise
   // samples: component row m = 32 c + r (c: real 0, imaginary 1; r: rhs) of
   // entry k at s_c[k][m mod 16][m / 16], so that a lane's four A values (one
-  // per 16-row block) are one 16-byte read
-  float* s_c = s_bx + NB * XS;
+  // per 16-row block) are one 16-byte read; [NB + 1][64]
+  float* s_c = s_bx + (NB + 1) * XS;
   __shared__ float s_cf[2 * MW * (DEG + 1)];
   // staged entries that reach each 4 x 4 sub-tile, per half of the round (in
-  // entry order), and their counts
-  __shared__ short s_list[16][2][64];
-  __shared__ int s_lcnt[16][2];
-  static_assert(NB == 128 && kGatherNt == 512, "two waves ballot the staged entries");
+  // entry order), padded to a multiple of 4 items; each wave lists its own
+  // two sub-tiles. An item packs the entry index (bits 0-7) with the
+  // footprint origin relative to the tile plus 64 (bits 8-15 rows, 16-23
+  // columns); a padding item names the zero entry NB at the sub-tile's own
+  // origin.
+  __shared__ int s_list[16][2][64];
+  static_assert(NB == 128 && kGatherNt == 512, "eight waves, 64-entry halves of a round");
   constexpr int NT = kGatherNt;
 
   const int* u = units + 4 * (int64_t)blockIdx.x;
@@ -95,6 +100,10 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
   const int rhs0 = blockIdx.y * kGatherRhs;
   const int64_t N = a.g.N;
   for (int i = tid; i < 2 * MW * (DEG + 1); i += NT) s_cf[i] = a.coef[i];
+  // the factor rows start zero (only cells 0 .. 2m are written per round),
+  // and entry NB is zero throughout
+  for (int i = tid; i < (NB + 1) * (XS + YS); i += NT) s_ay[i] = 0.0f;
+  if (tid < 2 * kGatherRhs) s_c[NB * 2 * kGatherRhs + tid] = 0.0f;
 
   // acc[q][mb]: sub-tile 2 wave + q, rows mb*16 .. mb*16+15 of the 64 x 16 sums
   gather_v4f acc[2][4];
@@ -122,32 +131,14 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
   for (int c0 = e_begin; c0 < e_end; c0 += NB) {
     const int nk = (e_end - c0) < NB ? (e_end - c0) : NB;
     __syncthreads();  // the previous round is consumed
-    // the prefetched entries into LDS, and per sub-tile the staged entries
-    // whose footprint reaches it (waves 0 and 1, 64 entries each)
+    // the prefetched entries into LDS (waves 0 and 1)
     if (tid < NB) {
-      uint32_t reach = 0;
       if (tid < nk) {
-        const int hd = p_hd;
-        const int b0 = (hd & 0xff) - 64, b1 = ((hd >> 8) & 0xff) - 64;
-        const int r0 = max(0, b0 + (((hd >> 16) & 1) ? 0 : 1)), r1 = min(15, b0 + 2 * MW);
-        const int k0 = max(0, b1 + (((hd >> 17) & 1) ? 0 : 1)), k1 = min(15, b1 + 2 * MW);
-        for (int sr = r0 >> 2; sr <= r1 >> 2; ++sr)
-          for (int sc = k0 >> 2; sc <= k1 >> 2; ++sc) reach |= 1u << (4 * sr + sc);
-        s_hdr[tid] = hd;
+        s_hdr[tid] = p_hd;
         s_perm[tid] = p_pm;
         s_y[tid] = p_y0;
         s_y[NB + tid] = p_y1;
         s_w[tid] = p_w;
-      }
-      const int h = tid >> 6;
-#pragma unroll
-      for (int st = 0; st < 16; ++st) {
-        const bool in = (reach >> st) & 1u;
-        const uint64_t bal = __builtin_amdgcn_ballot_w64(in);
-        const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
-        if (in) s_list[st][h][pos] = (short)tid;
-        if ((tid & 63) == 0) s_lcnt[st][h] = __popcll(bal);
       }
       fetch(c0 + NB);  // the next round's entries, in flight from here
     }
@@ -166,8 +157,8 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
       fv[j] = make_float2(0.0f, 0.0f);
       if (k < nk) fv[j] = fg[(int64_t)s_perm[k] * kGatherRhs + r];
     }
-    // window factors: entry 0 the closed-edge cell, 1 + i polynomial i (the
-    // row factors stored from index 4)
+    // window factors: cell 0 the closed-edge cell, 1 + i polynomial i (both
+    // dimensions stored from index 4)
     for (int e = tid; e < nk * 2 * K; e += NT) {
       const int k = e / (2 * K);
       const int rem = e - k * (2 * K);
@@ -176,7 +167,7 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
       const float hv = horner<float>(s_cf + (q > 0 ? q - 1 : 0) * (DEG + 1), s_y[dim * NB + k]);
       const float v = q == 0 ? (((s_hdr[k] >> (16 + dim)) & 1) ? a.edge : 0.0f) : hv;
       if (dim)
-        s_bx[k * XS + q] = v;
+        s_bx[k * XS + 4 + q] = v;
       else
         s_ay[k * YS + 4 + q] = v;
     }
@@ -193,30 +184,52 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
       }
     }
     __syncthreads();
-    // the wave's two sub-tiles: entries reaching a sub-tile, four at a time
+    // the wave's two sub-tiles: the lists of staged entries whose footprint
+    // reaches each (a ballot per half round), then those entries four at a
+    // time. The lists are this wave's own: written and read by it alone.
     const int kk = lane >> 4, j = lane & 15;
+    int hd2[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) hd2[h] = 64 * h + lane < nk ? s_hdr[64 * h + lane] : -1;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int st = 2 * wave + q;
       const int row = 4 * (st >> 2) + (j >> 2);  // tile cell of lane (kk, j) in B
       const int col = 4 * (st & 3) + (j & 3);
+      int cnt2[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-      const int cnt = __builtin_amdgcn_readfirstlane(s_lcnt[st][h]);
+        const int hd = hd2[h];
+        // footprint rows b0 + (edge ? 0 : 1) .. b0 + 2m against the
+        // sub-tile's rows 4 sr .. 4 sr + 3, likewise for the columns
+        const int b0 = (hd & 0xff) - 64, b1 = ((hd >> 8) & 0xff) - 64;
+        const int r0 = b0 + (((hd >> 16) & 1) ? 0 : 1), k0 = b1 + (((hd >> 17) & 1) ? 0 : 1);
+        const int sr = 4 * (st >> 2), sc = 4 * (st & 3);
+        const bool in = hd >= 0 && r0 <= sr + 3 && b0 + 2 * MW >= sr && k0 <= sc + 3 &&
+                        b1 + 2 * MW >= sc;
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(in);
+        const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+        if (in) s_list[st][h][pos] = (64 * h + lane) | ((hd & 0xffff) << 8);
+        const int c = __popcll(bal), c4 = (c + 3) & ~3;
+        if (lane < c4 - c) s_list[st][h][c + lane] = NB | ((64 + sr) << 8) | ((64 + sc) << 16);
+        cnt2[h] = c4;
+      }
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+      const int cnt = cnt2[h];
       for (int g = 0; g < cnt; g += 4) {
-        // lane (kk, j) takes entry g + kk of the sub-tile's list (none past its end)
-        const int kx = g + kk < cnt ? (int)s_list[st][h][g + kk] : -1;
-        // every load unconditional (indices clamped into the staged data), so
-        // that they are issued together; a missing entry (kx < 0, the last
-        // group) and cells outside the footprint get W = 0, which also
-        // cancels the A values loaded for them (staged, finite)
-        const int kc = kx >= 0 ? kx : 0;
-        const int hd = s_hdr[kc];
-        const int qy = row - ((hd & 0xff) - 64), qx = col - (((hd >> 8) & 0xff) - 64);
-        const bool in = kx >= 0 && qy >= 0 && qy <= 2 * MW && qx >= 0 && qx <= 2 * MW;
-        const float fa = s_ay[kc * YS + 4 + min(max(qy, 0), 2 * MW)];
-        const float fb = s_bx[kc * XS + min(max(qx, 0), 2 * MW)];
-        const float bw = in ? fa * fb : 0.0f;
+        // lane (kk, j) takes item g + kk of the sub-tile's list. An entry on
+        // the list reaches the sub-tile, so the cell offsets row - origin
+        // and col - origin lie in [-3, 2m + 3] and index the zero-padded
+        // factor rows; cells outside the footprint read a zero factor, and a
+        // padding item reads entry NB (zero factors and samples).
+        const int it = s_list[st][h][g + kk];
+        const int kc = it & 0xff;
+        const float fa = s_ay[kc * YS + 4 + row + 64 - ((it >> 8) & 0xff)];
+        const float fb = s_bx[kc * XS + 4 + col + 64 - ((it >> 16) & 0xff)];
+        const float bw = fa * fb;
         const float4 a4 = *reinterpret_cast<const float4*>(s_c + kc * 2 * kGatherRhs + j * 4);
         const float av[4] = {a4.x, a4.y, a4.z, a4.w};
 #pragma unroll
