@@ -79,14 +79,13 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
   // per 16-row block) are one 16-byte read; [NB + 1][64]
   float* s_c = s_bx + (NB + 1) * XS;
   __shared__ float s_cf[2 * MW * (DEG + 1)];
-  // staged entries that reach each 4 x 4 sub-tile, per half of the round (in
-  // entry order), padded to a multiple of 4 items; each wave lists its own
-  // two sub-tiles. An item packs the entry index (bits 0-7) with the
+  // staged entries that reach each 4 x 4 sub-tile, in entry order, padded
+  // to a multiple of 4 items; each wave lists its own two sub-tiles. An item packs the entry index (bits 0-7) with the
   // footprint origin relative to the tile plus 64 (bits 8-15 rows, 16-23
   // columns); a padding item names the zero entry NB at the sub-tile's own
   // origin.
-  __shared__ int s_list[16][2][64];
-  static_assert(NB == 128 && kGatherNt == 512, "eight waves, 64-entry halves of a round");
+  __shared__ int s_list[16][NB];
+  static_assert(NB == 128 && kGatherNt == 512, "eight waves, a round in two 64-entry ballots");
   constexpr int NT = kGatherNt;
 
   const int* u = units + 4 * (int64_t)blockIdx.x;
@@ -196,7 +195,7 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
       const int st = 2 * wave + q;
       const int row = 4 * (st >> 2) + (j >> 2);  // tile cell of lane (kk, j) in B
       const int col = 4 * (st & 3) + (j & 3);
-      int cnt2[2];
+      int cnt = 0;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int hd = hd2[h];
@@ -210,22 +209,20 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
         const uint64_t bal = __builtin_amdgcn_ballot_w64(in);
         const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
-        if (in) s_list[st][h][pos] = (64 * h + lane) | ((hd & 0xffff) << 8);
-        const int c = __popcll(bal), c4 = (c + 3) & ~3;
-        if (lane < c4 - c) s_list[st][h][c + lane] = NB | ((64 + sr) << 8) | ((64 + sc) << 16);
-        cnt2[h] = c4;
+        if (in) s_list[st][cnt + pos] = (64 * h + lane) | ((hd & 0xffff) << 8);
+        cnt += __popcll(bal);
       }
+      const int c4 = (cnt + 3) & ~3;  // <= NB
+      if (lane < c4 - cnt)
+        s_list[st][cnt + lane] = NB | ((64 + 4 * (st >> 2)) << 8) | ((64 + 4 * (st & 3)) << 16);
       __builtin_amdgcn_wave_barrier();
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-      const int cnt = cnt2[h];
-      for (int g = 0; g < cnt; g += 4) {
+      for (int g = 0; g < c4; g += 4) {
         // lane (kk, j) takes item g + kk of the sub-tile's list. An entry on
         // the list reaches the sub-tile, so the cell offsets row - origin
         // and col - origin lie in [-3, 2m + 3] and index the zero-padded
         // factor rows; cells outside the footprint read a zero factor, and a
         // padding item reads entry NB (zero factors and samples).
-        const int it = s_list[st][h][g + kk];
+        const int it = s_list[st][g + kk];
         const int kc = it & 0xff;
         const float fa = s_ay[kc * YS + 4 + row + 64 - ((it >> 8) & 0xff)];
         const float fb = s_bx[kc * XS + 4 + col + 64 - ((it >> 16) & 0xff)];
@@ -235,7 +232,6 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb)
           acc[q][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb], bw, acc[q][mb], 0, 0, 0);
-      }
       }
     }
   }
