@@ -1415,8 +1415,13 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
   if (d == 2) modes = {1, 2, 3, 4, 7};
   if (d == 2 && f32) modes = {1, 2, 3, 4, 5, 7};
   if (d == 3) modes = {1, 7};
-  // the grid-tile gather holds 32 right-hand sides in the lanes of a wave
-  if (d == 2 && f32 && nrhs >= 8) modes.push_back(6);
+  // the grid-tile gather holds 32 right-hand sides in the lanes of a wave;
+  // its units also try 768 list entries (fewer split tiles than 512, fewer
+  // long units than 1024)
+  if (d == 2 && f32 && nrhs >= 8) {
+    modes.push_back(6);
+    items.insert(std::find(items.begin(), items.end(), 1024), 768);
+  }
 
   nfft_plan_t best = nullptr;
   double best_t = -1.0;
@@ -1463,8 +1468,9 @@ int nfft_plan_autotune(nfft_plan_t* out, int d, int M, double sigma, int m, int6
             // the register-tile kernels (modes 5, 7) take one rhs per work-group
             // and no LDS tile layout
             if ((md == 5 || md == 7) && (nr > 1 || pl != planes[0])) continue;
-            // the gather (mode 6) has one shape
+            // the gather (mode 6) has one shape; 768 entries per unit are for it alone
             if (md == 6 && (nr > 1 || pl != planes[0] || nt != threads[0])) continue;
+            if (K == 768 && md != 6) continue;
             // float64: only mode 7 takes the thread count
             if (!f32 && md != 7 && nt != threads[0]) continue;
             if (nt == 512 && md < 5) continue;

@@ -48,8 +48,9 @@ struct GatherLds {
   static constexpr size_t staging =
       kGatherNb * (2 * sizeof(int) + 4 * sizeof(float)) +
       (kGatherNb + 1) * ((XS + YS) * sizeof(float) + 2 * kGatherRhs * sizeof(float));
-  // the output transpose, per band of four tile rows: [rhs][65 cells][2] floats
-  static constexpr size_t transpose = (size_t)4 * kGatherRhs * 65 * 2 * sizeof(float);
+  // the output transpose, per band of four tile rows and half of the
+  // right-hand sides: [rhs][65 cells][2] floats
+  static constexpr size_t transpose = (size_t)4 * (kGatherRhs / 2) * 65 * 2 * sizeof(float);
   static constexpr size_t bytes = staging > transpose ? staging : transpose;
 };
 
@@ -85,7 +86,8 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
   // columns); a padding item names the zero entry NB at the sub-tile's own
   // origin.
   __shared__ int s_list[16][NB];
-  static_assert(NB == 128 && kGatherNt == 512, "eight waves, a round in two 64-entry ballots");
+  constexpr int NH = NB / 64;  // ballots of 64 entries per round
+  static_assert(NB % 64 == 0 && NB <= 128 && kGatherNt == 512, "eight waves, 64-entry ballots");
   constexpr int NT = kGatherNt;
 
   const int* u = units + 4 * (int64_t)blockIdx.x;
@@ -187,9 +189,9 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
     // reaches each (a ballot per half round), then those entries four at a
     // time. The lists are this wave's own: written and read by it alone.
     const int kk = lane >> 4, j = lane & 15;
-    int hd2[2];
+    int hd2[NH];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) hd2[h] = 64 * h + lane < nk ? s_hdr[64 * h + lane] : -1;
+    for (int h = 0; h < NH; ++h) hd2[h] = 64 * h + lane < nk ? s_hdr[64 * h + lane] : -1;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int st = 2 * wave + q;
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
       const int col = 4 * (st & 3) + (j & 3);
       int cnt = 0;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < NH; ++h) {
         const int hd = hd2[h];
         // footprint rows b0 + (edge ? 0 : 1) .. b0 + 2m against the
         // sub-tile's rows 4 sr .. 4 sr + 3, likewise for the columns
@@ -236,54 +238,48 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
     }
   }
 
-  // output: the two waves of each band of four tile rows transpose their
-  // sub-tiles through the band's LDS area, so that a store writes 16
-  // consecutive cells of one right-hand side: to the grid, or to the unit's
-  // partial slot (cells in tile order). (Accumulator element v of lane l in
-  // block mb: row m = 16 mb + 4 (l >> 4) + v of the 64 (m < 32: real part of
-  // right-hand side m, else imaginary part of m - 32), cell l & 15 of the
-  // sub-tile.)
+  // output, in two passes of 16 right-hand sides: the two waves of each
+  // band of four tile rows transpose their sub-tiles through the band's LDS
+  // area, so that a store writes 16 consecutive cells of one right-hand
+  // side: to the grid, or to the unit's partial slot (cells in tile order).
+  // (Accumulator element v of lane l in block mb: row m = 16 mb + 4 (l >> 4)
+  // + v of the 64 (m < 32: real part of right-hand side m, else imaginary
+  // part of m - 32), cell l & 15 of the sub-tile; pass p takes the blocks p
+  // and 2 + p, right-hand sides 16 p + 4 (l >> 4) + v.)
   const int band = wave >> 1;
-  float* tr = lds_f + band * (kGatherRhs * 65 * 2);
-  {
-    const int b = band;
-    __syncthreads();
-    {
-      // element (q, mb, v) goes to float ((m mod 32) * 65 + cell) * 2 + m / 32:
-      // a lane-dependent base plus a constant
-      const int cj = lane & 15;
-      float* base = tr + (4 * (lane >> 4) * 65 + (cj >> 2) * 16 + (cj & 3)) * 2;
+  constexpr int RH = kGatherRhs / 2;
+  float* tr = lds_f + band * (RH * 65 * 2);
+  const int cj = lane & 15;
+  float* base = tr + (4 * (lane >> 4) * 65 + (cj >> 2) * 16 + (cj & 3)) * 2;
+  float2* dst;
+  int64_t rs;
+  if (slot < 0) {
+    dst = grid + (int64_t)(16 * t0 + 4 * band + (lane >> 4)) * a.g.Ms + 16 * t1 + cj;
+    rs = grid_rs;
+  } else {
+    dst = part + (int64_t)slot * 256 + 64 * band + lane;
+    rs = part_rs;
+  }
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int sc = (2 * wave + q) & 3;
+  for (int p = 0; p < 2; ++p) {
+    __syncthreads();  // the LDS is free: the rounds, or the previous pass, are done with it
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
+    for (int q = 0; q < 2; ++q) {
+      const int sc = (2 * wave + q) & 3;
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            base[((16 * (mb & 1) + v) * 65 + 4 * sc) * 2 + (mb >> 1)] = acc[q][mb][v];
-      }
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) base[(v * 65 + 4 * sc) * 2 + c] = acc[q][p + 2 * c][v];
     }
     __syncthreads();
-    {
-      const int i = lane >> 4, j = lane & 15;
-      float2* dst;
-      int64_t rs;
-      if (slot < 0) {
-        dst = grid + (int64_t)(16 * t0 + 4 * b + i) * a.g.Ms + 16 * t1 + j;
-        rs = grid_rs;
-      } else {
-        dst = part + (int64_t)slot * 256 + 64 * b + lane;
-        rs = part_rs;
-      }
-      // the band's two waves store right-hand sides 0..15 and 16..31
-      const int r0 = 16 * (wave & 1);
-      const int r1 = min(r0 + 16, nrhs - rhs0);
-      dst += (int64_t)(rhs0 + r0) * rs;
+    // the band's two waves store 8 right-hand sides each
+    const int r0 = (RH / 2) * (wave & 1);
+    const int r1 = min(r0 + RH / 2, nrhs - rhs0 - RH * p);
+    float2* d = dst + (int64_t)(rhs0 + RH * p + r0) * rs;
 #pragma unroll 2
-      for (int rr = r0; rr < r1; ++rr, dst += rs) {
-        const float* src = tr + (rr * 65 + lane) * 2;
-        *dst = make_float2(src[0], src[1]);
-      }
+    for (int rr = r0; rr < r1; ++rr, d += rs) {
+      const float* src = tr + (rr * 65 + lane) * 2;
+      *d = make_float2(src[0], src[1]);
     }
   }
 }
