@@ -579,10 +579,10 @@ static hipError_t fft_launch(const FftArgs<R>& a, int nbatch, hipStream_t s) {
   constexpr int L = 1 << LOG2L;
   // L / R0 threads per line, at most 512 (the launch bound)
   if constexpr (LD != kLoadMerge && L >= 64 && L <= 1024) {
-    if (a.lpw == 1 && a.r0 == 2) return fft_launch_r0<R, LOG2L, INV, LD, ST, 2>(a, nbatch, s);
+    if (a.r0 == 2) return fft_launch_r0<R, LOG2L, INV, LD, ST, 2>(a, nbatch, s);
   }
   if constexpr (LD != kLoadMerge && L >= 64 && L <= 2048) {
-    if (a.lpw == 1 && a.r0 == 4) return fft_launch_r0<R, LOG2L, INV, LD, ST, 4>(a, nbatch, s);
+    if (a.r0 == 4) return fft_launch_r0<R, LOG2L, INV, LD, ST, 4>(a, nbatch, s);
   }
   return fft_launch_r0<R, LOG2L, INV, LD, ST, 8>(a, nbatch, s);
 }
@@ -606,7 +606,8 @@ static hipError_t fft_modes(const FftArgs<R>& a, bool inverse, LoadMode ld, Stor
 // and still give few work-groups gets two or four times the threads per line
 // (first stage radix 4 or 2; the merge loader keeps 8). The radix is decided
 // from one batch's lines, so a batched call computes exactly what separate
-// calls compute; only the lines per work-group count all batches.
+// calls compute; only the lines per work-group count all batches (a batched
+// radix-4 pass may take several lines per work-group, up to 512 threads).
 template <typename R>
 static int fft_lines_per_wg(int L, int64_t lines, int min_wg) {
   const int lds_cap = max(1, 32768 / ((L + L / 8 + 1) * (int)sizeof(cplx<R>)));
@@ -624,7 +625,8 @@ static void fft_shape(FftArgs<R>& a, int L, int nbatch) {
   else if (lpw1 == 1 && a.nlines < 2 * (int64_t)a.min_wg)
     a.r0 = 4;
   while (a.r0 < 8 && L / a.r0 > 512) a.r0 *= 2;  // at most 512 threads per work-group
-  a.lpw = a.r0 < 8 ? 1 : fft_lines_per_wg<R>(L, a.nlines * (int64_t)nbatch, a.min_wg);
+  // lines per work-group from all batches' lines, at most 512 threads
+  a.lpw = min(fft_lines_per_wg<R>(L, a.nlines * (int64_t)nbatch, a.min_wg), 512 / (L / a.r0));
 }
 
 template <typename R>
