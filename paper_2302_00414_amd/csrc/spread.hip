@@ -399,19 +399,21 @@ __global__ __launch_bounds__(256) void interp_kernel(InterpArgs<R> a) {
     const bool tab = D == 2 && a.psi != nullptr;
     R pairs[4 * MW];
     if (tab) load_factors<R, 4 * MW>(pairs, a.psi + (int64_t)i * (4 * MW));
+    R y[D];
+    bool e[D];
 #pragma unroll
     for (int t = 0; t < D; ++t) {
       l[t] = (int)((L >> (kLocBits * t)) & kLocMask);
-      const bool e = (L >> (kEdgeShift + t)) & 1u;
-      any_edge |= e;
+      e[t] = (L >> (kEdgeShift + t)) & 1u;
+      any_edge |= e[t];
+      y[t] = tab ? (R)0 : (R)2 * a.frac[t * N + i] - (R)1;
       if (tab) {
-        psi[t][0] = e ? a.edge : (R)0;
+        psi[t][0] = e[t] ? a.edge : (R)0;
 #pragma unroll
         for (int c = 0; c < 2 * MW; ++c) psi[t][1 + c] = pairs[2 * c + t];
-        continue;
       }
-      kb_poly<R, MW>(a.frac[t * N + i], e, a.edge, a.coef, psi[t]);
     }
+    if (!tab) kb_poly<R, MW, D>(y, e, a.edge, a.coef, psi);
     cplx<R> v;
     if (__any(any_edge))
       v = sum_node<R, D, MW, true>(tile, P, l, psi);

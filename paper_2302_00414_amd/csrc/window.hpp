@@ -40,24 +40,30 @@ template <typename R> struct PolyDeg;
 template <> struct PolyDeg<double> { static constexpr int value = 16; };
 template <> struct PolyDeg<float> { static constexpr int value = 10; };
 
-// Window factors of one node in one dimension from per-cell polynomials:
-// for cell i = 0..2m-1 (offset t = frac + m - 1 - i) the host fits
+// Window factors of one node from per-cell polynomials, for its D offsets
+// at once: for cell i = 0..2m-1 (offset t = frac + m - 1 - i) the host fits
 // psi(t) ~ sum_p coef[i][p] y^p with y = 2 frac - 1 in [-1, 1] (Chebyshev
-// interpolation, converted to monomials, error checked at plan time).
-// psi[0] is the extra closed-edge cell of a node on a grid line.
-template <typename R, int MW>
-__device__ __forceinline__ void kb_poly(R frac, bool edge, R edge_val,
-                                        const R* __restrict__ coef, R* psi) {
+// interpolation, converted to monomials, error checked at plan time); each
+// coefficient is read once and feeds the D Horner evaluations. psi[t][0] is
+// the extra closed-edge cell of a node on a grid line of dimension t.
+template <typename R, int MW, int D>
+__device__ __forceinline__ void kb_poly(const R* y, const bool* edge, R edge_val,
+                                        const R* __restrict__ coef, R (*psi)[2 * MW + 1]) {
   constexpr int DEG = PolyDeg<R>::value;
-  const R y = (R)2 * frac - (R)1;
-  psi[0] = edge ? edge_val : (R)0;
+#pragma unroll
+  for (int t = 0; t < D; ++t) psi[t][0] = edge[t] ? edge_val : (R)0;
 #pragma unroll
   for (int i = 0; i < 2 * MW; ++i) {
     const R* c = coef + i * (DEG + 1);
-    R v = c[DEG];
+    R v[D];
 #pragma unroll
-    for (int p = DEG - 1; p >= 0; --p) v = v * y + c[p];
-    psi[1 + i] = v;
+    for (int t = 0; t < D; ++t) v[t] = c[DEG];
+#pragma unroll
+    for (int p = DEG - 1; p >= 0; --p)
+#pragma unroll
+      for (int t = 0; t < D; ++t) v[t] = v[t] * y[t] + c[p];
+#pragma unroll
+    for (int t = 0; t < D; ++t) psi[t][1 + i] = v[t];
   }
 }
 
