@@ -382,6 +382,14 @@ __global__ __launch_bounds__(256) void interp_kernel(InterpArgs<R> a) {
     }
     tile[i] = grid[lin];
   }
+  // float64: the window polynomials beside the tile (every lane of a wave
+  // reads the same coefficient, an LDS broadcast; measured faster than the
+  // cached device reads in float64, slower in float32)
+  constexpr bool kLdsCoef = std::is_same<R, double>::value;
+  constexpr int NCF = 2 * MW * (PolyDeg<R>::value + 1);
+  R* cf = reinterpret_cast<R*>(tile + Ptot);
+  if constexpr (kLdsCoef)
+    for (int i = threadIdx.x; i < NCF; i += blockDim.x) cf[i] = a.coef[i];
   __syncthreads();
 
   const int64_t N = a.g.N;
@@ -413,7 +421,7 @@ __global__ __launch_bounds__(256) void interp_kernel(InterpArgs<R> a) {
         for (int c = 0; c < 2 * MW; ++c) psi[t][1 + c] = pairs[2 * c + t];
       }
     }
-    if (!tab) kb_poly<R, MW, D>(y, e, a.edge, a.coef, psi);
+    if (!tab) kb_poly<R, MW, D>(y, e, a.edge, kLdsCoef ? cf : a.coef, psi);
     cplx<R> v;
     if (__any(any_edge))
       v = sum_node<R, D, MW, true>(tile, P, l, psi);
@@ -460,7 +468,8 @@ static hipError_t spread_dm(const SpreadArgs<R>& a, int nrhs, hipStream_t s) {
 
 template <typename R, int D, int MW>
 static hipError_t interp_dm(const InterpArgs<R>& a, int nrhs, hipStream_t s) {
-  size_t lds = (size_t)a.g.Ptot * sizeof(cplx<R>);
+  size_t lds = (size_t)a.g.Ptot * sizeof(cplx<R>) +
+               (std::is_same<R, double>::value ? 2 * MW * (PolyDeg<R>::value + 1) * sizeof(R) : 0);
   hipLaunchKernelGGL((interp_kernel<R, D, MW>), dim3(a.g.nsub, nrhs), dim3(256), lds, s, a);
   return hipGetLastError();
 }
