@@ -324,10 +324,19 @@ __global__ __launch_bounds__(256) void gather_reduce_kernel(const int32_t* __res
   const int cell = threadIdx.x;
   const float2* src = part + (int64_t)r * part_rs + (int64_t)first * 256 + cell;
   KSum<float> sx, sy;
-  for (int k = 0; k < cnt; ++k) {
-    const float2 v = src[(int64_t)k * 256];
-    sx.add(v.x);
-    sy.add(v.y);
+  // the loads of up to 8 units are issued before their adds (unit order kept)
+  for (int k0 = 0; k0 < cnt; k0 += 8) {
+    float2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      v[u] = k0 + u < cnt ? src[(int64_t)(k0 + u) * 256] : make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (k0 + u < cnt) {
+        sx.add(v[u].x);
+        sy.add(v[u].y);
+      }
+    }
   }
   const int t0 = tile / nb, t1 = tile - (tile / nb) * nb;
   grid[(int64_t)r * grid_rs + (int64_t)(16 * t0 + (cell >> 4)) * Ms + 16 * t1 + (cell & 15)] =
