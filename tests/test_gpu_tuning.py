@@ -378,6 +378,34 @@ def test_grid_tile_gather(M, nrhs, m):
     p.close()
 
 
+@pytest.mark.parametrize("m", [4, 6])
+@pytest.mark.parametrize("items", [768, 1000])
+def test_grid_tile_gather_long_units(items, m):
+    """Spread mode 6 with units of several 128-entry staging rounds (768
+    entries, the autotuner's choice on the spiral workload, and 1000, whose
+    last round is partial): against the oracle (O2), against the register
+    tile (mode 5) up to rounding order, and two calls give the same bits."""
+    x = _nodes(2, 64, 140 + m)
+    N = x.shape[0]
+    w = (1.0 + 0.3 * wl.complex_normal(N, 141)) / N
+    F = wl.complex_normal((40, N), 142)
+    p = _plan(x, 64, m, "f32", max_rhs=40, tuning={"spread_mode": 6, "item_nodes": items})
+    assert p.tuning()["spread_mode"] == 6 and p.tuning()["item_nodes"] == items
+    p.set_weights(w)
+    Ft = torch.from_numpy(F)
+    got = _np(p.adjoint(Ft))
+    again = _np(p.adjoint(Ft))
+    assert np.array_equal(got.view(np.uint32), again.view(np.uint32))
+    ref = onfft.adjoint(x, w[None, :] * F, 64, 2.0, m)
+    e = metrics.rel_err_rows(got, ref)
+    print(f"[gather] items={items} m={m}: max rel err vs O2 {e.max():.3e}", flush=True)
+    assert e.max() <= TOL_O2["f32"]
+    p.set_tuning("spread_mode", 5)
+    reg = _np(p.adjoint(Ft))
+    assert metrics.rel_err(got, reg) <= TOL_ORDER["f32"]
+    p.close()
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("m", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("items", [64, 256, 700])
