@@ -723,13 +723,24 @@ int build_plan(nfft_plan_t p, const double* nodes, hipStream_t s) {
   p->nempty = (int)ebins.size();
   g.nsub = (int)istart.size();
   // launch order: largest work items first, so that the work-groups that
-  // start last are the small remainders of tiles (every item writes its own
-  // tile or slot, so the order changes no result)
+  // start last are the small remainders of tiles, in blocks of one item per
+  // compute unit whose direction alternates: the first work-groups go one
+  // to each compute unit, so that unit c receives the items of rank c,
+  // 2C - 1 - c, 2C + c, ... (C compute units), large ones paired with small
+  // ones (every item writes its own tile or slot, so the order changes no
+  // result)
   {
     std::vector<int32_t> order(istart.size());
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t u, int32_t v) { return icount[u] > icount[v]; });
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
+        ncu < 1)
+      ncu = 256;
+    const size_t C = (size_t)ncu;
+    for (size_t b0 = C; b0 < order.size(); b0 += 2 * C)
+      std::reverse(order.begin() + b0, order.begin() + std::min(order.size(), b0 + C));
     auto permute = [&](std::vector<int32_t>& a) {
       std::vector<int32_t> t(a.size());
       for (size_t i = 0; i < a.size(); ++i) t[i] = a[order[i]];
