@@ -267,15 +267,15 @@ __device__ __forceinline__ cplx<R> merge_cell2(const cplx<R>* __restrict__ tilep
   return mkc<R>((R)sx, (R)sy);
 }
 
-// The eight elements j + r L/8 (r = 0..7) of grid line q merged from the tile
-// partials, d = 2 or 3, tiles at least 2m wide whose edge divides L/8: the
-// line fixes the leading d - 1 coordinates, and the eight elements sit at the
-// same offset within their tiles, so the candidate tiles, offsets and weights
-// are worked out once for all eight. Same candidates, weights and summation
-// order as merge_cell2, so the same values.
-template <typename R, int D, int TPL>
+// The NV elements j + r TPL (r < NV, TPL = L / NV threads per line) of grid
+// line q merged from the tile partials, d = 2 or 3, tiles at least 2m wide
+// whose edge divides TPL: the line fixes the leading d - 1 coordinates, and
+// the elements sit at the same offset within their tiles, so the candidate
+// tiles, offsets and weights are worked out once for all of them. Same
+// candidates, weights and summation order as merge_cell2, so the same values.
+template <typename R, int D, int TPL, int NV>
 __device__ __forceinline__ void merge_line(const FftArgs<R>& a, int b, int64_t q, int j,
-                                           cplx<R> (&v)[8]) {
+                                           cplx<R> (&v)[NV]) {
   static_assert(D == 2 || D == 3, "lines of a 2-D or 3-D grid");
   constexpr int NH = 1 << (D - 1);  // candidates over the leading coordinates
   const Geom& g = a.g;
@@ -336,7 +336,7 @@ __device__ __forceinline__ void merge_line(const FftArgs<R>& a, int b, int64_t q
   const int Ptot = g.Ptot;
   const int tstep = TPL >> ts;  // tiles between consecutive elements
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
+  for (int r = 0; r < NV; ++r) {
     const int t1 = (j >> ts) + r * tstep;  // element < M_sigma: no wrap
     const int t1n = (t1 + dq1) & nm;
     cplx<R> u[2 * NH];
@@ -443,7 +443,6 @@ __global__ __launch_bounds__(512) void fft_pass_kernel(FftArgs<R> a) {
   constexpr int L = 1 << LOG2L;
   constexpr int TPL = L / R0;  // threads per line (one radix-R0 butterfly each)
   constexpr int LS = L + L / 8 + 1;  // LDS line stride: padded line plus one slot
-  static_assert(R0 == 8 || LD != kLoadMerge, "the merge loader takes eight elements a thread");
   extern __shared__ unsigned char smem_raw[];
   const int lpw = a.lpw;      // blockDim.x == lpw * TPL
   cplx<R>* buf0 = reinterpret_cast<cplx<R>*>(smem_raw);
@@ -471,9 +470,9 @@ __global__ __launch_bounds__(512) void fft_pass_kernel(FftArgs<R> a) {
     if constexpr (LD == kLoadMerge) {
       if (q < nlines && per_line) {
         if (a.g.d == 2)
-          merge_line<R, 2, TPL>(a, b, q, j, v);
+          merge_line<R, 2, TPL, R0>(a, b, q, j, v);
         else
-          merge_line<R, 3, TPL>(a, b, q, j, v);
+          merge_line<R, 3, TPL, R0>(a, b, q, j, v);
       } else if (q < nlines) {
 #pragma unroll
         for (int r = 0; r < R0; ++r) v[r] = load_elem<R, LD>(a, b, q, j + r * TPL, L);
@@ -573,15 +572,15 @@ static hipError_t fft_launch_r0(const FftArgs<R>& a, int nbatch, hipStream_t s) 
 
 // A pass whose lines already go one per work-group and still give few
 // work-groups gets two or four times the threads per line (a.r0: first stage
-// radix 4 or 2); the merge loader keeps radix 8.
+// radix 4 or 2; the merge loader then takes 4 or 2 elements a thread).
 template <typename R, int LOG2L, bool INV, int LD, int ST>
 static hipError_t fft_launch(const FftArgs<R>& a, int nbatch, hipStream_t s) {
   constexpr int L = 1 << LOG2L;
   // L / R0 threads per line, at most 512 (the launch bound)
-  if constexpr (LD != kLoadMerge && L >= 64 && L <= 1024) {
+  if constexpr (L >= 64 && L <= 1024) {
     if (a.r0 == 2) return fft_launch_r0<R, LOG2L, INV, LD, ST, 2>(a, nbatch, s);
   }
-  if constexpr (LD != kLoadMerge && L >= 64 && L <= 2048) {
+  if constexpr (L >= 64 && L <= 2048) {
     if (a.r0 == 4) return fft_launch_r0<R, LOG2L, INV, LD, ST, 4>(a, nbatch, s);
   }
   return fft_launch_r0<R, LOG2L, INV, LD, ST, 8>(a, nbatch, s);
@@ -604,7 +603,7 @@ static hipError_t fft_modes(const FftArgs<R>& a, bool inverse, LoadMode ld, Stor
 // threads (L/8 butterflies per line; 512 measured slower) and lowered while
 // that leaves fewer than min_wg work-groups. A pass whose lines go one per work-group
 // and still give few work-groups gets two or four times the threads per line
-// (first stage radix 4 or 2; the merge loader keeps 8). The radix is decided
+// (first stage radix 4 or 2, also for the merge loader). The radix is decided
 // from one batch's lines, so a batched call computes exactly what separate
 // calls compute; only the lines per work-group count all batches (a batched
 // radix-4 pass may take several lines per work-group, up to 512 threads).
