@@ -111,7 +111,11 @@ int nfft_plan(nfft_plan_t *out, int d, int M, double sigma, int m, int64_t N,
  *                             factors are read and evaluated once for them all.
  *   NFFT_TUNE_FFT_MIN_WG      an FFT pass gives each work-group fewer lines
  *                             while it would launch fewer work-groups than
- *                             this, 1..65536 (default 256).
+ *                             this, 1..65536 (default 256); a pass whose lines
+ *                             (of one right-hand side) then still go one per
+ *                             work-group and number less than twice this gets
+ *                             two or four times the threads per line (first
+ *                             stage radix 4 or 2).
  *   NFFT_TUNE_SPREAD_PLANES   layout of the private LDS tiles of that float32
  *                             kernel: 1 = one complex tile per lane group,
  *                             2 = two groups per node, one for the real and
