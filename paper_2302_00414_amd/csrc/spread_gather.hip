@@ -159,18 +159,22 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
       if (k < nk) fv[j] = fg[(int64_t)s_perm[k] * kGatherRhs + r];
     }
     // window factors: cell 0 the closed-edge cell, 1 + i polynomial i (both
-    // dimensions stored from index 4)
-    for (int e = tid; e < nk * 2 * K; e += NT) {
-      const int k = e / (2 * K);
-      const int rem = e - k * (2 * K);
-      const int dim = rem >= K ? 1 : 0;
-      const int q = rem - dim * K;
-      const float hv = horner<float>(s_cf + (q > 0 ? q - 1 : 0) * (DEG + 1), s_y[dim * NB + k]);
-      const float v = q == 0 ? (((s_hdr[k] >> (16 + dim)) & 1) ? a.edge : 0.0f) : hv;
-      if (dim)
-        s_bx[k * XS + 4 + q] = v;
-      else
-        s_ay[k * YS + 4 + q] = v;
+    // dimensions stored from index 4). Thread (k, part), k = tid / 4, takes
+    // entry k in dimension part / 2 and evaluates half part % 2 of the 2m
+    // polynomials at its offset (m independent Horner chains)
+    static_assert(NB * 4 == NT, "four threads an entry");
+    {
+      const int k = tid >> 2, dim = (tid >> 1) & 1, half = tid & 1;
+      if (k < nk) {
+        const float y = s_y[dim * NB + k];
+        float* dst = (dim ? s_bx + k * XS : s_ay + k * YS) + 4;
+        if (half == 0) dst[0] = ((s_hdr[k] >> (16 + dim)) & 1) ? a.edge : 0.0f;
+#pragma unroll
+        for (int i = 0; i < MW; ++i) {
+          const int pi = half * MW + i;
+          dst[1 + pi] = horner<float>(s_cf + pi * (DEG + 1), y);
+        }
+      }
     }
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
