@@ -18,10 +18,10 @@
 // work unit is a run of at most item_nodes entries of one tile's list; the
 // work-group stages 128 entries at a time in LDS (window factors, and the
 // samples of the 32 right-hand sides, read from a node-major copy so that a
-// node's 32 samples are 256 contiguous bytes), a ballot lists for each
-// sub-tile the staged entries that reach it, and each wave feeds those entries
-// four at a time (K = 4) to the matrix cores: lane (k, cell) forms
-// W_k[cell], lane (k, m) loads C[m][k]. A tile with one unit writes its grid
+// node's 32 samples are 256 contiguous bytes), each wave ballots for its two
+// sub-tiles the staged entries that reach them and feeds those entries four
+// at a time (K = 4) to the matrix cores: lane (k, cell) forms W_k[cell],
+// lane (k, m) loads C[m][k]. A tile with one unit writes its grid
 // cells directly; a tile whose list was cut into several units (the crowded
 // tiles) writes one 16 x 16 partial per unit, and a second kernel sums the
 // partials in unit order with compensation (Neumaier) into the grid. Every
