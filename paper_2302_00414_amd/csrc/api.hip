@@ -80,6 +80,7 @@ struct SharedData {
   // units over them and the tiles cut into several units (nfft::GatherArgs)
   int32_t* gl_node = nullptr;
   int32_t* gl_hdr = nullptr;
+  int32_t* g_iperm = nullptr;      // caller index -> tile order (the node-major copy's weights)
   int32_t* g_units = nullptr;
   int32_t* g_split = nullptr;
   int g_nunits = 0, g_nsplit = 0, g_nslots = 0;
@@ -518,8 +519,11 @@ int ensure_gather(nfft_plan_t p, hipStream_t s) {
     const int64_t N = p->N;
     const int nb = g.nb, m = p->m, ntiles = g.nbins;
     std::vector<uint32_t> hloc(N);
+    std::vector<int32_t> hperm(N), hiperm(N);
     HIP_TRY(p, hipMemcpyAsync(hloc.data(), p->loc, N * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(p, hipMemcpyAsync(hperm.data(), p->perm, N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(p, hipStreamSynchronize(s));
+    for (int64_t i = 0; i < N; ++i) hiperm[hperm[i]] = (int32_t)i;
     const std::vector<int32_t>& bs = sd.hbin_start;
     std::vector<int64_t> start(ntiles + 1, 0);
     std::vector<int32_t> node, hdr;
@@ -602,6 +606,9 @@ int ensure_gather(nfft_plan_t p, hipStream_t s) {
     TRY(dalloc(p, &sd.gl_hdr, ne * sizeof(int32_t)));
     TRY(dalloc(p, &sd.g_units, order.size() * sizeof(int32_t)));
     TRY(dalloc(p, &sd.g_split, std::max<size_t>(4, split.size()) * sizeof(int32_t)));
+    TRY(dalloc(p, &sd.g_iperm, std::max<int64_t>(1, N) * sizeof(int32_t)));
+    if (N > 0)
+      HIP_TRY(p, hipMemcpyAsync(sd.g_iperm, hiperm.data(), N * 4, hipMemcpyHostToDevice, s));
     if (!node.empty()) {
       HIP_TRY(p, hipMemcpyAsync(sd.gl_node, node.data(), node.size() * 4, hipMemcpyHostToDevice, s));
       HIP_TRY(p, hipMemcpyAsync(sd.gl_hdr, hdr.data(), hdr.size() * 4, hipMemcpyHostToDevice, s));
@@ -638,10 +645,11 @@ void drop_gather(nfft_plan_t p) {
     p->gft = nullptr;
   }
   if (!sd.g_units) return;
-  for (void* q : {(void*)sd.gl_node, (void*)sd.gl_hdr, (void*)sd.g_units, (void*)sd.g_split})
+  for (void* q : {(void*)sd.gl_node, (void*)sd.gl_hdr, (void*)sd.g_units, (void*)sd.g_split,
+                 (void*)sd.g_iperm})
     release(sd.allocs, q);
   sd.bytes -= sd.g_bytes;
-  sd.gl_node = sd.gl_hdr = sd.g_units = sd.g_split = nullptr;
+  sd.gl_node = sd.gl_hdr = sd.g_units = sd.g_split = sd.g_iperm = nullptr;
   sd.g_nunits = sd.g_nsplit = sd.g_nslots = 0;
   sd.g_bytes = 0;
 }
@@ -905,6 +913,7 @@ int run_adjoint(nfft_plan_t p, const void* f, void* fhat, int nrhs, hipStream_t 
       ga.nunits = sd.g_nunits;
       ga.gl_node = sd.gl_node;
       ga.gl_hdr = sd.gl_hdr;
+      ga.iperm = sd.g_iperm;
       ga.split = sd.g_split;
       ga.nsplit = sd.g_nsplit;
       ga.grid = (float2*)w.grid;

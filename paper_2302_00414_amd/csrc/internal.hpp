@@ -95,7 +95,11 @@ struct GatherArgs {
   int64_t grid_rs;
   float2* part;
   int64_t part_rs;
-  float2* fT;             // node-major samples [ceil(nrhs/32)][N][32] (written first)
+  // node-major weighted samples c = w f, [ceil(nrhs/32)][N][16] float4, node j's
+  // float4 q = (Re c_q, Re c_16+q, Im c_q, Im c_16+q) of its group's 32
+  // right-hand sides (written first)
+  float2* fT;
+  const int32_t* iperm;   // caller index -> tile order (for the weights)
 };
 bool spread_gather_supported(int d, int T, bool f64, int m);
 size_t spread_gather_lds_bytes(int m);

@@ -43,10 +43,10 @@ struct GatherLds {
   // factors stored per node and dimension: 4 zeros, K values, 4 or more zeros
   static constexpr int YS = (K + 8 + 3) / 4 * 4;
   static constexpr int XS = YS;
-  // per entry: header, caller index, two offsets, weight; factors and
-  // samples also for entry kGatherNb, all zeros (the padding of the lists)
+  // per entry: header, caller index, two offsets; factors and samples also
+  // for entry kGatherNb, all zeros (the padding of the lists)
   static constexpr size_t staging =
-      kGatherNb * (2 * sizeof(int) + 4 * sizeof(float)) +
+      kGatherNb * (2 * sizeof(int) + 2 * sizeof(float)) +
       (kGatherNb + 1) * ((XS + YS) * sizeof(float) + 2 * kGatherRhs * sizeof(float));
   // the output transpose, per band of four tile rows and half of the
   // right-hand sides: [rhs][65 cells][2] floats
@@ -71,9 +71,8 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
   int* s_hdr = reinterpret_cast<int*>(lds_f);  // packed footprint origin and edge flags
   int* s_perm = s_hdr + NB;                     // caller index
   float* s_y = reinterpret_cast<float*>(s_perm + NB);  // offsets 2 frac - 1, [2][NB]
-  float2* s_w = reinterpret_cast<float2*>(s_y + 2 * NB);  // weights
   constexpr int YS = GatherLds<MW>::YS;
-  float* s_ay = reinterpret_cast<float*>(s_w + NB);  // row factors [NB + 1][YS], cell q at 4 + q
+  float* s_ay = s_y + 2 * NB;  // row factors [NB + 1][YS], cell q at 4 + q
   float* s_bx = s_ay + (NB + 1) * YS;                   // column factors [NB + 1][XS], likewise
   // samples: component row m = 32 c + r (c: real 0, imaginary 1; r: rhs) of
   // entry k at s_c[k][m mod 16][m / 16], so that a lane's four A values (one
@@ -117,14 +116,12 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
   // one round ahead, so that its latency hides behind the round before
   int p_hd = 0, p_pm = 0;
   float p_y0 = 0.0f, p_y1 = 0.0f;
-  float2 p_w = make_float2(0.0f, 0.0f);
   auto fetch = [&](int cb) {
     if (tid < NB && cb + tid < e_end) {
       p_hd = gl_hdr[cb + tid];
       const int i = gl_node[cb + tid];
       p_y0 = 2.0f * a.frac[i] - 1.0f;
       p_y1 = 2.0f * a.frac[N + i] - 1.0f;
-      p_w = a.w[i];
       p_pm = a.perm[i];
     }
   };
@@ -139,24 +136,24 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
         s_perm[tid] = p_pm;
         s_y[tid] = p_y0;
         s_y[NB + tid] = p_y1;
-        s_w[tid] = p_w;
       }
       fetch(c0 + NB);  // the next round's entries, in flight from here
     }
     __syncthreads();
     // samples c_j = w_j f_j of the work-group's right-hand sides, from the
-    // node-major copy (a node's 32 samples are 256 contiguous bytes): item
-    // e = tid + NT j is right-hand side e mod 32 of entry e / 32; the window
-    // factors are evaluated while the loads are in flight
-    constexpr int SPT = NB * kGatherRhs / NT;
-    const float2* fg = fT + (int64_t)blockIdx.y * N * kGatherRhs;
-    float2 fv[SPT];
+    // weighted node-major copy, which holds a node's 32 in the layout of s_c
+    // (256 contiguous bytes): float4 e = tid + NT j is float4 e mod 16 of
+    // entry e / 16; the window factors are evaluated while the loads are in
+    // flight
+    constexpr int SPT = NB * 16 / NT;
+    const float4* fg = reinterpret_cast<const float4*>(fT) + (int64_t)blockIdx.y * N * 16;
+    float4 fv[SPT];
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
       const int e = tid + NT * j;
-      const int k = e / kGatherRhs, r = e % kGatherRhs;
-      fv[j] = make_float2(0.0f, 0.0f);
-      if (k < nk) fv[j] = fg[(int64_t)s_perm[k] * kGatherRhs + r];
+      const int k = e >> 4;
+      fv[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (k < nk) fv[j] = fg[(int64_t)s_perm[k] * 16 + (e & 15)];
     }
     // window factors: cell 0 the closed-edge cell, 1 + i polynomial i (both
     // dimensions stored from index 4). Thread (k, part), k = tid / 4, takes
@@ -179,14 +176,7 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
       const int e = tid + NT * j;
-      const int k = e / kGatherRhs, r = e % kGatherRhs;
-      if (k < nk) {
-        const float2 wv = s_w[k];
-        // m = r (real part): block r / 16; m = 32 + r (imaginary): block 2 + r / 16
-        float* ck = s_c + k * 2 * kGatherRhs + (r & 15) * 4 + (r >> 4);
-        ck[0] = wv.x * fv[j].x - wv.y * fv[j].y;
-        ck[2] = wv.x * fv[j].y + wv.y * fv[j].x;
-      }
+      if ((e >> 4) < nk) reinterpret_cast<float4*>(s_c)[e] = fv[j];
     }
     __syncthreads();
     // the wave's two sub-tiles: the lists of staged entries whose footprint
@@ -288,16 +278,23 @@ __global__ __launch_bounds__(kGatherNt) void spread_gather_kernel(
   }
 }
 
-// The samples of every group of 32 right-hand sides node-major: fT[g][j][r]
-// = f[32 g + r][j] (caller order; zero for right-hand sides past nrhs), by
-// tiles of 32 right-hand sides x 64 nodes through LDS, both sides coalesced.
+// The weighted samples c = w f of every group of 32 right-hand sides
+// node-major: fT[g][j] = 16 float4, float4 q = (Re c_q, Re c_16+q, Im c_q,
+// Im c_16+q) with c_r = w_j f[32 g + r][j] (caller order j, its weight found
+// through the inverse node permutation; zero for right-hand sides past nrhs),
+// the layout in which the gather stages them. Tiles of 32 right-hand sides x
+// 64 nodes through LDS, loads and stores coalesced.
 __global__ __launch_bounds__(256) void gather_transpose_kernel(const float2* __restrict__ f,
                                                                int64_t f_rs, int64_t N, int nrhs,
-                                                               float2* __restrict__ fT) {
+                                                               const float2* __restrict__ w,
+                                                               const int32_t* __restrict__ iperm,
+                                                               float4* __restrict__ fT) {
   __shared__ float2 t[64][kGatherRhs + 1];
+  __shared__ float2 s_wv[64];
   const int64_t j0 = (int64_t)blockIdx.x * 64;
   const int g = blockIdx.y;
   const int tid = threadIdx.x;
+  if (tid < 64) s_wv[tid] = j0 + tid < N ? w[iperm[j0 + tid]] : make_float2(0.f, 0.f);
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int e = tid + 256 * q;
@@ -307,10 +304,15 @@ __global__ __launch_bounds__(256) void gather_transpose_kernel(const float2* __r
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < 4; ++q) {
     const int e = tid + 256 * q;
-    const int jj = e / kGatherRhs, r = e % kGatherRhs;
-    if (j0 + jj < N) fT[((int64_t)g * N + j0 + jj) * kGatherRhs + r] = t[jj][r];
+    const int jj = e >> 4, qq = e & 15;
+    if (j0 + jj < N) {
+      const float2 wv = s_wv[jj], u = t[jj][qq], v = t[jj][16 + qq];
+      fT[((int64_t)g * N + j0 + jj) * 16 + qq] =
+          make_float4(wv.x * u.x - wv.y * u.y, wv.x * v.x - wv.y * v.y, wv.x * u.y + wv.y * u.x,
+                      wv.x * v.y + wv.y * v.x);
+    }
   }
 }
 
@@ -379,7 +381,8 @@ hipError_t launch_spread_gather(const SpreadArgs<float>& a, const GatherArgs& ga
   if (ga.nunits == 0) return hipSuccess;
   const int groups = (nrhs + kGatherRhs - 1) / kGatherRhs;
   hipLaunchKernelGGL(gather_transpose_kernel, dim3((unsigned)((a.g.N + 63) / 64), groups), dim3(256),
-                     0, s, a.f, a.f_rs, a.g.N, nrhs, ga.fT);
+                     0, s, a.f, a.f_rs, a.g.N, nrhs, reinterpret_cast<const float2*>(a.w), ga.iperm,
+                     reinterpret_cast<float4*>(ga.fT));
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   switch (a.g.m) {
