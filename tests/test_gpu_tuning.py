@@ -257,6 +257,30 @@ def test_3d_m8_float32():
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("min_wg", [1024, 65536])
+def test_3d_merge_wide_first_stage(prec, min_wg):
+    """d = 3, M = 32 (64-point lines, 4096 per pass), tile edge 8: with the FFT
+    width tuning at 65536 work-groups every pass takes one line per
+    work-group and a radix-2 first stage, so the merge loader sums the tile
+    partials two elements a thread (at 1024, radix 8, eight a thread).
+    Against the oracle (O2), adjoint and forward."""
+    M, m = 32, 3
+    x = _nodes(3, M, 75)
+    N = x.shape[0]
+    w = (1.0 + 0.3 * wl.complex_normal(N, 76)) / N
+    f = wl.complex_normal(N, 77)
+    p = _plan(x, M, m, prec, tuning={"tile_edge": 8, "fft_min_wg": min_wg})
+    assert p.tuning()["fft_min_wg"] == min_wg
+    p.set_weights(w)
+    got = _np(p.adjoint(torch.from_numpy(f)))
+    assert metrics.rel_err(got, onfft.adjoint(x, w * f, M, 2.0, m)) <= TOL_O2[prec]
+    fh = wl.complex_normal(M ** 3, 78)
+    assert metrics.rel_err(_np(p.forward(torch.from_numpy(fh))),
+                           onfft.forward(x, fh, M, 2.0, m)) <= TOL_O2[prec]
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("m", [2, 6, 8])
 @pytest.mark.parametrize("rpg", [1, 2])
 def test_row_sweep_multi_rhs(prec, m, rpg):
